@@ -1,0 +1,167 @@
+/*
+ * rkhsba -- MI355X (gfx950) library for the data-parallel hot path of RKHS-BA
+ * (arXiv 2403.01254): the correspondence-free multi-frame RKHS objective, its
+ * Gauss-Newton / IRLS normal equations and the pose update.
+ *
+ * Objective (Sec. III-B, Eq. (eq:inner_product_actual_ba)):
+ *     F(T) = sum_{(m,n) in C} sum_{i,j} sigma^2 exp(-|T_m x_i - T_n z_j|^2 / (2 ell^2)) c_ij
+ * with c_ij = <l(x_i), l(z_j)> the inner product of the points' pose-invariant
+ * features (Sec. III-A, Eq. (eq:double_sum)), summed over the point pairs
+ * inside the truncation radius r_c = cutoff_factor * ell (the double sum is
+ * sparse, Sec. III-B).  The solver of Sec. V-A freezes the weights
+ * w_ij = c_ij exp(-|u|^2 / (2 ell^2)) (Eq. (eq:irls_weight)), u = T_m x_i - T_n z_j,
+ * and takes Gauss-Newton steps on the weighted least squares of
+ * Eq. (eq:irls_final) with right perturbations T exp(eps^), eps = [rho; phi],
+ * holding one frame fixed and recomputing the weights after every step.
+ *
+ * Conventions shared by every call
+ *   - All pointers are HOST pointers unless an argument says otherwise.  The
+ *     caller owns every buffer it passes; the library copies what it keeps.
+ *   - pose: 12 doubles [R (3x3 row-major) | t], mapping frame-local -> world.
+ *     poses: K*12 doubles, frame-major.
+ *   - edges: E*2 int32 (m, n), 0-based, m != n; each listed entry is one factor
+ *     F^{mn} (a duplicated entry counts twice).
+ *   - b: 6K doubles, b = sum w J^T u (so grad_eps F = -(sigma^2/ell^2) b).
+ *     H: (6K)^2 doubles row-major, H = sum w J^T J, J = du/d eps (Gauss-Newton
+ *     matrix with the weights frozen).  Frame-major, [rho(3); phi(3)] per frame.
+ *   - Every call returns an rkhsba_status; rkhsba_last_error() describes the
+ *     last failure on that context.  Calls on one context must not overlap.
+ *   - Membership in the truncation radius is decided by the FP32 rule below,
+ *     so the pair set is exactly reproducible on a CPU.
+ *
+ * FP32 membership rule (pair (i in frame m, j in frame n)):
+ *   R_nm[a][b] = fma(Rn[2][a], Rm[2][b], fma(Rn[1][a], Rm[1][b], Rn[0][a]*Rm[0][b]))
+ *   dt = t_m - t_n;  t_nm[a] = fma(Rn[2][a], dt[2], fma(Rn[1][a], dt[1], Rn[0][a]*dt[0]))
+ *   q[a] = fma(R_nm[a][2], x[2], fma(R_nm[a][1], x[1], fma(R_nm[a][0], x[0], t_nm[a])))
+ *   (all FP64, fma correctly rounded); q32 = float(q) (round to nearest even);
+ *   in float: d = q32 - z; s2 = fmaf(dz,dz, fmaf(dy,dy, dx*dx));
+ *   inside iff s2 <= float(r_c * r_c), r_c = cutoff_factor * ell in FP64.
+ *   With class-id features a pair also needs equal labels (c_ij = 0 otherwise).
+ *
+ * Voxel structure: each frame is hashed once, in its own local coordinates,
+ * into cubic cells of edge r_c / cell_subdiv: k = floor(x * inv_cell) in FP64
+ * with inv_cell = 1 / ((cutoff_factor * ell) / cell_subdiv), origin = min k,
+ * dims = max k - min k + 1, key = ((kz-oz)*NY + (ky-oy))*NX + (kx-ox); points
+ * are stably sorted by key (ties keep input order).
+ */
+#ifndef RKHSBA_H
+#define RKHSBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rkhsba_ctx rkhsba_ctx;
+
+typedef enum {
+  RKHSBA_OK = 0,
+  RKHSBA_EINVAL = -1,   /* invalid argument (sizes, indices, NaN/Inf, ell <= 0, ...) */
+  RKHSBA_ENOMEM = -2,   /* device allocation failed or a grid does not fit its limits */
+  RKHSBA_EDEVICE = -3,  /* HIP runtime error */
+  RKHSBA_ENOTPD = -4,   /* Cholesky pivot <= 0 in a Gauss-Newton step */
+  RKHSBA_ESTATE = -5    /* call out of order (e.g. no frames built yet) */
+} rkhsba_status;
+
+typedef enum {
+  RKHSBA_FEAT_CLASS_ID = 0,    /* one-hot labels passed as uint16 class ids (N_m values) */
+  RKHSBA_FEAT_DENSE_F32 = 1,   /* dense float32 rows (N_m * D values), D <= 64 */
+  RKHSBA_FEAT_DENSE_BF16 = 2,  /* as DENSE_F32, inner products on MFMA in bfloat16 */
+  RKHSBA_FEAT_DENSE_FP8 = 3    /* as DENSE_F32, inner products on MFMA in fp8 e4m3 */
+} rkhsba_feat_kind;
+
+typedef struct {
+  double ell;            /* lengthscale of Eq. (eq:kernel), > 0 */
+  double cutoff_factor;  /* truncation radius r_c = cutoff_factor * ell (default 3) */
+  double sigma;          /* kernel amplitude of Eq. (eq:kernel) (default 1) */
+  double damping_rel;    /* GN damping mu = damping_rel * trace(H_red) / dim(H_red) (default 1e-10) */
+  int fixed_frame;       /* gauge: this frame is not moved (default 0, Sec. V-A) */
+  int clamp_negative_c;  /* use max(c_ij, 0) for dense features (default 1) */
+  int device;            /* HIP device ordinal (default 0) */
+  int cell_subdiv;       /* voxel cells per truncation radius, 1..4 (default 3) */
+  int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
+  void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
+} rkhsba_options;
+
+/* Fills *opt with the defaults listed above (ell = 0.1). */
+void rkhsba_default_options(rkhsba_options* opt);
+
+/* Creates a context on opt->device.  *out is set to NULL on failure. */
+int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt);
+
+/* Releases every device buffer of the context.  NULL is allowed. */
+void rkhsba_destroy(rkhsba_ctx* ctx);
+
+/* Text of the last failure on ctx ("" if none).  Valid until the next call on ctx. */
+const char* rkhsba_last_error(const rkhsba_ctx* ctx);
+
+/* Stages K frames (Sec. III, problem setup: point sets X_m with pose-invariant
+ * features l(x), Eq. (eq:pc_function)) and builds each frame's voxel structure
+ * in local coordinates.
+ *   n_points: K counts (each >= 1).
+ *   xyz:      K pointers to N_m*3 float32 (x,y,z rows), frame-local coordinates.
+ *   feats:    K pointers: uint16 class ids (kind CLASS_ID) or N_m*D float32 rows.
+ *   is_device: 0 = xyz/feats are host pointers, 1 = device pointers on ctx's
+ *             device (read once on the context's stream).
+ * Replaces any frames built before.  Poses are not needed here. */
+int rkhsba_build_neighbors(rkhsba_ctx* ctx, int K, const int64_t* n_points, const float* const* xyz,
+                           int feat_kind, int D, const void* const* feats, int is_device);
+
+/* F at `poses` (Eq. (eq:inner_product_actual_ba), truncated), total and per
+ * edge (loss_per_edge: E doubles, nullable), and the number of in-radius pairs
+ * with c_ij != 0 (n_pairs, nullable). */
+int rkhsba_eval_loss(rkhsba_ctx* ctx, const double* poses, int E, const int32_t* edges,
+                     double* loss_total, double* loss_per_edge, int64_t* n_pairs);
+
+/* H (6K x 6K, full, no frame removed), b (6K) and F at `poses` (Sec. V-A,
+ * normal equations of Eq. (eq:irls_final) with the weights of
+ * Eq. (eq:irls_weight) frozen).  H, b, loss_total, n_pairs are nullable. */
+int rkhsba_accumulate_normal_eqs(rkhsba_ctx* ctx, const double* poses, int E, const int32_t* edges,
+                                 double* H, double* b, double* loss_total, int64_t* n_pairs);
+
+/* n_iter Gauss-Newton / IRLS steps in place on poses_inout (Sec. V-A): each
+ * step recomputes the weights at the current poses, solves
+ * (H_red + mu I) delta = -b_red over every frame except fixed_frame (FP64
+ * Cholesky on the GPU) and applies T_m <- T_m exp(delta_m^).
+ * loss_per_iter (n_iter+1, nullable): F at the poses entering each step and
+ * after the last; pairs_per_iter (n_iter+1, nullable): in-radius pair counts.
+ * Returns RKHSBA_ENOTPD if a Cholesky pivot is not positive (poses then hold
+ * the last successful step). */
+int rkhsba_gn_step(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* edges, int n_iter,
+                   double* loss_per_iter, int64_t* pairs_per_iter);
+
+/* Debug/parity: the in-radius pairs of edge (m, n) at `poses` under the FP32
+ * membership rule (and equal labels for class ids), as (i, j) original point
+ * indices sorted by (i, j).  Writes min(total, cap) pairs to pairs (cap*2
+ * int32) and the total count to *n_out. */
+int rkhsba_export_pairs(rkhsba_ctx* ctx, const double* poses, int m, int n, int64_t cap, int32_t* pairs,
+                        int64_t* n_out);
+
+/* Debug/parity: the voxel structure of one frame.  perm (N_m int32): sorted
+ * position -> original index; keys (N_m uint32): sorted cell keys; origin[3],
+ * dims[3]: the frame's cell grid.  Any pointer may be NULL. */
+int rkhsba_export_voxels(rkhsba_ctx* ctx, int frame, int32_t* perm, uint32_t* keys, int32_t* origin,
+                         int32_t* dims);
+
+/* Stage timing for measurement.  When enabled, the context brackets each
+ * stage's launches with HIP events on its own stream and, at the end of every
+ * call, adds the elapsed GPU time per stage.  Stages: */
+enum {
+  RKHSBA_PROF_BUILD = 0,       /* voxel build of rkhsba_build_neighbors */
+  RKHSBA_PROF_BIN = 1,         /* relative transforms + source binning sort, per evaluation */
+  RKHSBA_PROF_PAIRS = 2,       /* candidate sweep accumulating moments (Gauss-Newton evaluations) */
+  RKHSBA_PROF_PAIRS_LOSS = 3,  /* candidate sweep, loss-only evaluations */
+  RKHSBA_PROF_FINALIZE = 4,    /* per-point finalisation + per-edge reduction */
+  RKHSBA_PROF_SOLVE = 5,       /* assembly + Cholesky + pose update */
+  RKHSBA_PROF_STAGES = 6
+};
+int rkhsba_profile_enable(rkhsba_ctx* ctx, int on);
+/* total_ms / launches (nullable) accumulated for `stage` since the last reset. */
+int rkhsba_profile_read(rkhsba_ctx* ctx, int stage, double* total_ms, int64_t* launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKHSBA_H */

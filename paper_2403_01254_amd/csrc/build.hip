@@ -1,0 +1,226 @@
+// Voxel-structure build: cell coordinates, cell keys, gather into key order,
+// and the per-row cell tables used by the candidate sweeps.  Runs once per
+// set of frames; each frame is hashed in its own local coordinates, so the
+// structure does not depend on the poses.
+#include <climits>
+
+#include "rkhsba_device.h"
+
+namespace rkhsba {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline void frame_of(const int64_t* __restrict__ off, int K, int64_t i, int& f, int64_t& local) {
+  f = upper_segment(off, K, i);
+  local = i - off[f];
+}
+
+// k = floor(x * inv_cell) per axis (FP64), and per-frame min/max.
+// minmax layout: [f*6 + 0..2] min, [f*6 + 3..5] max; [K*6] error flag.
+__global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __restrict__ xyz,
+                                                          const int64_t* __restrict__ off, int K, int64_t n_total,
+                                                          double inv_cell, int32_t* __restrict__ cell,
+                                                          int32_t* __restrict__ minmax) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_total) return;
+  int f;
+  int64_t l;
+  frame_of(off, K, i, f, l);
+  const float* p = xyz[f] + 3 * l;
+  for (int a = 0; a < 3; ++a) {
+    const float v = p[a];
+    const double s = (double)v * inv_cell;
+    int k = 0;
+    if (!(fabs(s) < 1.0e9)) {  // NaN, Inf or beyond the int32 cell range
+      atomicOr(&minmax[K * 6], 1);
+    } else {
+      k = (int)floor(s);
+    }
+    cell[3 * i + a] = k;
+    atomicMin(&minmax[f * 6 + a], k);
+    atomicMax(&minmax[f * 6 + 3 + a], k);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cell_keys(const int32_t* __restrict__ cell,
+                                                        const int64_t* __restrict__ off,
+                                                        const FrameInfo* __restrict__ frames, int K, int64_t n_total,
+                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_total) return;
+  int f;
+  int64_t l;
+  frame_of(off, K, i, f, l);
+  const FrameInfo& F = frames[f];
+  const uint32_t kx = (uint32_t)(cell[3 * i] - F.org[0]);
+  const uint32_t ky = (uint32_t)(cell[3 * i + 1] - F.org[1]);
+  const uint32_t kz = (uint32_t)(cell[3 * i + 2] - F.org[2]);
+  keys[i] = (kz * (uint32_t)F.dim[1] + ky) * (uint32_t)F.dim[0] + kx;
+  vals[i] = (uint32_t)l;
+}
+
+// Gathers points (and features) into key order.  pts.w carries the class id
+// bits for one-hot features.
+__global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restrict__ xyz,
+                                                     const void* const* __restrict__ feats, int feat_kind, int D,
+                                                     int Dp, const FrameInfo* __restrict__ frames,
+                                                     const int64_t* __restrict__ off, int K, int64_t n_total,
+                                                     const uint32_t* __restrict__ sorted_vals,
+                                                     float4* __restrict__ pts, float* __restrict__ feat,
+                                                     int32_t* __restrict__ perm) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n_total) return;
+  int f;
+  int64_t s;
+  frame_of(off, K, p, f, s);
+  const int64_t o = sorted_vals[p];
+  const float* x = xyz[f] + 3 * o;
+  float w = 0.0f;
+  if (feat_kind == 0) w = __uint_as_float((uint32_t)((const uint16_t*)feats[f])[o]);
+  pts[p] = make_float4(x[0], x[1], x[2], w);
+  perm[p] = (int32_t)o;
+  if (feat_kind != 0) {
+    const float* src = (const float*)feats[f] + o * D;
+    float* dst = feat + p * Dp;
+    for (int k = 0; k < Dp; ++k) dst[k] = k < D ? src[k] : 0.0f;
+  }
+}
+
+__device__ inline void decode(uint32_t key, const FrameInfo& F, int& kx, int& ky, int& kz) {
+  const uint32_t nx = (uint32_t)F.dim[0], ny = (uint32_t)F.dim[1];
+  kx = (int)(key % nx);
+  const uint32_t r = key / nx;
+  ky = (int)(r % ny);
+  kz = (int)(r / ny);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_init(int4* __restrict__ rows, int64_t n_rows) {
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r < n_rows) rows[r] = make_int4(INT_MAX, INT_MIN, 0, 0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_extent(const uint32_t* __restrict__ keys,
+                                                         const FrameInfo* __restrict__ frames,
+                                                         const int64_t* __restrict__ off, int K, int64_t n_total,
+                                                         int4* __restrict__ rows) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n_total) return;
+  int f;
+  int64_t s;
+  frame_of(off, K, p, f, s);
+  const FrameInfo& F = frames[f];
+  int kx, ky, kz;
+  decode(keys[p], F, kx, ky, kz);
+  int4* row = rows + F.row_off + (int64_t)kz * F.dim[1] + ky;
+  atomicMin(&row->x, kx);
+  atomicMax(&row->y, kx);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_sizes(const int4* __restrict__ rows, int64_t n_rows,
+                                                        uint32_t* __restrict__ sizes) {
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n_rows) return;
+  const int4 v = rows[r];
+  sizes[r] = v.y >= v.x ? (uint32_t)(v.y - v.x + 2) : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_store_offsets(const uint32_t* __restrict__ offs, int64_t n_rows,
+                                                                int4* __restrict__ rows) {
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r < n_rows) rows[r].z = (int)offs[r];
+}
+
+// xtab[row][x - x_lo] = first point (frame-local sorted index) of cell x or,
+// for an empty cell, of the next occupied cell in the row; the entry after
+// x_hi is the end of the row.  Every entry is written by exactly one thread:
+// the head of each occupied cell fills the entries from the previous occupied
+// cell of the row (exclusive) up to its own; the row's last point writes the
+// end entry.
+__global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restrict__ keys,
+                                                        const FrameInfo* __restrict__ frames,
+                                                        const int64_t* __restrict__ off, int K, int64_t n_total,
+                                                        const int4* __restrict__ rows, uint32_t* __restrict__ xtab) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n_total) return;
+  int f;
+  int64_t s;
+  frame_of(off, K, p, f, s);
+  const FrameInfo& F = frames[f];
+  const uint32_t key = keys[p];
+  int kx, ky, kz;
+  decode(key, F, kx, ky, kz);
+  const int64_t row = (int64_t)kz * F.dim[1] + ky;
+  const int4 R = rows[F.row_off + row];
+  uint32_t* xt = xtab + F.xt_off + (uint32_t)R.z;
+  const bool has_prev = s > 0;
+  const bool has_next = s + 1 < F.n;
+  const uint32_t kprev = has_prev ? keys[p - 1] : 0u;
+  if (!has_prev || kprev != key) {  // head of an occupied cell
+    int x0 = R.x;
+    if (has_prev) {
+      int px, py, pz;
+      decode(kprev, F, px, py, pz);
+      if ((int64_t)pz * F.dim[1] + py == row) x0 = px + 1;
+    }
+    for (int x = x0; x <= kx; ++x) xt[x - R.x] = (uint32_t)s;
+  }
+  bool row_end = !has_next;
+  if (has_next) {
+    int nx, ny, nz;
+    decode(keys[p + 1], F, nx, ny, nz);
+    row_end = (int64_t)nz * F.dim[1] + ny != row;
+  }
+  if (row_end) xt[R.y + 1 - R.x] = (uint32_t)(s + 1);
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
+                              double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st) {
+  if (n_total > 0)
+    k_cell_coords<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_in_off, K, n_total, inv_cell, d_cell, d_minmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, const FrameInfo* d_frames, int K,
+                            int64_t n_total, uint32_t* d_keys, uint32_t* d_vals, hipStream_t st) {
+  if (n_total > 0)
+    k_cell_keys<<<blocks(n_total), kThreads, 0, st>>>(d_cell, d_in_off, d_frames, K, n_total, d_keys, d_vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
+                         const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
+                         const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
+                         hipStream_t st) {
+  if (n_total > 0)
+    k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, D, Dp, d_frames, d_in_off, K,
+                                                   n_total, d_sorted_vals, d_pts, d_feat, d_perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
+                       int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
+                       uint64_t* d_total, hipStream_t st) {
+  if (n_rows > 0) k_row_init<<<blocks(n_rows), kThreads, 0, st>>>(d_rows, n_rows);
+  if (n_total > 0) k_row_extent<<<blocks(n_total), kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows);
+  if (n_rows > 0) {
+    k_row_sizes<<<blocks(n_rows), kThreads, 0, st>>>(d_rows, n_rows, d_sizes);
+    hipError_t e = launch_exclusive_scan(d_sizes, d_sizes, n_rows, d_scan_tmp, d_total, st);
+    if (e != hipSuccess) return e;
+    k_row_store_offsets<<<blocks(n_rows), kThreads, 0, st>>>(d_sizes, n_rows, d_rows);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
+                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, hipStream_t st) {
+  if (n_total > 0)
+    k_xtab_fill<<<blocks(n_total), kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows, d_xtab);
+  return hipGetLastError();
+}
+
+}  // namespace rkhsba

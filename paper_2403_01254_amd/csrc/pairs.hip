@@ -1,0 +1,497 @@
+// Per-iteration hot path: relative transforms, source-point binning, the
+// candidate sweep that accumulates per-point moments, and the per-point
+// finalisation into per-edge Gauss-Newton blocks.
+//
+// Sweep (one wavefront per pass of P source points of one edge):
+//   * the P source points were binned by the Morton code of their cell in the
+//     target frame, so a pass is spatially compact;
+//   * the pass's bounding box (of the transformed points q = T_nm x) is
+//     grown by the reach (>= r_c) and walked row by row over the target
+//     frame's cell rows; each row trims its x-range to the part of the ball
+//     around the box that it can touch and yields one contiguous range of
+//     target points (the frame is stored in cell-key order);
+//   * G = 64/P lanes share a source point and split each range by stride G;
+//     each lane applies the FP32 membership rule to its candidates and, for
+//     pairs inside, accumulates the moments of the target-frame residual
+//     d = q - z with weight w = c exp(-|d|^2 / 2 ell^2)  (Eq. (eq:irls_weight)):
+//         A = sum w,  B = sum w d,  C = sum w d d^T         (10 floats)
+//   * the G partial moments are summed with cross-lane shuffles and stored
+//     per source point.
+// Finalisation turns each point's moments into its exact contribution to the
+// edge's F, b and H blocks (world-frame residual u = T_m x - T_n z, right
+// perturbations, Sec. V-A) in FP64, and reduces them per block of 256 points.
+#include <cfloat>
+
+#include "rkhsba_device.h"
+
+namespace rkhsba {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline int clamp_floor(double v, int lo, int hi) {
+  v = floor(v);
+  v = fmin(fmax(v, (double)lo), (double)hi);
+  return (int)v;
+}
+
+// Walks the target frame's cell rows that a ball of radius `reach` around the
+// box [lo, hi] can touch and calls fn(j0, j1) with each contiguous range of
+// target points (frame-local sorted indices).  Every target point whose
+// distance to some point of the box is <= reach lies in one of the ranges.
+template <typename Fn>
+__device__ inline void for_each_range(const FrameInfo& T, const int4* __restrict__ rows,
+                                      const uint32_t* __restrict__ xtab, const KConst& kc, float3 lo, float3 hi,
+                                      Fn&& fn) {
+  const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
+  const int z0 = clamp_floor(((double)lo.z - reach) * inv - T.org[2], -1, T.dim[2]);
+  const int z1 = clamp_floor(((double)hi.z + reach) * inv - T.org[2], -1, T.dim[2]);
+  const int y0 = clamp_floor(((double)lo.y - reach) * inv - T.org[1], -1, T.dim[1]);
+  const int y1 = clamp_floor(((double)hi.y + reach) * inv - T.org[1], -1, T.dim[1]);
+  for (int kz = max(z0, 0); kz <= min(z1, T.dim[2] - 1); ++kz) {
+    const double cz = (double)(kz + T.org[2]) * cell;
+    const double bz = fmax(0.0, fmax(cz - (double)hi.z, (double)lo.z - (cz + cell)));
+    for (int ky = max(y0, 0); ky <= min(y1, T.dim[1] - 1); ++ky) {
+      const double cy = (double)(ky + T.org[1]) * cell;
+      const double by = fmax(0.0, fmax(cy - (double)hi.y, (double)lo.y - (cy + cell)));
+      const double r2 = kc.reach2 - by * by - bz * bz;
+      if (r2 < 0.0) continue;
+      const double h = sqrt(r2);
+      const int4 R = rows[T.row_off + (int64_t)kz * T.dim[1] + ky];
+      if (R.y < R.x) continue;
+      const int xa = max(clamp_floor(((double)lo.x - h) * inv - T.org[0], -1, T.dim[0]), R.x);
+      const int xb = min(clamp_floor(((double)hi.x + h) * inv - T.org[0], -1, T.dim[0]), R.y);
+      if (xa > xb) continue;
+      const uint32_t* xt = xtab + (uint32_t)R.z;
+      fn(xt[xa - R.x], xt[xb + 1 - R.x]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- transforms and binning
+
+__global__ void k_edge_setup(const double* __restrict__ poses, const EdgeInfo* __restrict__ edges, int E,
+                             EdgeXf* __restrict__ xf) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  EdgeXf o;
+  rule_relative(poses + 12 * edges[e].m, poses + 12 * edges[e].n, o.R, o.t);
+  xf[e] = o;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts, const FrameInfo* __restrict__ frames,
+                                                  const EdgeInfo* __restrict__ edges,
+                                                  const int64_t* __restrict__ ent_off, const EdgeXf* __restrict__ xf,
+                                                  int E, int64_t n_entries, KConst kc, uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_entries) return;
+  const int e = upper_segment(ent_off, E, i);
+  const EdgeInfo& ed = edges[e];
+  const uint32_t src = (uint32_t)(i - ed.ent_off);
+  const FrameInfo& Fm = frames[ed.m];
+  const FrameInfo& Fn = frames[ed.n];
+  const float4 x = pts[Fm.pt_off + src];
+  const float3 q = rule_q32(xf[e], x.x, x.y, x.z);
+  const int r = kc.reach_cells;
+  const int lim = 1 << 30;
+  const int cx = clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r;
+  const int cy = clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r;
+  const int cz = clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r;
+  uint32_t key = kInvalidKey;
+  if (cx >= 0 && cy >= 0 && cz >= 0 && cx < Fn.dim[0] + 2 * r && cy < Fn.dim[1] + 2 * r && cz < Fn.dim[2] + 2 * r)
+    key = morton3((uint32_t)cx >> Fn.mort_shift, (uint32_t)cy >> Fn.mort_shift, (uint32_t)cz >> Fn.mort_shift);
+  keys[i] = key;
+  vals[i] = src;
+}
+
+// ---------------------------------------------------------------- candidate sweep
+
+template <int MODE, int FEAT, int G, int DP>
+__global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* __restrict__ pass_off) {
+  constexpr int P = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int pass = (int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6);
+  if (pass >= a.n_pass_total) return;  // whole wavefront leaves; no block barrier below
+  const int e = upper_segment(pass_off, a.E, pass);
+  const EdgeInfo ed = a.edges[e];
+  const EdgeXf X = a.xf[e];
+  const FrameInfo Fm = a.frames[ed.m];
+  const FrameInfo Fn = a.frames[ed.n];
+  const int s = lane % P, g = lane / P;
+  const int64_t entry = ed.ent_off + (int64_t)(pass - ed.pass_off) * P + s;
+  bool valid = entry < ed.ent_off + ed.n_src;
+  uint32_t src = 0;
+  if (valid) {
+    valid = a.keys[entry] != kInvalidKey;
+    src = a.vals[entry];
+  }
+  float3 q = make_float3(0.f, 0.f, 0.f);
+  uint32_t lbl = 0;
+  float fs[DP > 0 ? DP : 1];
+  if (valid) {
+    const float4 x = a.pts[Fm.pt_off + src];
+    q = rule_q32(X, x.x, x.y, x.z);
+    lbl = __float_as_uint(x.w);
+    if constexpr (FEAT == FEAT_DENSE) {
+      const float4* f4 = reinterpret_cast<const float4*>(a.feat + (Fm.pt_off + src) * DP);
+#pragma unroll
+      for (int k = 0; k < DP / 4; ++k) {
+        const float4 v = f4[k];
+        fs[4 * k] = v.x; fs[4 * k + 1] = v.y; fs[4 * k + 2] = v.z; fs[4 * k + 3] = v.w;
+      }
+    }
+  }
+  float3 lo, hi;
+  lo.x = wave_min(valid ? q.x : FLT_MAX);
+  lo.y = wave_min(valid ? q.y : FLT_MAX);
+  lo.z = wave_min(valid ? q.z : FLT_MAX);
+  hi.x = wave_max(valid ? q.x : -FLT_MAX);
+  hi.y = wave_max(valid ? q.y : -FLT_MAX);
+  hi.z = wave_max(valid ? q.z : -FLT_MAX);
+  if (lo.x > hi.x) return;  // no valid source point in the pass (uniform)
+
+  const float rc2 = a.kc.rc2, alpha = a.kc.alpha;
+  const bool clamp = a.kc.clamp != 0;
+  float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
+  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
+  uint32_t cnt = 0;
+  const float4* __restrict__ tp = a.pts + Fn.pt_off;
+  const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
+
+  for_each_range(Fn, a.rows, a.xtab, a.kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
+    for (uint32_t j = j0 + g; j < j1; j += G) {
+      const float4 z = tp[j];
+      float dx, dy, dz;
+      const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+      bool in = valid && s2 <= rc2;
+      if constexpr (FEAT == FEAT_CLASS) in = in && (__float_as_uint(z.w) == lbl);
+      if (in) {
+        float c = 1.0f;
+        if constexpr (FEAT == FEAT_DENSE) {
+          const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < DP / 4; ++k) {
+            const float4 v = f4[k];
+            acc = fmaf(fs[4 * k], v.x, acc);
+            acc = fmaf(fs[4 * k + 1], v.y, acc);
+            acc = fmaf(fs[4 * k + 2], v.z, acc);
+            acc = fmaf(fs[4 * k + 3], v.w, acc);
+          }
+          c = clamp ? fmaxf(acc, 0.f) : acc;
+        }
+        const float w = c * __builtin_amdgcn_exp2f(-alpha * s2);
+        A += w;
+        cnt += (c != 0.f) ? 1u : 0u;
+        if constexpr (MODE == MODE_NORMAL) {
+          const float wx = w * dx, wy = w * dy, wz = w * dz;
+          Bx += wx; By += wy; Bz += wz;
+          Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+          Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+        }
+      }
+    }
+  });
+
+  // Sum the G lanes that share a source point (lanes s, s+P, s+2P, ...).
+#pragma unroll
+  for (int o = P; o < 64; o <<= 1) {
+    A += __shfl_xor(A, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
+    if constexpr (MODE == MODE_NORMAL) {
+      Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
+      Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
+      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
+    }
+  }
+  if (g == 0 && valid) {
+    const int64_t N = a.n_entries;
+    a.cnt[entry] = cnt;
+    a.mom[entry] = A;
+    if constexpr (MODE == MODE_NORMAL) {
+      a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
+      a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
+      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Czz;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- per-point finalisation
+
+template <int N>
+__device__ inline void block_sum_store(const double (&v)[N], double* sh, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double t = wave_sum(v[k]);
+    if (lane == 0) sh[w * N + k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = 0.0;
+    for (int ww = 0; ww < kFinThreads / 64; ++ww) t += sh[ww * N + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+__device__ inline int sym_index(int r, int c) {  // upper triangle, row-major, r <= c
+  return r * 6 - (r * (r - 1)) / 2 + (c - r);
+}
+
+// Moments (A, B, C) of source point x (q = T_nm x in the target frame) ->
+// its terms of the edge's normal equations (world residual, right
+// perturbations; R_mn = R_nm^T):
+//   F   = A
+//   b_m = [R_mn B; x cross R_mn B]              b_n = -[B; q cross B]
+//   H_mm = A [[I, -[x]], [[x], |x|^2 I - x x^T]]
+//   S = A q - B (= sum w z),  Szz = A q q^T - q B^T - B q^T + C (= sum w z z^T)
+//   H_nn = [[A I, -[S]], [[S], tr(Szz) I - Szz]]
+//   H_mn = -[I; [x]] R_mn [A I, -[S]]
+template <int MODE>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32_t* __restrict__ fin_off) {
+  __shared__ double sh[(kFinThreads / 64) * 36];
+  const int blk = blockIdx.x;
+  const int e = upper_segment(fin_off, a.E, blk);
+  const EdgeInfo ed = a.edges[e];
+  const int64_t entry = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads + threadIdx.x;
+  bool valid = entry < ed.ent_off + ed.n_src;
+  if (valid) valid = a.keys[entry] != kInvalidKey;
+  uint32_t cnt = valid ? a.cnt[entry] : 0u;
+  valid = valid && cnt > 0;
+  double* out = a.partial + (int64_t)blk * kEdgeVals;
+  const int64_t N = a.n_entries;
+
+  double A = 0.0;
+  if (valid) A = a.mom[entry];
+  if constexpr (MODE == MODE_LOSS) {
+    double v[1] = {A};
+    block_sum_store<1>(v, sh, out);  // out[0] = F
+    double c1[1] = {(double)cnt};
+    block_sum_store<1>(c1, sh, out + 91);  // out[91] = pairs
+    for (int k = 1 + (int)threadIdx.x; k < 91; k += kFinThreads) out[k] = 0.0;
+    return;
+  }
+  double B[3] = {0, 0, 0}, C[6] = {0, 0, 0, 0, 0, 0}, x[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+  const EdgeXf X = a.xf[e];
+  if (valid) {
+    for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
+    for (int k = 0; k < 6; ++k) C[k] = a.mom[(4 + k) * N + entry];
+    const uint32_t src = a.vals[entry];
+    const float4 p = a.pts[a.frames[ed.m].pt_off + src];
+    const float3 qq = rule_q32(X, p.x, p.y, p.z);
+    x[0] = p.x; x[1] = p.y; x[2] = p.z;
+    q[0] = qq.x; q[1] = qq.y; q[2] = qq.z;
+  }
+  // R_mn B (R_mn = R_nm^T)
+  double Bm[3];
+  for (int a0 = 0; a0 < 3; ++a0) Bm[a0] = X.R[a0] * B[0] + X.R[3 + a0] * B[1] + X.R[6 + a0] * B[2];
+  {  // F, b_m, b_n -> out[0..12]; pair count -> out[91]
+    double v[13];
+    v[0] = A;
+    v[1] = Bm[0]; v[2] = Bm[1]; v[3] = Bm[2];
+    v[4] = x[1] * Bm[2] - x[2] * Bm[1];
+    v[5] = x[2] * Bm[0] - x[0] * Bm[2];
+    v[6] = x[0] * Bm[1] - x[1] * Bm[0];
+    v[7] = -B[0]; v[8] = -B[1]; v[9] = -B[2];
+    v[10] = -(q[1] * B[2] - q[2] * B[1]);
+    v[11] = -(q[2] * B[0] - q[0] * B[2]);
+    v[12] = -(q[0] * B[1] - q[1] * B[0]);
+    block_sum_store<13>(v, sh, out);
+    double c1[1] = {(double)cnt};
+    block_sum_store<1>(c1, sh, out + 91);
+  }
+  {  // H_mm
+    double M[21];
+    const double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    double H[6][6];
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) H[r][c] = 0.0;
+    H[0][0] = H[1][1] = H[2][2] = A;
+    // -A [x]_x in the top-right block, A [x]_x in the bottom-left
+    H[0][4] = A * x[2];  H[0][5] = -A * x[1];
+    H[1][3] = -A * x[2]; H[1][5] = A * x[0];
+    H[2][3] = A * x[1];  H[2][4] = -A * x[0];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) H[3 + r][3 + c] = A * ((r == c ? xx : 0.0) - x[r] * x[c]);
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c) M[sym_index(r, c)] = H[r][c];
+    block_sum_store<21>(M, sh, out + 13);
+  }
+  double S[3], Szz[3][3];
+  for (int k = 0; k < 3; ++k) S[k] = A * q[k] - B[k];
+  {
+    const double Cm[3][3] = {{C[0], C[1], C[2]}, {C[1], C[3], C[4]}, {C[2], C[4], C[5]}};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Szz[r][c] = A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + Cm[r][c];
+  }
+  {  // H_nn
+    double M[21];
+    double H[6][6];
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) H[r][c] = 0.0;
+    H[0][0] = H[1][1] = H[2][2] = A;
+    H[0][4] = S[2];  H[0][5] = -S[1];
+    H[1][3] = -S[2]; H[1][5] = S[0];
+    H[2][3] = S[1];  H[2][4] = -S[0];
+    const double tr = Szz[0][0] + Szz[1][1] + Szz[2][2];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) H[3 + r][3 + c] = (r == c ? tr : 0.0) - Szz[r][c];
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c) M[sym_index(r, c)] = H[r][c];
+    block_sum_store<21>(M, sh, out + 34);
+  }
+  {  // H_mn = -[I; [x]] M1,  M1 = R_mn [A I | -[S]]  (3 x 6)
+    double M1[3][6];
+    double Rmn[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Rmn[r][c] = X.R[3 * c + r];
+    const double Sx[3][3] = {{0.0, -S[2], S[1]}, {S[2], 0.0, -S[0]}, {-S[1], S[0], 0.0}};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        M1[r][c] = A * Rmn[r][c];
+        M1[r][3 + c] = -(Rmn[r][0] * Sx[0][c] + Rmn[r][1] * Sx[1][c] + Rmn[r][2] * Sx[2][c]);
+      }
+    double M[36];
+    for (int c = 0; c < 6; ++c) {
+      for (int r = 0; r < 3; ++r) M[6 * r + c] = -M1[r][c];
+      // rows 3..5: -[x]_x M1
+      M[6 * 3 + c] = -(-x[2] * M1[1][c] + x[1] * M1[2][c]);
+      M[6 * 4 + c] = -(x[2] * M1[0][c] - x[0] * M1[2][c]);
+      M[6 * 5 + c] = -(-x[1] * M1[0][c] + x[0] * M1[1][c]);
+    }
+    block_sum_store<36>(M, sh, out + 55);
+  }
+}
+
+// One block per edge: deterministic sum of the edge's finalisation blocks.
+__global__ void k_edge_reduce(const double* __restrict__ partial, const EdgeInfo* __restrict__ edges, int n_vals,
+                              double* __restrict__ edge_out) {
+  const EdgeInfo ed = edges[blockIdx.x];
+  for (int t = threadIdx.x; t < n_vals; t += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < ed.n_fin; ++b) s += partial[(int64_t)(ed.fin_off + b) * kEdgeVals + t];
+    edge_out[(int64_t)blockIdx.x * kEdgeVals + t] = s;
+  }
+}
+
+// ---------------------------------------------------------------- pair export (parity)
+
+template <int FEAT>
+__global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restrict__ pts, const int4* __restrict__ rows,
+                                                           const uint32_t* __restrict__ xtab,
+                                                           const FrameInfo* __restrict__ frames,
+                                                           const int32_t* __restrict__ perm,
+                                                           const EdgeXf* __restrict__ xf, int m, int n, KConst kc,
+                                                           int64_t cap, int32_t* __restrict__ out,
+                                                           unsigned long long* __restrict__ count) {
+  const FrameInfo Fm = frames[m];
+  const FrameInfo Fn = frames[n];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= Fm.n) return;
+  const float4 x = pts[Fm.pt_off + i];
+  const float3 q = rule_q32(xf[0], x.x, x.y, x.z);
+  const uint32_t lbl = __float_as_uint(x.w);
+  const int32_t oi = perm[Fm.pt_off + i];
+  for_each_range(Fn, rows, xtab, kc, q, q, [&](uint32_t j0, uint32_t j1) {
+    for (uint32_t j = j0; j < j1; ++j) {
+      const float4 z = pts[Fn.pt_off + j];
+      float dx, dy, dz;
+      const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+      bool in = s2 <= kc.rc2;
+      if constexpr (FEAT == FEAT_CLASS) in = in && __float_as_uint(z.w) == lbl;
+      if (in) {
+        const unsigned long long k = atomicAdd(count, 1ull);
+        if ((int64_t)k < cap) {
+          out[2 * k] = oi;
+          out[2 * k + 1] = perm[Fn.pt_off + j];
+        }
+      }
+    }
+  });
+}
+
+template <int MODE, int FEAT>
+hipError_t dispatch_pairs(const PairArgs& a, const int32_t* pass_off, int G, int DP, hipStream_t st) {
+  const unsigned nb = (unsigned)((a.n_pass_total + 3) / 4);
+  if (nb == 0) return hipSuccess;
+#define RKHSBA_LAUNCH(GG, DD) k_pairs<MODE, FEAT, GG, DD><<<nb, kThreads, 0, st>>>(a, pass_off)
+  if constexpr (FEAT == FEAT_CLASS) {
+    if (G == 1) RKHSBA_LAUNCH(1, 0);
+    else if (G == 2) RKHSBA_LAUNCH(2, 0);
+    else RKHSBA_LAUNCH(4, 0);
+  } else {
+#define RKHSBA_DENSE(GG)                        \
+  if (DP <= 8) RKHSBA_LAUNCH(GG, 8);            \
+  else if (DP <= 16) RKHSBA_LAUNCH(GG, 16);     \
+  else if (DP <= 24) RKHSBA_LAUNCH(GG, 24);     \
+  else if (DP <= 32) RKHSBA_LAUNCH(GG, 32);     \
+  else RKHSBA_LAUNCH(GG, 64);
+    if (G == 1) { RKHSBA_DENSE(1) }
+    else if (G == 2) { RKHSBA_DENSE(2) }
+    else { RKHSBA_DENSE(4) }
+#undef RKHSBA_DENSE
+  }
+#undef RKHSBA_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int dense_pad(int D) { return D <= 8 ? 8 : D <= 16 ? 16 : D <= 24 ? 24 : D <= 32 ? 32 : 64; }
+
+hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st) {
+  if (E > 0) k_edge_setup<<<(E + 63) / 64, 64, 0, st>>>(d_poses, d_edges, E, d_xf);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
+                      const EdgeXf* d_xf, int E, int64_t n_entries, KConst kc, uint32_t* d_keys, uint32_t* d_vals,
+                      hipStream_t st) {
+  if (n_entries > 0)
+    k_bin<<<(unsigned)((n_entries + kThreads - 1) / kThreads), kThreads, 0, st>>>(d_pts, d_frames, d_edges, d_ent_off,
+                                                                                d_xf, E, n_entries, kc, d_keys, d_vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
+                        hipStream_t st) {
+  const int G = 64 / pass_points;
+  const int DP = a.kc.Dp;
+  if (mode == MODE_LOSS)
+    return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_LOSS, FEAT_CLASS>(a, d_pass_off, G, DP, st)
+                                   : dispatch_pairs<MODE_LOSS, FEAT_DENSE>(a, d_pass_off, G, DP, st);
+  return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_NORMAL, FEAT_CLASS>(a, d_pass_off, G, DP, st)
+                                 : dispatch_pairs<MODE_NORMAL, FEAT_DENSE>(a, d_pass_off, G, DP, st);
+}
+
+hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st) {
+  if (a.n_fin_total <= 0) return hipSuccess;
+  if (mode == MODE_LOSS) k_finalize<MODE_LOSS><<<a.n_fin_total, kFinThreads, 0, st>>>(a, d_fin_off);
+  else k_finalize<MODE_NORMAL><<<a.n_fin_total, kFinThreads, 0, st>>>(a, d_fin_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, int E, int n_vals, double* d_edge_out,
+                              hipStream_t st) {
+  if (E > 0) k_edge_reduce<<<E, 128, 0, st>>>(d_partial, d_edges, n_vals, d_edge_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
+                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const EdgeXf* d_xf, int m,
+                               int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
+                               unsigned long long* d_count, hipStream_t st) {
+  if (n_src <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n_src + kThreads - 1) / kThreads);
+  if (feat_path == FEAT_CLASS)
+    k_export_pairs<FEAT_CLASS><<<nb, kThreads, 0, st>>>(d_pts, d_rows, d_xtab, d_frames, d_perm, d_xf, m, n, kc, cap,
+                                                        d_out, d_count);
+  else
+    k_export_pairs<FEAT_DENSE><<<nb, kThreads, 0, st>>>(d_pts, d_rows, d_xtab, d_frames, d_perm, d_xf, m, n, kc, cap,
+                                                        d_out, d_count);
+  return hipGetLastError();
+}
+
+}  // namespace rkhsba

@@ -1,0 +1,83 @@
+// Device helpers shared by the rkhsba kernels: the FP32 membership rule, cell
+// arithmetic and wavefront reductions.
+#pragma once
+
+#include "rkhsba_internal.h"
+
+namespace rkhsba {
+
+// Relative transform T_nm = T_n^-1 T_m of the documented membership rule, in
+// FP64 with a fixed fma order (R_n^T R_m, R_n^T (t_m - t_n)).  Poses are
+// [R row-major | t].
+__device__ inline void rule_relative(const double* __restrict__ Tm, const double* __restrict__ Tn, double* R,
+                                     double* t) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) R[3 * a + b] = fma(Tn[6 + a], Tm[6 + b], fma(Tn[3 + a], Tm[3 + b], Tn[a] * Tm[b]));
+  const double d0 = Tm[9] - Tn[9], d1 = Tm[10] - Tn[10], d2 = Tm[11] - Tn[11];
+  for (int a = 0; a < 3; ++a) t[a] = fma(Tn[6 + a], d2, fma(Tn[3 + a], d1, Tn[a] * d0));
+}
+
+// q32 = float(T_nm x): the source point in the target frame, computed in FP64
+// and rounded once.
+__device__ inline float3 rule_q32(const EdgeXf& xf, float x0, float x1, float x2) {
+#pragma clang fp contract(off)
+  const double a = x0, b = x1, c = x2;
+  float3 q;
+  q.x = (float)fma(xf.R[2], c, fma(xf.R[1], b, fma(xf.R[0], a, xf.t[0])));
+  q.y = (float)fma(xf.R[5], c, fma(xf.R[4], b, fma(xf.R[3], a, xf.t[1])));
+  q.z = (float)fma(xf.R[8], c, fma(xf.R[7], b, fma(xf.R[6], a, xf.t[2])));
+  return q;
+}
+
+// The FP32 squared distance of the membership rule.
+__device__ inline float rule_s2(float3 q, float zx, float zy, float zz, float& dx, float& dy, float& dz) {
+#pragma clang fp contract(off)
+  dx = q.x - zx;
+  dy = q.y - zy;
+  dz = q.z - zz;
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+__device__ inline int cell_of(float v, double inv_cell) { return (int)floor((double)v * inv_cell); }
+
+// 10-bit-per-axis Morton interleave.
+__device__ inline uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return spread10(x) | (spread10(y) << 1) | (spread10(z) << 2);
+}
+
+// Wavefront (64-lane) reductions; every lane receives the result.
+__device__ inline float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Index of the segment containing `pos` in an ascending offset table
+// off[0..n) (off[0] == 0): the largest s with off[s] <= pos.
+template <typename T>
+__device__ inline int upper_segment(const T* off, int n, int64_t pos) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= pos) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace rkhsba

@@ -1,0 +1,182 @@
+// Internal declarations shared by the rkhsba HIP translation units.
+// Device data layout (all frames concatenated, HBM-resident between calls):
+//   pts   float4[N_total]  frame-local xyz of each frame's points in cell-key order;
+//                          .w holds the class id bits (class features) or 0
+//   feat  float[N_total*Dp] dense feature rows in the same order (zero padded to Dp)
+//   perm  int32[N_total]   sorted position -> original index within the frame
+//   keys  uint32[N_total]  sorted cell keys
+//   rows  int4[sum NY*NZ]  per (ky,kz) row of cells: (x_lo, x_hi, xtab offset, 0)
+//   xtab  uint32[...]      per row, for x in [x_lo, x_hi+1]: first point of cell x
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace rkhsba {
+
+constexpr uint32_t kInvalidKey = 0xffffffffu;
+constexpr int kMaxDense = 64;
+
+enum Mode { MODE_LOSS = 0, MODE_NORMAL = 1 };
+enum FeatPath { FEAT_CLASS = 0, FEAT_DENSE = 1 };
+
+// Per-frame grid description (device and host copies).
+struct FrameInfo {
+  int64_t pt_off;    // first point of the frame in pts/feat/perm/keys
+  int32_t n;         // points
+  int32_t org[3];    // cell coordinates of the grid origin
+  int32_t dim[3];    // cells per axis
+  int32_t mort_shift;  // source-binning Morton code: (k + reach) >> mort_shift
+  int64_t row_off;   // first row descriptor of the frame
+  int64_t xt_off;    // first xtab entry of the frame
+};
+
+// Static per-edge layout of one edge list (host-computed once per list).
+struct EdgeInfo {
+  int32_t m, n;      // source frame, target frame
+  int64_t ent_off;   // first binning entry (one per source point)
+  int32_t n_src;     // source points (= frame m's count)
+  int32_t pass_off;  // first candidate-sweep pass of the edge
+  int32_t n_pass;
+  int32_t fin_off;   // first finalize block of the edge
+  int32_t n_fin;
+  int32_t pad;
+};
+
+// Relative transform of an edge, T_nm = T_n^-1 T_m (FP64), written on device.
+struct EdgeXf {
+  double R[9];
+  double t[3];
+};
+
+// Kernel constants derived from the options (host-computed in FP64).
+struct KConst {
+  double inv_cell;   // 1 / cell edge
+  double cell;       // cell edge = r_c / cell_subdiv
+  double reach;      // r_c * (1 + 2^-12): covers every pair the FP32 rule accepts
+  double reach2;
+  float rc2;         // float(r_c * r_c), the FP32 membership threshold
+  float alpha;       // log2(e) / (2 ell^2), so that exp(-r^2/2l^2) = exp2(-alpha r^2)
+  int reach_cells;   // cell_subdiv + 1
+  int clamp;         // clamp negative c to 0
+  int Dp;            // padded dense feature width (0 for class ids)
+  int pad;
+};
+
+// Segmented LSD radix sort: tiles never straddle a segment.
+struct SortTile {
+  int64_t start;     // first element
+  int32_t count;     // elements (<= kSortTile)
+  int32_t seg;       // segment id
+};
+struct SortSeg {
+  int64_t start;
+  int64_t count;
+  int32_t tile0;     // first tile
+  int32_t n_tiles;
+};
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the first HIP error.  All run on `st`.
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                             uint32_t* hist, const SortTile* d_tiles, int n_tiles, const SortSeg* d_segs,
+                             int n_segs, int bits, hipStream_t st, bool* result_in_tmp);
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint64_t* d_total,
+                                 hipStream_t st);
+constexpr int kScanTileElems = 2048;
+
+int dense_pad(int D);
+
+hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
+                              double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st);
+hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, const FrameInfo* d_frames, int K,
+                            int64_t n_total, uint32_t* d_keys, uint32_t* d_vals, hipStream_t st);
+hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
+                         const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
+                         const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
+                         hipStream_t st);
+hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
+                       int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
+                       uint64_t* d_total, hipStream_t st);
+hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
+                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, hipStream_t st);
+
+hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
+hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
+                      const EdgeXf* d_xf, int E, int64_t n_entries, KConst kc, uint32_t* d_keys, uint32_t* d_vals,
+                      hipStream_t st);
+
+struct PairArgs {
+  const float4* pts;
+  const float* feat;
+  const int4* rows;
+  const uint32_t* xtab;
+  const FrameInfo* frames;
+  const EdgeInfo* edges;
+  const EdgeXf* xf;
+  const uint32_t* keys;   // sorted binning keys
+  const uint32_t* vals;   // sorted binning values (source point, frame-local sorted index)
+  float* mom;             // moments, component-major: mom[c * n_entries + entry]
+  uint32_t* cnt;          // in-radius pair count per entry
+  int64_t n_entries;
+  int32_t E;
+  int32_t n_pass_total;
+  KConst kc;
+};
+hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
+                        hipStream_t st);
+
+struct FinArgs {
+  const float4* pts;
+  const EdgeInfo* edges;
+  const EdgeXf* xf;
+  const FrameInfo* frames;
+  const uint32_t* keys;
+  const uint32_t* vals;
+  const float* mom;
+  const uint32_t* cnt;
+  double* partial;        // [n_fin_total][kEdgeVals]
+  int64_t n_entries;
+  int32_t E;
+  int32_t n_fin_total;
+};
+constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
+constexpr int kFinThreads = 256;
+hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st);
+hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, int E, int n_vals, double* d_edge_out,
+                              hipStream_t st);
+
+struct SolveArgs {
+  const double* edge_out;  // [E][kEdgeVals]
+  const EdgeInfo* edges;
+  int32_t E;
+  int32_t K;
+  int32_t fixed;           // frame removed from the system (-1: none)
+  double sigma2;
+  double damping_rel;
+  double* H;               // n x n scratch, n = 6K or 6(K-1)
+  double* b;               // n
+  double* delta;           // n
+  double* poses;           // K*12, updated in place by the solve
+  double* loss_hist;       // [iter] F
+  double* pairs_hist;      // [iter] pair count
+  int32_t* status;         // 0 ok, -4 not positive definite (sticky)
+  int32_t iter;
+};
+hipError_t launch_assemble(const SolveArgs& a, hipStream_t st);
+hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);
+hipError_t launch_loss_only(const SolveArgs& a, hipStream_t st);
+
+hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
+                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const EdgeXf* d_xf, int m,
+                               int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
+                               unsigned long long* d_count, hipStream_t st);
+
+}  // namespace rkhsba

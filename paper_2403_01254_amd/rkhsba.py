@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the rkhsba C ABI (include/rkhsba.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library ``_lib/librkhsba.so``.  Importing this module without the built
+library raises, so nothing can silently fall back to a CPU path.
+
+Host inputs are numpy arrays; device inputs are torch CUDA tensors (their
+``data_ptr()`` is passed with ``is_device=1``).  PyTorch is only used for
+device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librkhsba.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ESTATE = 0, -1, -2, -3, -4, -5
+FEAT_CLASS_ID, FEAT_DENSE_F32, FEAT_DENSE_BF16, FEAT_DENSE_FP8 = 0, 1, 2, 3
+_FEAT_NAMES = {"class": FEAT_CLASS_ID, "dense": FEAT_DENSE_F32, "bf16": FEAT_DENSE_BF16, "fp8": FEAT_DENSE_FP8}
+
+
+class RkhsbaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rkhsba error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("ell", ctypes.c_double),
+        ("cutoff_factor", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("damping_rel", ctypes.c_double),
+        ("fixed_frame", ctypes.c_int),
+        ("clamp_negative_c", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("cell_subdiv", ctypes.c_int),
+        ("pass_points", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"rkhsba HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.rkhsba_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.rkhsba_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Options)]
+        L.rkhsba_destroy.argtypes = [vp]
+        L.rkhsba_last_error.argtypes = [vp]
+        L.rkhsba_last_error.restype = ctypes.c_char_p
+        L.rkhsba_build_neighbors.argtypes = [vp, ctypes.c_int, _i64p, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(vp), ctypes.c_int]
+        L.rkhsba_eval_loss.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _i64p]
+        L.rkhsba_accumulate_normal_eqs.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _dp, _i64p]
+        L.rkhsba_gn_step.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _dp, _i64p]
+        L.rkhsba_export_pairs.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _i64p]
+        L.rkhsba_export_voxels.argtypes = [vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), _i32p, _i32p]
+        L.rkhsba_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.rkhsba_profile_read.argtypes = [vp, ctypes.c_int, _dp, _i64p, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _p(a, t=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().rkhsba_default_options(ctypes.byref(o))
+    return o
+
+
+class Context:
+    """One rkhsba context (one stream, one set of resident frames)."""
+
+    def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
+                 fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 3,
+                 pass_points: int = 16, stream=None):
+        o = default_options()
+        o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel
+        o.fixed_frame, o.clamp_negative_c, o.device = fixed_frame, int(bool(clamp_negative_c)), device
+        o.cell_subdiv, o.pass_points = cell_subdiv, pass_points
+        o.stream = ctypes.c_void_p(int(stream)) if stream else None
+        self._h = ctypes.c_void_p()
+        rc = lib().rkhsba_create(ctypes.byref(self._h), ctypes.byref(o))
+        if rc != OK:
+            raise RkhsbaError(rc, "rkhsba_create failed")
+        self.K = 0
+        self.opts = o
+
+    def close(self):
+        if self._h:
+            lib().rkhsba_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise RkhsbaError(rc, lib().rkhsba_last_error(self._h).decode())
+
+    # -- rkhsba_build_neighbors
+    def build_neighbors(self, points, feats, feat_kind="class"):
+        """points: K arrays (N,3) float32 (numpy) or CUDA tensors; feats: K arrays of uint16 class
+        ids (N,) or float32 rows (N, D)."""
+        kind = _FEAT_NAMES[feat_kind] if isinstance(feat_kind, str) else int(feat_kind)
+        K = len(points)
+        on_device = not isinstance(points[0], np.ndarray)
+        keep = []
+        if on_device:
+            n = np.array([int(p.shape[0]) for p in points], dtype=np.int64)
+            xp = [p.data_ptr() for p in points]
+            fp = [f.data_ptr() for f in feats]
+            D = 0 if kind == FEAT_CLASS_ID else int(feats[0].shape[1])
+        else:
+            pts = [np.ascontiguousarray(p, dtype=np.float32).reshape(-1, 3) for p in points]
+            if kind == FEAT_CLASS_ID:
+                fs = [np.ascontiguousarray(f, dtype=np.uint16).reshape(-1) for f in feats]
+                D = 0
+            else:
+                fs = [np.ascontiguousarray(f, dtype=np.float32) for f in feats]
+                D = int(fs[0].shape[1])
+            keep = [pts, fs]
+            n = np.array([len(p) for p in pts], dtype=np.int64)
+            xp = [p.ctypes.data for p in pts]
+            fp = [f.ctypes.data for f in fs]
+        xarr = (ctypes.c_void_p * K)(*xp)
+        farr = (ctypes.c_void_p * K)(*fp)
+        rc = lib().rkhsba_build_neighbors(self._h, K, _p(n, ctypes.c_int64), xarr, kind, D, farr, int(on_device))
+        del keep
+        self._check(rc)
+        self.K = K
+
+    def _poses(self, poses):
+        return np.ascontiguousarray(poses, dtype=np.float64).reshape(self.K, 12)
+
+    @staticmethod
+    def _edges(edges):
+        return np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+
+    # -- rkhsba_eval_loss
+    def eval_loss(self, poses, edges):
+        p, e = self._poses(poses), self._edges(edges)
+        F = ctypes.c_double()
+        Fe = np.zeros(len(e))
+        npairs = ctypes.c_int64()
+        self._check(lib().rkhsba_eval_loss(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(F), _p(Fe),
+                                           ctypes.byref(npairs)))
+        return F.value, Fe, npairs.value
+
+    # -- rkhsba_accumulate_normal_eqs
+    def accumulate_normal_eqs(self, poses, edges):
+        p, e = self._poses(poses), self._edges(edges)
+        n = 6 * self.K
+        H = np.zeros((n, n))
+        b = np.zeros(n)
+        F = ctypes.c_double()
+        npairs = ctypes.c_int64()
+        self._check(lib().rkhsba_accumulate_normal_eqs(self._h, _p(p), len(e), _p(e, ctypes.c_int32), _p(H), _p(b),
+                                                       ctypes.byref(F), ctypes.byref(npairs)))
+        return H, b, F.value, npairs.value
+
+    # -- rkhsba_gn_step
+    def gn_step(self, poses, edges, n_iter):
+        p, e = self._poses(poses).copy(), self._edges(edges)
+        lpi = np.zeros(n_iter + 1)
+        ppi = np.zeros(n_iter + 1, dtype=np.int64)
+        self._check(lib().rkhsba_gn_step(self._h, _p(p), len(e), _p(e, ctypes.c_int32), int(n_iter), _p(lpi),
+                                         _p(ppi, ctypes.c_int64)))
+        return p, lpi, ppi
+
+    # -- rkhsba_export_pairs
+    def export_pairs(self, poses, m, n):
+        p = self._poses(poses)
+        total = ctypes.c_int64()
+        null = ctypes.cast(None, _i32p)
+        self._check(lib().rkhsba_export_pairs(self._h, _p(p), int(m), int(n), 0, null, ctypes.byref(total)))
+        out = np.zeros((max(total.value, 1), 2), dtype=np.int32)
+        self._check(lib().rkhsba_export_pairs(self._h, _p(p), int(m), int(n), total.value, _p(out, ctypes.c_int32),
+                                              ctypes.byref(total)))
+        return out[:total.value]
+
+    # -- rkhsba_export_voxels
+    def export_voxels(self, frame, n_points):
+        perm = np.zeros(n_points, dtype=np.int32)
+        keys = np.zeros(n_points, dtype=np.uint32)
+        org = np.zeros(3, dtype=np.int32)
+        dims = np.zeros(3, dtype=np.int32)
+        self._check(lib().rkhsba_export_voxels(self._h, int(frame), _p(perm, ctypes.c_int32),
+                                               _p(keys, ctypes.c_uint32), _p(org, ctypes.c_int32),
+                                               _p(dims, ctypes.c_int32)))
+        return perm, keys, org, dims
+
+
+    # -- rkhsba_profile_enable / rkhsba_profile_read
+    def profile_enable(self, on=True):
+        self._check(lib().rkhsba_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self, stage, reset=False):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(lib().rkhsba_profile_read(self._h, int(stage), ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        return ms.value, n.value
+
+
+PROF_BUILD, PROF_BIN, PROF_PAIRS, PROF_PAIRS_LOSS, PROF_FINALIZE, PROF_SOLVE = range(6)
+PROF_NAMES = ["build", "bin+sort", "pairs", "pairs(loss)", "finalize", "solve"]
+
+
+# ABI names, for callers that prefer the C spelling.
+def rkhsba_create(**kw) -> Context:
+    return Context(**kw)
+
+
+def rkhsba_build_neighbors(ctx: Context, points, feats, feat_kind="class"):
+    return ctx.build_neighbors(points, feats, feat_kind)
+
+
+def rkhsba_eval_loss(ctx: Context, poses, edges):
+    return ctx.eval_loss(poses, edges)
+
+
+def rkhsba_accumulate_normal_eqs(ctx: Context, poses, edges):
+    return ctx.accumulate_normal_eqs(poses, edges)
+
+
+def rkhsba_gn_step(ctx: Context, poses, edges, n_iter):
+    return ctx.gn_step(poses, edges, n_iter)
+
+
+def rkhsba_export_pairs(ctx: Context, poses, m, n):
+    return ctx.export_pairs(poses, m, n)
+
+
+def rkhsba_export_voxels(ctx: Context, frame, n_points):
+    return ctx.export_voxels(frame, n_points)

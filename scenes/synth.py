@@ -493,14 +493,15 @@ class _Street:
 
 def lidar(seed: int = 0, n_frames: int = 64, n_points: int = 100_000, ell: float = 0.3, n_iter: int = 10,
           n_beams: int = 64, n_azimuth: int = 1563, max_range: float = 50.0, outlier_frac: float = 0.2,
-          flip_frac: float = 0.1, n_classes: int = 20, n_neighbours: int = 6) -> Problem:
+          flip_frac: float = 0.1, n_classes: int = 20, n_neighbours: int = 6, spacing: float | None = None) -> Problem:
     """Spinning 64-beam LiDAR around a 200 m street loop; 20% outliers, 10% flipped labels,
-    each frame paired with its n_neighbours nearest poses (directed edges)."""
+    each frame paired with its n_neighbours nearest poses (directed edges).  Poses are evenly
+    spaced over the loop, or `spacing` metres apart along it."""
     rng = np.random.default_rng(seed)
     st = _Street(rng, n_classes=n_classes)
     gt = []
     for k in range(n_frames):
-        p, tang = st.at(k * st.length / n_frames)
+        p, tang = st.at(k * (st.length / n_frames if spacing is None else spacing))
         R = _rot([0, 0, 1], math.atan2(tang[1], tang[0]))
         gt.append(pose_from_rt(R, np.array([p[0], p[1], 1.8])))
     gt = np.stack(gt)

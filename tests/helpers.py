@@ -1,0 +1,74 @@
+"""Shared test helpers: tolerances, pose errors, library availability."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Relative tolerance of FP32 loss, gradient and Gauss-Newton matrix against the
+# FP64 oracle, and the pose tolerance after Gauss-Newton steps.
+REL_TOL = 1e-5
+ROT_TOL = 1e-4   # rad
+TRANS_TOL = 1e-4  # m
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def inv_cell(ell, cutoff_factor, subdiv):
+    """Cell size formula of the voxel structure: edge r_c / cell_subdiv, inverse in FP64."""
+    rc = cutoff_factor * ell
+    cell = rc / subdiv
+    return 1.0 / cell
+
+
+def normwise_rel(x_hat, x):
+    x_hat = np.asarray(x_hat, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    den = np.linalg.norm(x)
+    return np.linalg.norm(x_hat - x) / den if den > 0 else np.linalg.norm(x_hat)
+
+
+def assert_blocks_close(x_hat, x, block, rel=REL_TOL, floor=1e-2, what=""):
+    """Normwise relative error over the whole array and per block (6-vectors of b,
+    6x6 blocks of H); blocks much smaller than the largest (below `floor` of it)
+    are held to rel * floor * largest instead (cancellation, near-empty blocks)."""
+    x_hat = np.asarray(x_hat, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    tot = normwise_rel(x_hat, x)
+    assert tot <= rel, f"{what}: normwise relative error {tot:.3g} > {rel}"
+    if x.ndim == 1:
+        blocks = [(slice(i, i + block),) for i in range(0, len(x), block)]
+    else:
+        blocks = [(slice(i, i + block), slice(j, j + block)) for i in range(0, x.shape[0], block)
+                  for j in range(0, x.shape[1], block)]
+    norms = [np.linalg.norm(x[s]) for s in blocks]
+    big = max(norms) if norms else 0.0
+    for s, nrm in zip(blocks, norms):
+        err = np.linalg.norm(x_hat[s] - x[s])
+        lim = rel * max(nrm, floor * big)
+        assert err <= lim + 1e-300, f"{what}: block {s} error {err:.3g} > {lim:.3g} (block norm {nrm:.3g})"
+
+
+def pose_errors(P_hat, P):
+    """Per-frame rotation angle |log(R_hat^T R)| and translation distance."""
+    P_hat = np.asarray(P_hat).reshape(-1, 12)
+    P = np.asarray(P).reshape(-1, 12)
+    rot, tr = [], []
+    for a, b in zip(P_hat, P):
+        Ra, Rb = a[:9].reshape(3, 3), b[:9].reshape(3, 3)
+        rot.append(np.linalg.norm(Rotation.from_matrix(Ra.T @ Rb).as_rotvec()))
+        tr.append(np.linalg.norm(a[9:] - b[9:]))
+    return np.array(rot), np.array(tr)
+
+
+def ident():
+    return np.concatenate([np.eye(3).reshape(9), np.zeros(3)])

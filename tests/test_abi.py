@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point include/rkhsba.h
+declares (no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from helpers import ROOT, gpu_available
+
+HEADER = os.path.join(ROOT, "include", "rkhsba.h")
+LIB = os.path.join(ROOT, "paper_2403_01254_amd", "_lib", "librkhsba.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(rkhsba_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2403_01254_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for required in ("rkhsba_build_neighbors", "rkhsba_eval_loss", "rkhsba_accumulate_normal_eqs", "rkhsba_gn_step"):
+        assert required in names
+    assert len(names) >= 10
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} missing from {LIB}"
+
+
+def test_default_options_and_create_without_device(lib):
+    from paper_2403_01254_amd import rkhsba
+    o = rkhsba.default_options()
+    assert o.ell == 0.1 and o.cutoff_factor == 3.0 and o.sigma == 1.0 and o.cell_subdiv == 3 and o.pass_points == 16
+    h = ctypes.c_void_p()
+    bad = rkhsba.default_options()
+    bad.ell = -1.0
+    assert rkhsba.lib().rkhsba_create(ctypes.byref(h), ctypes.byref(bad)) == rkhsba.EINVAL
+    bad = rkhsba.default_options()
+    bad.pass_points = 48
+    assert rkhsba.lib().rkhsba_create(ctypes.byref(h), ctypes.byref(bad)) == rkhsba.EINVAL
+    if not gpu_available():
+        assert rkhsba.lib().rkhsba_create(ctypes.byref(h), ctypes.byref(o)) == rkhsba.EDEVICE
+        assert not h.value
+
+
+def test_product_code_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2403_01254_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f"{f} references the oracle"

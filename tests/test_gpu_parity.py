@@ -1,0 +1,208 @@
+"""GPU path (through the C ABI) against the FP64 oracle.
+
+Neighbour structures and pair lists must match bit for bit; F, b and H within
+1e-5 normwise relative; poses after Gauss-Newton steps within 1e-4 rad and
+1e-4 m.  Inputs are the seeded synthetic scenes at sizes the oracle finishes
+in seconds (several sweep passes, finalisation blocks and sort tiles, with
+ragged tails).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from helpers import (REL_TOL, ROT_TOL, TRANS_TOL, assert_blocks_close, ident, inv_cell, normwise_rel,
+                     pose_errors)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_2403_01254_amd import rkhsba
+    rkhsba.lib()
+    return rkhsba
+
+
+def make_ctx(rk, p, **kw):
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, **kw)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    return ctx
+
+
+SCENES = {
+    "two_view": lambda: scenes.two_view(0),
+    "odometry_small": lambda: scenes.odometry(1, n_frames=4, n_points=4000, n_iter=4),
+    "lidar_small": lambda: scenes.lidar(2, n_frames=4, n_points=6000, n_neighbours=2, n_iter=3, spacing=3.125),
+    "two_view_ragged": lambda: scenes.two_view(3, n_points=1237),
+}
+
+
+@pytest.fixture(scope="module", params=list(SCENES))
+def scene(request):
+    say(f"[scene] {request.param}")
+    return request.param, SCENES[request.param]()
+
+
+def test_voxel_structure_bit_exact(rk, scene):
+    name, p = scene
+    for subdiv in (1, 3):
+        ctx = make_ctx(rk, p, cell_subdiv=subdiv)
+        inv = inv_cell(p.ell, p.cutoff_factor, subdiv)
+        for f in range(p.K):
+            perm, keys, org, dims = ctx.export_voxels(f, len(p.points[f]))
+            operm, okeys, oorg, odims = oracle.voxels(p.points[f], inv, margin=0)
+            np.testing.assert_array_equal(org, oorg)
+            np.testing.assert_array_equal(dims, odims)
+            np.testing.assert_array_equal(keys, okeys)
+            np.testing.assert_array_equal(perm, operm)
+        ctx.close()
+
+
+def test_pair_lists_bit_exact(rk, scene):
+    name, p = scene
+    op = oracle.Problem.from_scene(p)
+    ctx = make_ctx(rk, p)
+    for poses in (p.init_poses, p.gt_poses):
+        for (m, n) in p.edges[:3]:
+            got = ctx.export_pairs(poses, m, n)
+            ref = oracle.pairs(op, poses, m, n)
+            say(f"[pairs] {name} edge ({m},{n}) gpu {len(got)} oracle {len(ref)}")
+            assert len(ref) > 0
+            np.testing.assert_array_equal(got, ref)
+
+
+def test_loss_parity(rk, scene):
+    name, p = scene
+    op = oracle.Problem.from_scene(p)
+    ctx = make_ctx(rk, p)
+    F, Fe, npairs = ctx.eval_loss(p.init_poses, p.edges)
+    oF, ob, oH, oFe, onp = oracle.normal_eqs(op, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
+    say(f"[loss] {name} F gpu {F:.9g} oracle {oF:.9g} pairs {npairs} / {onp}")
+    assert npairs == onp
+    assert abs(F - oF) <= REL_TOL * abs(oF)
+    assert normwise_rel(Fe, oFe) <= REL_TOL
+    # the FP64 definition of membership differs only on the cutoff sphere
+    dF = oracle.loss(op, p.init_poses, p.edges, oracle.MEMBER_FP64)
+    assert abs(F - dF) <= REL_TOL * abs(dF)
+
+
+def test_normal_equations_parity(rk, scene):
+    name, p = scene
+    op = oracle.Problem.from_scene(p)
+    ctx = make_ctx(rk, p)
+    H, b, F, npairs = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    oF, ob, oH, oFe, onp = oracle.normal_eqs(op, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
+    say(f"[normal] {name} |b| {np.linalg.norm(ob):.4g} rel {normwise_rel(b, ob):.3g} "
+        f"|H| {np.linalg.norm(oH):.4g} rel {normwise_rel(H, oH):.3g}")
+    assert npairs == onp
+    assert abs(F - oF) <= REL_TOL * abs(oF)
+    assert_blocks_close(b, ob, 6, what=f"{name} b")
+    assert_blocks_close(H, oH, 6, what=f"{name} H")
+    np.testing.assert_allclose(H, H.T, rtol=0, atol=1e-12 * np.abs(H).max())
+
+
+def test_gauss_newton_parity(rk, scene):
+    name, p = scene
+    op = oracle.Problem.from_scene(p)
+    ctx = make_ctx(rk, p)
+    n_iter = min(p.n_iter, 4)
+    poses, lpi, ppi = ctx.gn_step(p.init_poses, p.edges, n_iter)
+    oposes, olpi = oracle.gn(op, p.init_poses, p.edges, n_iter, membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(poses, oposes)
+    say(f"[gn] {name} rot err {rot.max():.3g} trans err {tr.max():.3g} loss {lpi[-1]:.9g} / {olpi[-1]:.9g}")
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+    np.testing.assert_array_equal(poses[0], p.init_poses[0])  # the fixed frame does not move
+
+
+@pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1)])
+def test_launch_shapes_agree(rk, pass_points, subdiv):
+    """Every sweep shape and cell size gives the same pair count and, up to
+    FP32 summation order, the same F, b and H."""
+    p = scenes.odometry(4, n_frames=3, n_points=3000)
+    ref = make_ctx(rk, p)
+    H0, b0, F0, n0 = ref.accumulate_normal_eqs(p.init_poses, p.edges)
+    ctx = make_ctx(rk, p, pass_points=pass_points, cell_subdiv=subdiv)
+    H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    assert n == n0
+    assert abs(F - F0) <= REL_TOL * abs(F0)
+    assert normwise_rel(b, b0) <= REL_TOL and normwise_rel(H, H0) <= REL_TOL
+
+
+def test_degenerate_inputs(rk):
+    """One-point frames, a frame with no pair in range, duplicated edges and
+    zero pairs overall."""
+    rng = np.random.default_rng(5)
+    x = (rng.normal(size=(500, 3)) * 0.3).astype(np.float32)
+    lone = np.array([[50.0, 50.0, 50.0]], np.float32)
+    one = x[:1].copy()
+    pts = [x, x + np.float32(0.01), lone, one]
+    feats = [np.zeros(len(a), np.uint16) for a in pts]
+    ctx = rk.Context(ell=0.1)
+    ctx.build_neighbors(pts, feats, "class")
+    poses = np.stack([ident()] * 4)
+    op = oracle.Problem(pts, feats, "class", 0.1)
+    edges = [[0, 1], [0, 2], [3, 0], [0, 1]]
+    H, b, F, n = ctx.accumulate_normal_eqs(poses, edges)
+    oF, ob, oH, _, on = oracle.normal_eqs(op, poses, edges, oracle.MEMBER_FP32_RULE)
+    assert n == on and abs(F - oF) <= REL_TOL * oF
+    assert normwise_rel(H, oH) <= REL_TOL and normwise_rel(b, ob) <= REL_TOL
+    assert np.all(H[12:18] == 0) and np.all(b[12:18] == 0)   # the lone frame sees nothing
+    F2, Fe2, n2 = ctx.eval_loss(poses, [[0, 2]])
+    assert F2 == 0.0 and n2 == 0 and Fe2[0] == 0.0
+    # a Gauss-Newton step leaves an isolated frame in place
+    out, lpi, ppi = ctx.gn_step(poses, edges, 2)
+    np.testing.assert_array_equal(out[2], poses[2])
+
+
+def test_common_rigid_motion_invariance_gpu(rk):
+    p = scenes.odometry(6, n_frames=3, n_points=3000)
+    ctx = make_ctx(rk, p)
+    H0, b0, F0, n0 = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    from scipy.spatial.transform import Rotation
+    G = np.eye(4)
+    G[:3, :3] = Rotation.from_rotvec([0.3, -0.2, 0.5]).as_matrix()
+    G[:3, 3] = [1.5, -2.0, 0.7]
+    moved = []
+    for q in p.init_poses:
+        T = np.eye(4)
+        T[:3, :3] = q[:9].reshape(3, 3)
+        T[:3, 3] = q[9:]
+        T = G @ T
+        moved.append(np.concatenate([T[:3, :3].reshape(9), T[:3, 3]]))
+    H1, b1, F1, n1 = ctx.accumulate_normal_eqs(np.stack(moved), p.edges)
+    assert abs(n1 - n0) <= max(2, 1e-5 * n0)   # membership is decided in FP32 after the motion
+    assert abs(F1 - F0) <= 1e-5 * F0
+    assert normwise_rel(b1, b0) <= 1e-4 and normwise_rel(H1, H0) <= 1e-5
+
+
+def test_invalid_arguments(rk):
+    p = scenes.two_view(7, n_points=300)
+    ctx = make_ctx(rk, p)
+    with pytest.raises(rk.RkhsbaError) as e:
+        ctx.eval_loss(p.init_poses, [[0, 0]])
+    assert e.value.code == rk.EINVAL
+    with pytest.raises(rk.RkhsbaError) as e:
+        ctx.eval_loss(p.init_poses, [[0, 5]])
+    assert e.value.code == rk.EINVAL
+    bad = p.init_poses.copy()
+    bad[1, 9] = np.nan
+    with pytest.raises(rk.RkhsbaError) as e:
+        ctx.gn_step(bad, p.edges, 1)
+    assert e.value.code == rk.EINVAL
+    with pytest.raises(rk.RkhsbaError) as e:
+        ctx.build_neighbors([np.full((3, 3), np.inf, np.float32)], [np.zeros(3, np.uint16)], "class")
+    assert e.value.code == rk.EINVAL
+    fresh = rk.Context(ell=0.1)
+    fresh.K = 2  # the library itself holds no frames yet
+    with pytest.raises(rk.RkhsbaError) as e:
+        fresh.eval_loss(np.stack([ident(), ident()]), [[0, 1]])
+    assert e.value.code == rk.ESTATE
