@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the RKHS-BA hot path on one MI355X.
+
+One step = one whole solve of the odometry workload: the voxel build of all
+frames from device-resident clouds (rkhsba_build_neighbors) followed by the
+Gauss-Newton / IRLS iterations (rkhsba_gn_step: per iteration, transforms,
+binning, candidate sweep, finalisation, assembly, Cholesky and pose update,
+plus the final loss evaluation).  Workload: 8 depth-camera frames x 30,000
+points, 23-dim features (20-class Dirichlet(0.3) soft label + RGB), all 28
+frame pairs, ell = 0.08 m, cutoff 3 ell, 15 iterations (seeded synthetic
+scene).
+
+The printed JSON line reports pair evaluations per second (in-radius pairs
+with c != 0, summed over every evaluation of the step), Gauss-Newton
+iterations per second, the roofline position of the candidate-sweep kernel
+measured with HIP events on the library's stream, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kernel pair-evals/s + GN iters/s at 1 GPU; p50/p99 solve latency at fixed QPS"
+PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
+# Algorithmic work per in-radius pair of the sweep (FMA = 2 flops, exp = 1):
+# residual 3 + squared distance 5 + scale 1 + exp 1 + weight 1 + A 1 + w*d 3 + B 3 + C 12
+FLOPS_PER_PAIR_GEOM = 30
+PAIR_KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_01254_amd", "csrc", "pairs.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_odometry_traffic.json")
+
+
+def kernel_source_hash():
+    with open(PAIR_KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(p, n_edges):
+    import oracle
+    op = oracle.Problem.from_scene(p)
+    edges = p.edges[:n_edges]
+    t0 = time.perf_counter()
+    _, _, _, _, npairs = oracle.normal_eqs(op, p.init_poses, edges)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": npairs / dt, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"one normal-equation evaluation (loss, b, H; brute force over all point pairs, FP64) of the "
+                      f"first {len(edges)} of the 28 frame pairs at the initial poses: {npairs} in-radius pairs "
+                      f"in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pass-points", type=int, default=16)
+    ap.add_argument("--cell-subdiv", type=int, default=3)
+    ap.add_argument("--cpu-edges", type=int, default=8, help="frame pairs in the CPU oracle sample (0: skip)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2403_01254_amd import rkhsba
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    p = scenes.odometry(0)
+    log(f"[bench] workload {p.recipe}: {len(p.edges)} edges, {p.n_iter} GN iterations")
+    dev = torch.device("cuda:0")
+    pts = [torch.from_numpy(x).to(dev) for x in p.points]
+    feats = [torch.from_numpy(f).to(dev) for f in p.feats]
+    torch.cuda.synchronize()
+    ctx = rkhsba.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, pass_points=args.pass_points,
+                         cell_subdiv=args.cell_subdiv)
+
+    def step():
+        ctx.build_neighbors(pts, feats, "dense")
+        return ctx.gn_step(p.init_poses, p.edges, p.n_iter)
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    for s in range(rkhsba.PROF_SOLVE + 1):
+        ctx.profile_read(s, reset=True)
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs_total = 0
+    for k in range(args.steps):
+        poses, lpi, ppi = step()
+        pairs_total += int(ppi.sum())
+        log(f"[bench] step {k + 1}/{args.steps}: F {lpi[0]:.6g} -> {lpi[-1]:.6g}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    prof = {rkhsba.PROF_NAMES[s]: ctx.profile_read(s) for s in range(rkhsba.PROF_SOLVE + 1)}
+    for name, (ms, n) in prof.items():
+        log(f"[bench] stage {name:12s} {ms / args.steps:9.3f} ms/step over {n // max(args.steps, 1)} launches/step")
+
+    # roofline of the sweep kernel (Gauss-Newton evaluations): algorithmic flops per launch / mean launch time
+    pair_ms, pair_launches = prof["pairs"]
+    gn_pairs_per_launch = float(np.mean(ppi[:-1])) if p.n_iter > 0 else 0.0
+    flops_per_pair = FLOPS_PER_PAIR_GEOM + 2 * p.D
+    mean_launch_s = pair_ms / max(pair_launches, 1) / 1e3
+    achieved = flops_per_pair * gn_pairs_per_launch / mean_launch_s / 1e12 if mean_launch_s > 0 else 0.0
+    traffic = load_traffic()
+
+    result = {
+        "metric": METRIC,
+        "value": pairs_total / elapsed,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "odometry: 8 depth-camera frames x 30,000 points, 23-dim soft-label+RGB features, "
+                        "all 28 frame pairs, ell=0.08 m, cutoff 3 ell, 15 Gauss-Newton iterations "
+                        "(one step = voxel build + 15 iterations + final loss)",
+            "frames": p.K, "points_per_frame": int(p.n_points[0]), "edges": int(len(p.edges)),
+            "gn_iterations": p.n_iter, "feature_dim": p.D, "ell": p.ell,
+            "pass_points": args.pass_points, "cell_subdiv": args.cell_subdiv,
+        },
+        "gn_iters_per_s": p.n_iter * args.steps / elapsed,
+        "pairs_per_step": pairs_total // args.steps,
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pairs (candidate sweep, Gauss-Newton moments)",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+            "flops_per_pair": flops_per_pair,
+            "pairs_per_launch": gn_pairs_per_launch,
+            "mean_launch_ms": mean_launch_s * 1e3,
+        },
+    }
+    rank = int(os.environ.get("RANK", "0"))
+    if rank == 0 and args.cpu_edges > 0:
+        log(f"[bench] CPU oracle on {args.cpu_edges} frame pairs ...")
+        result["cpu_baseline"] = cpu_baseline(p, args.cpu_edges)
+    ctx.close()
+    if rank == 0:
+        print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

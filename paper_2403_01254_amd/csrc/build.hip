@@ -23,23 +23,43 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __
                                                           double inv_cell, int32_t* __restrict__ cell,
                                                           int32_t* __restrict__ minmax) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n_total) return;
-  int f;
-  int64_t l;
-  frame_of(off, K, i, f, l);
-  const float* p = xyz[f] + 3 * l;
-  for (int a = 0; a < 3; ++a) {
-    const float v = p[a];
-    const double s = (double)v * inv_cell;
-    int k = 0;
-    if (!(fabs(s) < 1.0e9)) {  // NaN, Inf or beyond the int32 cell range
-      atomicOr(&minmax[K * 6], 1);
-    } else {
-      k = (int)floor(s);
+  const bool live = i < n_total;
+  int f = -1;
+  int64_t l = 0;
+  if (live) frame_of(off, K, i, f, l);
+  int k[3] = {0, 0, 0};
+  bool bad = false;
+  if (live) {
+    const float* p = xyz[f] + 3 * l;
+    for (int a = 0; a < 3; ++a) {
+      const double s = (double)p[a] * inv_cell;
+      if (!(fabs(s) < 1.0e9)) bad = true;  // NaN, Inf or beyond the int32 cell range
+      else k[a] = (int)floor(s);
+      cell[3 * i + a] = k[a];
     }
-    cell[3 * i + a] = k;
-    atomicMin(&minmax[f * 6 + a], k);
-    atomicMax(&minmax[f * 6 + 3 + a], k);
+  }
+  if (__ballot(bad)) {
+    if (bad) atomicOr(&minmax[K * 6], 1);
+  }
+  // One atomic per wavefront when all its live lanes belong to one frame (the
+  // common case); per-lane atomics at frame boundaries.
+  const int f0 = __builtin_amdgcn_readfirstlane(f);
+  const bool same = __ballot(live && f != f0) == 0ull;
+  for (int a = 0; a < 3; ++a) {
+    int mn = live ? k[a] : INT_MAX, mx = live ? k[a] : INT_MIN;
+    if (same) {
+      for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, 64));
+        mx = max(mx, __shfl_xor(mx, o, 64));
+      }
+      if ((threadIdx.x & 63) == 0 && f0 >= 0) {
+        atomicMin(&minmax[f0 * 6 + a], mn);
+        atomicMax(&minmax[f0 * 6 + 3 + a], mx);
+      }
+    } else if (live) {
+      atomicMin(&minmax[f * 6 + a], mn);
+      atomicMax(&minmax[f * 6 + 3 + a], mx);
+    }
   }
 }
 

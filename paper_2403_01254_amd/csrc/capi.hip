@@ -353,7 +353,10 @@ void evaluate(rkhsba_ctx* c, int mode) {
   pa.kc = c->kc;
   const int feat_path = c->feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
   hipEvent_t t1 = prof_begin(c);
-  RK_HIP(launch_pairs(pa, c->d_pass_off.p, mode, feat_path, c->opt.pass_points, st));
+  if (c->opt.pass_points == 16)
+    RK_HIP(launch_sweep16(pa, c->d_pass_off.p, mode, feat_path, st));
+  else
+    RK_HIP(launch_pairs(pa, c->d_pass_off.p, mode, feat_path, c->opt.pass_points, st));
   prof_end(c, mode == MODE_NORMAL ? RKHSBA_PROF_PAIRS : RKHSBA_PROF_PAIRS_LOSS, t1);
   FinArgs fa{};
   fa.pts = c->pts.p;

@@ -1,0 +1,283 @@
+// Tiled candidate sweep (16 source points per wavefront, 64-candidate tiles).
+//
+// One wavefront (= one workgroup of 64 lanes) handles a pass of P = 16
+// Morton-adjacent source points of one edge.  Lane l works for source point
+// s = l % 16 and candidate stream g = l / 16.
+//   1. The pass's box of transformed points q = T_nm x is grown by the reach
+//      (>= r_c).  The target cell rows the ball around the box can touch are
+//      evaluated 64 at a time, one row per lane (x-range trimmed to the ball,
+//      contiguous target-point range from the row table), and concatenated by
+//      a wavefront prefix sum into one virtual candidate list.
+//   2. The list is consumed in tiles of 64 candidates: each lane fetches one
+//      candidate (position, label and, for dense features, its feature row)
+//      into LDS; the fetch of the next tile is issued before the current one
+//      is processed.
+//   3. Each 16-candidate sub-tile is processed by all lanes: lane (s, g)
+//      takes candidates 4g..4g+3, so 64 (source, candidate) pairs per step.
+//      Dense feature inner products c = <f_x, f_z> come from one
+//      16x16x4 FP32 MFMA per 4 feature dimensions; its accumulator layout
+//      (row 4(l/16)+r, column l%16) is exactly candidate 4g+r for source s.
+//   4. Inside the FP32 membership rule the pair adds w = c exp(-|d|^2/2l^2)
+//      to the moments A, B = sum w d, C = sum w d d^T (d = q - z); the four
+//      streams of each source are summed with cross-lane shuffles at the end.
+#include <cfloat>
+
+#include "rkhsba_device.h"
+
+namespace rkhsba {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLanes = 64;
+constexpr int kTile = 64;
+
+__device__ inline int clamp_floor_d(double v, int lo, int hi) {
+  v = floor(v);
+  v = fmin(fmax(v, (double)lo), (double)hi);
+  return (int)v;
+}
+
+__device__ inline float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+template <int MODE, int FEAT, int DP>
+__global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __restrict__ pass_off) {
+  constexpr int P = 16;
+  constexpr int FS = DP > 0 ? DP + 1 : 1;  // LDS feature row stride (odd: conflict-free column reads)
+  __shared__ uint32_t row_j0[kLanes];
+  __shared__ uint32_t row_off[kLanes + 1];
+  __shared__ float4 tpos[kTile];
+  __shared__ float tfeat[DP > 0 ? kTile * FS : 1];
+
+  const int lane = threadIdx.x;
+  const int pass = blockIdx.x;
+  const int e = upper_segment(pass_off, a.E, pass);
+  const EdgeInfo ed = a.edges[e];
+  const EdgeXf X = a.xf[e];
+  const FrameInfo Fm = a.frames[ed.m];
+  const FrameInfo Fn = a.frames[ed.n];
+  const int s = lane & 15, g = lane >> 4;
+  const int64_t entry = ed.ent_off + (int64_t)(pass - ed.pass_off) * P + s;
+  bool valid = entry < ed.ent_off + ed.n_src;
+  uint32_t src = 0;
+  if (valid) {
+    valid = a.keys[entry] != kInvalidKey;
+    src = a.vals[entry];
+  }
+  float3 q = make_float3(0.f, 0.f, 0.f);
+  uint32_t lbl = 0;
+  float fsrc[DP > 0 ? DP / 4 : 1];
+#pragma unroll
+  for (int k = 0; k < (DP > 0 ? DP / 4 : 1); ++k) fsrc[k] = 0.f;
+  if (valid) {
+    const float4 x = a.pts[Fm.pt_off + src];
+    q = rule_q32(X, x.x, x.y, x.z);
+    lbl = __float_as_uint(x.w);
+    if constexpr (FEAT == FEAT_DENSE) {
+      // B operand of the MFMA: feature 4k + g of this lane's source point
+      const float* f = a.feat + (Fm.pt_off + src) * DP;
+#pragma unroll
+      for (int k = 0; k < DP / 4; ++k) fsrc[k] = f[4 * k + g];
+    }
+  }
+  float3 lo, hi;
+  lo.x = uniform_f(wave_min(valid ? q.x : FLT_MAX));
+  lo.y = uniform_f(wave_min(valid ? q.y : FLT_MAX));
+  lo.z = uniform_f(wave_min(valid ? q.z : FLT_MAX));
+  hi.x = uniform_f(wave_max(valid ? q.x : -FLT_MAX));
+  hi.y = uniform_f(wave_max(valid ? q.y : -FLT_MAX));
+  hi.z = uniform_f(wave_max(valid ? q.z : -FLT_MAX));
+  if (!(lo.x <= hi.x)) return;  // no valid source point in this pass (uniform)
+
+  const KConst kc = a.kc;
+  const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
+  const int z0 = max(clamp_floor_d(((double)lo.z - reach) * inv - Fn.org[2], -1, Fn.dim[2]), 0);
+  const int z1 = min(clamp_floor_d(((double)hi.z + reach) * inv - Fn.org[2], -1, Fn.dim[2]), Fn.dim[2] - 1);
+  const int y0 = max(clamp_floor_d(((double)lo.y - reach) * inv - Fn.org[1], -1, Fn.dim[1]), 0);
+  const int y1 = min(clamp_floor_d(((double)hi.y + reach) * inv - Fn.org[1], -1, Fn.dim[1]), Fn.dim[1] - 1);
+  const int ny = y1 - y0 + 1;
+  const int n_rows = (z1 >= z0 && y1 >= y0) ? (z1 - z0 + 1) * ny : 0;
+
+  const float rc2 = kc.rc2, alpha = kc.alpha;
+  const bool clamp = kc.clamp != 0;
+  float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
+  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
+  uint32_t cnt = 0;
+  const float4* __restrict__ tp = a.pts + Fn.pt_off;
+  const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
+  const float nanf_ = __int_as_float(0x7fc00000);
+
+  for (int rb = 0; rb < n_rows; rb += kLanes) {
+    // ---- one row per lane: its contiguous candidate range
+    uint32_t j0 = 0, cntr = 0;
+    const int r = rb + lane;
+    if (r < n_rows) {
+      const int kz = z0 + r / ny, ky = y0 + r % ny;
+      const double cz = (double)(kz + Fn.org[2]) * cell;
+      const double cy = (double)(ky + Fn.org[1]) * cell;
+      const double bz = fmax(0.0, fmax(cz - (double)hi.z, (double)lo.z - (cz + cell)));
+      const double by = fmax(0.0, fmax(cy - (double)hi.y, (double)lo.y - (cy + cell)));
+      const double r2 = kc.reach2 - by * by - bz * bz;
+      if (r2 >= 0.0) {
+        const int4 R = a.rows[Fn.row_off + (int64_t)kz * Fn.dim[1] + ky];
+        if (R.y >= R.x) {
+          const double h = sqrt(r2);
+          const int xa = max(clamp_floor_d(((double)lo.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
+          const int xb = min(clamp_floor_d(((double)hi.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R.y);
+          if (xa <= xb) {
+            const uint32_t* xt = a.xtab + (uint32_t)R.z;
+            j0 = xt[xa - R.x];
+            cntr = xt[xb + 1 - R.x] - j0;
+          }
+        }
+      }
+    }
+    const uint32_t incl = wave_inclusive_scan(cntr, lane);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    __syncthreads();  // previous users of row_j0/row_off are done
+    row_j0[lane] = j0;
+    row_off[lane] = incl - cntr;
+    if (lane == 63) row_off[64] = incl;
+    __syncthreads();
+    if (total == 0) continue;
+
+    // ---- tiles of 64 candidates, next tile fetched while the current one is processed
+    auto fetch = [&](uint32_t c, float4& pos, float* fr) {
+      if (c < total) {
+        int lo_r = 0, hi_r = 63;  // largest row with row_off[row] <= c
+        while (lo_r < hi_r) {
+          const int mid = (lo_r + hi_r + 1) >> 1;
+          if (row_off[mid] <= c) lo_r = mid; else hi_r = mid - 1;
+        }
+        const uint32_t j = row_j0[lo_r] + (c - row_off[lo_r]);
+        pos = tp[j];
+        if constexpr (FEAT == FEAT_DENSE) {
+          const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
+#pragma unroll
+          for (int k = 0; k < DP / 4; ++k) {
+            const float4 v = f4[k];
+            fr[4 * k] = v.x; fr[4 * k + 1] = v.y; fr[4 * k + 2] = v.z; fr[4 * k + 3] = v.w;
+          }
+        }
+      } else {
+        pos = make_float4(nanf_, nanf_, nanf_, 0.f);  // fails every membership test
+        if constexpr (FEAT == FEAT_DENSE) {
+#pragma unroll
+          for (int k = 0; k < DP; ++k) fr[k] = 0.f;
+        }
+      }
+    };
+    float4 npos;
+    float nfeat[DP > 0 ? DP : 1];
+    fetch((uint32_t)lane, npos, nfeat);
+    for (uint32_t cb = 0; cb < total; cb += kTile) {
+      tpos[lane] = npos;
+      if constexpr (FEAT == FEAT_DENSE) {
+#pragma unroll
+        for (int k = 0; k < DP; ++k) tfeat[lane * FS + k] = nfeat[k];
+      }
+      __syncthreads();
+      if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat);
+      const uint32_t left = total - cb;
+      const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
+      for (int sub = 0; sub < n_sub; ++sub) {
+        floatx4 cv = {1.f, 1.f, 1.f, 1.f};
+        if constexpr (FEAT == FEAT_DENSE) {
+          cv = floatx4{0.f, 0.f, 0.f, 0.f};
+          const float* arow = tfeat + (16 * sub + s) * FS + g;
+#pragma unroll
+          for (int k = 0; k < DP / 4; ++k) cv = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * k], fsrc[k], cv, 0, 0, 0);
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const float4 z = tpos[16 * sub + 4 * g + rr];
+          float dx, dy, dz;
+          const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+          bool in = valid && s2 <= rc2;
+          float c = 1.f;
+          if constexpr (FEAT == FEAT_CLASS) {
+            in = in && (__float_as_uint(z.w) == lbl);
+          } else {
+            c = clamp ? fmaxf(cv[rr], 0.f) : cv[rr];
+            in = in && c != 0.f;
+          }
+          if (in) {
+            const float w = c * __builtin_amdgcn_exp2f(-alpha * s2);
+            A += w;
+            cnt += 1u;
+            if constexpr (MODE == MODE_NORMAL) {
+              const float wx = w * dx, wy = w * dy, wz = w * dz;
+              Bx += wx; By += wy; Bz += wz;
+              Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+              Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+            }
+          }
+        }
+      }
+      __syncthreads();  // the tile buffer is rewritten next
+    }
+  }
+
+  // sum the four candidate streams of each source point
+#pragma unroll
+  for (int o = 16; o < 64; o <<= 1) {
+    A += __shfl_xor(A, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
+    if constexpr (MODE == MODE_NORMAL) {
+      Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
+      Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
+      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
+    }
+  }
+  if (g == 0 && valid) {
+    const int64_t N = a.n_entries;
+    a.cnt[entry] = cnt;
+    a.mom[entry] = A;
+    if constexpr (MODE == MODE_NORMAL) {
+      a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
+      a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
+      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Czz;
+    }
+  }
+}
+
+template <int MODE, int FEAT>
+hipError_t dispatch(const PairArgs& a, const int32_t* pass_off, int DP, hipStream_t st) {
+  const unsigned nb = (unsigned)a.n_pass_total;
+  if (nb == 0) return hipSuccess;
+  if constexpr (FEAT == FEAT_CLASS) {
+    k_sweep<MODE, FEAT, 0><<<nb, kLanes, 0, st>>>(a, pass_off);
+  } else {
+    if (DP <= 8) k_sweep<MODE, FEAT, 8><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else k_sweep<MODE, FEAT, 64><<<nb, kLanes, 0, st>>>(a, pass_off);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Tiled sweep for passes of 16 source points.
+hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, hipStream_t st) {
+  const int DP = a.kc.Dp;
+  if (mode == MODE_LOSS)
+    return feat_path == FEAT_CLASS ? dispatch<MODE_LOSS, FEAT_CLASS>(a, d_pass_off, DP, st)
+                                   : dispatch<MODE_LOSS, FEAT_DENSE>(a, d_pass_off, DP, st);
+  return feat_path == FEAT_CLASS ? dispatch<MODE_NORMAL, FEAT_CLASS>(a, d_pass_off, DP, st)
+                                 : dispatch<MODE_NORMAL, FEAT_DENSE>(a, d_pass_off, DP, st);
+}
+
+}  // namespace rkhsba
