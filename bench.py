@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pass-points", type=int, default=16)
-    ap.add_argument("--cell-subdiv", type=int, default=3)
+    ap.add_argument("--cell-subdiv", type=int, default=4)
     ap.add_argument("--cpu-edges", type=int, default=8, help="frame pairs in the CPU oracle sample (0: skip)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()

@@ -79,7 +79,7 @@ typedef struct {
   int fixed_frame;       /* gauge: this frame is not moved (default 0, Sec. V-A) */
   int clamp_negative_c;  /* use max(c_ij, 0) for dense features (default 1) */
   int device;            /* HIP device ordinal (default 0) */
-  int cell_subdiv;       /* voxel cells per truncation radius, 1..4 (default 3) */
+  int cell_subdiv;       /* voxel cells per truncation radius, 1..8 (default 4) */
   int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
   void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
 } rkhsba_options;

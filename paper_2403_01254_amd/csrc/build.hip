@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restr
                                                      const int64_t* __restrict__ off, int K, int64_t n_total,
                                                      const uint32_t* __restrict__ sorted_vals,
                                                      float4* __restrict__ pts, float* __restrict__ feat,
-                                                     int32_t* __restrict__ perm) {
+                                                     int32_t* __restrict__ perm, int32_t* __restrict__ neg_flag) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n_total) return;
   int f;
@@ -103,7 +103,13 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restr
   if (feat_kind != 0) {
     const float* src = (const float*)feats[f] + o * D;
     float* dst = feat + p * Dp;
-    for (int k = 0; k < Dp; ++k) dst[k] = k < D ? src[k] : 0.0f;
+    bool neg = false;
+    for (int k = 0; k < Dp; ++k) {
+      const float v = k < D ? src[k] : 0.0f;
+      neg = neg || v < 0.0f;
+      dst[k] = v;
+    }
+    if (neg) atomicOr(neg_flag, 1);  // some inner products may be negative
   }
 }
 
@@ -215,10 +221,10 @@ hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, cons
 hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
                          const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
-                         hipStream_t st) {
+                         int32_t* d_neg_flag, hipStream_t st) {
   if (n_total > 0)
     k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, D, Dp, d_frames, d_in_off, K,
-                                                   n_total, d_sorted_vals, d_pts, d_feat, d_perm);
+                                                   n_total, d_sorted_vals, d_pts, d_feat, d_perm, d_neg_flag);
   return hipGetLastError();
 }
 

@@ -66,6 +66,7 @@ struct rkhsba_ctx {
   std::vector<FrameInfo> frames;
   std::vector<int64_t> in_off;  // K+1
   int bin_bits = 0;
+  bool negative_features = false;  // some dense feature value < 0: inner products may be negative
   DBuf<float4> pts;
   DBuf<float> feat;
   DBuf<int32_t> perm;
@@ -223,7 +224,7 @@ void compute_constants(rkhsba_ctx* c) {
   k.rc2 = (float)(rc * rc);
   k.alpha = (float)(1.4426950408889634 / (2.0 * o.ell * o.ell));
   k.reach_cells = o.cell_subdiv + 1;
-  k.clamp = o.clamp_negative_c ? 1 : 0;
+  k.clamp = (o.clamp_negative_c && c->negative_features) ? 1 : 0;
   k.Dp = c->Dp;
   c->kc = k;
 }
@@ -420,7 +421,7 @@ void rkhsba_default_options(rkhsba_options* o) {
   o->fixed_frame = 0;
   o->clamp_negative_c = 1;
   o->device = 0;
-  o->cell_subdiv = 3;
+  o->cell_subdiv = 4;
   o->pass_points = 16;
   o->stream = nullptr;
 }
@@ -431,7 +432,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   if (!opt) return RKHSBA_EINVAL;
   if (!(opt->ell > 0.0) || !std::isfinite(opt->ell) || !(opt->cutoff_factor > 0.0) ||
       !std::isfinite(opt->cutoff_factor) || !std::isfinite(opt->sigma) || !(opt->damping_rel >= 0.0) ||
-      opt->cell_subdiv < 1 || opt->cell_subdiv > 4 ||
+      opt->cell_subdiv < 1 || opt->cell_subdiv > 8 ||
       (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) || opt->fixed_frame < 0)
     return RKHSBA_EINVAL;
   int ndev = 0;
@@ -530,13 +531,14 @@ int rkhsba_build_neighbors(rkhsba_ctx* c, int K, const int64_t* n_points, const 
     RK_HIP(hipMemcpyAsync(c->d_in_off.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
 
     // cell coordinates and per-frame bounds
-    std::vector<int32_t> mm(6 * K + 1);
+    std::vector<int32_t> mm(6 * K + 2);
     for (int f = 0; f < K; ++f)
       for (int a = 0; a < 3; ++a) {
         mm[6 * f + a] = INT_MAX;
         mm[6 * f + 3 + a] = INT_MIN;
       }
     mm[6 * K] = 0;
+    mm[6 * K + 1] = 0;
     RK_HIP(c->cell.reserve((size_t)N * 3));
     RK_HIP(c->minmax.reserve(mm.size()));
     RK_HIP(hipMemcpyAsync(c->minmax.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, st));
@@ -616,7 +618,8 @@ int rkhsba_build_neighbors(rkhsba_ctx* c, int K, const int64_t* n_points, const 
     RK_HIP(c->keys.reserve(N));
     RK_HIP(c->feat.reserve(c->Dp > 0 ? (size_t)N * c->Dp : 1));
     RK_HIP(launch_gather(c->d_xyz_ptrs.p, c->d_feat_ptrs.p, feat_kind == RKHSBA_FEAT_CLASS_ID ? 0 : 1, c->D, c->Dp,
-                         c->d_frames.p, c->d_in_off.p, K, N, sv, c->pts.p, c->feat.p, c->perm.p, st));
+                         c->d_frames.p, c->d_in_off.p, K, N, sv, c->pts.p, c->feat.p, c->perm.p, c->minmax.p + 6 * K + 1,
+                         st));
     RK_HIP(hipMemcpyAsync(c->keys.p, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, st));
 
     // cell-row tables
@@ -627,8 +630,12 @@ int rkhsba_build_neighbors(rkhsba_ctx* c, int K, const int64_t* n_points, const 
     RK_HIP(launch_rows(c->keys.p, c->d_frames.p, c->d_in_off.p, K, N, c->rows.p, rows_total, c->row_sizes.p,
                        c->scan_tmp.p, c->d_total.p, st));
     uint64_t xt_total = 0;
+    int32_t neg = 0;
     RK_HIP(hipMemcpyAsync(&xt_total, c->d_total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipMemcpyAsync(&neg, c->minmax.p + 6 * K + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RK_HIP(hipStreamSynchronize(st));
+    c->negative_features = neg != 0;
+    compute_constants(c);
     RK_REQUIRE(xt_total < (1ull << 31), RKHSBA_ENOMEM, "cell table too large");
     RK_HIP(c->xtab.reserve(xt_total));
     RK_HIP(launch_xtab(c->keys.p, c->d_frames.p, c->d_in_off.p, K, N, c->rows.p, c->xtab.p, st));

@@ -149,7 +149,10 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
   hi.x = wave_max(valid ? q.x : -FLT_MAX);
   hi.y = wave_max(valid ? q.y : -FLT_MAX);
   hi.z = wave_max(valid ? q.z : -FLT_MAX);
-  if (lo.x > hi.x) return;  // no valid source point in the pass (uniform)
+  if (lo.x > hi.x) {  // no valid source point in the pass (uniform)
+    if (g == 0 && entry < ed.ent_off + ed.n_src) a.cnt[entry] = 0u;
+    return;
+  }
 
   const float rc2 = a.kc.rc2, alpha = a.kc.alpha;
   const bool clamp = a.kc.clamp != 0;
@@ -205,9 +208,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
       Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
     }
   }
+  if (g == 0 && entry < ed.ent_off + ed.n_src) a.cnt[entry] = valid ? cnt : 0u;
   if (g == 0 && valid) {
     const int64_t N = a.n_entries;
-    a.cnt[entry] = cnt;
     a.mom[entry] = A;
     if constexpr (MODE == MODE_NORMAL) {
       a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
@@ -256,10 +259,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   const int e = upper_segment(fin_off, a.E, blk);
   const EdgeInfo ed = a.edges[e];
   const int64_t entry = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads + threadIdx.x;
-  bool valid = entry < ed.ent_off + ed.n_src;
-  if (valid) valid = a.keys[entry] != kInvalidKey;
-  uint32_t cnt = valid ? a.cnt[entry] : 0u;
-  valid = valid && cnt > 0;
+  const bool in_range = entry < ed.ent_off + ed.n_src;
+  const bool valid = in_range && a.keys[entry] != kInvalidKey;
+  const uint32_t cnt = in_range ? a.cnt[entry] : 0u;  // per-entry or per-pass pair counts
   double* out = a.partial + (int64_t)blk * kEdgeVals;
   const int64_t N = a.n_entries;
 

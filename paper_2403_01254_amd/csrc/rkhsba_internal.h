@@ -60,7 +60,7 @@ struct KConst {
   float rc2;         // float(r_c * r_c), the FP32 membership threshold
   float alpha;       // log2(e) / (2 ell^2), so that exp(-r^2/2l^2) = exp2(-alpha r^2)
   int reach_cells;   // cell_subdiv + 1
-  int clamp;         // clamp negative c to 0
+  int clamp;         // clamp negative c to 0 (only set when some feature value is negative)
   int Dp;            // padded dense feature width (0 for class ids)
   int pad;
 };
@@ -101,7 +101,7 @@ hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, cons
 hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
                          const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
-                         hipStream_t st);
+                         int32_t* d_neg_flag, hipStream_t st);
 hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
                        int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
                        uint64_t* d_total, hipStream_t st);

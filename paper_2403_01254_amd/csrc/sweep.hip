@@ -51,7 +51,20 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v, int lane) {
   return v;
 }
 
-template <int MODE, int FEAT, int DP>
+// Feature inner products of one 16-candidate sub-tile with the pass's 16
+// source points: D[cand 4(l/16)+r][source l%16] += F_cand[., 4k + l/16] *
+// F_src[4k + l/16][.], accumulated over the DP/4 slices of 4 dimensions.
+template <int DP, int FS>
+__device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, int g, int sub,
+                                        const float (&fsrc)[DP / 4]) {
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  const float* arow = tfeat + (16 * sub + s) * FS + g;
+#pragma unroll
+  for (int k = 0; k < DP / 4; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * k], fsrc[k], acc, 0, 0, 0);
+  return acc;
+}
+
+template <int MODE, int FEAT, int DP, bool CLAMP>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __restrict__ pass_off) {
   constexpr int P = 16;
   constexpr int FS = DP > 0 ? DP + 1 : 1;  // LDS feature row stride (odd: conflict-free column reads)
@@ -77,9 +90,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   }
   float3 q = make_float3(0.f, 0.f, 0.f);
   uint32_t lbl = 0;
-  float fsrc[DP > 0 ? DP / 4 : 1];
-#pragma unroll
-  for (int k = 0; k < (DP > 0 ? DP / 4 : 1); ++k) fsrc[k] = 0.f;
+  float fsrc[DP > 0 ? DP / 4 : 1] = {};
   if (valid) {
     const float4 x = a.pts[Fm.pt_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
@@ -98,7 +109,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   hi.x = uniform_f(wave_max(valid ? q.x : -FLT_MAX));
   hi.y = uniform_f(wave_max(valid ? q.y : -FLT_MAX));
   hi.z = uniform_f(wave_max(valid ? q.z : -FLT_MAX));
-  if (!(lo.x <= hi.x)) return;  // no valid source point in this pass (uniform)
+  const bool in_range = entry < ed.ent_off + ed.n_src;
+  if (!(lo.x <= hi.x)) {  // no valid source point in this pass (uniform)
+    if (g == 0 && in_range) a.cnt[entry] = 0u;
+    return;
+  }
 
   const KConst kc = a.kc;
   const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
@@ -110,13 +125,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   const int n_rows = (z1 >= z0 && y1 >= y0) ? (z1 - z0 + 1) * ny : 0;
 
   const float rc2 = kc.rc2, alpha = kc.alpha;
-  const bool clamp = kc.clamp != 0;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
   uint32_t cnt = 0;
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
   const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
-  const float nanf_ = __int_as_float(0x7fc00000);
+  const float far_ = 1.0e30f;
 
   for (int rb = 0; rb < n_rows; rb += kLanes) {
     // ---- one row per lane: its contiguous candidate range
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
           }
         }
       } else {
-        pos = make_float4(nanf_, nanf_, nanf_, 0.f);  // fails every membership test
+        pos = make_float4(far_, far_, far_, 0.f);  // fails every membership test, keeps the products finite
         if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
           for (int k = 0; k < DP; ++k) fr[k] = 0.f;
@@ -191,17 +205,20 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
       if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat);
       const uint32_t left = total - cb;
       const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
+      floatx4 cv = {1.f, 1.f, 1.f, 1.f};
+      if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
       for (int sub = 0; sub < n_sub; ++sub) {
-        floatx4 cv = {1.f, 1.f, 1.f, 1.f};
+        // this lane's four candidates of the sub-tile, read before any use
+        const float4* zp = tpos + 16 * sub + 4 * g;
+        const float4 z4[4] = {zp[0], zp[1], zp[2], zp[3]};
+        floatx4 cur = cv;
         if constexpr (FEAT == FEAT_DENSE) {
-          cv = floatx4{0.f, 0.f, 0.f, 0.f};
-          const float* arow = tfeat + (16 * sub + s) * FS + g;
-#pragma unroll
-          for (int k = 0; k < DP / 4; ++k) cv = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * k], fsrc[k], cv, 0, 0, 0);
+          // issue the next sub-tile's products now: the matrix core works while the VALU runs below
+          if (sub + 1 < n_sub) cv = tile_products<DP, FS>(tfeat, s, g, sub + 1, fsrc);
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const float4 z = tpos[16 * sub + 4 * g + rr];
+          const float4 z = z4[rr];
           float dx, dy, dz;
           const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
           bool in = valid && s2 <= rc2;
@@ -209,19 +226,19 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
           if constexpr (FEAT == FEAT_CLASS) {
             in = in && (__float_as_uint(z.w) == lbl);
           } else {
-            c = clamp ? fmaxf(cv[rr], 0.f) : cv[rr];
-            in = in && c != 0.f;
+            c = CLAMP ? fmaxf(cur[rr], 0.f) : cur[rr];
           }
-          if (in) {
-            const float w = c * __builtin_amdgcn_exp2f(-alpha * s2);
-            A += w;
-            cnt += 1u;
-            if constexpr (MODE == MODE_NORMAL) {
-              const float wx = w * dx, wy = w * dy, wz = w * dz;
-              Bx += wx; By += wy; Bz += wz;
-              Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-              Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
-            }
+          const float k = __builtin_amdgcn_exp2f(-alpha * s2);
+          const float w = in ? c * k : 0.f;
+          A += w;
+          // pairs counted per pass from the wavefront's lane mask (scalar unit)
+          if constexpr (FEAT == FEAT_CLASS) cnt += (uint32_t)__popcll(__ballot(in));
+          else cnt += (uint32_t)__popcll(__ballot(in && c != 0.f));
+          if constexpr (MODE == MODE_NORMAL) {
+            const float wx = w * dx, wy = w * dy, wz = w * dz;
+            Bx += wx; By += wy; Bz += wz;
+            Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
           }
         }
       }
@@ -233,16 +250,16 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
 #pragma unroll
   for (int o = 16; o < 64; o <<= 1) {
     A += __shfl_xor(A, o, 64);
-    cnt += __shfl_xor(cnt, o, 64);
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
       Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
       Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
     }
   }
+  // the pass's pair count goes to its first entry, zeros to the others
+  if (g == 0 && in_range) a.cnt[entry] = s == 0 ? cnt : 0u;
   if (g == 0 && valid) {
     const int64_t N = a.n_entries;
-    a.cnt[entry] = cnt;
     a.mom[entry] = A;
     if constexpr (MODE == MODE_NORMAL) {
       a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
@@ -252,32 +269,35 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   }
 }
 
-template <int MODE, int FEAT>
+template <int MODE, int FEAT, bool CLAMP>
 hipError_t dispatch(const PairArgs& a, const int32_t* pass_off, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass_total;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0><<<nb, kLanes, 0, st>>>(a, pass_off);
+    k_sweep<MODE, FEAT, 0, false><<<nb, kLanes, 0, st>>>(a, pass_off);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else k_sweep<MODE, FEAT, 64><<<nb, kLanes, 0, st>>>(a, pass_off);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else k_sweep<MODE, FEAT, 64, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
   }
   return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t dispatch_mode(const PairArgs& a, const int32_t* pass_off, int feat_path, hipStream_t st) {
+  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false>(a, pass_off, 0, st);
+  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true>(a, pass_off, a.kc.Dp, st);
+  return dispatch<MODE, FEAT_DENSE, false>(a, pass_off, a.kc.Dp, st);
 }
 
 }  // namespace
 
 // Tiled sweep for passes of 16 source points.
 hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, hipStream_t st) {
-  const int DP = a.kc.Dp;
-  if (mode == MODE_LOSS)
-    return feat_path == FEAT_CLASS ? dispatch<MODE_LOSS, FEAT_CLASS>(a, d_pass_off, DP, st)
-                                   : dispatch<MODE_LOSS, FEAT_DENSE>(a, d_pass_off, DP, st);
-  return feat_path == FEAT_CLASS ? dispatch<MODE_NORMAL, FEAT_CLASS>(a, d_pass_off, DP, st)
-                                 : dispatch<MODE_NORMAL, FEAT_DENSE>(a, d_pass_off, DP, st);
+  return mode == MODE_LOSS ? dispatch_mode<MODE_LOSS>(a, d_pass_off, feat_path, st)
+                           : dispatch_mode<MODE_NORMAL>(a, d_pass_off, feat_path, st);
 }
 
 }  // namespace rkhsba

@@ -90,7 +90,7 @@ class Context:
     """One rkhsba context (one stream, one set of resident frames)."""
 
     def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
-                 fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 3,
+                 fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 4,
                  pass_points: int = 16, stream=None):
         o = default_options()
         o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel

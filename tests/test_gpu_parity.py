@@ -42,6 +42,7 @@ SCENES = {
     "odometry_small": lambda: scenes.odometry(1, n_frames=4, n_points=4000, n_iter=4),
     "lidar_small": lambda: scenes.lidar(2, n_frames=4, n_points=6000, n_neighbours=2, n_iter=3, spacing=3.125),
     "two_view_ragged": lambda: scenes.two_view(3, n_points=1237),
+    "dense64_small": lambda: scenes.dense64(5, n_frames=3, n_points=3000, n_iter=3),
 }
 
 
