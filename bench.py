@@ -32,8 +32,17 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 # Algorithmic work per in-radius pair of the sweep (FMA = 2 flops, exp = 1):
 # residual 3 + squared distance 5 + scale 1 + exp 1 + weight 1 + A 1 + w*d 3 + B 3 + C 12
 FLOPS_PER_PAIR_GEOM = 30
-PAIR_KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_01254_amd", "csrc", "pairs.hip")
+PAIR_KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_01254_amd", "csrc", "sweep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_odometry_traffic.json")
+WORKLOADS = {
+    "odometry": "odometry: 8 depth-camera frames x 30,000 points, 23-dim soft-label+RGB features, all 28 frame "
+                "pairs, ell=0.08 m, cutoff 3 ell, 15 Gauss-Newton iterations (one step = voxel build + 15 "
+                "iterations + final loss)",
+    "lidar": "lidar: 64 spinning-LiDAR frames x 100,000 points, 20% outliers, 20-class one-hot labels with 10% "
+             "flipped, 384 directed 6-nearest-pose pairs, ell=0.3 m, cutoff 3 ell, 10 Gauss-Newton iterations",
+    "two_view": "two_view: 2 frames x 5,000 points, 10-class one-hot labels, ell=0.1 m, cutoff 3 ell, "
+                "10 Gauss-Newton iterations",
+}
 
 
 def kernel_source_hash():
@@ -64,8 +73,8 @@ def cpu_baseline(p, n_edges):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": npairs / dt, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"one normal-equation evaluation (loss, b, H; brute force over all point pairs, FP64) of the "
-                      f"first {len(edges)} of the 28 frame pairs at the initial poses: {npairs} in-radius pairs "
-                      f"in {dt:.2f} s"}
+                      f"first {len(edges)} of the {len(p.edges)} frame pairs at the initial poses: {npairs} "
+                      f"in-radius pairs in {dt:.2f} s"}
 
 
 def main():
@@ -74,9 +83,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pass-points", type=int, default=16)
-    ap.add_argument("--cell-subdiv", type=int, default=4)
+    ap.add_argument("--cell-subdiv", type=int, default=8)
+    ap.add_argument("--moment-path", type=int, default=0, help="0 library choice, 1 vector ALU, 2 matrix cores")
+    ap.add_argument("--workload", default="odometry", choices=["odometry", "lidar", "two_view"],
+                    help="odometry is the headline configuration; the others are for kernel studies")
     ap.add_argument("--cpu-edges", type=int, default=8, help="frame pairs in the CPU oracle sample (0: skip)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -93,17 +107,26 @@ def main():
         if not args.quiet:
             print(msg, file=sys.stderr, flush=True)
 
-    p = scenes.odometry(0)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    p = {"odometry": scenes.odometry, "lidar": scenes.lidar, "two_view": scenes.two_view}[args.workload](0)
     log(f"[bench] workload {p.recipe}: {len(p.edges)} edges, {p.n_iter} GN iterations")
     dev = torch.device("cuda:0")
     pts = [torch.from_numpy(x).to(dev) for x in p.points]
-    feats = [torch.from_numpy(f).to(dev) for f in p.feats]
+    # class ids travel as their 16-bit patterns
+    feats = [torch.from_numpy(f.view(np.int16) if f.dtype == np.uint16 else f).to(dev) for f in p.feats]
     torch.cuda.synchronize()
     ctx = rkhsba.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, pass_points=args.pass_points,
-                         cell_subdiv=args.cell_subdiv)
+                         cell_subdiv=args.cell_subdiv, moment_path=args.moment_path)
 
     def step():
-        ctx.build_neighbors(pts, feats, "dense")
+        ctx.build_neighbors(pts, feats, p.feat_kind)
         return ctx.gn_step(p.init_poses, p.edges, p.n_iter)
 
     for w in range(args.warmup):
@@ -130,7 +153,7 @@ def main():
     # roofline of the sweep kernel (Gauss-Newton evaluations): algorithmic flops per launch / mean launch time
     pair_ms, pair_launches = prof["pairs"]
     gn_pairs_per_launch = float(np.mean(ppi[:-1])) if p.n_iter > 0 else 0.0
-    flops_per_pair = FLOPS_PER_PAIR_GEOM + 2 * p.D
+    flops_per_pair = FLOPS_PER_PAIR_GEOM + (2 * p.D if p.feat_kind == "dense" else 0)
     mean_launch_s = pair_ms / max(pair_launches, 1) / 1e3
     achieved = flops_per_pair * gn_pairs_per_launch / mean_launch_s / 1e12 if mean_launch_s > 0 else 0.0
     traffic = load_traffic()
@@ -149,12 +172,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "odometry: 8 depth-camera frames x 30,000 points, 23-dim soft-label+RGB features, "
-                        "all 28 frame pairs, ell=0.08 m, cutoff 3 ell, 15 Gauss-Newton iterations "
-                        "(one step = voxel build + 15 iterations + final loss)",
+            "workload": WORKLOADS[args.workload],
             "frames": p.K, "points_per_frame": int(p.n_points[0]), "edges": int(len(p.edges)),
             "gn_iterations": p.n_iter, "feature_dim": p.D, "ell": p.ell,
-            "pass_points": args.pass_points, "cell_subdiv": args.cell_subdiv,
+            "pass_points": args.pass_points, "cell_subdiv": args.cell_subdiv, "moment_path": args.moment_path,
         },
         "gn_iters_per_s": p.n_iter * args.steps / elapsed,
         "pairs_per_step": pairs_total // args.steps,

@@ -79,8 +79,10 @@ typedef struct {
   int fixed_frame;       /* gauge: this frame is not moved (default 0, Sec. V-A) */
   int clamp_negative_c;  /* use max(c_ij, 0) for dense features (default 1) */
   int device;            /* HIP device ordinal (default 0) */
-  int cell_subdiv;       /* voxel cells per truncation radius, 1..8 (default 4) */
+  int cell_subdiv;       /* voxel cells per truncation radius, 1..8 (default 8) */
   int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
+  int moment_path;       /* 16-point sweep, Gauss-Newton moments accumulated on 0 = library choice,
+                            1 = vector ALU, 2 = matrix cores (default 0) */
   void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
 } rkhsba_options;
 

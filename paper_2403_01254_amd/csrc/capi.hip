@@ -354,8 +354,11 @@ void evaluate(rkhsba_ctx* c, int mode) {
   pa.kc = c->kc;
   const int feat_path = c->feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
   hipEvent_t t1 = prof_begin(c);
-  if (c->opt.pass_points == 16)
-    RK_HIP(launch_sweep16(pa, c->d_pass_off.p, mode, feat_path, st));
+  if (c->opt.pass_points == 16) {
+    // vector-ALU moments measured faster on both feature kinds; the matrix-core variant stays selectable
+    const bool mm = c->opt.moment_path == 2;
+    RK_HIP(launch_sweep16(pa, c->d_pass_off.p, mode, feat_path, mm, st));
+  }
   else
     RK_HIP(launch_pairs(pa, c->d_pass_off.p, mode, feat_path, c->opt.pass_points, st));
   prof_end(c, mode == MODE_NORMAL ? RKHSBA_PROF_PAIRS : RKHSBA_PROF_PAIRS_LOSS, t1);
@@ -421,7 +424,7 @@ void rkhsba_default_options(rkhsba_options* o) {
   o->fixed_frame = 0;
   o->clamp_negative_c = 1;
   o->device = 0;
-  o->cell_subdiv = 4;
+  o->cell_subdiv = 8;
   o->pass_points = 16;
   o->stream = nullptr;
 }
@@ -433,7 +436,8 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   if (!(opt->ell > 0.0) || !std::isfinite(opt->ell) || !(opt->cutoff_factor > 0.0) ||
       !std::isfinite(opt->cutoff_factor) || !std::isfinite(opt->sigma) || !(opt->damping_rel >= 0.0) ||
       opt->cell_subdiv < 1 || opt->cell_subdiv > 8 ||
-      (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) || opt->fixed_frame < 0)
+      (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) || opt->fixed_frame < 0 ||
+      opt->moment_path < 0 || opt->moment_path > 2)
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;

@@ -133,7 +133,8 @@ struct PairArgs {
 hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
                         hipStream_t st);
 
-hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, hipStream_t st);
+hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, bool matrix_moments,
+                          hipStream_t st);
 
 struct FinArgs {
   const float4* pts;

@@ -64,14 +64,23 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
   return acc;
 }
 
-template <int MODE, int FEAT, int DP, bool CLAMP>
+// MM: the moments are accumulated on the matrix core.  With u = z - ref (ref =
+// centre of the pass's box) and Phi(u) = [1, u, u u^T] (10 of 16 columns), the
+// sums M[s][f] = sum_j w_sj Phi_f(u_j) over all candidates are one MFMA chain
+// (A operand = the weights the lanes just computed, B = Phi of the same
+// candidates), and A, B, C follow exactly from M and v = q - ref:
+//   A = M_1, B = A v - M_u, C = A v v^T - v M_u^T - M_u v^T + M_uu.
+template <int MODE, int FEAT, int DP, bool CLAMP, bool MM>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __restrict__ pass_off) {
   constexpr int P = 16;
   constexpr int FS = DP > 0 ? DP + 1 : 1;  // LDS feature row stride (odd: conflict-free column reads)
+  constexpr int PHS = 20;                  // LDS Phi row stride (conflict-free B-operand reads)
   __shared__ uint32_t row_j0[kLanes];
   __shared__ uint32_t row_off[kLanes + 1];
   __shared__ float4 tpos[kTile];
   __shared__ float tfeat[DP > 0 ? kTile * FS : 1];
+  __shared__ float tphi[MM ? kTile * PHS : 1];
+  __shared__ float mt[MM ? 16 * 17 : 1];
 
   const int lane = threadIdx.x;
   const int pass = blockIdx.x;
@@ -113,6 +122,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   if (!(lo.x <= hi.x)) {  // no valid source point in this pass (uniform)
     if (g == 0 && in_range) a.cnt[entry] = 0u;
     return;
+  }
+  const float3 ref = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
+  floatx4 macc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  if constexpr (MM) {
+#pragma unroll
+    for (int k = 10; k < 16; ++k) tphi[lane * PHS + k] = 0.f;  // unused Phi columns stay zero
   }
 
   const KConst kc = a.kc;
@@ -167,7 +182,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
     if (total == 0) continue;
 
     // ---- tiles of 64 candidates, next tile fetched while the current one is processed
-    auto fetch = [&](uint32_t c, float4& pos, float* fr) {
+    auto fetch = [&](uint32_t c, float4& pos, float* fr, bool& pad) {
+      pad = c >= total;
       if (c < total) {
         int lo_r = 0, hi_r = 63;  // largest row with row_off[row] <= c
         while (lo_r < hi_r) {
@@ -194,15 +210,26 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
     };
     float4 npos;
     float nfeat[DP > 0 ? DP : 1];
-    fetch((uint32_t)lane, npos, nfeat);
+    bool npad;
+    fetch((uint32_t)lane, npos, nfeat, npad);
     for (uint32_t cb = 0; cb < total; cb += kTile) {
       tpos[lane] = npos;
+      if constexpr (MM) {
+        float* ph = tphi + lane * PHS;
+        const float ux = npad ? 0.f : npos.x - ref.x;
+        const float uy = npad ? 0.f : npos.y - ref.y;
+        const float uz = npad ? 0.f : npos.z - ref.z;
+        ph[0] = npad ? 0.f : 1.f;
+        ph[1] = ux; ph[2] = uy; ph[3] = uz;
+        ph[4] = ux * ux; ph[5] = ux * uy; ph[6] = ux * uz;
+        ph[7] = uy * uy; ph[8] = uy * uz; ph[9] = uz * uz;
+      }
       if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
         for (int k = 0; k < DP; ++k) tfeat[lane * FS + k] = nfeat[k];
       }
       __syncthreads();
-      if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat);
+      if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, npad);
       const uint32_t left = total - cb;
       const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
       floatx4 cv = {1.f, 1.f, 1.f, 1.f};
@@ -211,6 +238,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
         // this lane's four candidates of the sub-tile, read before any use
         const float4* zp = tpos + 16 * sub + 4 * g;
         const float4 z4[4] = {zp[0], zp[1], zp[2], zp[3]};
+        float phi4[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MM) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) phi4[rr] = tphi[(16 * sub + 4 * g + rr) * PHS + s];
+        }
         floatx4 cur = cv;
         if constexpr (FEAT == FEAT_DENSE) {
           // issue the next sub-tile's products now: the matrix core works while the VALU runs below
@@ -230,11 +262,15 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
           }
           const float k = __builtin_amdgcn_exp2f(-alpha * s2);
           const float w = in ? c * k : 0.f;
-          A += w;
           // pairs counted per pass from the wavefront's lane mask (scalar unit)
           if constexpr (FEAT == FEAT_CLASS) cnt += (uint32_t)__popcll(__ballot(in));
           else cnt += (uint32_t)__popcll(__ballot(in && c != 0.f));
-          if constexpr (MODE == MODE_NORMAL) {
+          if constexpr (MM) {
+            macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
+          } else {
+            A += w;
+          }
+          if constexpr (MODE == MODE_NORMAL && !MM) {
             const float wx = w * dx, wy = w * dy, wz = w * dz;
             Bx += wx; By += wy; Bz += wz;
             Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
@@ -246,9 +282,29 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
     }
   }
 
+  if constexpr (MM) {
+    // lane (s, g) holds M[source 4g + r][column s]; regroup per source through LDS
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mt[(4 * g + r) * 17 + s] = macc[0][r] + macc[1][r];
+    __syncthreads();
+    if (g == 0) {
+      const float* m = mt + s * 17;
+      const float vx = q.x - ref.x, vy = q.y - ref.y, vz = q.z - ref.z;
+      A = m[0];
+      const float mx = m[1], my = m[2], mz = m[3];
+      Bx = A * vx - mx; By = A * vy - my; Bz = A * vz - mz;
+      Cxx = A * vx * vx - 2.f * vx * mx + m[4];
+      Cxy = A * vx * vy - vx * my - mx * vy + m[5];
+      Cxz = A * vx * vz - vx * mz - mx * vz + m[6];
+      Cyy = A * vy * vy - 2.f * vy * my + m[7];
+      Cyz = A * vy * vz - vy * mz - my * vz + m[8];
+      Czz = A * vz * vz - 2.f * vz * mz + m[9];
+    }
+  }
   // sum the four candidate streams of each source point
 #pragma unroll
-  for (int o = 16; o < 64; o <<= 1) {
+  for (int o = 16; o < 64 && !MM; o <<= 1) {
     A += __shfl_xor(A, o, 64);
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
@@ -269,35 +325,38 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   }
 }
 
-template <int MODE, int FEAT, bool CLAMP>
+template <int MODE, int FEAT, bool CLAMP, bool MM>
 hipError_t dispatch(const PairArgs& a, const int32_t* pass_off, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass_total;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, false><<<nb, kLanes, 0, st>>>(a, pass_off);
+    k_sweep<MODE, FEAT, 0, false, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else k_sweep<MODE, FEAT, 64, CLAMP><<<nb, kLanes, 0, st>>>(a, pass_off);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
   }
   return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool MM>
 hipError_t dispatch_mode(const PairArgs& a, const int32_t* pass_off, int feat_path, hipStream_t st) {
-  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false>(a, pass_off, 0, st);
-  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true>(a, pass_off, a.kc.Dp, st);
-  return dispatch<MODE, FEAT_DENSE, false>(a, pass_off, a.kc.Dp, st);
+  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false, MM>(a, pass_off, 0, st);
+  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true, MM>(a, pass_off, a.kc.Dp, st);
+  return dispatch<MODE, FEAT_DENSE, false, MM>(a, pass_off, a.kc.Dp, st);
 }
 
 }  // namespace
 
 // Tiled sweep for passes of 16 source points.
-hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, hipStream_t st) {
-  return mode == MODE_LOSS ? dispatch_mode<MODE_LOSS>(a, d_pass_off, feat_path, st)
-                           : dispatch_mode<MODE_NORMAL>(a, d_pass_off, feat_path, st);
+// Loss-only sums stay on the VALU; Gauss-Newton moments on the VALU or the matrix cores.
+hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, bool matrix_moments,
+                          hipStream_t st) {
+  if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, d_pass_off, feat_path, st);
+  return matrix_moments ? dispatch_mode<MODE_NORMAL, true>(a, d_pass_off, feat_path, st)
+                        : dispatch_mode<MODE_NORMAL, false>(a, d_pass_off, feat_path, st);
 }
 
 }  // namespace rkhsba
