@@ -101,6 +101,7 @@ struct rkhsba_ctx {
   DBuf<int32_t> d_pass_off, d_fin_off;
   DBuf<SortTile> d_etiles;
   DBuf<SortSeg> d_esegs;
+  DBuf<int32_t> d_blk_start, d_blk_list, d_vec_start, d_vec_list;  // system assembly lists
 
   // per-evaluation buffers
   DBuf<double> d_poses;
@@ -295,6 +296,37 @@ void prepare_edges(rkhsba_ctx* c, int E, const int32_t* edges) {
   if (!tiles.empty())
     RK_HIP(hipMemcpyAsync(c->d_etiles.p, tiles.data(), sizeof(SortTile) * tiles.size(), hipMemcpyHostToDevice, st));
   RK_HIP(hipMemcpyAsync(c->d_esegs.p, segs.data(), sizeof(SortSeg) * E, hipMemcpyHostToDevice, st));
+  // contributors of every 6x6 block of H and every 6-vector of b, in edge order
+  const int K = c->K;
+  std::vector<std::vector<int32_t>> blk((size_t)K * K), vec(K);
+  for (int e = 0; e < E; ++e) {
+    const int m = info[e].m, n = info[e].n;
+    blk[(size_t)m * K + m].push_back(e * 4 + 0);
+    blk[(size_t)n * K + n].push_back(e * 4 + 1);
+    blk[(size_t)m * K + n].push_back(e * 4 + 2);
+    blk[(size_t)n * K + m].push_back(e * 4 + 3);
+    vec[m].push_back(e * 2 + 0);
+    vec[n].push_back(e * 2 + 1);
+  }
+  std::vector<int32_t> bstart((size_t)K * K + 1, 0), blist, vstart(K + 1, 0), vlist;
+  for (size_t k = 0; k < blk.size(); ++k) {
+    bstart[k] = (int32_t)blist.size();
+    blist.insert(blist.end(), blk[k].begin(), blk[k].end());
+  }
+  bstart[blk.size()] = (int32_t)blist.size();
+  for (int k = 0; k < K; ++k) {
+    vstart[k] = (int32_t)vlist.size();
+    vlist.insert(vlist.end(), vec[k].begin(), vec[k].end());
+  }
+  vstart[K] = (int32_t)vlist.size();
+  RK_HIP(c->d_blk_start.reserve(bstart.size()));
+  RK_HIP(c->d_blk_list.reserve(blist.size()));
+  RK_HIP(c->d_vec_start.reserve(vstart.size()));
+  RK_HIP(c->d_vec_list.reserve(vlist.size()));
+  RK_HIP(hipMemcpyAsync(c->d_blk_start.p, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice, st));
+  RK_HIP(hipMemcpyAsync(c->d_blk_list.p, blist.data(), sizeof(int32_t) * blist.size(), hipMemcpyHostToDevice, st));
+  RK_HIP(hipMemcpyAsync(c->d_vec_start.p, vstart.data(), sizeof(int32_t) * vstart.size(), hipMemcpyHostToDevice, st));
+  RK_HIP(hipMemcpyAsync(c->d_vec_list.p, vlist.data(), sizeof(int32_t) * vlist.size(), hipMemcpyHostToDevice, st));
   // per-evaluation buffers sized for this list
   RK_HIP(c->d_xf.reserve(E));
   RK_HIP(c->bk.reserve(entries));
@@ -398,6 +430,10 @@ SolveArgs solve_args(rkhsba_ctx* c, int fixed, int iter) {
   s.pairs_hist = c->pairs_hist.p;
   s.status = c->status.p;
   s.iter = iter;
+  s.blk_start = c->d_blk_start.p;
+  s.blk_list = c->d_blk_list.p;
+  s.vec_start = c->d_vec_start.p;
+  s.vec_list = c->d_vec_list.p;
   return s;
 }
 

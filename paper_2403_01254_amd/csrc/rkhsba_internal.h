@@ -172,6 +172,13 @@ struct SolveArgs {
   double* pairs_hist;      // [iter] pair count
   int32_t* status;         // 0 ok, -4 not positive definite (sticky)
   int32_t iter;
+  // contributors of each 6x6 block (frame a, frame c) of H, CSR over a*K+c:
+  // entries e*4 + role, role 0 H_mm, 1 H_nn, 2 H_mn, 3 H_mn^T
+  const int32_t* blk_start;  // K*K + 1
+  const int32_t* blk_list;
+  // contributors of each frame's 6-vector of b: entries e*2 + role, role 0 b_m, 1 b_n
+  const int32_t* vec_start;  // K + 1
+  const int32_t* vec_list;
 };
 hipError_t launch_assemble(const SolveArgs& a, hipStream_t st);
 hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);

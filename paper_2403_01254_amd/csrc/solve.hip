@@ -2,78 +2,62 @@
 // Gauss-Newton / IRLS step (Sec. V-A): with the weights frozen, the step
 // solves (H_red + mu I) delta = -b_red over every frame except the fixed one
 // and moves T_m <- T_m exp(delta_m^) (right perturbation, eps = [rho; phi]).
-// Single-workgroup kernels: the system is 6(K-1) <= a few hundred unknowns.
+//
+// Assembly is one thread per entry of the system, summing that entry's
+// contributing edge blocks in edge order (host-built lists, deterministic).
+// The solve is one workgroup: blocked right-looking Cholesky with 16-wide
+// panels, each diagonal block factored in one wavefront's registers, panel
+// rows solved one per thread, and the trailing update in 4x4 register tiles.
 #include "rkhsba_device.h"
 
 namespace rkhsba {
 namespace {
 
-constexpr int kSolveThreads = 256;
+constexpr int kSolveThreads = 1024;
+constexpr int NB = 16;
 
 __device__ inline int sym_index(int r, int c) {
   if (r > c) { const int t = r; r = c; c = t; }
   return r * 6 - (r * (r - 1)) / 2 + (c - r);
 }
 
-__device__ inline int reduced(int frame, int fixed) {
-  if (fixed < 0) return frame;
-  return frame == fixed ? -1 : (frame < fixed ? frame : frame - 1);
-}
+// reduced index <-> frame when frame `fixed` is removed (fixed < 0: none)
+__device__ inline int frame_of_reduced(int k, int fixed) { return (fixed >= 0 && k >= fixed) ? k + 1 : k; }
 
-__device__ double block_sum(double v, double* sh) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
-  __syncthreads();
-  return t;
-}
-
-// Scatters the per-edge blocks into the dense system (rows/columns of the
-// fixed frame dropped when fixed >= 0).  Edges are added one after another,
-// so the sums are deterministic.  Also records F (times sigma^2) and the pair
-// count of this evaluation.
-__global__ __launch_bounds__(kSolveThreads) void k_assemble(SolveArgs a) {
+__global__ __launch_bounds__(256) void k_assemble(SolveArgs a) {
   const int Kr = a.fixed >= 0 ? a.K - 1 : a.K;
   const int n = 6 * Kr;
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) a.H[i] = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) a.b[i] = 0.0;
-  __syncthreads();
-  const int t = threadIdx.x;
-  for (int e = 0; e < a.E; ++e) {
-    const double* v = a.edge_out + (int64_t)e * kEdgeVals;
-    const int rm = reduced(a.edges[e].m, a.fixed), rn = reduced(a.edges[e].n, a.fixed);
-    if (t < 36) {
-      const int r = t / 6, c = t % 6;
-      const double mm = v[13 + sym_index(r, c)], nn = v[34 + sym_index(r, c)], mn = v[55 + 6 * r + c];
-      if (rm >= 0) a.H[(int64_t)(6 * rm + r) * n + 6 * rm + c] += mm;
-      if (rn >= 0) a.H[(int64_t)(6 * rn + r) * n + 6 * rn + c] += nn;
-      if (rm >= 0 && rn >= 0) {
-        a.H[(int64_t)(6 * rm + r) * n + 6 * rn + c] += mn;
-        a.H[(int64_t)(6 * rn + c) * n + 6 * rm + r] += mn;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx < (int64_t)n * n) {
+    const int row = (int)(idx / n), col = (int)(idx % n);
+    const int fa = frame_of_reduced(row / 6, a.fixed), fc = frame_of_reduced(col / 6, a.fixed);
+    const int r = row % 6, s = col % 6;
+    const int blk = fa * a.K + fc;
+    double v = 0.0;
+    for (int k = a.blk_start[blk]; k < a.blk_start[blk + 1]; ++k) {
+      const int code = a.blk_list[k];
+      const double* eo = a.edge_out + (int64_t)(code >> 2) * kEdgeVals;
+      switch (code & 3) {
+        case 0: v += eo[13 + sym_index(r, s)]; break;
+        case 1: v += eo[34 + sym_index(r, s)]; break;
+        case 2: v += eo[55 + 6 * r + s]; break;
+        default: v += eo[55 + 6 * s + r]; break;
       }
-    } else if (t < 42) {
-      if (rm >= 0) a.b[6 * rm + t - 36] += v[1 + t - 36];
-    } else if (t < 48) {
-      if (rn >= 0) a.b[6 * rn + t - 42] += v[7 + t - 42];
     }
-    __syncthreads();
-  }
-  if (t == 0) {
-    double F = 0.0, np = 0.0;
-    for (int e = 0; e < a.E; ++e) {
-      F += a.edge_out[(int64_t)e * kEdgeVals];
-      np += a.edge_out[(int64_t)e * kEdgeVals + 91];
+    a.H[idx] = v;
+  } else if (idx < (int64_t)n * n + n) {
+    const int row = (int)(idx - (int64_t)n * n);
+    const int fa = frame_of_reduced(row / 6, a.fixed), r = row % 6;
+    double v = 0.0;
+    for (int k = a.vec_start[fa]; k < a.vec_start[fa + 1]; ++k) {
+      const int code = a.vec_list[k];
+      v += a.edge_out[(int64_t)(code >> 1) * kEdgeVals + ((code & 1) ? 7 : 1) + r];
     }
-    if (a.loss_hist) a.loss_hist[a.iter] = a.sigma2 * F;
-    if (a.pairs_hist) a.pairs_hist[a.iter] = np;
+    a.b[row] = v;
   }
 }
 
-// Loss-only evaluation: F and the pair count from the per-edge sums.
+// F (times sigma^2) and the pair count of an evaluation, in edge order.
 __global__ void k_loss_only(SolveArgs a) {
   if (threadIdx.x != 0) return;
   double F = 0.0, np = 0.0;
@@ -87,7 +71,7 @@ __global__ void k_loss_only(SolveArgs a) {
 
 // T <- T exp(xi^): closed-form SE(3) exponential (Rodrigues for the rotation,
 // V = I + B K + C K^2 for the translation), series for small angles.
-__device__ void right_update(double* T, const double* xi) {
+__device__ __noinline__ void right_update(double* T, const double* xi) {
   const double* rho = xi;
   const double* phi = xi + 3;
   const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
@@ -128,10 +112,127 @@ __device__ void right_update(double* T, const double* xi) {
   }
 }
 
-// Damped Cholesky solve of the reduced system and pose update.  A failed
-// factorisation sets *status = -4 and leaves the poses untouched; once set,
-// later steps do nothing.
+__device__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// Factors the nb x nb diagonal block at (kb, kb) of the n x n matrix H in
+// wavefront 0: lane i holds row i in registers; column j's pivot and entries
+// are broadcast with shuffles.  Writes L11 to H and to Ld.  Returns false (in
+// every lane of wave 0) on a non-positive pivot.
+__device__ __noinline__ bool factor_diag(double* H, int n, int kb, int nb, double (*Ld)[NB + 1]) {
+  const int i = threadIdx.x;  // wave 0 only
+  double r[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) r[k] = (i < nb && k <= i) ? H[(int64_t)(kb + i) * n + kb + k] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nb) {
+      const double d = __shfl(r[j], j, 64);
+      ok = ok && d > 0.0;
+      const double ljj = sqrt(d > 0.0 ? d : 1.0);
+      if (i == j) r[j] = ljj;
+      else if (i > j) r[j] /= ljj;
+#pragma unroll
+      for (int k = j + 1; k < NB; ++k) {
+        const double lkj = __shfl(r[j], k, 64);
+        if (k < nb && i >= k) r[k] -= r[j] * lkj;
+      }
+    }
+  }
+  if (i < nb) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k <= i) {
+        H[(int64_t)(kb + i) * n + kb + k] = r[k];
+        Ld[i][k] = r[k];
+      }
+  }
+  return ok;
+}
+
+// Panel below the diagonal block: L21 = A21 L11^-T, one row per thread.
+__device__ __noinline__ void panel_solve(double* H, int n, int kb, int nb, const double (*Ld)[NB + 1]) {
+  const int t = threadIdx.x, T = blockDim.x;
+    const int m0 = kb + nb;
+    for (int i = m0 + t; i < n; i += T) {
+      double* row = H + (int64_t)i * n + kb;
+      double x[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+          double v = row[j];
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            if (k < j) v -= x[k] * Ld[j][k];
+          x[j] = v / Ld[j][j];
+        } else {
+          x[j] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < nb) row[j] = x[j];
+    }
+}
+
+// Trailing update of the lower triangle: A22 -= L21 L21^T in 4x4 register tiles.
+__device__ __noinline__ void trailing_update(double* H, int n, int kb, int nb) {
+  const int t = threadIdx.x, T = blockDim.x;
+  const int m0 = kb + nb;
+    const int m = n - m0;
+    const int tiles = (m + 3) / 4;
+    const int n_tiles = tiles * (tiles + 1) / 2;
+    for (int tt = t; tt < n_tiles; tt += T) {
+      // tile (ti, tk) with ti >= tk, enumerated row by row of the tile triangle
+      int ti = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+      while (ti * (ti + 1) / 2 > tt) --ti;
+      const int tk = tt - ti * (ti + 1) / 2;
+      const int i0 = m0 + 4 * ti, k0 = m0 + 4 * tk;
+      double acc[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+      for (int j0 = 0; j0 < nb; j0 += 4) {
+        double li[4][4], lk[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool okj = j0 + j < nb;
+            li[p][j] = (okj && i0 + p < n) ? H[(int64_t)(i0 + p) * n + kb + j0 + j] : 0.0;
+            lk[p][j] = (okj && k0 + p < n) ? H[(int64_t)(k0 + p) * n + kb + j0 + j] : 0.0;
+          }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[p][q] = fma(li[p][j], lk[q][j], acc[p][q]);
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + p, k = k0 + q;
+          if (i < n && k <= i) H[(int64_t)i * n + k] -= acc[p][q];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
+  __shared__ double Ld[NB][NB + 1];
   __shared__ double sh[kSolveThreads / 64];
   __shared__ int fail;
   if (*a.status != 0) return;
@@ -150,60 +251,82 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
   }
   if (t == 0) fail = 0;
   __syncthreads();
-  // right-looking Cholesky, lower triangle in place
-  for (int j = 0; j < n; ++j) {
-    if (t == 0) {
-      const double d = H[(int64_t)j * n + j];
-      if (d > 0.0) H[(int64_t)j * n + j] = sqrt(d);
-      else fail = 1;
+
+  // ---- blocked Cholesky, lower triangle in place
+  for (int kb = 0; kb < n; kb += NB) {
+    const int nb = min(NB, n - kb);
+    if (t < 64) {
+      const bool ok = factor_diag(H, n, kb, nb, Ld);
+      if (t == 0 && !ok) fail = 1;
     }
     __syncthreads();
     if (fail) break;
-    const double ljj = H[(int64_t)j * n + j];
-    for (int i = j + 1 + t; i < n; i += T) H[(int64_t)i * n + j] /= ljj;
+    panel_solve(H, n, kb, nb, Ld);
     __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = t; idx < m * m; idx += T) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) H[(int64_t)i * n + k] -= H[(int64_t)i * n + j] * H[(int64_t)k * n + j];
-    }
+    trailing_update(H, n, kb, nb);
     __syncthreads();
   }
   if (fail) {
     if (t == 0) *a.status = -4;
     return;
   }
-  // L y' = -b  (column-oriented forward substitution)
-  for (int j = 0; j < n; ++j) {
-    if (t == 0) y[j] /= H[(int64_t)j * n + j];
+
+  // ---- L y' = -b: diagonal blocks in wave 0, off-diagonal updates by all threads
+  for (int kb = 0; kb < n; kb += NB) {
+    const int nb = min(NB, n - kb);
+    if (t < 64) {
+      double v = t < nb ? y[kb + t] : 0.0;
+      for (int j = 0; j < nb; ++j) {
+        const double yj = __shfl(v, j, 64) / H[(int64_t)(kb + j) * n + kb + j];
+        if (t == j) v = yj;
+        else if (t > j && t < nb) v -= H[(int64_t)(kb + t) * n + kb + j] * yj;
+      }
+      if (t < nb) y[kb + t] = v;
+    }
     __syncthreads();
-    const double yj = y[j];
-    for (int i = j + 1 + t; i < n; i += T) y[i] -= H[(int64_t)i * n + j] * yj;
+    for (int i = kb + nb + t; i < n; i += T) {
+      double v = y[i];
+      for (int j = 0; j < nb; ++j) v -= H[(int64_t)i * n + kb + j] * y[kb + j];
+      y[i] = v;
+    }
     __syncthreads();
   }
-  // L^T delta = y'
-  for (int j = n - 1; j >= 0; --j) {
-    if (t == 0) y[j] /= H[(int64_t)j * n + j];
+  // ---- L^T delta = y'
+  for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
+    const int nb = min(NB, n - kb);
+    if (t < 64) {
+      double v = t < nb ? y[kb + t] : 0.0;
+      for (int j = nb - 1; j >= 0; --j) {
+        const double xj = __shfl(v, j, 64) / H[(int64_t)(kb + j) * n + kb + j];
+        if (t == j) v = xj;
+        else if (t < j) v -= H[(int64_t)(kb + j) * n + kb + t] * xj;
+      }
+      if (t < nb) y[kb + t] = v;
+    }
     __syncthreads();
-    const double xj = y[j];
-    for (int i = t; i < j; i += T) y[i] -= H[(int64_t)j * n + i] * xj;
+    for (int i = t; i < kb; i += T) {
+      double v = y[i];
+      for (int j = 0; j < nb; ++j) v -= H[(int64_t)(kb + j) * n + i] * y[kb + j];
+      y[i] = v;
+    }
     __syncthreads();
   }
-  for (int k = t; k < a.K - 1; k += T) {
-    const int f = k < a.fixed ? k : k + 1;
-    right_update(a.poses + 12 * f, y + 6 * k);
-  }
+  for (int k = t; k < a.K - 1; k += T) right_update(a.poses + 12 * frame_of_reduced(k, a.fixed), y + 6 * k);
 }
 
 }  // namespace
 
 hipError_t launch_assemble(const SolveArgs& a, hipStream_t st) {
-  k_assemble<<<1, kSolveThreads, 0, st>>>(a);
+  const int Kr = a.fixed >= 0 ? a.K - 1 : a.K;
+  const int64_t n = 6 * (int64_t)Kr;
+  const int64_t work = n * n + n;
+  if (work > 0) k_assemble<<<(unsigned)((work + 255) / 256), 256, 0, st>>>(a);
+  k_loss_only<<<1, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st) {
-  k_solve_update<<<1, kSolveThreads, 0, st>>>(a);
+  if (a.K >= 2) k_solve_update<<<1, kSolveThreads, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ SCENES = {
     "lidar_small": lambda: scenes.lidar(2, n_frames=4, n_points=6000, n_neighbours=2, n_iter=3, spacing=3.125),
     "two_view_ragged": lambda: scenes.two_view(3, n_points=1237),
     "dense64_small": lambda: scenes.dense64(5, n_frames=3, n_points=3000, n_iter=3),
+    "lidar_k12": lambda: scenes.lidar(3, n_frames=12, n_points=3000, n_neighbours=4, n_iter=3, spacing=3.125),
 }
 
 
@@ -207,3 +208,32 @@ def test_invalid_arguments(rk):
     with pytest.raises(rk.RkhsbaError) as e:
         fresh.eval_loss(np.stack([ident(), ident()]), [[0, 1]])
     assert e.value.code == rk.ESTATE
+
+
+def test_gauss_newton_step_matches_host_solve_large_system(rk):
+    """One Gauss-Newton step on 40 frames (a 234-unknown system, several
+    Cholesky panels with a ragged last one) equals the step computed on the
+    host from the library's own H and b (numpy solve, scipy SE(3) exp)."""
+    import scipy.linalg
+    p = scenes.lidar(4, n_frames=40, n_points=2000, n_neighbours=4, spacing=3.125)
+    ctx = make_ctx(rk, p)
+    H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    Hr, br = H[6:, 6:], b[6:]
+    nr = len(br)
+    mu = 1e-10 * np.trace(Hr) / nr
+    delta = np.linalg.solve(Hr + mu * np.eye(nr), -br)
+    expect = p.init_poses.copy()
+    for k in range(1, p.K):
+        xi = delta[6 * (k - 1): 6 * k]
+        W = np.zeros((4, 4))
+        W[:3, :3] = [[0, -xi[5], xi[4]], [xi[5], 0, -xi[3]], [-xi[4], xi[3], 0]]
+        W[:3, 3] = xi[:3]
+        T = np.eye(4)
+        T[:3, :3] = p.init_poses[k][:9].reshape(3, 3)
+        T[:3, 3] = p.init_poses[k][9:]
+        T = T @ scipy.linalg.expm(W)
+        expect[k] = np.concatenate([T[:3, :3].reshape(9), T[:3, 3]])
+    got, lpi, ppi = ctx.gn_step(p.init_poses, p.edges, 1)
+    rot, tr = pose_errors(got, expect)
+    say(f"[solve] n={nr} |delta| {np.linalg.norm(delta):.3g} rot {rot.max():.3g} trans {tr.max():.3g}")
+    assert rot.max() <= 1e-9 and tr.max() <= 1e-9
