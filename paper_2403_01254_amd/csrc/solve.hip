@@ -185,54 +185,60 @@ __device__ __noinline__ void panel_solve(double* H, int n, int kb, int nb, const
     }
 }
 
-// Trailing update of the lower triangle: A22 -= L21 L21^T in 4x4 register tiles.
-__device__ __noinline__ void trailing_update(double* H, int n, int kb, int nb) {
+// Trailing update of the lower triangle: A22 -= L21 L21^T in 4x4 register
+// tiles.  The panel L21 is read from LDS (P, row stride NB) when it fits, else
+// from global memory.
+constexpr int kPanelRows = 896;  // LDS panel capacity: 896 x 16 doubles = 112 KB
+__device__ __noinline__ void trailing_update(double* H, int n, int kb, int nb, const double* P) {
   const int t = threadIdx.x, T = blockDim.x;
   const int m0 = kb + nb;
-    const int m = n - m0;
-    const int tiles = (m + 3) / 4;
-    const int n_tiles = tiles * (tiles + 1) / 2;
-    for (int tt = t; tt < n_tiles; tt += T) {
-      // tile (ti, tk) with ti >= tk, enumerated row by row of the tile triangle
-      int ti = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-      while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
-      while (ti * (ti + 1) / 2 > tt) --ti;
-      const int tk = tt - ti * (ti + 1) / 2;
-      const int i0 = m0 + 4 * ti, k0 = m0 + 4 * tk;
-      double acc[4][4];
+  const int m = n - m0;
+  const bool lds = m <= kPanelRows;
+  const int tiles = (m + 3) / 4;
+  const int n_tiles = tiles * (tiles + 1) / 2;
+  for (int tt = t; tt < n_tiles; tt += T) {
+    // tile (ti, tk) with ti >= tk, enumerated row by row of the tile triangle
+    int ti = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+    while (ti * (ti + 1) / 2 > tt) --ti;
+    const int tk = tt - ti * (ti + 1) / 2;
+    const int i0 = 4 * ti, k0 = 4 * tk;  // panel-relative rows
+    double acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+    for (int j0 = 0; j0 < nb; j0 += 4) {
+      double li[4][4], lk[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-      for (int j0 = 0; j0 < nb; j0 += 4) {
-        double li[4][4], lk[4][4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const bool okj = j0 + j < nb;
-            li[p][j] = (okj && i0 + p < n) ? H[(int64_t)(i0 + p) * n + kb + j0 + j] : 0.0;
-            lk[p][j] = (okj && k0 + p < n) ? H[(int64_t)(k0 + p) * n + kb + j0 + j] : 0.0;
-          }
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[p][q] = fma(li[p][j], lk[q][j], acc[p][q]);
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = i0 + p, k = k0 + q;
-          if (i < n && k <= i) H[(int64_t)i * n + k] -= acc[p][q];
+        for (int j = 0; j < 4; ++j) {
+          const bool okj = j0 + j < nb;
+          const int ri = i0 + p, rk = k0 + p;
+          li[p][j] = (okj && ri < m) ? (lds ? P[ri * NB + j0 + j] : H[(int64_t)(m0 + ri) * n + kb + j0 + j]) : 0.0;
+          lk[p][j] = (okj && rk < m) ? (lds ? P[rk * NB + j0 + j] : H[(int64_t)(m0 + rk) * n + kb + j0 + j]) : 0.0;
         }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[p][q] = fma(li[p][j], lk[q][j], acc[p][q]);
     }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = m0 + i0 + p, k = m0 + k0 + q;
+        if (i < n && k <= i) H[(int64_t)i * n + k] -= acc[p][q];
+      }
+  }
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
   __shared__ double Ld[NB][NB + 1];
+  __shared__ double P[kPanelRows * NB];
   __shared__ double sh[kSolveThreads / 64];
   __shared__ int fail;
   if (*a.status != 0) return;
@@ -263,7 +269,14 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
     if (fail) break;
     panel_solve(H, n, kb, nb, Ld);
     __syncthreads();
-    trailing_update(H, n, kb, nb);
+    if (n - (kb + nb) <= kPanelRows) {  // stage the panel in LDS for the trailing update
+      for (int idx = threadIdx.x; idx < (n - kb - nb) * NB; idx += blockDim.x) {
+        const int r = idx / NB, j = idx % NB;
+        P[idx] = j < nb ? H[(int64_t)(kb + nb + r) * n + kb + j] : 0.0;
+      }
+      __syncthreads();
+    }
+    trailing_update(H, n, kb, nb, P);
     __syncthreads();
   }
   if (fail) {
