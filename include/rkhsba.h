@@ -83,6 +83,8 @@ typedef struct {
   int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
   int moment_path;       /* 16-point sweep, Gauss-Newton moments accumulated on 0 = library choice,
                             1 = vector ALU, 2 = matrix cores (default 0) */
+  int use_graphs;        /* 1 = capture one Gauss-Newton iteration in a HIP graph and replay it (default 1;
+                            stage timing, when enabled, runs the launches one by one instead) */
   void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
 } rkhsba_options;
 

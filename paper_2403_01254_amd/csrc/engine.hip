@@ -1,0 +1,832 @@
+// Engine: resident problem storage, set layouts and the launch sequences of
+// the voxel build, the evaluation and the Gauss-Newton iteration.
+#include "engine.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/rkhsba.h"
+
+namespace rkhsba {
+
+void throw_hip(hipError_t e, const char* what) {
+  throw Fail{e == hipErrorOutOfMemory ? RKHSBA_ENOMEM : RKHSBA_EDEVICE,
+             std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// ---------------------------------------------------------------- RangeAlloc
+
+int64_t RangeAlloc::alloc(int64_t n) {
+  if (n <= 0) n = 1;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < n) continue;
+    const int64_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > n) free_[off + n] = len - n;
+    used_ += n;
+    return off;
+  }
+  return -1;
+}
+
+void RangeAlloc::free(int64_t off, int64_t n) {
+  if (n <= 0) n = 1;
+  used_ -= n;
+  auto next = free_.lower_bound(off);
+  if (next != free_.end() && off + n == next->first) {
+    n += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += n;
+      return;
+    }
+  }
+  free_[off] = n;
+}
+
+void RangeAlloc::grow(int64_t new_cap) {
+  if (new_cap <= cap_) return;
+  const int64_t add = new_cap - cap_;
+  if (!free_.empty()) {
+    auto last = std::prev(free_.end());
+    if (last->first + last->second == cap_) {
+      last->second += add;
+      cap_ = new_cap;
+      return;
+    }
+  }
+  free_[cap_] = add;
+  cap_ = new_cap;
+}
+
+int64_t RangeAlloc::largest_free() const {
+  int64_t m = 0;
+  for (const auto& kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
+// ---------------------------------------------------------------- Pool
+
+Pool::~Pool() {
+  for (void* p : ptr_)
+    if (p) (void)hipFree(p);
+}
+
+size_t Pool::bytes() const {
+  size_t b = 0;
+  for (size_t e : eb_) b += e * (size_t)ra_.capacity();
+  return b;
+}
+
+void Pool::set_elem_bytes(int i, size_t b) {
+  if (eb_[i] == b) return;
+  if (ptr_[i]) (void)hipFree(ptr_[i]);
+  ptr_[i] = nullptr;
+  eb_[i] = b;
+  if (ra_.capacity() > 0) RK_HIP(hipMalloc(&ptr_[i], b * (size_t)ra_.capacity()));
+  ++gen_;
+}
+
+int64_t Pool::alloc(int64_t n, hipStream_t st) {
+  if (n <= 0) n = 1;
+  int64_t off = ra_.alloc(n);
+  if (off >= 0) return off;
+  const int64_t cap = ra_.capacity();
+  const int64_t new_cap = std::max<int64_t>({cap + n, cap + cap / 2, 1024});
+  std::vector<void*> fresh(eb_.size(), nullptr);
+  for (size_t i = 0; i < eb_.size(); ++i) {
+    hipError_t e = hipMalloc(&fresh[i], eb_[i] * (size_t)new_cap);
+    if (e != hipSuccess) {
+      for (void* p : fresh)
+        if (p) (void)hipFree(p);
+      throw_hip(e, "pool growth");
+    }
+    if (ptr_[i] && cap > 0) RK_HIP(hipMemcpyAsync(fresh[i], ptr_[i], eb_[i] * (size_t)cap, hipMemcpyDeviceToDevice, st));
+  }
+  RK_HIP(hipStreamSynchronize(st));
+  for (size_t i = 0; i < eb_.size(); ++i) {
+    if (ptr_[i]) (void)hipFree(ptr_[i]);
+    ptr_[i] = fresh[i];
+  }
+  ++gen_;
+  ra_.grow(new_cap);
+  off = ra_.alloc(n);
+  RK_REQUIRE(off >= 0, RKHSBA_ENOMEM, "pool allocation failed after growth");
+  return off;
+}
+
+// ---------------------------------------------------------------- SetLayout
+
+void SetLayout::drop_graph() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+  graph = nullptr;
+  graph_mode = -1;
+}
+
+SetLayout::~SetLayout() { drop_graph(); }
+
+// ---------------------------------------------------------------- Engine
+
+Engine::Engine(int dev, hipStream_t stream, int pp, int mp)
+    : device(dev), st(stream), pass_points(pp), moment_path(mp) {}
+
+Engine::~Engine() {
+  for (auto& s : stages)
+    for (auto& pr : s.pending) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t ev : event_pool_) (void)hipEventDestroy(ev);
+}
+
+uint64_t Engine::generation() const {
+  return points_.generation() + rows_.generation() + xtab_.generation() + slots_.generation() +
+         hist_.generation() + state_.generation() + scratch_gen_;
+}
+
+hipEvent_t Engine::prof_begin() {
+  if (!prof) return nullptr;
+  hipEvent_t ev = nullptr;
+  if (!event_pool_.empty()) {
+    ev = event_pool_.back();
+    event_pool_.pop_back();
+  } else if (hipEventCreate(&ev) != hipSuccess) {
+    return nullptr;
+  }
+  (void)hipEventRecord(ev, st);
+  return ev;
+}
+
+void Engine::prof_end(int stage, hipEvent_t start) {
+  if (!prof || !start) return;
+  hipEvent_t ev = nullptr;
+  if (!event_pool_.empty()) {
+    ev = event_pool_.back();
+    event_pool_.pop_back();
+  } else if (hipEventCreate(&ev) != hipSuccess) {
+    return;
+  }
+  (void)hipEventRecord(ev, st);
+  stages[stage].pending.emplace_back(start, ev);
+}
+
+void Engine::prof_collect() {
+  for (auto& s : stages) {
+    for (auto& pr : s.pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        s.ms += ms;
+        s.launches += 1;
+      }
+      event_pool_.push_back(pr.first);
+      event_pool_.push_back(pr.second);
+    }
+    s.pending.clear();
+  }
+}
+
+Problem* Engine::problem(int id) {
+  auto it = probs_.find(id);
+  return it == probs_.end() ? nullptr : it->second.get();
+}
+
+int64_t Engine::device_bytes() const {
+  int64_t b = (int64_t)(points_.bytes() + rows_.bytes() + xtab_.bytes() + slots_.bytes() + hist_.bytes() +
+                        state_.bytes());
+  b += (int64_t)(raw_xyz_.bytes() + raw_feat_.bytes() + cell_.bytes() + k1_.bytes() + v1_.bytes() + k2_.bytes() +
+                 v2_.bytes() + hist_scratch_.bytes() + row_sizes_.bytes() + scan_tmp_.bytes());
+  b += (int64_t)(xf_.bytes() + bk_.bytes() + bv_.bytes() + bk2_.bytes() + bv2_.bytes() + bhist_.bytes() +
+                 mom_.bytes() + cnt_.bytes() + partial_.bytes() + edge_out_.bytes() + H_.bytes() + b_.bytes() +
+                 delta_.bytes());
+  return b;
+}
+
+int64_t Engine::estimate_problem_bytes(int K, const int64_t* n_points, int E) const {
+  int64_t N = 0, nmax = 0;
+  for (int f = 0; f < K; ++f) {
+    N += n_points[f];
+    nmax = std::max(nmax, n_points[f]);
+  }
+  const int64_t per_point = 28 + 4 * std::max(Dp, 1) + 12;  // pools + cell tables (typical occupancy)
+  const int64_t per_entry = 16 + 40 + 4 + 3;                // binning keys/values (x2), moments, count, partials
+  const int64_t n = 6 * (int64_t)K;
+  return N * per_point + (int64_t)E * nmax * per_entry + 2 * n * n * 8 + (int64_t)E * 2 * kEdgeVals * 8;
+}
+
+void Engine::compute_constants(Problem* p) {
+  const ProbParams& o = p->par;
+  const double rc = o.cutoff_factor * o.ell;
+  const double cell = rc / o.cell_subdiv;
+  KConst k{};
+  k.inv_cell = 1.0 / cell;
+  k.cell = cell;
+  k.reach = rc * (1.0 + std::ldexp(1.0, -12));
+  k.reach2 = k.reach * k.reach;
+  k.rc2 = (float)(rc * rc);
+  k.alpha = (float)(1.4426950408889634 / (2.0 * o.ell * o.ell));
+  k.reach_cells = o.cell_subdiv + 1;
+  k.clamp = (o.clamp_negative_c && p->negative_features) ? 1 : 0;
+  k.Dp = Dp;
+  p->kc = k;
+}
+
+int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
+                        int Din, const void* const* feats, bool is_device) {
+  RK_REQUIRE(K >= 1 && n_points && xyz && feats, RKHSBA_EINVAL, "K >= 1 and non-NULL n_points/xyz/feats required");
+  RK_REQUIRE(kind == RKHSBA_FEAT_CLASS_ID || kind == RKHSBA_FEAT_DENSE_F32, RKHSBA_EINVAL,
+             "feature kind not supported by this build (class ids or dense float32)");
+  if (kind != RKHSBA_FEAT_CLASS_ID)
+    RK_REQUIRE(Din >= 1 && Din <= kMaxDense, RKHSBA_EINVAL, "dense feature dimension must be in [1, 64]");
+  RK_REQUIRE(par.ell > 0.0 && std::isfinite(par.ell) && par.cutoff_factor > 0.0 && std::isfinite(par.cutoff_factor) &&
+                 par.cell_subdiv >= 1 && par.cell_subdiv <= 8 && std::isfinite(par.sigma) && par.damping_rel >= 0.0,
+             RKHSBA_EINVAL, "invalid problem parameters");
+  const int Dk = kind == RKHSBA_FEAT_CLASS_ID ? 0 : Din;
+  if (probs_.empty()) {
+    feat_kind = kind;
+    D = Dk;
+    Dp = kind == RKHSBA_FEAT_CLASS_ID ? 0 : dense_pad(Din);
+    points_.set_elem_bytes(3, sizeof(float) * (size_t)std::max(Dp, 1));
+  } else {
+    RK_REQUIRE(kind == feat_kind && Dk == D, RKHSBA_EINVAL,
+               "all resident problems share one feature kind and dimension");
+  }
+  std::vector<int64_t> off(K + 1, 0);
+  for (int f = 0; f < K; ++f) {
+    RK_REQUIRE(n_points[f] >= 1 && n_points[f] < (1LL << 31), RKHSBA_EINVAL, "each frame needs 1..2^31-1 points");
+    RK_REQUIRE(xyz[f] && feats[f], RKHSBA_EINVAL, "NULL frame pointer");
+    off[f + 1] = off[f] + n_points[f];
+  }
+  const int64_t N = off[K];
+  RK_REQUIRE(N < (1LL << 32), RKHSBA_EINVAL, "too many points in one problem");
+
+  auto P = std::make_unique<Problem>();
+  Problem* p = P.get();
+  p->par = par;
+  p->K = K;
+  p->N = N;
+  p->n_points.assign(n_points, n_points + K);
+  compute_constants(p);
+  const KConst kc0 = p->kc;
+  const size_t fbytes = kind == RKHSBA_FEAT_CLASS_ID ? sizeof(uint16_t) : sizeof(float) * (size_t)Din;
+
+  auto release = [&]() {
+    if (p->pbase >= 0) points_.free(p->pbase, N);
+    if (p->rbase >= 0) rows_.free(p->rbase, p->n_rows);
+    if (p->xbase >= 0) xtab_.free(p->xbase, p->n_xt);
+    if (p->slot0 >= 0) slots_.free(p->slot0, K);
+    if (p->sbase >= 0) state_.free(p->sbase, 1);
+  };
+  try {
+    // stage inputs and per-frame pointers
+    std::vector<const float*> xp(K);
+    std::vector<const void*> fp(K);
+    if (is_device) {
+      for (int f = 0; f < K; ++f) {
+        xp[f] = xyz[f];
+        fp[f] = feats[f];
+      }
+    } else {
+      for (int f = 0; f < K; ++f)
+        for (int64_t i = 0; i < 3 * n_points[f]; ++i)
+          RK_REQUIRE(std::isfinite(xyz[f][i]), RKHSBA_EINVAL, "non-finite point coordinate");
+      if (kind != RKHSBA_FEAT_CLASS_ID)
+        for (int f = 0; f < K; ++f) {
+          const float* v = static_cast<const float*>(feats[f]);
+          for (int64_t i = 0; i < (int64_t)Din * n_points[f]; ++i)
+            RK_REQUIRE(std::isfinite(v[i]), RKHSBA_EINVAL, "non-finite feature value");
+        }
+      RK_HIP(raw_xyz_.reserve((size_t)N * 3));
+      RK_HIP(raw_feat_.reserve((size_t)N * fbytes));
+      for (int f = 0; f < K; ++f) {
+        RK_HIP(hipMemcpyAsync(raw_xyz_.p + 3 * off[f], xyz[f], sizeof(float) * 3 * n_points[f],
+                              hipMemcpyHostToDevice, st));
+        RK_HIP(hipMemcpyAsync(raw_feat_.p + fbytes * off[f], feats[f], fbytes * n_points[f], hipMemcpyHostToDevice,
+                              st));
+        xp[f] = raw_xyz_.p + 3 * off[f];
+        fp[f] = raw_feat_.p + fbytes * off[f];
+      }
+    }
+    hipEvent_t tb = prof_begin();
+    RK_HIP(d_xyz_ptrs_.reserve(K));
+    RK_HIP(d_feat_ptrs_.reserve(K));
+    RK_HIP(d_in_off_.reserve(K + 1));
+    RK_HIP(hipMemcpyAsync(d_xyz_ptrs_.p, xp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_feat_ptrs_.p, fp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
+
+    // cell coordinates and per-frame bounds
+    std::vector<int32_t> mm(6 * K + 2);
+    for (int f = 0; f < K; ++f)
+      for (int a = 0; a < 3; ++a) {
+        mm[6 * f + a] = INT_MAX;
+        mm[6 * f + 3 + a] = INT_MIN;
+      }
+    mm[6 * K] = 0;
+    mm[6 * K + 1] = 0;
+    RK_HIP(cell_.reserve((size_t)N * 3));
+    RK_HIP(minmax_.reserve(mm.size()));
+    RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, st));
+    RK_HIP(launch_cell_coords(d_xyz_ptrs_.p, d_in_off_.p, K, N, kc0.inv_cell, cell_.p, minmax_.p, st));
+    RK_HIP(hipMemcpyAsync(mm.data(), minmax_.p, sizeof(int32_t) * mm.size(), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipStreamSynchronize(st));
+    RK_REQUIRE(mm[6 * K] == 0, RKHSBA_EINVAL, "non-finite or out-of-range point coordinate");
+
+    // grids (frame-local offsets for the build)
+    std::vector<FrameInfo> fr(K);
+    int64_t rows_total = 0;
+    uint64_t max_cells = 1;
+    int bin_axis_bits = 1;
+    for (int f = 0; f < K; ++f) {
+      FrameInfo& F = fr[f];
+      F.pt_off = off[f];
+      F.n = (int32_t)n_points[f];
+      uint64_t cells = 1;
+      for (int a = 0; a < 3; ++a) {
+        F.org[a] = mm[6 * f + a];
+        const int64_t d = (int64_t)mm[6 * f + 3 + a] - mm[6 * f + a] + 1;
+        RK_REQUIRE(d >= 1 && d < (1 << 24), RKHSBA_ENOMEM, "frame extent too large for its cell grid");
+        F.dim[a] = (int32_t)d;
+        cells *= (uint64_t)d;
+      }
+      RK_REQUIRE(cells < 0xffffffffull, RKHSBA_ENOMEM,
+                 "frame spans more than 2^32 cells; raise ell or lower cell_subdiv");
+      max_cells = std::max(max_cells, cells);
+      F.row_off = rows_total;
+      rows_total += (int64_t)F.dim[1] * F.dim[2];
+      F.xt_off = 0;
+      int ext_max = 0;
+      for (int a = 0; a < 3; ++a) ext_max = std::max(ext_max, F.dim[a] + 2 * kc0.reach_cells);
+      int shift = 0;
+      while (((ext_max - 1) >> shift) >= 1023) ++shift;
+      F.mort_shift = shift;
+      const int maxc = (ext_max - 1) >> shift;
+      int bits = 1;
+      while ((1 << bits) < maxc + 2) ++bits;
+      bin_axis_bits = std::max(bin_axis_bits, bits);
+    }
+    RK_REQUIRE(rows_total < (1LL << 31), RKHSBA_ENOMEM, "cell-row table too large");
+    p->bin_bits = 3 * bin_axis_bits;
+    RK_HIP(d_bframes_.reserve(K));
+    RK_HIP(hipMemcpyAsync(d_bframes_.p, fr.data(), sizeof(FrameInfo) * K, hipMemcpyHostToDevice, st));
+
+    // resident ranges
+    p->pbase = points_.alloc(N, st);
+    p->n_rows = std::max<int64_t>(rows_total, 1);
+    p->rbase = rows_.alloc(p->n_rows, st);
+    float4* d_pts = static_cast<float4*>(points_.ptr(0)) + p->pbase;
+    int32_t* d_perm = static_cast<int32_t*>(points_.ptr(1)) + p->pbase;
+    uint32_t* d_keys = static_cast<uint32_t*>(points_.ptr(2)) + p->pbase;
+    float* d_feat = static_cast<float*>(points_.ptr(3)) + p->pbase * std::max(Dp, 1);
+    int4* d_rows = static_cast<int4*>(rows_.ptr(0)) + p->rbase;
+
+    // keys, segmented sort by frame, gather
+    RK_HIP(k1_.reserve(N));
+    RK_HIP(v1_.reserve(N));
+    RK_HIP(k2_.reserve(N));
+    RK_HIP(v2_.reserve(N));
+    RK_HIP(launch_cell_keys(cell_.p, d_in_off_.p, d_bframes_.p, K, N, k1_.p, v1_.p, st));
+    std::vector<SortTile> tiles;
+    std::vector<SortSeg> segs(K);
+    for (int f = 0; f < K; ++f) {
+      segs[f].start = off[f];
+      segs[f].count = n_points[f];
+      segs[f].tile0 = (int32_t)tiles.size();
+      for (int64_t s = 0; s < n_points[f]; s += kSortTile)
+        tiles.push_back(SortTile{off[f] + s, (int32_t)std::min<int64_t>(kSortTile, n_points[f] - s), f});
+      segs[f].n_tiles = (int32_t)tiles.size() - segs[f].tile0;
+    }
+    RK_HIP(d_tiles_.reserve(tiles.size()));
+    RK_HIP(d_segs_.reserve(K));
+    RK_HIP(hist_scratch_.reserve(tiles.size() * 256));
+    RK_HIP(hipMemcpyAsync(d_tiles_.p, tiles.data(), sizeof(SortTile) * tiles.size(), hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_segs_.p, segs.data(), sizeof(SortSeg) * K, hipMemcpyHostToDevice, st));
+    int key_bits = 1;
+    while (key_bits < 32 && (1ull << key_bits) < max_cells) ++key_bits;
+    bool in_tmp = false;
+    RK_HIP(launch_radix_sort(k1_.p, v1_.p, k2_.p, v2_.p, hist_scratch_.p, d_tiles_.p, (int)tiles.size(), d_segs_.p, K,
+                             key_bits, st, &in_tmp));
+    uint32_t* sk = in_tmp ? k2_.p : k1_.p;
+    uint32_t* sv = in_tmp ? v2_.p : v1_.p;
+    RK_HIP(launch_gather(d_xyz_ptrs_.p, d_feat_ptrs_.p, kind == RKHSBA_FEAT_CLASS_ID ? 0 : 1, D, std::max(Dp, 1),
+                         d_bframes_.p, d_in_off_.p, K, N, sv, d_pts, d_feat, d_perm, minmax_.p + 6 * K + 1, st));
+    RK_HIP(hipMemcpyAsync(d_keys, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, st));
+
+    // cell-row tables
+    RK_HIP(row_sizes_.reserve(rows_total));
+    RK_HIP(scan_tmp_.reserve(rows_total / kScanTileElems + 2));
+    RK_HIP(d_total_.reserve(1));
+    RK_HIP(launch_rows(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows, rows_total, row_sizes_.p, scan_tmp_.p,
+                       d_total_.p, st));
+    uint64_t xt_total = 0;
+    int32_t neg = 0;
+    RK_HIP(hipMemcpyAsync(&xt_total, d_total_.p, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipMemcpyAsync(&neg, minmax_.p + 6 * K + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipStreamSynchronize(st));
+    p->negative_features = neg != 0;
+    compute_constants(p);
+    RK_REQUIRE(xt_total < (1ull << 31), RKHSBA_ENOMEM, "cell table too large");
+    p->n_xt = std::max<int64_t>((int64_t)xt_total, 1);
+    p->xbase = xtab_.alloc(p->n_xt, st);
+    RK_HIP(launch_xtab(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows,
+                       static_cast<uint32_t*>(xtab_.ptr(0)) + p->xbase, st));
+
+    // frame table entries with pool offsets
+    p->slot0 = slots_.alloc(K, st);
+    p->sbase = state_.alloc(1, st);
+    for (int f = 0; f < K; ++f) {
+      fr[f].pt_off += p->pbase;
+      fr[f].row_off += p->rbase;
+      fr[f].xt_off = p->xbase;
+    }
+    RK_HIP(hipMemcpyAsync(static_cast<FrameInfo*>(slots_.ptr(0)) + p->slot0, fr.data(), sizeof(FrameInfo) * K,
+                          hipMemcpyHostToDevice, st));
+    prof_end(RKHSBA_PROF_BUILD, tb);
+    RK_HIP(hipStreamSynchronize(st));
+    prof_collect();
+    p->frames = std::move(fr);
+    p->resident_bytes = N * (int64_t)(28 + 4 * std::max(Dp, 1)) + p->n_rows * 16 + p->n_xt * 4 +
+                        (int64_t)K * (int64_t)(sizeof(FrameInfo) + 96) + 8;
+  } catch (...) {
+    release();
+    throw;
+  }
+  p->id = next_id_++;
+  probs_[p->id] = std::move(P);
+  return p->id;
+}
+
+void Engine::remove_problem(int id) {
+  auto it = probs_.find(id);
+  if (it == probs_.end()) return;
+  Problem* p = it->second.get();
+  points_.free(p->pbase, p->N);
+  rows_.free(p->rbase, p->n_rows);
+  xtab_.free(p->xbase, p->n_xt);
+  slots_.free(p->slot0, p->K);
+  state_.free(p->sbase, 1);
+  if (p->hbase >= 0) hist_.free(p->hbase, p->n_hist);
+  probs_.erase(it);
+}
+
+void Engine::upload_poses(Problem* p, const double* poses) {
+  RK_REQUIRE(poses != nullptr, RKHSBA_EINVAL, "poses is NULL");
+  for (int i = 0; i < 12 * p->K; ++i) RK_REQUIRE(std::isfinite(poses[i]), RKHSBA_EINVAL, "non-finite pose entry");
+  RK_HIP(hipMemcpyAsync(poses_ptr(p), poses, sizeof(double) * 12 * p->K, hipMemcpyHostToDevice, st));
+}
+
+void Engine::download_poses(Problem* p, double* poses) {
+  RK_HIP(hipMemcpyAsync(poses, poses_ptr(p), sizeof(double) * 12 * p->K, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipStreamSynchronize(st));
+}
+
+void Engine::ensure_history(Problem* p, int n_iter) {
+  const int64_t need = (int64_t)n_iter + 1;
+  if (p->hbase >= 0 && p->n_hist >= need) return;
+  if (p->hbase >= 0) hist_.free(p->hbase, p->n_hist);
+  p->hbase = -1;
+  p->hbase = hist_.alloc(need, st);
+  p->n_hist = need;
+}
+
+void Engine::reset_state(Problem* p) {
+  static const int32_t zero[2] = {0, 0};
+  RK_HIP(hipMemcpyAsync(static_cast<int32_t*>(state_.ptr(0)) + 2 * p->sbase, zero, sizeof(zero),
+                        hipMemcpyHostToDevice, st));
+}
+
+void Engine::read_history(Problem* p, int count, double* loss, double* pairs) {
+  RK_REQUIRE(p->hbase >= 0 && count <= p->n_hist, RKHSBA_ESTATE, "no history of that length");
+  if (loss)
+    RK_HIP(hipMemcpyAsync(loss, static_cast<double*>(hist_.ptr(0)) + p->hbase, sizeof(double) * count,
+                          hipMemcpyDeviceToHost, st));
+  if (pairs)
+    RK_HIP(hipMemcpyAsync(pairs, static_cast<double*>(hist_.ptr(1)) + p->hbase, sizeof(double) * count,
+                          hipMemcpyDeviceToHost, st));
+  RK_HIP(hipStreamSynchronize(st));
+}
+
+int32_t Engine::read_status(Problem* p) {
+  int32_t s[2] = {0, 0};
+  RK_HIP(hipMemcpyAsync(s, static_cast<int32_t*>(state_.ptr(0)) + 2 * p->sbase, sizeof(s), hipMemcpyDeviceToHost,
+                        st));
+  RK_HIP(hipStreamSynchronize(st));
+  return s[1];
+}
+
+// ---------------------------------------------------------------- set layout
+
+void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
+  RK_REQUIRE(!items.empty(), RKHSBA_EINVAL, "empty set");
+  for (const SetItem& it : items) {
+    RK_REQUIRE(it.p != nullptr, RKHSBA_ESTATE, "no frames: call rkhsba_build_neighbors first");
+    RK_REQUIRE(it.E >= 1, RKHSBA_EINVAL, "need at least one edge");
+    RK_REQUIRE(it.edges != nullptr, RKHSBA_EINVAL, "edges is NULL");
+    RK_REQUIRE(it.fixed >= -1 && it.fixed < it.p->K, RKHSBA_EINVAL, "fixed_frame out of range");
+    RK_REQUIRE(it.n_iter >= 0, RKHSBA_EINVAL, "n_iter must be >= 0");
+    for (int e = 0; e < it.E; ++e) {
+      const int m = it.edges[2 * e], n = it.edges[2 * e + 1];
+      RK_REQUIRE(m >= 0 && n >= 0 && m < it.p->K && n < it.p->K, RKHSBA_EINVAL, "edge frame index out of range");
+      RK_REQUIRE(m != n, RKHSBA_EINVAL, "self-edge (m == n)");
+    }
+    ensure_history(it.p, it.n_iter);
+  }
+  std::vector<int32_t> key;
+  std::vector<int> ids;
+  for (const SetItem& it : items) {
+    ids.push_back(it.p->id);
+    key.push_back(it.p->id);
+    key.push_back(it.E);
+    key.push_back(it.fixed);
+    key.push_back(it.n_iter);
+    key.push_back((int32_t)it.p->hbase);
+    key.insert(key.end(), it.edges, it.edges + 2 * it.E);
+  }
+  if (key == lay.edge_key && !lay.sys.empty()) return;
+  lay.drop_graph();
+
+  const int P = pass_points;
+  int E_total = 0;
+  for (const SetItem& it : items) E_total += it.E;
+  std::vector<EdgeInfo> info(E_total);
+  std::vector<int64_t> ent(E_total);
+  std::vector<int32_t> poff(E_total), foff(E_total);
+  std::vector<SortTile> tiles;
+  std::vector<SortSeg> segs(E_total);
+  std::vector<KConst> kcs(items.size());
+  std::vector<ProbSys> sys(items.size());
+  std::vector<int32_t> bstart_all, blist, vstart_all, vlist;
+  int64_t entries = 0, passes = 0, fins = 0, h_total = 0, v_total = 0;
+  int bin_bits = 3, n_max = 0;
+  bool clamp = false;
+  int e_glob = 0;
+  for (size_t pi = 0; pi < items.size(); ++pi) {
+    const SetItem& it = items[pi];
+    Problem* p = it.p;
+    kcs[pi] = p->kc;
+    kcs[pi].Dp = Dp;
+    clamp = clamp || p->kc.clamp;
+    bin_bits = std::max(bin_bits, p->bin_bits);
+    ProbSys& S = sys[pi];
+    S.K = p->K;
+    S.fixed = it.fixed;
+    S.n = 6 * (it.fixed >= 0 ? p->K - 1 : p->K);
+    S.e0 = e_glob;
+    S.E = it.E;
+    S.n_iter = it.n_iter;
+    S.slot0 = p->slot0;
+    S.h_off = h_total;
+    S.v_off = v_total;
+    S.hist_off = p->hbase;
+    S.state_off = 2 * p->sbase;
+    S.sigma2 = p->par.sigma * p->par.sigma;
+    S.damping_rel = p->par.damping_rel;
+    h_total += (int64_t)S.n * S.n;
+    v_total += S.n;
+    n_max = std::max(n_max, S.n);
+    const int K = p->K;
+    std::vector<std::vector<int32_t>> blk((size_t)K * K), vec(K);
+    for (int e = 0; e < it.E; ++e, ++e_glob) {
+      const int m = it.edges[2 * e], n = it.edges[2 * e + 1];
+      EdgeInfo& I = info[e_glob];
+      I.m = (int32_t)(p->slot0 + m);
+      I.n = (int32_t)(p->slot0 + n);
+      I.ent_off = entries;
+      I.n_src = p->frames[m].n;
+      I.pass_off = (int32_t)passes;
+      I.n_pass = (I.n_src + P - 1) / P;
+      I.fin_off = (int32_t)fins;
+      I.n_fin = (I.n_src + kFinThreads - 1) / kFinThreads;
+      I.prob = (int32_t)pi;
+      ent[e_glob] = entries;
+      poff[e_glob] = I.pass_off;
+      foff[e_glob] = I.fin_off;
+      segs[e_glob].start = entries;
+      segs[e_glob].count = I.n_src;
+      segs[e_glob].tile0 = (int32_t)tiles.size();
+      for (int64_t s = 0; s < I.n_src; s += kSortTile)
+        tiles.push_back(SortTile{entries + s, (int32_t)std::min<int64_t>(kSortTile, I.n_src - s), e_glob});
+      segs[e_glob].n_tiles = (int32_t)tiles.size() - segs[e_glob].tile0;
+      entries += I.n_src;
+      passes += I.n_pass;
+      fins += I.n_fin;
+      blk[(size_t)m * K + m].push_back(e_glob * 4 + 0);
+      blk[(size_t)n * K + n].push_back(e_glob * 4 + 1);
+      blk[(size_t)m * K + n].push_back(e_glob * 4 + 2);
+      blk[(size_t)n * K + m].push_back(e_glob * 4 + 3);
+      vec[m].push_back(e_glob * 2 + 0);
+      vec[n].push_back(e_glob * 2 + 1);
+    }
+    S.blk0 = (int32_t)bstart_all.size();
+    for (size_t k = 0; k < blk.size(); ++k) {
+      bstart_all.push_back((int32_t)blist.size());
+      blist.insert(blist.end(), blk[k].begin(), blk[k].end());
+    }
+    bstart_all.push_back((int32_t)blist.size());
+    S.vec0 = (int32_t)vstart_all.size();
+    for (int k = 0; k < K; ++k) {
+      vstart_all.push_back((int32_t)vlist.size());
+      vlist.insert(vlist.end(), vec[k].begin(), vec[k].end());
+    }
+    vstart_all.push_back((int32_t)vlist.size());
+  }
+  RK_REQUIRE(passes < INT_MAX && fins < INT_MAX && entries < (int64_t)INT_MAX * 4 && blist.size() < INT_MAX,
+             RKHSBA_EINVAL, "edge list too large");
+  if (blist.empty()) blist.push_back(0);
+  if (vlist.empty()) vlist.push_back(0);
+  RK_HIP(lay.d_edges.reserve(E_total));
+  RK_HIP(lay.d_ent_off.reserve(E_total));
+  RK_HIP(lay.d_pass_off.reserve(E_total));
+  RK_HIP(lay.d_fin_off.reserve(E_total));
+  RK_HIP(lay.d_etiles.reserve(tiles.size()));
+  RK_HIP(lay.d_esegs.reserve(E_total));
+  RK_HIP(lay.d_kcs.reserve(items.size()));
+  RK_HIP(lay.d_sys.reserve(items.size()));
+  RK_HIP(lay.d_blk_start.reserve(bstart_all.size()));
+  RK_HIP(lay.d_blk_list.reserve(blist.size()));
+  RK_HIP(lay.d_vec_start.reserve(vstart_all.size()));
+  RK_HIP(lay.d_vec_list.reserve(vlist.size()));
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes) RK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  };
+  up(lay.d_edges.p, info.data(), sizeof(EdgeInfo) * E_total);
+  up(lay.d_ent_off.p, ent.data(), sizeof(int64_t) * E_total);
+  up(lay.d_pass_off.p, poff.data(), sizeof(int32_t) * E_total);
+  up(lay.d_fin_off.p, foff.data(), sizeof(int32_t) * E_total);
+  up(lay.d_etiles.p, tiles.data(), sizeof(SortTile) * tiles.size());
+  up(lay.d_esegs.p, segs.data(), sizeof(SortSeg) * E_total);
+  up(lay.d_kcs.p, kcs.data(), sizeof(KConst) * kcs.size());
+  up(lay.d_sys.p, sys.data(), sizeof(ProbSys) * sys.size());
+  up(lay.d_blk_start.p, bstart_all.data(), sizeof(int32_t) * bstart_all.size());
+  up(lay.d_blk_list.p, blist.data(), sizeof(int32_t) * blist.size());
+  up(lay.d_vec_start.p, vstart_all.data(), sizeof(int32_t) * vstart_all.size());
+  up(lay.d_vec_list.p, vlist.data(), sizeof(int32_t) * vlist.size());
+
+  // per-evaluation scratch
+  const void* before[] = {xf_.p, bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, mom_.p, cnt_.p, partial_.p, edge_out_.p,
+                          H_.p, b_.p, delta_.p};
+  RK_HIP(xf_.reserve(E_total));
+  RK_HIP(bk_.reserve(entries));
+  RK_HIP(bv_.reserve(entries));
+  RK_HIP(bk2_.reserve(entries));
+  RK_HIP(bv2_.reserve(entries));
+  RK_HIP(bhist_.reserve(tiles.size() * 256));
+  RK_HIP(mom_.reserve((size_t)entries * 10));
+  RK_HIP(cnt_.reserve(entries));
+  RK_HIP(partial_.reserve((size_t)fins * kEdgeVals));
+  RK_HIP(edge_out_.reserve((size_t)E_total * kEdgeVals));
+  RK_HIP(H_.reserve(h_total));
+  RK_HIP(b_.reserve(v_total));
+  RK_HIP(delta_.reserve(v_total));
+  const void* after[] = {xf_.p, bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, mom_.p, cnt_.p, partial_.p, edge_out_.p,
+                         H_.p, b_.p, delta_.p};
+  for (size_t i = 0; i < sizeof(before) / sizeof(before[0]); ++i)
+    if (before[i] != after[i]) ++scratch_gen_;
+  RK_HIP(hipStreamSynchronize(st));  // host tables above go out of scope
+
+  lay.ids = std::move(ids);
+  lay.edge_key = std::move(key);
+  lay.sys = std::move(sys);
+  lay.n_prob = (int)items.size();
+  lay.n_max = n_max;
+  lay.E = E_total;
+  lay.n_entries = entries;
+  lay.n_pass_total = (int)passes;
+  lay.n_fin_total = (int)fins;
+  lay.n_edge_tiles = (int)tiles.size();
+  lay.bin_bits = bin_bits;
+  lay.clamp = clamp;
+  lay.h_total = h_total;
+  lay.v_total = v_total;
+}
+
+// ---------------------------------------------------------------- launches
+
+void Engine::evaluate(SetLayout& lay, int mode) {
+  hipEvent_t t0 = prof_begin();
+  RK_HIP(launch_edge_setup(poses(), lay.d_edges.p, lay.E, xf_.p, st));
+  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_ent_off.p, xf_.p, lay.E, lay.n_entries, lay.d_kcs.p, bk_.p,
+                    bv_.p, st));
+  bool in_tmp = false;
+  RK_HIP(launch_radix_sort(bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,
+                           lay.E, lay.bin_bits, st, &in_tmp));
+  sorted_k_ = in_tmp ? bk2_.p : bk_.p;
+  sorted_v_ = in_tmp ? bv2_.p : bv_.p;
+  prof_end(RKHSBA_PROF_BIN, t0);
+  PairArgs pa{};
+  pa.pts = pts();
+  pa.feat = feat();
+  pa.rows = rows();
+  pa.xtab = xtab();
+  pa.frames = frames();
+  pa.edges = lay.d_edges.p;
+  pa.xf = xf_.p;
+  pa.keys = sorted_k_;
+  pa.vals = sorted_v_;
+  pa.mom = mom_.p;
+  pa.cnt = cnt_.p;
+  pa.kcs = lay.d_kcs.p;
+  pa.n_entries = lay.n_entries;
+  pa.E = lay.E;
+  pa.n_pass_total = lay.n_pass_total;
+  pa.kc.Dp = Dp;
+  pa.kc.clamp = lay.clamp ? 1 : 0;
+  const int feat_path = feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
+  hipEvent_t t1 = prof_begin();
+  if (pass_points == 16)
+    RK_HIP(launch_sweep16(pa, lay.d_pass_off.p, mode, feat_path, moment_path == 2, st));
+  else
+    RK_HIP(launch_pairs(pa, lay.d_pass_off.p, mode, feat_path, pass_points, st));
+  prof_end(mode == MODE_NORMAL ? RKHSBA_PROF_PAIRS : RKHSBA_PROF_PAIRS_LOSS, t1);
+  FinArgs fa{};
+  fa.pts = pts();
+  fa.edges = lay.d_edges.p;
+  fa.xf = xf_.p;
+  fa.frames = frames();
+  fa.keys = sorted_k_;
+  fa.vals = sorted_v_;
+  fa.mom = mom_.p;
+  fa.cnt = cnt_.p;
+  fa.partial = partial_.p;
+  fa.n_entries = lay.n_entries;
+  fa.E = lay.E;
+  fa.n_fin_total = lay.n_fin_total;
+  hipEvent_t t2 = prof_begin();
+  RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, st));
+  RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, lay.E, kEdgeVals, edge_out_.p, st));
+  prof_end(RKHSBA_PROF_FINALIZE, t2);
+}
+
+SolveArgs Engine::solve_args(SetLayout& lay) {
+  SolveArgs s{};
+  s.edge_out = edge_out_.p;
+  s.sys = lay.d_sys.p;
+  s.n_prob = lay.n_prob;
+  s.n_max = lay.n_max;
+  s.H = H_.p;
+  s.b = b_.p;
+  s.delta = delta_.p;
+  s.poses = poses();
+  s.loss_hist = static_cast<double*>(hist_.ptr(0));
+  s.pairs_hist = static_cast<double*>(hist_.ptr(1));
+  s.state = static_cast<int32_t*>(state_.ptr(0));
+  s.blk_start = lay.d_blk_start.p;
+  s.blk_list = lay.d_blk_list.p;
+  s.vec_start = lay.d_vec_start.p;
+  s.vec_list = lay.d_vec_list.p;
+  return s;
+}
+
+void Engine::assemble(SetLayout& lay) { RK_HIP(launch_assemble(solve_args(lay), st)); }
+
+void Engine::loss_only(SetLayout& lay) { RK_HIP(launch_loss_only(solve_args(lay), st)); }
+
+void Engine::solve(SetLayout& lay) {
+  hipEvent_t t = prof_begin();
+  RK_HIP(launch_solve_update(solve_args(lay), st));
+  prof_end(RKHSBA_PROF_SOLVE, t);
+}
+
+void Engine::record_iteration(SetLayout& lay) {
+  evaluate(lay, MODE_NORMAL);
+  hipEvent_t t = prof_begin();
+  RK_HIP(launch_assemble(solve_args(lay), st));
+  RK_HIP(launch_solve_update(solve_args(lay), st));
+  prof_end(RKHSBA_PROF_SOLVE, t);
+}
+
+void Engine::iterate(SetLayout& lay, int n) {
+  if (n <= 0) return;
+  if (!use_graphs || prof) {
+    for (int i = 0; i < n; ++i) record_iteration(lay);
+    return;
+  }
+  const uint64_t g = generation();
+  if (!lay.graph || lay.graph_gen != g) {
+    lay.drop_graph();
+    RK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+      record_iteration(lay);
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    RK_HIP(hipStreamEndCapture(st, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    RK_HIP(e);
+    lay.graph = exec;
+    lay.graph_gen = g;
+    lay.graph_mode = MODE_NORMAL;
+  }
+  for (int i = 0; i < n; ++i) RK_HIP(hipGraphLaunch(lay.graph, st));
+}
+
+}  // namespace rkhsba

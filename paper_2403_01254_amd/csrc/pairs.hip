@@ -62,7 +62,7 @@ __device__ inline void for_each_range(const FrameInfo& T, const int4* __restrict
       const int xa = max(clamp_floor(((double)lo.x - h) * inv - T.org[0], -1, T.dim[0]), R.x);
       const int xb = min(clamp_floor(((double)hi.x + h) * inv - T.org[0], -1, T.dim[0]), R.y);
       if (xa > xb) continue;
-      const uint32_t* xt = xtab + (uint32_t)R.z;
+      const uint32_t* xt = xtab + T.xt_off + (uint32_t)R.z;
       fn(xt[xa - R.x], xt[xb + 1 - R.x]);
     }
   }
@@ -82,12 +82,13 @@ __global__ void k_edge_setup(const double* __restrict__ poses, const EdgeInfo* _
 __global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts, const FrameInfo* __restrict__ frames,
                                                   const EdgeInfo* __restrict__ edges,
                                                   const int64_t* __restrict__ ent_off, const EdgeXf* __restrict__ xf,
-                                                  int E, int64_t n_entries, KConst kc, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals) {
+                                                  int E, int64_t n_entries, const KConst* __restrict__ kcs,
+                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n_entries) return;
   const int e = upper_segment(ent_off, E, i);
   const EdgeInfo& ed = edges[e];
+  const KConst kc = kcs[ed.prob];
   const uint32_t src = (uint32_t)(i - ed.ent_off);
   const FrameInfo& Fm = frames[ed.m];
   const FrameInfo& Fn = frames[ed.n];
@@ -154,7 +155,8 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
     return;
   }
 
-  const float rc2 = a.kc.rc2, alpha = a.kc.alpha;
+  const KConst kc = a.kcs[ed.prob];
+  const float rc2 = kc.rc2, alpha = kc.alpha;
   const bool clamp = a.kc.clamp != 0;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
   const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
 
-  for_each_range(Fn, a.rows, a.xtab, a.kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
+  for_each_range(Fn, a.rows, a.xtab, kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0 + g; j < j1; j += G) {
       const float4 z = tp[j];
       float dx, dy, dz;
@@ -449,11 +451,12 @@ hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int
 }
 
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
-                      const EdgeXf* d_xf, int E, int64_t n_entries, KConst kc, uint32_t* d_keys, uint32_t* d_vals,
-                      hipStream_t st) {
+                      const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,
+                      uint32_t* d_vals, hipStream_t st) {
   if (n_entries > 0)
     k_bin<<<(unsigned)((n_entries + kThreads - 1) / kThreads), kThreads, 0, st>>>(d_pts, d_frames, d_edges, d_ent_off,
-                                                                                d_xf, E, n_entries, kc, d_keys, d_vals);
+                                                                                d_xf, E, n_entries, d_kcs, d_keys,
+                                                                                d_vals);
   return hipGetLastError();
 }
 

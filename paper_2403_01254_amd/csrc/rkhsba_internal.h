@@ -42,7 +42,7 @@ struct EdgeInfo {
   int32_t n_pass;
   int32_t fin_off;   // first finalize block of the edge
   int32_t n_fin;
-  int32_t pad;
+  int32_t prob;      // problem of the edge within the evaluated set (constants, system)
 };
 
 // Relative transform of an edge, T_nm = T_n^-1 T_m (FP64), written on device.
@@ -110,8 +110,8 @@ hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
-                      const EdgeXf* d_xf, int E, int64_t n_entries, KConst kc, uint32_t* d_keys, uint32_t* d_vals,
-                      hipStream_t st);
+                      const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,
+                      uint32_t* d_vals, hipStream_t st);
 
 struct PairArgs {
   const float4* pts;
@@ -125,10 +125,11 @@ struct PairArgs {
   const uint32_t* vals;   // sorted binning values (source point, frame-local sorted index)
   float* mom;             // moments, component-major: mom[c * n_entries + entry]
   uint32_t* cnt;          // in-radius pair count per entry
+  const KConst* kcs;      // per problem of the set, indexed by EdgeInfo::prob
   int64_t n_entries;
   int32_t E;
   int32_t n_pass_total;
-  KConst kc;
+  KConst kc;              // set-wide: Dp and clamp (clamping is exact for non-negative features)
 };
 hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
                         hipStream_t st);
@@ -156,33 +157,52 @@ hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode,
 hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, int E, int n_vals, double* d_edge_out,
                               hipStream_t st);
 
-struct SolveArgs {
-  const double* edge_out;  // [E][kEdgeVals]
-  const EdgeInfo* edges;
-  int32_t E;
-  int32_t K;
-  int32_t fixed;           // frame removed from the system (-1: none)
+// One problem's Gauss-Newton system within an evaluated set.
+struct ProbSys {
+  int32_t K;          // frames
+  int32_t fixed;      // frame removed from the system (-1: none)
+  int32_t n;          // system size: 6K, or 6(K-1) with a fixed frame
+  int32_t e0, E;      // edges of the problem in the set's edge table
+  int32_t blk0;       // first entry of the problem's K*K+1 block-contributor starts
+  int32_t vec0;       // first entry of the problem's K+1 vector-contributor starts
+  int32_t n_iter;     // Gauss-Newton iterations; solves stop once iter reaches it
+  int64_t slot0;      // first frame slot (frame table, poses)
+  int64_t h_off;      // offset of the problem's n x n matrix in the set's H buffer
+  int64_t v_off;      // offset of its n-vectors in b and delta
+  int64_t hist_off;   // offset of its loss and pair-count histories (n_iter + 1 each)
+  int64_t state_off;  // offset of its (iter, status) pair
   double sigma2;
   double damping_rel;
-  double* H;               // n x n scratch, n = 6K or 6(K-1)
-  double* b;               // n
-  double* delta;           // n
-  double* poses;           // K*12, updated in place by the solve
-  double* loss_hist;       // [iter] F
-  double* pairs_hist;      // [iter] pair count
-  int32_t* status;         // 0 ok, -4 not positive definite (sticky)
-  int32_t iter;
-  // contributors of each 6x6 block (frame a, frame c) of H, CSR over a*K+c:
-  // entries e*4 + role, role 0 H_mm, 1 H_nn, 2 H_mn, 3 H_mn^T
-  const int32_t* blk_start;  // K*K + 1
+};
+
+struct SolveArgs {
+  const double* edge_out;  // [E][kEdgeVals]
+  const ProbSys* sys;      // [n_prob]
+  int32_t n_prob;
+  int32_t n_max;           // largest system size of the set
+  double* H;
+  double* b;
+  double* delta;
+  double* poses;           // [slot][12], updated in place by the solve
+  double* loss_hist;       // F per evaluation, at hist_off + iter
+  double* pairs_hist;      // in-radius pair count per evaluation
+  int32_t* state;          // per problem: iter (evaluations whose solve ran), status (0 ok, -4 not PD; sticky)
+  // contributors of each 6x6 block (frame a, frame c) of a problem's H, CSR over blk0 + a*K + c:
+  // entries e*4 + role (set-wide edge index), role 0 H_mm, 1 H_nn, 2 H_mn, 3 H_mn^T
+  const int32_t* blk_start;
   const int32_t* blk_list;
-  // contributors of each frame's 6-vector of b: entries e*2 + role, role 0 b_m, 1 b_n
-  const int32_t* vec_start;  // K + 1
+  // contributors of each frame's 6-vector of b, CSR over vec0 + a: entries e*2 + role, role 0 b_m, 1 b_n
+  const int32_t* vec_start;
   const int32_t* vec_list;
 };
+// Writes H, b of every problem (and the loss / pair-count history entry of the
+// current iteration).
 hipError_t launch_assemble(const SolveArgs& a, hipStream_t st);
-hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);
+// Loss / pair-count history entry only (loss evaluations).
 hipError_t launch_loss_only(const SolveArgs& a, hipStream_t st);
+// Damped Cholesky solve and pose update of every problem whose iteration count
+// is below its n_iter; advances the iteration count of every problem.
+hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);
 
 hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
                                const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const EdgeXf* d_xf, int m,

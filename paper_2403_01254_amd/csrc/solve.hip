@@ -24,17 +24,20 @@ __device__ inline int sym_index(int r, int c) {
 // reduced index <-> frame when frame `fixed` is removed (fixed < 0: none)
 __device__ inline int frame_of_reduced(int k, int fixed) { return (fixed >= 0 && k >= fixed) ? k + 1 : k; }
 
+// One thread per entry of a problem's system (grid.y = problem).
 __global__ __launch_bounds__(256) void k_assemble(SolveArgs a) {
-  const int Kr = a.fixed >= 0 ? a.K - 1 : a.K;
-  const int n = 6 * Kr;
+  const ProbSys S = a.sys[blockIdx.y];
+  const int n = S.n;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int32_t* blk_start = a.blk_start + S.blk0;
+  const int32_t* vec_start = a.vec_start + S.vec0;
   if (idx < (int64_t)n * n) {
     const int row = (int)(idx / n), col = (int)(idx % n);
-    const int fa = frame_of_reduced(row / 6, a.fixed), fc = frame_of_reduced(col / 6, a.fixed);
+    const int fa = frame_of_reduced(row / 6, S.fixed), fc = frame_of_reduced(col / 6, S.fixed);
     const int r = row % 6, s = col % 6;
-    const int blk = fa * a.K + fc;
+    const int blk = fa * S.K + fc;
     double v = 0.0;
-    for (int k = a.blk_start[blk]; k < a.blk_start[blk + 1]; ++k) {
+    for (int k = blk_start[blk]; k < blk_start[blk + 1]; ++k) {
       const int code = a.blk_list[k];
       const double* eo = a.edge_out + (int64_t)(code >> 2) * kEdgeVals;
       switch (code & 3) {
@@ -44,29 +47,35 @@ __global__ __launch_bounds__(256) void k_assemble(SolveArgs a) {
         default: v += eo[55 + 6 * s + r]; break;
       }
     }
-    a.H[idx] = v;
+    a.H[S.h_off + idx] = v;
   } else if (idx < (int64_t)n * n + n) {
     const int row = (int)(idx - (int64_t)n * n);
-    const int fa = frame_of_reduced(row / 6, a.fixed), r = row % 6;
+    const int fa = frame_of_reduced(row / 6, S.fixed), r = row % 6;
     double v = 0.0;
-    for (int k = a.vec_start[fa]; k < a.vec_start[fa + 1]; ++k) {
+    for (int k = vec_start[fa]; k < vec_start[fa + 1]; ++k) {
       const int code = a.vec_list[k];
       v += a.edge_out[(int64_t)(code >> 1) * kEdgeVals + ((code & 1) ? 7 : 1) + r];
     }
-    a.b[row] = v;
+    a.b[S.v_off + row] = v;
   }
 }
 
-// F (times sigma^2) and the pair count of an evaluation, in edge order.
-__global__ void k_loss_only(SolveArgs a) {
-  if (threadIdx.x != 0) return;
+// F (times sigma^2) and the pair count of the current evaluation of each
+// problem (one wavefront per problem, fixed summation order).
+__global__ __launch_bounds__(64) void k_loss_only(SolveArgs a) {
+  const ProbSys S = a.sys[blockIdx.x];
   double F = 0.0, np = 0.0;
-  for (int e = 0; e < a.E; ++e) {
+  for (int e = S.e0 + (int)threadIdx.x; e < S.e0 + S.E; e += 64) {
     F += a.edge_out[(int64_t)e * kEdgeVals];
     np += a.edge_out[(int64_t)e * kEdgeVals + 91];
   }
-  if (a.loss_hist) a.loss_hist[a.iter] = a.sigma2 * F;
-  if (a.pairs_hist) a.pairs_hist[a.iter] = np;
+  F = wave_sum(F);
+  np = wave_sum(np);
+  const int iter = a.state[S.state_off];
+  if (threadIdx.x == 0 && iter >= 0 && iter <= S.n_iter) {
+    a.loss_hist[S.hist_off + iter] = S.sigma2 * F;
+    a.pairs_hist[S.hist_off + iter] = np;
+  }
 }
 
 // T <- T exp(xi^): closed-form SE(3) exponential (Rodrigues for the rotation,
@@ -236,38 +245,37 @@ __device__ __noinline__ void trailing_update(double* H, int n, int kb, int nb, c
   }
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
-  __shared__ double Ld[NB][NB + 1];
-  __shared__ double P[kPanelRows * NB];
-  __shared__ double sh[kSolveThreads / 64];
-  __shared__ int fail;
-  if (*a.status != 0) return;
-  const int n = 6 * (a.K - 1);
+// Damped Cholesky solve of one problem's system and its pose update.  Every
+// return is block-uniform.
+__device__ __noinline__ void solve_one(const ProbSys& S, const SolveArgs& a, double* Ld, double* P, double* sh,
+                                       int* fail_flag, int32_t* status) {
+  const int n = S.n;
   const int t = threadIdx.x, T = blockDim.x;
-  double* H = a.H;
-  double* y = a.delta;
+  double* H = a.H + S.h_off;
+  double* y = a.delta + S.v_off;
+  const double* b = a.b + S.v_off;
   double tr = 0.0;
   for (int i = t; i < n; i += T) tr += H[(int64_t)i * n + i];
   tr = block_sum(tr, sh);
   if (!(tr > 0.0)) return;  // no pair touches a free frame: nothing moves
-  const double mu = a.damping_rel * tr / n;
+  const double mu = S.damping_rel * tr / n;
   for (int i = t; i < n; i += T) {
     H[(int64_t)i * n + i] += mu;
-    y[i] = -a.b[i];
+    y[i] = -b[i];
   }
-  if (t == 0) fail = 0;
+  if (t == 0) *fail_flag = 0;
   __syncthreads();
 
   // ---- blocked Cholesky, lower triangle in place
   for (int kb = 0; kb < n; kb += NB) {
     const int nb = min(NB, n - kb);
     if (t < 64) {
-      const bool ok = factor_diag(H, n, kb, nb, Ld);
-      if (t == 0 && !ok) fail = 1;
+      const bool ok = factor_diag(H, n, kb, nb, reinterpret_cast<double(*)[NB + 1]>(Ld));
+      if (t == 0 && !ok) *fail_flag = 1;
     }
     __syncthreads();
-    if (fail) break;
-    panel_solve(H, n, kb, nb, Ld);
+    if (*fail_flag) break;
+    panel_solve(H, n, kb, nb, reinterpret_cast<double(*)[NB + 1]>(Ld));
     __syncthreads();
     if (n - (kb + nb) <= kPanelRows) {  // stage the panel in LDS for the trailing update
       for (int idx = threadIdx.x; idx < (n - kb - nb) * NB; idx += blockDim.x) {
@@ -279,8 +287,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
     trailing_update(H, n, kb, nb, P);
     __syncthreads();
   }
-  if (fail) {
-    if (t == 0) *a.status = -4;
+  if (*fail_flag) {
+    if (t == 0) *status = -4;
     return;
   }
 
@@ -324,27 +332,45 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
     }
     __syncthreads();
   }
-  for (int k = t; k < a.K - 1; k += T) right_update(a.poses + 12 * frame_of_reduced(k, a.fixed), y + 6 * k);
+  for (int k = t; k < n / 6; k += T)
+    right_update(a.poses + 12 * (S.slot0 + frame_of_reduced(k, S.fixed)), y + 6 * k);
+}
+
+// One workgroup per problem.  A problem whose iteration count has reached
+// n_iter (its last evaluation gave the final loss) is left unchanged.
+__global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
+  __shared__ double Ld[NB * (NB + 1)];
+  __shared__ double P[kPanelRows * NB];
+  __shared__ double sh[kSolveThreads / 64];
+  __shared__ int fail;
+  const ProbSys S = a.sys[blockIdx.x];
+  int32_t* st = a.state + S.state_off;
+  const int iter = st[0];
+  const bool run = iter < S.n_iter && st[1] == 0 && S.n > 0;
+  __syncthreads();
+  if (run) solve_one(S, a, Ld, P, sh, &fail, st + 1);
+  __syncthreads();
+  if (threadIdx.x == 0 && iter <= S.n_iter) st[0] = iter + 1;
 }
 
 }  // namespace
 
 hipError_t launch_assemble(const SolveArgs& a, hipStream_t st) {
-  const int Kr = a.fixed >= 0 ? a.K - 1 : a.K;
-  const int64_t n = 6 * (int64_t)Kr;
+  if (a.n_prob <= 0) return hipSuccess;
+  const int64_t n = a.n_max;
   const int64_t work = n * n + n;
-  if (work > 0) k_assemble<<<(unsigned)((work + 255) / 256), 256, 0, st>>>(a);
-  k_loss_only<<<1, 64, 0, st>>>(a);
+  if (work > 0) k_assemble<<<dim3((unsigned)((work + 255) / 256), (unsigned)a.n_prob), 256, 0, st>>>(a);
+  k_loss_only<<<a.n_prob, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st) {
-  if (a.K >= 2) k_solve_update<<<1, kSolveThreads, 0, st>>>(a);
+  if (a.n_prob > 0) k_solve_update<<<a.n_prob, kSolveThreads, 0, st>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_loss_only(const SolveArgs& a, hipStream_t st) {
-  k_loss_only<<<1, 64, 0, st>>>(a);
+  if (a.n_prob > 0) k_loss_only<<<a.n_prob, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 

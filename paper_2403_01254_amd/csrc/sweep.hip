@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
     for (int k = 10; k < 16; ++k) tphi[lane * PHS + k] = 0.f;  // unused Phi columns stay zero
   }
 
-  const KConst kc = a.kc;
+  const KConst kc = a.kcs[ed.prob];
   const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
   const int z0 = max(clamp_floor_d(((double)lo.z - reach) * inv - Fn.org[2], -1, Fn.dim[2]), 0);
   const int z1 = min(clamp_floor_d(((double)hi.z + reach) * inv - Fn.org[2], -1, Fn.dim[2]), Fn.dim[2] - 1);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
           const int xa = max(clamp_floor_d(((double)lo.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
           const int xb = min(clamp_floor_d(((double)hi.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R.y);
           if (xa <= xb) {
-            const uint32_t* xt = a.xtab + (uint32_t)R.z;
+            const uint32_t* xt = a.xtab + Fn.xt_off + (uint32_t)R.z;
             j0 = xt[xa - R.x];
             cntr = xt[xb + 1 - R.x] - j0;
           }

@@ -41,6 +41,7 @@ class Options(ctypes.Structure):
         ("cell_subdiv", ctypes.c_int),
         ("pass_points", ctypes.c_int),
         ("moment_path", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -92,11 +93,12 @@ class Context:
 
     def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
                  fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 8,
-                 pass_points: int = 16, moment_path: int = 0, stream=None):
+                 pass_points: int = 16, moment_path: int = 0, use_graphs: bool = True, stream=None):
         o = default_options()
         o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel
         o.fixed_frame, o.clamp_negative_c, o.device = fixed_frame, int(bool(clamp_negative_c)), device
         o.cell_subdiv, o.pass_points, o.moment_path = cell_subdiv, pass_points, moment_path
+        o.use_graphs = int(bool(use_graphs))
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_create(ctypes.byref(self._h), ctypes.byref(o))
