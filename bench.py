@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pass-points", type=int, default=16)
     ap.add_argument("--cell-subdiv", type=int, default=8)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep --cell-subdiv/--pass-points instead of the autotuner's choice (made during warm-up)")
+    ap.add_argument("--no-graphs", action="store_true", help="issue every launch eagerly (no HIP graph replay)")
     ap.add_argument("--moment-path", type=int, default=0, help="0 library choice, 1 vector ALU, 2 matrix cores")
     ap.add_argument("--workload", default="odometry", choices=["odometry", "lidar", "two_view"],
                     help="odometry is the headline configuration; the others are for kernel studies")
@@ -123,7 +126,11 @@ def main():
     feats = [torch.from_numpy(f.view(np.int16) if f.dtype == np.uint16 else f).to(dev) for f in p.feats]
     torch.cuda.synchronize()
     ctx = rkhsba.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, pass_points=args.pass_points,
-                         cell_subdiv=args.cell_subdiv, moment_path=args.moment_path)
+                         cell_subdiv=args.cell_subdiv, moment_path=args.moment_path,
+                         use_graphs=not args.no_graphs)
+    if not args.no_autotune:
+        S, P, ms = ctx.autotune(pts, feats, p.feat_kind, p.init_poses, p.edges, trials=2)
+        log(f"[bench] autotuner: cell_subdiv {S}, pass_points {P} ({ms:.3f} ms per normal-equation evaluation)")
 
     def step():
         ctx.build_neighbors(pts, feats, p.feat_kind)
@@ -146,7 +153,18 @@ def main():
     elapsed = time.perf_counter() - t0
     ctx.profile_enable(False)
     ms_per_step = 1e3 * elapsed / args.steps
+    # the same steps without stage events: Gauss-Newton iterations replayed from a HIP graph
+    graph_ms = None
+    if not args.no_graphs:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+        log(f"[bench] graph-replayed steps: {graph_ms:.3f} ms/step")
     prof = {rkhsba.PROF_NAMES[s]: ctx.profile_read(s) for s in range(rkhsba.PROF_SOLVE + 1)}
+    cfg_subdiv, cfg_pass, cfg_occ = ctx.config()
     for name, (ms, n) in prof.items():
         log(f"[bench] stage {name:12s} {ms / args.steps:9.3f} ms/step over {n // max(args.steps, 1)} launches/step")
 
@@ -175,9 +193,11 @@ def main():
             "workload": WORKLOADS[args.workload],
             "frames": p.K, "points_per_frame": int(p.n_points[0]), "edges": int(len(p.edges)),
             "gn_iterations": p.n_iter, "feature_dim": p.D, "ell": p.ell,
-            "pass_points": args.pass_points, "cell_subdiv": args.cell_subdiv, "moment_path": args.moment_path,
+            "pass_points": cfg_pass, "cell_subdiv": cfg_subdiv, "moment_path": args.moment_path,
+            "autotuned": not args.no_autotune, "points_per_rc_cube": cfg_occ,
         },
         "gn_iters_per_s": p.n_iter * args.steps / elapsed,
+        "graph_replay_ms_per_step": graph_ms,
         "pairs_per_step": pairs_total // args.steps,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "roofline": {
@@ -197,9 +217,9 @@ def main():
     if rank == 0 and args.cpu_edges > 0:
         log(f"[bench] CPU oracle on {args.cpu_edges} frame pairs ...")
         result["cpu_baseline"] = cpu_baseline(p, args.cpu_edges)
-    ctx.close()
     if rank == 0:
         print(json.dumps(result), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":

@@ -79,7 +79,9 @@ typedef struct {
   int fixed_frame;       /* gauge: this frame is not moved (default 0, Sec. V-A) */
   int clamp_negative_c;  /* use max(c_ij, 0) for dense features (default 1) */
   int device;            /* HIP device ordinal (default 0) */
-  int cell_subdiv;       /* voxel cells per truncation radius, 1..8 (default 8) */
+  int cell_subdiv;       /* voxel cells per truncation radius, 1..8, or 0 = chosen at each build from the
+                            points per occupied r_c-cube (the table rkhsba_autotune fills, else a default
+                            rule) (default 8) */
   int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
   int moment_path;       /* 16-point sweep, Gauss-Newton moments accumulated on 0 = library choice,
                             1 = vector ALU, 2 = matrix cores (default 0) */
@@ -134,6 +136,24 @@ int rkhsba_accumulate_normal_eqs(rkhsba_ctx* ctx, const double* poses, int E, co
  * the last successful step). */
 int rkhsba_gn_step(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* edges, int n_iter,
                    double* loss_per_iter, int64_t* pairs_per_iter);
+
+/* Autotuner for the launch configuration.  Builds the frames (arguments as
+ * rkhsba_build_neighbors) with every cell size in {1,2,3,4,6,8} cells per r_c
+ * and every sweep size in {16,32,64} source points, times `trials` normal-
+ * equation evaluations of each at `poses` / `edges` (HIP events on the
+ * context's stream, after one warm-up), and leaves the context built with the
+ * fastest pair; outputs (nullable): that pair and its time per evaluation in
+ * ms.  The choice is also recorded, for this feature layout and the frames'
+ * points per occupied r_c-cube, in a process-wide table that builds with
+ * cell_subdiv = 0 consult.  Results (pair sets, F, b, H) do not depend on the
+ * configuration beyond FP32 summation order. */
+int rkhsba_autotune(rkhsba_ctx* ctx, int K, const int64_t* n_points, const float* const* xyz, int feat_kind, int D,
+                    const void* const* feats, int is_device, const double* poses, int E, const int32_t* edges,
+                    int trials, int* best_cell_subdiv, int* best_pass_points, double* best_ms);
+
+/* The configuration of the resident frames: cells per r_c, sweep size, and
+ * points per occupied r_c-cube (0 if that was not measured).  Nullable outputs. */
+int rkhsba_get_config(rkhsba_ctx* ctx, int* cell_subdiv, int* pass_points, double* occupancy);
 
 /* Debug/parity: the in-radius pairs of edge (m, n) at `poses` under the FP32
  * membership rule (and equal labels for class ids), as (i, j) original point

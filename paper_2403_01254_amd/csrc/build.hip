@@ -166,7 +166,8 @@ __global__ __launch_bounds__(kThreads) void k_row_store_offsets(const uint32_t* 
 __global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restrict__ keys,
                                                         const FrameInfo* __restrict__ frames,
                                                         const int64_t* __restrict__ off, int K, int64_t n_total,
-                                                        const int4* __restrict__ rows, uint32_t* __restrict__ xtab) {
+                                                        const int4* __restrict__ rows, uint32_t* __restrict__ xtab,
+                                                        uint32_t* __restrict__ n_cells) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n_total) return;
   int f;
@@ -182,7 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restri
   const bool has_prev = s > 0;
   const bool has_next = s + 1 < F.n;
   const uint32_t kprev = has_prev ? keys[p - 1] : 0u;
-  if (!has_prev || kprev != key) {  // head of an occupied cell
+  const bool head = !has_prev || kprev != key;
+  {  // occupied cells: one atomic per wavefront
+    const unsigned long long heads = __ballot(head), live = __ballot(1);
+    if ((int)(threadIdx.x & 63) == __builtin_ctzll(live)) atomicAdd(n_cells, (uint32_t)__popcll(heads));
+  }
+  if (head) {  // head of an occupied cell
     int x0 = R.x;
     if (has_prev) {
       int px, py, pz;
@@ -243,9 +249,10 @@ hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 }
 
 hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
-                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, hipStream_t st) {
+                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, uint32_t* d_n_cells, hipStream_t st) {
   if (n_total > 0)
-    k_xtab_fill<<<blocks(n_total), kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows, d_xtab);
+    k_xtab_fill<<<blocks(n_total), kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows, d_xtab,
+                                                      d_n_cells);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ struct rkhsba_ctx {
   int prob = -1;         // the resident problem
   SetLayout lay_eval;    // evaluations without a fixed frame (loss, normal equations)
   SetLayout lay_gn;      // Gauss-Newton runs
+  double occ_r = 0.0;    // points per occupied r_c-cube of the frames last measured
 };
 
 namespace {
@@ -95,7 +96,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   if (!opt) return RKHSBA_EINVAL;
   if (!(opt->ell > 0.0) || !std::isfinite(opt->ell) || !(opt->cutoff_factor > 0.0) ||
       !std::isfinite(opt->cutoff_factor) || !std::isfinite(opt->sigma) || !(opt->damping_rel >= 0.0) ||
-      opt->cell_subdiv < 1 || opt->cell_subdiv > 8 ||
+      opt->cell_subdiv < 0 || opt->cell_subdiv > 8 ||
       (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) || opt->fixed_frame < 0 ||
       opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1)
     return RKHSBA_EINVAL;
@@ -148,7 +149,87 @@ int rkhsba_build_neighbors(rkhsba_ctx* c, int K, const int64_t* n_points, const 
       c->eng->remove_problem(c->prob);
       c->prob = -1;
     }
-    c->prob = c->eng->add_problem(params_of(c->opt), K, n_points, xyz, feat_kind, D, feats, is_device != 0);
+    c->prob = c->eng->add_problem_auto(params_of(c->opt), K, n_points, xyz, feat_kind, D, feats, is_device != 0);
+    const double occ = c->eng->problem(c->prob)->occupancy_r;
+    if (occ > 0.0) c->occ_r = occ;
+    return RKHSBA_OK;
+  });
+}
+
+int rkhsba_autotune(rkhsba_ctx* c, int K, const int64_t* n_points, const float* const* xyz, int feat_kind, int D,
+                    const void* const* feats, int is_device, const double* poses, int E, const int32_t* edges,
+                    int trials, int* best_cell_subdiv, int* best_pass_points, double* best_ms) {
+  return guarded(c, [&]() -> int {
+    RK_REQUIRE(trials >= 1 && trials <= 100, RKHSBA_EINVAL, "trials must be in [1, 100]");
+    Engine& g = *c->eng;
+    const bool prof = g.prof;
+    g.prof = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    RK_HIP(hipEventCreate(&ev[0]));
+    RK_HIP(hipEventCreate(&ev[1]));
+    struct Cleanup {
+      hipEvent_t* ev;
+      Engine& g;
+      bool prof;
+      ~Cleanup() {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        g.prof = prof;
+      }
+    } cleanup{ev, g, prof};
+    const int subdivs[] = {1, 2, 3, 4, 6, 8};
+    const int passes[] = {16, 32, 64};
+    double best = 1e300, occ_r = 0.0;
+    int bestS = 0, bestP = 0;
+    for (int P : passes) {
+      g.pass_points = P;
+      for (int S : subdivs) {
+        if (c->prob >= 0) g.remove_problem(c->prob);
+        c->prob = -1;
+        ProbParams par = params_of(c->opt);
+        par.cell_subdiv = S;
+        c->prob = g.add_problem(par, K, n_points, xyz, feat_kind, D, feats, is_device != 0);
+        Problem* p = g.problem(c->prob);
+        if (S == 1) occ_r = p->occupancy;
+        g.prepare(c->lay_eval, {SetItem{p, edges, E, -1, 0}});
+        g.upload_poses(p, poses);
+        g.evaluate(c->lay_eval, MODE_NORMAL);  // warm-up
+        RK_HIP(hipEventRecord(ev[0], c->stream));
+        for (int t = 0; t < trials; ++t) g.evaluate(c->lay_eval, MODE_NORMAL);
+        RK_HIP(hipEventRecord(ev[1], c->stream));
+        RK_HIP(hipEventSynchronize(ev[1]));
+        float ms = 0.f;
+        RK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        const double per = ms / trials;
+        if (per < best) {
+          best = per;
+          bestS = S;
+          bestP = P;
+        }
+      }
+    }
+    // leave the context on the best configuration
+    g.pass_points = bestP;
+    c->opt.pass_points = bestP;
+    c->opt.cell_subdiv = bestS;
+    g.tune_record(occ_r, bestS);
+    c->occ_r = occ_r;
+    g.remove_problem(c->prob);
+    c->prob = -1;
+    c->prob = g.add_problem(params_of(c->opt), K, n_points, xyz, feat_kind, D, feats, is_device != 0);
+    if (best_cell_subdiv) *best_cell_subdiv = bestS;
+    if (best_pass_points) *best_pass_points = bestP;
+    if (best_ms) *best_ms = best;
+    return RKHSBA_OK;
+  });
+}
+
+int rkhsba_get_config(rkhsba_ctx* c, int* cell_subdiv, int* pass_points, double* occupancy) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    if (cell_subdiv) *cell_subdiv = p->par.cell_subdiv;
+    if (pass_points) *pass_points = c->eng->pass_points;
+    if (occupancy) *occupancy = p->occupancy_r > 0.0 ? p->occupancy_r : c->occ_r;
     return RKHSBA_OK;
   });
 }

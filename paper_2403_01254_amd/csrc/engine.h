@@ -144,6 +144,8 @@ struct Problem {
   std::vector<FrameInfo> frames;    // pool offsets
   std::vector<int64_t> n_points;
   int64_t resident_bytes = 0;       // pool bytes held by the problem
+  double occupancy = 0.0;           // points per occupied cell of the problem's grid
+  double occupancy_r = 0.0;         // points per occupied cell of edge r_c (0: not measured)
 };
 
 // One item of an evaluated set.
@@ -158,7 +160,7 @@ struct SetItem {
 // Work layout of a set (rebuilt when the set changes).
 struct SetLayout {
   std::vector<int> ids;             // problem ids, in item order
-  std::vector<int32_t> edge_key;    // concatenated edge lists + fixed + n_iter (change detection)
+  std::vector<int32_t> edge_key;    // pass size, problem ids, edge lists, fixed, n_iter (change detection)
   uint64_t gen = 0;                 // pool generation the tables were built for
   int n_prob = 0, n_max = 0, E = 0;
   int64_t n_entries = 0;
@@ -202,6 +204,12 @@ class Engine {
   // device pointers) and keeps it resident.  Returns its id.
   int add_problem(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind, int D,
                   const void* const* feats, bool is_device);
+  // As add_problem; cell_subdiv == 0 picks the cell size from the occupancy
+  // of a first build with cells of edge r_c (tuned table, else a default rule).
+  int add_problem_auto(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
+                       int D, const void* const* feats, bool is_device);
+  int choose_subdiv(double occupancy_r) const;
+  void tune_record(double occupancy_r, int subdiv);  // process-wide tuned table
   void remove_problem(int id);
   Problem* problem(int id);
   int n_problems() const { return (int)probs_.size(); }

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/rkhsba.h"
 
@@ -320,14 +321,15 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
 
     // cell coordinates and per-frame bounds
-    std::vector<int32_t> mm(6 * K + 2);
+    std::vector<int32_t> mm(6 * K + 3);
     for (int f = 0; f < K; ++f)
       for (int a = 0; a < 3; ++a) {
         mm[6 * f + a] = INT_MAX;
         mm[6 * f + 3 + a] = INT_MIN;
       }
-    mm[6 * K] = 0;
-    mm[6 * K + 1] = 0;
+    mm[6 * K] = 0;      // bad coordinate flag
+    mm[6 * K + 1] = 0;  // negative feature flag
+    mm[6 * K + 2] = 0;  // occupied cells
     RK_HIP(cell_.reserve((size_t)N * 3));
     RK_HIP(minmax_.reserve(mm.size()));
     RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, st));
@@ -433,7 +435,10 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     p->n_xt = std::max<int64_t>((int64_t)xt_total, 1);
     p->xbase = xtab_.alloc(p->n_xt, st);
     RK_HIP(launch_xtab(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows,
-                       static_cast<uint32_t*>(xtab_.ptr(0)) + p->xbase, st));
+                       static_cast<uint32_t*>(xtab_.ptr(0)) + p->xbase,
+                       reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 2), st));
+    uint32_t n_cells = 0;
+    RK_HIP(hipMemcpyAsync(&n_cells, minmax_.p + 6 * K + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
 
     // frame table entries with pool offsets
     p->slot0 = slots_.alloc(K, st);
@@ -449,15 +454,64 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(hipStreamSynchronize(st));
     prof_collect();
     p->frames = std::move(fr);
+    p->occupancy = (double)N / std::max<uint32_t>(n_cells, 1u);
     p->resident_bytes = N * (int64_t)(28 + 4 * std::max(Dp, 1)) + p->n_rows * 16 + p->n_xt * 4 +
                         (int64_t)K * (int64_t)(sizeof(FrameInfo) + 96) + 8;
   } catch (...) {
     release();
     throw;
   }
+  if (par.cell_subdiv == 1) p->occupancy_r = p->occupancy;
   p->id = next_id_++;
   probs_[p->id] = std::move(P);
   return p->id;
+}
+
+// ---------------------------------------------------------------- cell-size choice
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::vector<int>, int> g_tune;  // (feature kind, Dp, pass points, occupancy bucket) -> cell_subdiv
+}  // namespace
+
+int occupancy_bucket(double occ) {
+  const double b = std::floor(2.0 * std::log2(std::max(occ, 1.0)));
+  return (int)std::min(40.0, std::max(0.0, b));
+}
+
+void Engine::tune_record(double occ_r, int subdiv) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[{feat_kind, Dp, pass_points, occupancy_bucket(occ_r)}] = subdiv;
+}
+
+int Engine::choose_subdiv(double occ_r) const {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({feat_kind, Dp, pass_points, occupancy_bucket(occ_r)});
+    if (it != g_tune.end()) return it->second;
+  }
+  // Untuned default: finer cells as the points per truncation-radius cube grow.
+  if (occ_r < 3.0) return 1;
+  if (occ_r < 12.0) return 2;
+  if (occ_r < 48.0) return 4;
+  return 8;
+}
+
+int Engine::add_problem_auto(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
+                             int Din, const void* const* feats, bool is_device) {
+  if (par.cell_subdiv != 0) return add_problem(par, K, n_points, xyz, kind, Din, feats, is_device);
+  ProbParams probe = par;
+  probe.cell_subdiv = 1;  // cells of one truncation radius: occupancy probe
+  const int id = add_problem(probe, K, n_points, xyz, kind, Din, feats, is_device);
+  const double occ = problem(id)->occupancy;
+  const int S = choose_subdiv(occ);
+  if (S == 1) return id;
+  remove_problem(id);
+  ProbParams fine = par;
+  fine.cell_subdiv = S;
+  const int id2 = add_problem(fine, K, n_points, xyz, kind, Din, feats, is_device);
+  problem(id2)->occupancy_r = occ;
+  return id2;
 }
 
 void Engine::remove_problem(int id) {
@@ -535,7 +589,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     }
     ensure_history(it.p, it.n_iter);
   }
-  std::vector<int32_t> key;
+  std::vector<int32_t> key{pass_points};
   std::vector<int> ids;
   for (const SetItem& it : items) {
     ids.push_back(it.p->id);

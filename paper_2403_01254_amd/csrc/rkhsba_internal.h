@@ -106,7 +106,7 @@ hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const 
                        int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
                        uint64_t* d_total, hipStream_t st);
 hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
-                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, hipStream_t st);
+                       int64_t n_total, const int4* d_rows, uint32_t* d_xtab, uint32_t* d_n_cells, hipStream_t st);
 
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,

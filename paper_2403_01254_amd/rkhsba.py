@@ -72,6 +72,10 @@ def lib():
         L.rkhsba_gn_step.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _dp, _i64p]
         L.rkhsba_export_pairs.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _i64p]
         L.rkhsba_export_voxels.argtypes = [vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), _i32p, _i32p]
+        L.rkhsba_autotune.argtypes = [vp, ctypes.c_int, _i64p, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(vp), ctypes.c_int, _dp, ctypes.c_int, _i32p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
+        L.rkhsba_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
         L.rkhsba_profile_enable.argtypes = [vp, ctypes.c_int]
         L.rkhsba_profile_read.argtypes = [vp, ctypes.c_int, _dp, _i64p, ctypes.c_int]
         _lib = L
@@ -128,10 +132,9 @@ class Context:
         if rc != OK:
             raise RkhsbaError(rc, lib().rkhsba_last_error(self._h).decode())
 
-    # -- rkhsba_build_neighbors
-    def build_neighbors(self, points, feats, feat_kind="class"):
-        """points: K arrays (N,3) float32 (numpy) or CUDA tensors; feats: K arrays of uint16 class
-        ids (N,) or float32 rows (N, D)."""
+    @staticmethod
+    def _frames(points, feats, feat_kind):
+        """Marshals K clouds (numpy host arrays or device tensors) for the C ABI."""
         kind = _FEAT_NAMES[feat_kind] if isinstance(feat_kind, str) else int(feat_kind)
         K = len(points)
         on_device = not isinstance(points[0], np.ndarray)
@@ -155,10 +158,38 @@ class Context:
             fp = [f.ctypes.data for f in fs]
         xarr = (ctypes.c_void_p * K)(*xp)
         farr = (ctypes.c_void_p * K)(*fp)
-        rc = lib().rkhsba_build_neighbors(self._h, K, _p(n, ctypes.c_int64), xarr, kind, D, farr, int(on_device))
+        return K, kind, D, n, xarr, farr, int(on_device), keep
+
+    # -- rkhsba_build_neighbors
+    def build_neighbors(self, points, feats, feat_kind="class"):
+        """points: K arrays (N,3) float32 (numpy) or CUDA tensors; feats: K arrays of uint16 class
+        ids (N,) or float32 rows (N, D)."""
+        K, kind, D, n, xarr, farr, dev, keep = self._frames(points, feats, feat_kind)
+        rc = lib().rkhsba_build_neighbors(self._h, K, _p(n, ctypes.c_int64), xarr, kind, D, farr, dev)
         del keep
         self._check(rc)
         self.K = K
+
+    # -- rkhsba_autotune
+    def autotune(self, points, feats, feat_kind, poses, edges, trials=2):
+        """Times every (cell size, sweep size) pair on these frames and leaves the context
+        built with the fastest.  Returns (cell_subdiv, pass_points, ms per evaluation)."""
+        K, kind, D, n, xarr, farr, dev, keep = self._frames(points, feats, feat_kind)
+        self.K = K
+        p, e = self._poses(poses), self._edges(edges)
+        S, P, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        rc = lib().rkhsba_autotune(self._h, K, _p(n, ctypes.c_int64), xarr, kind, D, farr, dev, _p(p), len(e),
+                                   _p(e, ctypes.c_int32), trials, ctypes.byref(S), ctypes.byref(P), ctypes.byref(ms))
+        del keep
+        self._check(rc)
+        return S.value, P.value, ms.value
+
+    # -- rkhsba_get_config
+    def config(self):
+        """(cell_subdiv, pass_points, points per occupied r_c-cube) of the resident frames."""
+        S, P, occ = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(lib().rkhsba_get_config(self._h, ctypes.byref(S), ctypes.byref(P), ctypes.byref(occ)))
+        return S.value, P.value, occ.value
 
     def _poses(self, poses):
         return np.ascontiguousarray(poses, dtype=np.float64).reshape(self.K, 12)

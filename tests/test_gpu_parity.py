@@ -259,3 +259,26 @@ def test_graph_replay_matches_eager(rk):
     e.build_neighbors(q.points, q.feats, q.feat_kind)
     for x, y in zip(g.gn_step(q.init_poses, q.edges, 2), e.gn_step(q.init_poses, q.edges, 2)):
         np.testing.assert_array_equal(x, y)
+
+
+def test_autotune_and_auto_cell_size(rk):
+    """The autotuner leaves the context on the configuration it reports, the
+    results stay those of the default configuration, and a build with
+    cell_subdiv = 0 on the same kind of frames picks the tuned cell size."""
+    p = scenes.odometry(10, n_frames=3, n_points=3000, n_iter=2)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    S, P, ms = ctx.autotune(p.points, p.feats, p.feat_kind, p.init_poses, p.edges, trials=1)
+    say(f"[tune] best cell_subdiv {S} pass_points {P}: {ms:.3f} ms per evaluation")
+    assert S in (1, 2, 3, 4, 6, 8) and P in (16, 32, 64) and ms > 0
+    cS, cP, occ = ctx.config()
+    assert (cS, cP) == (S, P) and occ > 0
+    ref = make_ctx(rk, p)
+    H0, b0, F0, n0 = ref.accumulate_normal_eqs(p.init_poses, p.edges)
+    H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    assert n == n0 and abs(F - F0) <= REL_TOL * abs(F0)
+    assert normwise_rel(b, b0) <= REL_TOL and normwise_rel(H, H0) <= REL_TOL
+    auto = make_ctx(rk, p, cell_subdiv=0, pass_points=P)
+    aS, aP, aocc = auto.config()
+    assert aS == S and aocc == occ
+    H2, b2, F2, n2 = auto.accumulate_normal_eqs(p.init_poses, p.edges)
+    assert n2 == n0 and normwise_rel(H2, H0) <= REL_TOL
