@@ -223,161 +223,221 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
 }
 
 // ---------------------------------------------------------------- per-point finalisation
-
-template <int N>
-__device__ inline void block_sum_store(const double (&v)[N], double* sh, double* out) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const double t = wave_sum(v[k]);
-    if (lane == 0) sh[w * N + k] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < N) {
-    double t = 0.0;
-    for (int ww = 0; ww < kFinThreads / 64; ++ww) t += sh[ww * N + threadIdx.x];
-    out[threadIdx.x] = t;
-  }
-  __syncthreads();
-}
-
-__device__ inline int sym_index(int r, int c) {  // upper triangle, row-major, r <= c
-  return r * 6 - (r * (r - 1)) / 2 + (c - r);
-}
-
-// Moments (A, B, C) of source point x (q = T_nm x in the target frame) ->
-// its terms of the edge's normal equations (world residual, right
-// perturbations; R_mn = R_nm^T):
-//   F   = A
-//   b_m = [R_mn B; x cross R_mn B]              b_n = -[B; q cross B]
-//   H_mm = A [[I, -[x]], [[x], |x|^2 I - x x^T]]
-//   S = A q - B (= sum w z),  Szz = A q q^T - q B^T - B q^T + C (= sum w z z^T)
+//
+// The normal-equation blocks of an edge are linear in a few per-point
+// products of the moments (A, B, C), the source point x (frame m) and
+// q = T_nm x (frame n).  With R_mn = R_nm^T, Bm = R_mn B, S = A q - B and
+// Szz = A q q^T - q B^T - B q^T + C (S and Szz are the weighted sums of the
+// target points z and z z^T in frame n), the per-point terms are (world
+// residual u = T_m x - T_n z, right perturbations):
+//   F = A,  b_m = [Bm; x cross Bm],  b_n = -[B; q cross B]
+//   H_mm = [[A I, -[A x]], [[A x], tr(A x x^T) I - A x x^T]]
 //   H_nn = [[A I, -[S]], [[S], tr(Szz) I - Szz]]
 //   H_mn = -[I; [x]] R_mn [A I, -[S]]
+//        = [[-A R_mn, R_mn [S]], [-[A x] R_mn, [x] R_mn [S]]]
+// so it suffices to sum, per edge, the 37 products
+//   A, B, x cross Bm, q cross B, A x, A x x^T (6), A q, Szz (6), x S^T (9)
+// (plus the pair count) and to expand the sums into the 91 values once per
+// edge.  Sums run in FP64: per thread over its entries, then per block in a
+// fixed order, then per edge over the blocks in order (deterministic).
+constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
+              kStXS = 28, kStCnt = 37;
+
 template <int MODE>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32_t* __restrict__ fin_off) {
-  __shared__ double sh[(kFinThreads / 64) * 36];
+  constexpr int NS = MODE == MODE_LOSS ? 2 : kFinStats;
+  __shared__ double sh[(kFinThreads / 64) * kFinStats];
   const int blk = blockIdx.x;
   const int e = upper_segment(fin_off, a.E, blk);
   const EdgeInfo ed = a.edges[e];
-  const int64_t entry = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads + threadIdx.x;
-  const bool in_range = entry < ed.ent_off + ed.n_src;
-  const bool valid = in_range && a.keys[entry] != kInvalidKey;
-  const uint32_t cnt = in_range ? a.cnt[entry] : 0u;  // per-entry or per-pass pair counts
-  double* out = a.partial + (int64_t)blk * kEdgeVals;
-  const int64_t N = a.n_entries;
-
-  double A = 0.0;
-  if (valid) A = a.mom[entry];
-  if constexpr (MODE == MODE_LOSS) {
-    double v[1] = {A};
-    block_sum_store<1>(v, sh, out);  // out[0] = F
-    double c1[1] = {(double)cnt};
-    block_sum_store<1>(c1, sh, out + 91);  // out[91] = pairs
-    for (int k = 1 + (int)threadIdx.x; k < 91; k += kFinThreads) out[k] = 0.0;
-    return;
-  }
-  double B[3] = {0, 0, 0}, C[6] = {0, 0, 0, 0, 0, 0}, x[3] = {0, 0, 0}, q[3] = {0, 0, 0};
   const EdgeXf X = a.xf[e];
-  if (valid) {
-    for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
-    for (int k = 0; k < 6; ++k) C[k] = a.mom[(4 + k) * N + entry];
-    const uint32_t src = a.vals[entry];
-    const float4 p = a.pts[a.frames[ed.m].pt_off + src];
-    const float3 qq = rule_q32(X, p.x, p.y, p.z);
-    x[0] = p.x; x[1] = p.y; x[2] = p.z;
-    q[0] = qq.x; q[1] = qq.y; q[2] = qq.z;
-  }
-  // R_mn B (R_mn = R_nm^T)
-  double Bm[3];
-  for (int a0 = 0; a0 < 3; ++a0) Bm[a0] = X.R[a0] * B[0] + X.R[3 + a0] * B[1] + X.R[6 + a0] * B[2];
-  {  // F, b_m, b_n -> out[0..12]; pair count -> out[91]
-    double v[13];
-    v[0] = A;
-    v[1] = Bm[0]; v[2] = Bm[1]; v[3] = Bm[2];
-    v[4] = x[1] * Bm[2] - x[2] * Bm[1];
-    v[5] = x[2] * Bm[0] - x[0] * Bm[2];
-    v[6] = x[0] * Bm[1] - x[1] * Bm[0];
-    v[7] = -B[0]; v[8] = -B[1]; v[9] = -B[2];
-    v[10] = -(q[1] * B[2] - q[2] * B[1]);
-    v[11] = -(q[2] * B[0] - q[0] * B[2]);
-    v[12] = -(q[0] * B[1] - q[1] * B[0]);
-    block_sum_store<13>(v, sh, out);
-    double c1[1] = {(double)cnt};
-    block_sum_store<1>(c1, sh, out + 91);
-  }
-  {  // H_mm
-    double M[21];
-    const double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-    double H[6][6];
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 6; ++c) H[r][c] = 0.0;
-    H[0][0] = H[1][1] = H[2][2] = A;
-    // -A [x]_x in the top-right block, A [x]_x in the bottom-left
-    H[0][4] = A * x[2];  H[0][5] = -A * x[1];
-    H[1][3] = -A * x[2]; H[1][5] = A * x[0];
-    H[2][3] = A * x[1];  H[2][4] = -A * x[0];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) H[3 + r][3 + c] = A * ((r == c ? xx : 0.0) - x[r] * x[c]);
-    for (int r = 0; r < 6; ++r)
-      for (int c = r; c < 6; ++c) M[sym_index(r, c)] = H[r][c];
-    block_sum_store<21>(M, sh, out + 13);
-  }
-  double S[3], Szz[3][3];
-  for (int k = 0; k < 3; ++k) S[k] = A * q[k] - B[k];
-  {
-    const double Cm[3][3] = {{C[0], C[1], C[2]}, {C[1], C[3], C[4]}, {C[2], C[4], C[5]}};
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) Szz[r][c] = A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + Cm[r][c];
-  }
-  {  // H_nn
-    double M[21];
-    double H[6][6];
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 6; ++c) H[r][c] = 0.0;
-    H[0][0] = H[1][1] = H[2][2] = A;
-    H[0][4] = S[2];  H[0][5] = -S[1];
-    H[1][3] = -S[2]; H[1][5] = S[0];
-    H[2][3] = S[1];  H[2][4] = -S[0];
-    const double tr = Szz[0][0] + Szz[1][1] + Szz[2][2];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) H[3 + r][3 + c] = (r == c ? tr : 0.0) - Szz[r][c];
-    for (int r = 0; r < 6; ++r)
-      for (int c = r; c < 6; ++c) M[sym_index(r, c)] = H[r][c];
-    block_sum_store<21>(M, sh, out + 34);
-  }
-  {  // H_mn = -[I; [x]] M1,  M1 = R_mn [A I | -[S]]  (3 x 6)
-    double M1[3][6];
-    double Rmn[3][3];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) Rmn[r][c] = X.R[3 * c + r];
-    const double Sx[3][3] = {{0.0, -S[2], S[1]}, {S[2], 0.0, -S[0]}, {-S[1], S[0], 0.0}};
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) {
-        M1[r][c] = A * Rmn[r][c];
-        M1[r][3 + c] = -(Rmn[r][0] * Sx[0][c] + Rmn[r][1] * Sx[1][c] + Rmn[r][2] * Sx[2][c]);
+  const float4* __restrict__ src_pts = a.pts + a.frames[ed.m].pt_off;
+  const int64_t end = ed.ent_off + ed.n_src;
+  const int64_t base = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads * a.per_thread;
+  const int64_t N = a.n_entries;
+  double st[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) st[k] = 0.0;
+  for (int j = 0; j < a.per_thread; ++j) {
+    const int64_t entry = base + (int64_t)j * kFinThreads + threadIdx.x;
+    if (entry >= end) break;
+    const double cnt = (double)a.cnt[entry];  // per-entry or per-pass pair counts
+    if constexpr (MODE == MODE_LOSS) {
+      st[1] += cnt;
+      if (a.keys[entry] != kInvalidKey) st[0] += (double)a.mom[entry];
+    } else {
+      st[kStCnt] += cnt;
+      if (a.keys[entry] == kInvalidKey) continue;
+      const double A = a.mom[entry];
+      double B[3], C[6], x[3], q[3];
+      for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
+      for (int k = 0; k < 6; ++k) C[k] = a.mom[(4 + k) * N + entry];
+      const float4 p = src_pts[a.vals[entry]];
+      const float3 qq = rule_q32(X, p.x, p.y, p.z);
+      x[0] = p.x; x[1] = p.y; x[2] = p.z;
+      q[0] = qq.x; q[1] = qq.y; q[2] = qq.z;
+      double Bm[3];
+      for (int r = 0; r < 3; ++r) Bm[r] = X.R[r] * B[0] + X.R[3 + r] * B[1] + X.R[6 + r] * B[2];
+      st[kStA] += A;
+      for (int k = 0; k < 3; ++k) st[kStB + k] += B[k];
+      st[kStXBm + 0] += x[1] * Bm[2] - x[2] * Bm[1];
+      st[kStXBm + 1] += x[2] * Bm[0] - x[0] * Bm[2];
+      st[kStXBm + 2] += x[0] * Bm[1] - x[1] * Bm[0];
+      st[kStQB + 0] += q[1] * B[2] - q[2] * B[1];
+      st[kStQB + 1] += q[2] * B[0] - q[0] * B[2];
+      st[kStQB + 2] += q[0] * B[1] - q[1] * B[0];
+      double Ax[3], S[3];
+      for (int k = 0; k < 3; ++k) {
+        Ax[k] = A * x[k];
+        st[kStAx + k] += Ax[k];
+        st[kStAq + k] += A * q[k];
+        S[k] = A * q[k] - B[k];
       }
-    double M[36];
-    for (int c = 0; c < 6; ++c) {
-      for (int r = 0; r < 3; ++r) M[6 * r + c] = -M1[r][c];
-      // rows 3..5: -[x]_x M1
-      M[6 * 3 + c] = -(-x[2] * M1[1][c] + x[1] * M1[2][c]);
-      M[6 * 4 + c] = -(x[2] * M1[0][c] - x[0] * M1[2][c]);
-      M[6 * 5 + c] = -(-x[1] * M1[0][c] + x[0] * M1[1][c]);
+      st[kStAxx + 0] += Ax[0] * x[0]; st[kStAxx + 1] += Ax[0] * x[1]; st[kStAxx + 2] += Ax[0] * x[2];
+      st[kStAxx + 3] += Ax[1] * x[1]; st[kStAxx + 4] += Ax[1] * x[2]; st[kStAxx + 5] += Ax[2] * x[2];
+      // Szz (upper triangle xx, xy, xz, yy, yz, zz), C in the same order
+      const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int r = ri[k], c = ci[k];
+        st[kStSzz + k] += A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + C[k];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st[kStXS + 3 * r + c] += x[r] * S[c];
     }
-    block_sum_store<36>(M, sh, out + 55);
+  }
+  // block sum in a fixed order: wavefront shuffles, then the four waves
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double t = wave_sum(st[k]);
+    if (lane == 0) sh[w * NS + k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    double t = 0.0;
+    for (int ww = 0; ww < kFinThreads / 64; ++ww) t += sh[ww * NS + threadIdx.x];
+    a.partial[(int64_t)blk * kFinStats + threadIdx.x] = t;
   }
 }
 
-// One block per edge: deterministic sum of the edge's finalisation blocks.
-__global__ void k_edge_reduce(const double* __restrict__ partial, const EdgeInfo* __restrict__ edges, int n_vals,
-                              double* __restrict__ edge_out) {
+__device__ inline int sym_index(int r, int c) {  // upper triangle of a 6x6, row-major, r <= c
+  if (r > c) { const int t = r; r = c; c = t; }
+  return r * 6 - (r * (r - 1)) / 2 + (c - r);
+}
+
+// One block per edge: deterministic sum of the edge's finalisation blocks,
+// then the expansion of the 37 sums into F, b_m, b_n, H_mm, H_nn, H_mn.
+__global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ partial,
+                                                    const EdgeInfo* __restrict__ edges,
+                                                    const EdgeXf* __restrict__ xf, int mode,
+                                                    double* __restrict__ edge_out) {
+  __shared__ double T[kFinStats];
   const EdgeInfo ed = edges[blockIdx.x];
-  for (int t = threadIdx.x; t < n_vals; t += blockDim.x) {
+  const int ns = mode == MODE_LOSS ? 2 : kFinStats;
+  for (int t = threadIdx.x; t < kFinStats; t += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < ed.n_fin; ++b) s += partial[(int64_t)(ed.fin_off + b) * kEdgeVals + t];
-    edge_out[(int64_t)blockIdx.x * kEdgeVals + t] = s;
+    if (t < ns)
+      for (int b = 0; b < ed.n_fin; ++b) s += partial[(int64_t)(ed.fin_off + b) * kFinStats + t];
+    T[t] = s;
   }
+  __syncthreads();
+  double* out = edge_out + (int64_t)blockIdx.x * kEdgeVals;
+  if (mode == MODE_LOSS) {
+    for (int k = threadIdx.x; k < kEdgeVals; k += blockDim.x) out[k] = k == 0 ? T[0] : k == 91 ? T[1] : 0.0;
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  const EdgeXf X = xf[blockIdx.x];
+  double Rmn[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Rmn[r][c] = X.R[3 * c + r];
+  const double A = T[kStA];
+  const double* B = T + kStB;
+  double v[kEdgeVals];
+  for (int k = 0; k < kEdgeVals; ++k) v[k] = 0.0;
+  v[0] = A;
+  for (int r = 0; r < 3; ++r) {
+    v[1 + r] = Rmn[r][0] * B[0] + Rmn[r][1] * B[1] + Rmn[r][2] * B[2];
+    v[4 + r] = T[kStXBm + r];
+    v[7 + r] = -B[r];
+    v[10 + r] = -T[kStQB + r];
+  }
+  auto skew = [](const double* a, double (&M)[3][3]) {
+    M[0][0] = 0.0;   M[0][1] = -a[2]; M[0][2] = a[1];
+    M[1][0] = a[2];  M[1][1] = 0.0;   M[1][2] = -a[0];
+    M[2][0] = -a[1]; M[2][1] = a[0];  M[2][2] = 0.0;
+  };
+  const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
+  double Axx[3][3], Szz[3][3];
+  for (int k = 0; k < 6; ++k) {
+    Axx[ri[k]][ci[k]] = Axx[ci[k]][ri[k]] = T[kStAxx + k];
+    Szz[ri[k]][ci[k]] = Szz[ci[k]][ri[k]] = T[kStSzz + k];
+  }
+  double S[3];
+  for (int k = 0; k < 3; ++k) S[k] = T[kStAq + k] - B[k];
+  double Hmm[6][6], Hnn[6][6], Hmn[6][6];
+  double Kx[3][3], Ks[3][3];
+  skew(T + kStAx, Kx);
+  skew(S, Ks);
+  const double trx = Axx[0][0] + Axx[1][1] + Axx[2][2];
+  const double trs = Szz[0][0] + Szz[1][1] + Szz[2][2];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const double I = r == c ? 1.0 : 0.0;
+      Hmm[r][c] = A * I;
+      Hmm[r][3 + c] = -Kx[r][c];
+      Hmm[3 + r][c] = Kx[r][c];
+      Hmm[3 + r][3 + c] = trx * I - Axx[r][c];
+      Hnn[r][c] = A * I;
+      Hnn[r][3 + c] = -Ks[r][c];
+      Hnn[3 + r][c] = Ks[r][c];
+      Hnn[3 + r][3 + c] = trs * I - Szz[r][c];
+    }
+  // H_mn: [[-A R_mn, R_mn [S]], [-[A x] R_mn, sum [x] R_mn [S]]]
+  double RKs[3][3], KxR[3][3], XRS[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      RKs[r][c] = Rmn[r][0] * Ks[0][c] + Rmn[r][1] * Ks[1][c] + Rmn[r][2] * Ks[2][c];
+      KxR[r][c] = Kx[r][0] * Rmn[0][c] + Kx[r][1] * Rmn[1][c] + Kx[r][2] * Rmn[2][c];
+      XRS[r][c] = 0.0;
+    }
+  // sum_p [x_p] R_mn [S_p] = sum_{i,j} (sum_p x_i S_j) [e_i] R_mn [e_j]
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double mij = T[kStXS + 3 * i + j];
+      double ei[3] = {0, 0, 0}, ej[3] = {0, 0, 0};
+      ei[i] = 1.0;
+      ej[j] = 1.0;
+      double Ki[3][3], Kj[3][3];
+      skew(ei, Ki);
+      skew(ej, Kj);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double t = 0.0;
+          for (int a0 = 0; a0 < 3; ++a0)
+            for (int b0 = 0; b0 < 3; ++b0) t += Ki[r][a0] * Rmn[a0][b0] * Kj[b0][c];
+          XRS[r][c] += mij * t;
+        }
+    }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      Hmn[r][c] = -A * Rmn[r][c];
+      Hmn[r][3 + c] = RKs[r][c];
+      Hmn[3 + r][c] = -KxR[r][c];
+      Hmn[3 + r][3 + c] = XRS[r][c];
+    }
+  for (int r = 0; r < 6; ++r)
+    for (int c = r; c < 6; ++c) {
+      v[13 + sym_index(r, c)] = Hmm[r][c];
+      v[34 + sym_index(r, c)] = Hnn[r][c];
+    }
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) v[55 + 6 * r + c] = Hmn[r][c];
+  v[91] = T[kStCnt];
+  for (int k = 0; k < kEdgeVals; ++k) out[k] = v[k];
 }
 
 // ---------------------------------------------------------------- pair export (parity)
@@ -478,9 +538,9 @@ hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode,
   return hipGetLastError();
 }
 
-hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, int E, int n_vals, double* d_edge_out,
-                              hipStream_t st) {
-  if (E > 0) k_edge_reduce<<<E, 128, 0, st>>>(d_partial, d_edges, n_vals, d_edge_out);
+hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, const EdgeXf* d_xf, int E, int mode,
+                              double* d_edge_out, hipStream_t st) {
+  if (E > 0) k_edge_reduce<<<E, 64, 0, st>>>(d_partial, d_edges, d_xf, mode, d_edge_out);
   return hipGetLastError();
 }
 

@@ -146,16 +146,18 @@ struct FinArgs {
   const uint32_t* vals;
   const float* mom;
   const uint32_t* cnt;
-  double* partial;        // [n_fin_total][kEdgeVals]
+  double* partial;        // [n_fin_total][kFinStats]
   int64_t n_entries;
   int32_t E;
   int32_t n_fin_total;
+  int32_t per_thread;     // entries per thread: a finalisation block covers kFinThreads * per_thread entries
 };
 constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
 constexpr int kFinThreads = 256;
+constexpr int kFinStats = 38;  // per-edge sums the normal-equation blocks are expanded from (+ pair count)
 hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st);
-hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, int E, int n_vals, double* d_edge_out,
-                              hipStream_t st);
+hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, const EdgeXf* d_xf, int E, int mode,
+                              double* d_edge_out, hipStream_t st);
 
 // One problem's Gauss-Newton system within an evaluated set.
 struct ProbSys {
