@@ -61,7 +61,8 @@ typedef enum {
   RKHSBA_ENOMEM = -2,   /* device allocation failed or a grid does not fit its limits */
   RKHSBA_EDEVICE = -3,  /* HIP runtime error */
   RKHSBA_ENOTPD = -4,   /* Cholesky pivot <= 0 in a Gauss-Newton step */
-  RKHSBA_ESTATE = -5    /* call out of order (e.g. no frames built yet) */
+  RKHSBA_ESTATE = -5,   /* call out of order (e.g. no frames built yet), or a request cancelled */
+  RKHSBA_EBUSY = -6     /* a served request has not finished within the wait's timeout */
 } rkhsba_status;
 
 typedef enum {
@@ -183,6 +184,84 @@ enum {
 int rkhsba_profile_enable(rkhsba_ctx* ctx, int on);
 /* total_ms / launches (nullable) accumulated for `stage` since the last reset. */
 int rkhsba_profile_read(rkhsba_ctx* ctx, int stage, double* total_ms, int64_t* launches, int reset);
+
+/* ------------------------------------------------------------------------
+ * Request loop (continuous batching of whole solves).
+ *
+ * A server owns one device stream and a worker thread.  Each request is one
+ * multi-frame problem (its own frames, edge list, ell, n_iter and initial
+ * poses) solved exactly as rkhsba_gn_step solves it.  Requests wait in FIFO
+ * order and are admitted while fewer than max_active are active and the sum
+ * of their estimated device footprints stays within hbm_budget_bytes (one
+ * request is always admitted when none is active).  Admission builds the
+ * request's voxel structures into memory that stays resident until it
+ * finishes; every batch iteration then advances every active request by one
+ * Gauss-Newton step in shared launches (one edge table over all requests, one
+ * Cholesky workgroup per request).  A request joins at the batch iteration
+ * after its admission and leaves after its final loss evaluation, so the
+ * requests in flight overlap on the device.  A request's result does not
+ * depend on the other requests in flight beyond FP32 summation order in its
+ * last loss value (the final evaluation may run with or without the
+ * Gauss-Newton moments).
+ */
+typedef struct rkhsba_server rkhsba_server;
+
+typedef struct {
+  int device;
+  int feat_kind;            /* feature kind of every request (CLASS_ID or DENSE_F32) */
+  int D;                    /* dense feature dimension of every request */
+  int max_active;           /* requests iterating together (default 64) */
+  int64_t hbm_budget_bytes; /* admission limit on the estimated footprints (0: 80% of free memory) */
+  int pass_points;          /* sweep size (default 16) */
+  int use_graphs;           /* replay a batch iteration from a HIP graph while the active set is unchanged */
+  void* stream;             /* hipStream_t for all work; NULL = a stream owned by the server */
+} rkhsba_server_options;
+
+typedef struct {
+  int K;                       /* frames */
+  const int64_t* n_points;     /* K counts */
+  const float* const* xyz;     /* K pointers to N_m*3 float32 (frame-local) */
+  const void* const* feats;    /* K pointers (class ids or N_m*D float32) */
+  int is_device;               /* xyz/feats are device pointers on the server's device */
+  int feat_kind, D;            /* must equal the server's */
+  const double* poses;         /* K*12 initial poses (copied at submit) */
+  int E;
+  const int32_t* edges;        /* E*2 (copied at submit) */
+  double ell, cutoff_factor, sigma, damping_rel;
+  int fixed_frame;
+  int clamp_negative_c;
+  int cell_subdiv;             /* 1..8, or 0 = chosen from the frames' occupancy */
+  int n_iter;                  /* Gauss-Newton steps */
+} rkhsba_request;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued;
+  int64_t batch_iterations;    /* shared launches of Gauss-Newton iterations */
+  int64_t max_active;          /* most requests seen in one batch iteration */
+  int64_t peak_device_bytes;   /* largest engine footprint observed */
+  int64_t pair_evals;          /* in-radius pairs summed over every evaluation of completed requests */
+} rkhsba_server_stats;
+
+void rkhsba_server_default_options(rkhsba_server_options* opt);
+int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt);
+/* Stops the worker after its current batch iteration; requests still queued
+ * or active finish with RKHSBA_ESTATE.  NULL is allowed. */
+void rkhsba_server_destroy(rkhsba_server* srv);
+/* Queues a request and returns at once with its ticket.  xyz and feats are
+ * read when the request is admitted: the caller keeps them valid until
+ * rkhsba_server_wait has returned for the ticket. */
+int rkhsba_server_submit(rkhsba_server* srv, const rkhsba_request* req, int64_t* ticket);
+/* Waits up to timeout_s seconds (< 0: no limit) for the ticket; returns the
+ * request's status (RKHSBA_EBUSY on timeout, the ticket stays valid).  On
+ * RKHSBA_OK / RKHSBA_ENOTPD the outputs (nullable) receive the final poses
+ * (K*12), loss and pair count per evaluation (n_iter+1 each, as
+ * rkhsba_gn_step), the time from submission to completion and the time spent
+ * queued before admission (seconds). */
+int rkhsba_server_wait(rkhsba_server* srv, int64_t ticket, double timeout_s, double* poses_out,
+                       double* loss_per_iter, int64_t* pairs_per_iter, double* latency_s, double* queue_s);
+int rkhsba_server_stats_get(rkhsba_server* srv, rkhsba_server_stats* out);
+/* Text of the failure of the last request waited for. */
+const char* rkhsba_server_last_error(const rkhsba_server* srv);
 
 #ifdef __cplusplus
 }

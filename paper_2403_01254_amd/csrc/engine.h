@@ -180,6 +180,7 @@ struct SetLayout {
   hipGraphExec_t graph = nullptr;
   uint64_t graph_gen = 0;
   int graph_mode = -1;
+  int uses = 0;                     // iterate() calls since the layout was built
   ~SetLayout();
   void drop_graph();
 };

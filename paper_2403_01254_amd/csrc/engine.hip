@@ -748,6 +748,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     if (before[i] != after[i]) ++scratch_gen_;
   RK_HIP(hipStreamSynchronize(st));  // host tables above go out of scope
 
+  lay.uses = 0;
   lay.ids = std::move(ids);
   lay.edge_key = std::move(key);
   lay.sys = std::move(sys);
@@ -863,7 +864,11 @@ void Engine::record_iteration(SetLayout& lay) {
 
 void Engine::iterate(SetLayout& lay, int n) {
   if (n <= 0) return;
-  if (!use_graphs || prof) {
+  // A graph pays for its capture only when it is replayed: capture on a
+  // layout's second use, or when this call runs several iterations.
+  const bool graph = use_graphs && !prof && (n > 1 || lay.uses >= 1);
+  ++lay.uses;
+  if (!graph) {
     for (int i = 0; i < n; ++i) record_iteration(lay);
     return;
   }

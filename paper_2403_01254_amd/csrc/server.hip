@@ -1,0 +1,379 @@
+// Request loop: continuous batching of whole solves (each request = the
+// multi-frame Gauss-Newton problem of Sec. V-A on its own frames, graph and
+// length scale).  A worker thread owns one engine; requests wait in a FIFO
+// queue and are admitted while the number of active requests and the sum of
+// their estimated device footprints stay within the limits (a request is
+// always admitted when nothing is active).  Admission builds the request's
+// voxel structures into the engine's resident pools; then every active
+// request advances by one Gauss-Newton iteration per batch iteration, all of
+// them in the same launches (one edge table, one system per request).  A
+// request that has taken its n_iter steps gets its final loss evaluation in
+// the next batch iteration and is retired: poses and histories are copied
+// out, its pools are freed and its waiter is woken.  Requests that arrive
+// meanwhile join at the next batch iteration.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/rkhsba.h"
+#include "engine.h"
+
+using namespace rkhsba;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  int64_t ticket = 0;
+  ProbParams par;
+  int K = 0, E = 0, n_iter = 0, is_device = 0, feat_kind = 0, D = 0;
+  std::vector<int64_t> n_points;
+  std::vector<const float*> xyz;
+  std::vector<const void*> feats;
+  std::vector<double> poses;
+  std::vector<int32_t> edges;
+  int64_t est_bytes = 0;
+  bool admitted = false;  // est_bytes counted in the server's committed total
+  // progress (worker thread)
+  int prob = -1;
+  int evals = 0;
+  // result (guarded by the server mutex once published)
+  bool done = false;
+  int status = RKHSBA_OK;
+  std::string err;
+  std::vector<double> loss, pairs;
+  Clock::time_point t_submit, t_admit, t_done;
+};
+
+}  // namespace
+
+struct rkhsba_server {
+  rkhsba_server_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::unique_ptr<Engine> eng;
+  SetLayout lay;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Req>> queue;
+  std::map<int64_t, std::shared_ptr<Req>> tickets;
+  std::vector<std::shared_ptr<Req>> active;  // worker thread only
+  bool stop = false;
+  int64_t next_ticket = 1;
+  int64_t committed = 0;  // estimated bytes of admitted requests
+  rkhsba_server_stats stats{};
+  std::string err;
+
+  void finish(const std::shared_ptr<Req>& q, int status, const std::string& msg) {
+    std::lock_guard<std::mutex> lk(mu);
+    q->status = status;
+    q->err = msg;
+    q->done = true;
+    q->t_done = Clock::now();
+    if (status == RKHSBA_OK) stats.completed += 1;
+    else stats.failed += 1;
+    if (q->admitted) committed -= q->est_bytes;
+    q->admitted = false;
+    cv_done.notify_all();
+  }
+
+  void retire(const std::shared_ptr<Req>& q) {
+    Problem* p = eng->problem(q->prob);
+    int status = RKHSBA_OK;
+    std::string msg;
+    try {
+      q->loss.assign(q->n_iter + 1, 0.0);
+      q->pairs.assign(q->n_iter + 1, 0.0);
+      eng->download_poses(p, q->poses.data());
+      eng->read_history(p, q->n_iter + 1, q->loss.data(), q->pairs.data());
+      if (eng->read_status(p) != 0) {
+        status = RKHSBA_ENOTPD;
+        msg = "Cholesky pivot not positive in a Gauss-Newton step";
+      }
+    } catch (const Fail& f) {
+      status = f.code;
+      msg = f.msg;
+    }
+    eng->remove_problem(q->prob);
+    q->prob = -1;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (double v : q->pairs) stats.pair_evals += (int64_t)v;
+    }
+    finish(q, status, msg);
+  }
+
+  void run() {
+    (void)hipSetDevice(opt.device);
+    for (;;) {
+      std::vector<std::shared_ptr<Req>> admit;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        if (active.empty()) cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        if (stop) break;
+        while (!queue.empty() && (int)(active.size() + admit.size()) < opt.max_active) {
+          const std::shared_ptr<Req>& q = queue.front();
+          const bool idle = active.empty() && admit.empty();
+          if (!idle && committed + q->est_bytes > opt.hbm_budget_bytes) break;
+          committed += q->est_bytes;
+          q->admitted = true;
+          admit.push_back(q);
+          queue.pop_front();
+        }
+      }
+      for (auto& q : admit) {
+        try {
+          q->prob = eng->add_problem_auto(q->par, q->K, q->n_points.data(), q->xyz.data(), q->feat_kind, q->D,
+                                          q->feats.data(), q->is_device != 0);
+          Problem* p = eng->problem(q->prob);
+          eng->upload_poses(p, q->poses.data());
+          eng->reset_state(p);
+          q->t_admit = Clock::now();
+          active.push_back(q);
+        } catch (const Fail& f) {
+          if (q->prob >= 0) eng->remove_problem(q->prob);
+          q->prob = -1;
+          finish(q, f.code, f.msg);
+        } catch (...) {
+          if (q->prob >= 0) eng->remove_problem(q->prob);
+          q->prob = -1;
+          finish(q, RKHSBA_EDEVICE, "unexpected exception at admission");
+        }
+      }
+      if (active.empty()) continue;
+      try {
+        std::vector<SetItem> items;
+        bool all_final = true;
+        for (auto& q : active) {
+          items.push_back(SetItem{eng->problem(q->prob), q->edges.data(), q->E, q->par.fixed_frame, q->n_iter});
+          all_final = all_final && q->evals == q->n_iter;
+        }
+        eng->prepare(lay, items);
+        if (all_final) {
+          eng->evaluate(lay, MODE_LOSS);
+          eng->loss_only(lay);
+        } else {
+          eng->iterate(lay, 1);
+        }
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          stats.batch_iterations += 1;
+          stats.max_active = std::max<int64_t>(stats.max_active, (int64_t)active.size());
+          stats.peak_device_bytes = std::max<int64_t>(stats.peak_device_bytes, eng->device_bytes());
+        }
+        std::vector<std::shared_ptr<Req>> still;
+        for (auto& q : active) {
+          q->evals += 1;
+          if (q->evals > q->n_iter) retire(q);
+          else still.push_back(q);
+        }
+        active.swap(still);
+      } catch (const Fail& f) {
+        for (auto& q : active) {
+          if (q->prob >= 0) eng->remove_problem(q->prob);
+          q->prob = -1;
+          finish(q, f.code, f.msg);
+        }
+        active.clear();
+      }
+    }
+    // shutting down: drop what is active or queued
+    for (auto& q : active) {
+      if (q->prob >= 0) eng->remove_problem(q->prob);
+      q->prob = -1;
+      finish(q, RKHSBA_ESTATE, "server shut down");
+    }
+    active.clear();
+    std::deque<std::shared_ptr<Req>> rest;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      rest.swap(queue);
+    }
+    for (auto& q : rest) finish(q, RKHSBA_ESTATE, "server shut down");
+  }
+};
+
+extern "C" {
+
+void rkhsba_server_default_options(rkhsba_server_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->device = 0;
+  o->feat_kind = RKHSBA_FEAT_CLASS_ID;
+  o->D = 0;
+  o->max_active = 64;
+  o->hbm_budget_bytes = 0;
+  o->pass_points = 16;
+  o->use_graphs = 1;
+  o->stream = nullptr;
+}
+
+int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
+  if (!out) return RKHSBA_EINVAL;
+  *out = nullptr;
+  if (!opt || opt->max_active < 1 || opt->hbm_budget_bytes < 0 ||
+      (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) ||
+      (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && opt->feat_kind != RKHSBA_FEAT_DENSE_F32) ||
+      (opt->feat_kind == RKHSBA_FEAT_DENSE_F32 && (opt->D < 1 || opt->D > kMaxDense)))
+    return RKHSBA_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
+  if (hipSetDevice(opt->device) != hipSuccess) return RKHSBA_EDEVICE;
+  rkhsba_server* s = new (std::nothrow) rkhsba_server();
+  if (!s) return RKHSBA_ENOMEM;
+  s->opt = *opt;
+  if (s->opt.hbm_budget_bytes == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      delete s;
+      return RKHSBA_EDEVICE;
+    }
+    s->opt.hbm_budget_bytes = (int64_t)(0.8 * (double)free_b);
+  }
+  if (opt->stream) {
+    s->stream = static_cast<hipStream_t>(opt->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return RKHSBA_EDEVICE;
+    }
+    s->own_stream = true;
+  }
+  s->eng.reset(new (std::nothrow) Engine(opt->device, s->stream, opt->pass_points, 0));
+  if (!s->eng) {
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return RKHSBA_ENOMEM;
+  }
+  s->eng->use_graphs = opt->use_graphs != 0;
+  try {
+    s->worker = std::thread([s] { s->run(); });
+  } catch (...) {
+    s->eng.reset();
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return RKHSBA_EDEVICE;
+  }
+  *out = s;
+  return RKHSBA_OK;
+}
+
+void rkhsba_server_destroy(rkhsba_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->opt.device);
+  (void)hipStreamSynchronize(s->stream);
+  s->lay.drop_graph();
+  s->eng.reset();
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int rkhsba_server_submit(rkhsba_server* s, const rkhsba_request* r, int64_t* ticket) {
+  if (!s || !r || !ticket) return RKHSBA_EINVAL;
+  *ticket = 0;
+  if (r->K < 1 || !r->n_points || !r->xyz || !r->feats || !r->poses || r->E < 1 || !r->edges || r->n_iter < 0 ||
+      r->feat_kind != s->opt.feat_kind || (r->feat_kind == RKHSBA_FEAT_DENSE_F32 && r->D != s->opt.D) ||
+      !(r->ell > 0.0) || !(r->cutoff_factor > 0.0) || r->cell_subdiv < 0 || r->cell_subdiv > 8 ||
+      r->fixed_frame < 0 || r->fixed_frame >= r->K)
+    return RKHSBA_EINVAL;
+  for (int e = 0; e < r->E; ++e) {
+    const int m = r->edges[2 * e], n = r->edges[2 * e + 1];
+    if (m < 0 || n < 0 || m >= r->K || n >= r->K || m == n) return RKHSBA_EINVAL;
+  }
+  for (int f = 0; f < r->K; ++f)
+    if (r->n_points[f] < 1 || !r->xyz[f] || !r->feats[f]) return RKHSBA_EINVAL;
+  try {
+    auto q = std::make_shared<Req>();
+    q->par.ell = r->ell;
+    q->par.cutoff_factor = r->cutoff_factor;
+    q->par.sigma = r->sigma;
+    q->par.damping_rel = r->damping_rel;
+    q->par.fixed_frame = r->fixed_frame;
+    q->par.clamp_negative_c = r->clamp_negative_c;
+    q->par.cell_subdiv = r->cell_subdiv;
+    q->K = r->K;
+    q->E = r->E;
+    q->n_iter = r->n_iter;
+    q->is_device = r->is_device;
+    q->feat_kind = r->feat_kind;
+    q->D = r->feat_kind == RKHSBA_FEAT_CLASS_ID ? 0 : r->D;
+    q->n_points.assign(r->n_points, r->n_points + r->K);
+    q->xyz.assign(r->xyz, r->xyz + r->K);
+    q->feats.assign(r->feats, r->feats + r->K);
+    q->poses.assign(r->poses, r->poses + 12 * (size_t)r->K);
+    q->edges.assign(r->edges, r->edges + 2 * (size_t)r->E);
+    q->est_bytes = s->eng->estimate_problem_bytes(r->K, r->n_points, r->E);
+    q->t_submit = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->stop) return RKHSBA_ESTATE;
+      q->ticket = s->next_ticket++;
+      s->tickets[q->ticket] = q;
+      s->queue.push_back(q);
+      s->stats.submitted += 1;
+    }
+    s->cv_work.notify_one();
+    *ticket = q->ticket;
+    return RKHSBA_OK;
+  } catch (const std::bad_alloc&) {
+    return RKHSBA_ENOMEM;
+  }
+}
+
+int rkhsba_server_wait(rkhsba_server* s, int64_t ticket, double timeout_s, double* poses_out, double* loss_per_iter,
+                       int64_t* pairs_per_iter, double* latency_s, double* queue_s) {
+  if (!s) return RKHSBA_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return RKHSBA_EINVAL;
+  std::shared_ptr<Req> q = it->second;
+  auto ready = [&] { return q->done; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    return RKHSBA_EBUSY;
+  }
+  s->tickets.erase(it);
+  if (q->status == RKHSBA_OK || q->status == RKHSBA_ENOTPD) {
+    if (poses_out) std::copy(q->poses.begin(), q->poses.end(), poses_out);
+    for (int i = 0; i <= q->n_iter && i < (int)q->loss.size(); ++i) {
+      if (loss_per_iter) loss_per_iter[i] = q->loss[i];
+      if (pairs_per_iter) pairs_per_iter[i] = (int64_t)q->pairs[i];
+    }
+  }
+  if (latency_s) *latency_s = std::chrono::duration<double>(q->t_done - q->t_submit).count();
+  if (queue_s)
+    *queue_s = q->t_admit.time_since_epoch().count() == 0
+                   ? 0.0
+                   : std::chrono::duration<double>(q->t_admit - q->t_submit).count();
+  s->err = q->err;
+  return q->status;
+}
+
+int rkhsba_server_stats_get(rkhsba_server* s, rkhsba_server_stats* out) {
+  if (!s || !out) return RKHSBA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->queued = (int64_t)s->queue.size();
+  return RKHSBA_OK;
+}
+
+const char* rkhsba_server_last_error(const rkhsba_server* s) { return s ? s->err.c_str() : "null server"; }
+
+}  // extern "C"

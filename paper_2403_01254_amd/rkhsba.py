@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "librkhsba.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ESTATE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 FEAT_CLASS_ID, FEAT_DENSE_F32, FEAT_DENSE_BF16, FEAT_DENSE_FP8 = 0, 1, 2, 3
 _FEAT_NAMES = {"class": FEAT_CLASS_ID, "dense": FEAT_DENSE_F32, "bf16": FEAT_DENSE_BF16, "fp8": FEAT_DENSE_FP8}
 
@@ -44,6 +44,47 @@ class Options(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("feat_kind", ctypes.c_int),
+        ("D", ctypes.c_int),
+        ("max_active", ctypes.c_int),
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("pass_points", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int),
+        ("n_points", ctypes.POINTER(ctypes.c_int64)),
+        ("xyz", ctypes.POINTER(ctypes.c_void_p)),
+        ("feats", ctypes.POINTER(ctypes.c_void_p)),
+        ("is_device", ctypes.c_int),
+        ("feat_kind", ctypes.c_int),
+        ("D", ctypes.c_int),
+        ("poses", ctypes.POINTER(ctypes.c_double)),
+        ("E", ctypes.c_int),
+        ("edges", ctypes.POINTER(ctypes.c_int32)),
+        ("ell", ctypes.c_double),
+        ("cutoff_factor", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("damping_rel", ctypes.c_double),
+        ("fixed_frame", ctypes.c_int),
+        ("clamp_negative_c", ctypes.c_int),
+        ("cell_subdiv", ctypes.c_int),
+        ("n_iter", ctypes.c_int),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "queued", "batch_iterations",
+                                               "max_active", "peak_device_bytes", "pair_evals")]
 
 
 _lib = None
@@ -76,6 +117,14 @@ def lib():
                                       ctypes.POINTER(vp), ctypes.c_int, _dp, ctypes.c_int, _i32p, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
         L.rkhsba_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
+        L.rkhsba_server_default_options.argtypes = [ctypes.POINTER(ServerOptions)]
+        L.rkhsba_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ServerOptions)]
+        L.rkhsba_server_destroy.argtypes = [vp]
+        L.rkhsba_server_submit.argtypes = [vp, ctypes.POINTER(Request), _i64p]
+        L.rkhsba_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.c_double, _dp, _dp, _i64p, _dp, _dp]
+        L.rkhsba_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.rkhsba_server_last_error.argtypes = [vp]
+        L.rkhsba_server_last_error.restype = ctypes.c_char_p
         L.rkhsba_profile_enable.argtypes = [vp, ctypes.c_int]
         L.rkhsba_profile_read.argtypes = [vp, ctypes.c_int, _dp, _i64p, ctypes.c_int]
         _lib = L
@@ -261,6 +310,90 @@ class Context:
         n = ctypes.c_int64()
         self._check(lib().rkhsba_profile_read(self._h, int(stage), ctypes.byref(ms), ctypes.byref(n), int(reset)))
         return ms.value, n.value
+
+
+class Server:
+    """Request loop with continuous batching (rkhsba_server_*): submit() queues a whole
+    solve and returns a ticket at once; wait() returns its result."""
+
+    def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=16,
+                 use_graphs=True, stream=None):
+        o = ServerOptions()
+        lib().rkhsba_server_default_options(ctypes.byref(o))
+        o.device = device
+        o.feat_kind = _FEAT_NAMES[feat_kind] if isinstance(feat_kind, str) else int(feat_kind)
+        o.D, o.max_active, o.hbm_budget_bytes = D, max_active, hbm_budget_bytes
+        o.pass_points, o.use_graphs = pass_points, int(bool(use_graphs))
+        o.stream = ctypes.c_void_p(int(stream)) if stream else None
+        self.opts = o
+        self._h = ctypes.c_void_p()
+        rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))
+        if rc != OK:
+            raise RkhsbaError(rc, "rkhsba_server_create failed")
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().rkhsba_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, points, feats, poses, edges, ell, n_iter, cutoff_factor=3.0, sigma=1.0, damping_rel=1e-10,
+               fixed_frame=0, clamp_negative_c=True, cell_subdiv=0):
+        """points/feats as for Context.build_neighbors (host arrays or device tensors, kept
+        alive here until wait()).  Returns the ticket."""
+        K, kind, D, n, xarr, farr, dev, keep = Context._frames(points, feats, self.opts.feat_kind)
+        p = np.ascontiguousarray(poses, dtype=np.float64).reshape(K, 12)
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        r = Request()
+        r.K, r.n_points, r.xyz, r.feats, r.is_device = K, _p(n, ctypes.c_int64), xarr, farr, dev
+        r.feat_kind, r.D = kind, D
+        r.poses, r.E, r.edges = _p(p), len(e), _p(e, ctypes.c_int32)
+        r.ell, r.cutoff_factor, r.sigma, r.damping_rel = ell, cutoff_factor, sigma, damping_rel
+        r.fixed_frame, r.clamp_negative_c, r.cell_subdiv, r.n_iter = fixed_frame, int(bool(clamp_negative_c)), \
+            cell_subdiv, n_iter
+        t = ctypes.c_int64()
+        rc = lib().rkhsba_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
+        if rc != OK:
+            raise RkhsbaError(rc, "rkhsba_server_submit rejected the request")
+        self._keep[t.value] = (keep, n, xarr, farr, points, feats, K, n_iter)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """(poses (K,12), loss per evaluation, pairs per evaluation, latency s, queued s)."""
+        keep = self._keep[ticket]
+        K, n_iter = keep[6], keep[7]
+        poses = np.zeros((K, 12))
+        lpi = np.zeros(n_iter + 1)
+        ppi = np.zeros(n_iter + 1, dtype=np.int64)
+        lat, qs = ctypes.c_double(), ctypes.c_double()
+        rc = lib().rkhsba_server_wait(self._h, ticket, float(timeout), _p(poses), _p(lpi), _p(ppi, ctypes.c_int64),
+                                      ctypes.byref(lat), ctypes.byref(qs))
+        if rc == EBUSY:
+            raise TimeoutError(f"request {ticket} not finished within {timeout} s")
+        del self._keep[ticket]
+        if rc != OK:
+            raise RkhsbaError(rc, lib().rkhsba_server_last_error(self._h).decode())
+        return poses, lpi, ppi, lat.value, qs.value
+
+    def stats(self):
+        st = ServerStats()
+        rc = lib().rkhsba_server_stats_get(self._h, ctypes.byref(st))
+        if rc != OK:
+            raise RkhsbaError(rc, "rkhsba_server_stats_get failed")
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
 
 
 PROF_BUILD, PROF_BIN, PROF_PAIRS, PROF_PAIRS_LOSS, PROF_FINALIZE, PROF_SOLVE = range(6)

@@ -1,0 +1,106 @@
+"""Request loop (continuous batching) through the C ABI: each request's
+result is the same alone and in a mix of overlapping requests, equals the
+single-problem context's, and matches the FP64 oracle within the pose and
+loss tolerances; admission by memory footprint and argument checks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from helpers import REL_TOL, ROT_TOL, TRANS_TOL, pose_errors
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_2403_01254_amd import rkhsba
+    rkhsba.lib()
+    return rkhsba
+
+
+@pytest.fixture(scope="module")
+def requests():
+    # mixed frame counts, point counts and length scales (0.08 m and 0.3 m)
+    return [scenes.request(s, k_range=(2, 5), n_range=(1500, 4000), n_iter=3) for s in range(5)]
+
+
+def submit(srv, p):
+    return srv.submit(p.points, p.feats, p.init_poses, p.edges, p.ell, p.n_iter)
+
+
+def test_alone_and_in_mix_agree(rk, requests):
+    say("[server] " + "; ".join(p.recipe[:60] for p in requests))
+    with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
+        alone = [srv.wait(submit(srv, p), timeout=120) for p in requests]
+        assert srv.stats()["max_active"] == 1
+        tickets = [submit(srv, p) for p in requests]       # all in flight together
+        mix = [srv.wait(t, timeout=120) for t in tickets]
+        st = srv.stats()
+        say(f"[server] stats {st}")
+        assert st["max_active"] >= 2 and st["completed"] == 2 * len(requests) and st["failed"] == 0
+    for p, a, m in zip(requests, alone, mix):
+        np.testing.assert_array_equal(a[0], m[0])          # poses
+        np.testing.assert_array_equal(a[1][:-1], m[1][:-1])  # loss entering each step
+        np.testing.assert_allclose(a[1][-1], m[1][-1], rtol=1e-6)
+        np.testing.assert_array_equal(a[2], m[2])          # pair counts
+
+
+def test_served_matches_context_and_oracle(rk, requests):
+    with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
+        tickets = [submit(srv, p) for p in requests]
+        served = [srv.wait(t, timeout=120) for t in tickets]
+    for p, (poses, lpi, ppi, lat, qs) in zip(requests, served):
+        ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, cell_subdiv=0)
+        ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+        cposes, clpi, cppi = ctx.gn_step(p.init_poses, p.edges, p.n_iter)
+        np.testing.assert_array_equal(poses, cposes)
+        np.testing.assert_array_equal(ppi, cppi)
+        np.testing.assert_allclose(lpi, clpi, rtol=1e-6)
+        op = oracle.Problem.from_scene(p)
+        oposes, olpi = oracle.gn(op, p.init_poses, p.edges, p.n_iter, membership=oracle.MEMBER_FP32_RULE)
+        rot, tr = pose_errors(poses, oposes)
+        say(f"[server] {p.recipe[:50]}: latency {lat * 1e3:.1f} ms (queued {qs * 1e3:.1f}), rot {rot.max():.2g} "
+            f"trans {tr.max():.2g}")
+        assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+        np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+
+
+def test_admission_by_footprint(rk, requests):
+    """With a budget smaller than any request, requests run one at a time
+    (a request is always admitted when nothing is active), with the same
+    results."""
+    with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
+        ref = [srv.wait(submit(srv, p), timeout=120) for p in requests[:3]]
+    with rk.Server(feat_kind="dense", D=20, max_active=8, hbm_budget_bytes=1) as srv:
+        tickets = [submit(srv, p) for p in requests[:3]]
+        got = [srv.wait(t, timeout=120) for t in tickets]
+        st = srv.stats()
+    assert st["max_active"] == 1 and st["completed"] == 3
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a[0], b[0])
+        assert b[4] >= 0.0
+
+
+def test_invalid_requests(rk, requests):
+    p = requests[0]
+    with rk.Server(feat_kind="dense", D=20) as srv:
+        with pytest.raises(rk.RkhsbaError) as e:
+            srv.submit(p.points, p.feats, p.init_poses, [[0, 0]], p.ell, 2)
+        assert e.value.code == rk.EINVAL
+        with pytest.raises(rk.RkhsbaError) as e:
+            srv.submit(p.points, [f[:, :10] for f in p.feats], p.init_poses, p.edges, p.ell, 2)
+        assert e.value.code == rk.EINVAL
+        with pytest.raises(rk.RkhsbaError) as e:
+            srv.submit(p.points, p.feats, p.init_poses, p.edges, -1.0, 2)
+        assert e.value.code == rk.EINVAL
+        # the server still works after rejected submissions
+        poses, lpi, ppi, lat, qs = srv.wait(submit(srv, p), timeout=120)
+        assert np.all(np.isfinite(poses))
