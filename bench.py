@@ -63,6 +63,125 @@ def load_traffic():
     return t.get("bytes_per_launch")
 
 
+def _make_request(seed):
+    import scenes
+    return scenes.request(seed)
+
+
+def start_request_generation(n, workers):
+    """Generates the serving requests in worker processes (spawned, so the
+    parent's GPU state is never inherited); returns the pending futures."""
+    import concurrent.futures
+    import multiprocessing
+    if n <= 0:
+        return None, []
+    ex = concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn"))
+    return ex, [ex.submit(_make_request, 1000 + i) for i in range(n)]
+
+
+def percentile_ms(lat, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(lat) * 1e3, q)) if len(lat) else None
+
+
+def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
+    """Seeded Poisson stream of whole solves: capacity of the one-at-a-time
+    FP32 form, then, at 0.5x and 0.9x of it, latency percentiles and
+    throughput of the continuous-batching request loop and of the
+    one-at-a-time form fed the same arrivals."""
+    import threading
+    import numpy as np
+    dev = torch.device("cuda:0")
+    staged = []
+    for p in reqs:
+        staged.append(([torch.from_numpy(x).to(dev) for x in p.points], [torch.from_numpy(f).to(dev) for f in p.feats]))
+    torch.cuda.synchronize()
+    D = reqs[0].D
+    ctxs = {}
+
+    def ctx_for(ell):
+        if ell not in ctxs:
+            ctxs[ell] = rkhsba.Context(ell=ell, cell_subdiv=0)
+        return ctxs[ell]
+
+    def solve_one(i):
+        p = reqs[i]
+        c = ctx_for(p.ell)
+        c.build_neighbors(staged[i][0], staged[i][1], p.feat_kind)
+        return c.gn_step(p.init_poses, p.edges, p.n_iter)
+
+    solve_one(0)  # warm-up (library load, first allocations)
+    t0 = time.perf_counter()
+    seq = [solve_one(i) for i in range(len(reqs))]
+    cap_s = time.perf_counter() - t0
+    capacity = len(reqs) / cap_s
+    seq_pairs = sum(int(r[2].sum()) for r in seq)
+    log(f"[serving] one-at-a-time capacity {capacity:.2f} solves/s ({len(reqs)} requests in {cap_s:.2f} s)")
+    rng = np.random.default_rng(seed)
+    runs = []
+    max_pose_diff = 0.0
+    for frac in (0.5, 0.9):
+        qps = frac * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
+        arrivals -= arrivals[0]
+        # continuous batching
+        srv = rkhsba.Server(feat_kind="dense", D=D, max_active=64)
+        tickets = [None] * len(reqs)
+        start = time.perf_counter() + 0.05
+
+        def submitter():
+            for i, p in enumerate(reqs):
+                dt = start + arrivals[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(staged[i][0], staged[i][1], p.init_poses, p.edges, p.ell, p.n_iter)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat, out = [], []
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                time.sleep(1e-4)
+            r = srv.wait(tickets[i])
+            out.append(r)
+            lat.append(r[3])
+        th.join()
+        end = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        for r, q in zip(out, seq):
+            max_pose_diff = max(max_pose_diff, float(np.abs(r[0] - q[0]).max()))
+        served = {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+                  "solves_per_s": len(reqs) / (end - start), "pair_evals_per_s": st["pair_evals"] / (end - start),
+                  "max_active": st["max_active"], "batch_iterations": st["batch_iterations"],
+                  "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out]))}
+        # one at a time, same arrivals
+        lat1 = []
+        start1 = time.perf_counter()
+        for i in range(len(reqs)):
+            dt = start1 + arrivals[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            solve_one(i)
+            lat1.append(time.perf_counter() - (start1 + arrivals[i]))
+        end1 = time.perf_counter()
+        single = {"p50_ms": percentile_ms(lat1, 50), "p99_ms": percentile_ms(lat1, 99),
+                  "solves_per_s": len(reqs) / (end1 - start1), "pair_evals_per_s": seq_pairs / (end1 - start1)}
+        log(f"[serving] {qps:.2f} req/s: batched p50 {served['p50_ms']:.1f} ms p99 {served['p99_ms']:.1f} ms "
+            f"({served['solves_per_s']:.2f} solves/s, up to {served['max_active']} active); one-at-a-time p50 "
+            f"{single['p50_ms']:.1f} ms p99 {single['p99_ms']:.1f} ms")
+        runs.append({"qps": qps, "load": frac, "batched": served, "one_at_a_time": single})
+    for c in ctxs.values():
+        c.close()
+    return {"requests": len(reqs), "capacity_one_at_a_time_solves_per_s": capacity,
+            "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
+            "max_pose_diff_batched_vs_one_at_a_time": max_pose_diff,
+            "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
+                      "depth-camera trajectory (p = 1/2), 20-class Dirichlet(0.3) soft labels (D = 20), ell in "
+                      "{0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs resident in HBM; Poisson "
+                      "arrivals at 0.5x and 0.9x of the measured one-at-a-time capacity"}
+
+
 def cpu_baseline(p, n_edges):
     import oracle
     op = oracle.Problem.from_scene(p)
@@ -92,6 +211,8 @@ def main():
                     help="odometry is the headline configuration; the others are for kernel studies")
     ap.add_argument("--cpu-edges", type=int, default=8, help="frame pairs in the CPU oracle sample (0: skip)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests in the serving measurement (0: skip); the serving workload's full stream is 512")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -99,6 +220,8 @@ def main():
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+
+    gen_pool, gen_futures = start_request_generation(args.serving_requests, workers=8)
 
     import numpy as np
     import torch
@@ -213,6 +336,11 @@ def main():
             "mean_launch_ms": mean_launch_s * 1e3,
         },
     }
+    if gen_futures:
+        reqs = [f.result() for f in gen_futures]
+        gen_pool.shutdown()
+        log(f"[bench] serving: {len(reqs)} requests generated")
+        result["serving"] = serving_benchmark(reqs, rkhsba, torch, log)
     rank = int(os.environ.get("RANK", "0"))
     if rank == 0 and args.cpu_edges > 0:
         log(f"[bench] CPU oracle on {args.cpu_edges} frame pairs ...")

@@ -164,7 +164,7 @@ struct SetLayout {
   uint64_t gen = 0;                 // pool generation the tables were built for
   int n_prob = 0, n_max = 0, E = 0;
   int64_t n_entries = 0;
-  int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, bin_bits = 3, fin_per_thread = 1;
+  int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, bin_bits = 3;
   bool clamp = false;
   DBuf<EdgeInfo> d_edges;
   DBuf<int64_t> d_ent_off;

@@ -605,13 +605,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
 
   const int P = pass_points;
   int E_total = 0;
-  int64_t entries_total = 0;
-  for (const SetItem& it : items) {
-    E_total += it.E;
-    for (int e = 0; e < it.E; ++e) entries_total += it.p->frames[it.edges[2 * e]].n;
-  }
-  // finalisation: about 4096 blocks, up to 16 entries per thread
-  const int fin_pt = (int)std::min<int64_t>(16, std::max<int64_t>(1, entries_total / ((int64_t)kFinThreads * 4096)));
+  for (const SetItem& it : items) E_total += it.E;
   std::vector<EdgeInfo> info(E_total);
   std::vector<int64_t> ent(E_total);
   std::vector<int32_t> poff(E_total), foff(E_total);
@@ -660,7 +654,9 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       I.pass_off = (int32_t)passes;
       I.n_pass = (I.n_src + P - 1) / P;
       I.fin_off = (int32_t)fins;
-      I.n_fin = (I.n_src + kFinThreads * fin_pt - 1) / (kFinThreads * fin_pt);
+      // finalisation split from the edge's own size: 1..16 entries per thread
+      I.fin_pt = std::min(16, std::max(1, I.n_src / 16384));
+      I.n_fin = (I.n_src + kFinThreads * I.fin_pt - 1) / (kFinThreads * I.fin_pt);
       I.prob = (int32_t)pi;
       ent[e_glob] = entries;
       poff[e_glob] = I.pass_off;
@@ -758,7 +754,6 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   lay.n_entries = entries;
   lay.n_pass_total = (int)passes;
   lay.n_fin_total = (int)fins;
-  lay.fin_per_thread = fin_pt;
   lay.n_edge_tiles = (int)tiles.size();
   lay.bin_bits = bin_bits;
   lay.clamp = clamp;
@@ -817,7 +812,6 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   fa.n_entries = lay.n_entries;
   fa.E = lay.E;
   fa.n_fin_total = lay.n_fin_total;
-  fa.per_thread = lay.fin_per_thread;
   hipEvent_t t2 = prof_begin();
   RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, st));
   RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, xf_.p, lay.E, mode, edge_out_.p, st));

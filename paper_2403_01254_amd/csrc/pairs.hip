@@ -239,7 +239,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
 //   A, B, x cross Bm, q cross B, A x, A x x^T (6), A q, Szz (6), x S^T (9)
 // (plus the pair count) and to expand the sums into the 91 values once per
 // edge.  Sums run in FP64: per thread over its entries, then per block in a
-// fixed order, then per edge over the blocks in order (deterministic).
+// fixed order, then per edge over the blocks in order; the split into
+// blocks depends only on the edge's source count, so an edge's sums do not
+// depend on what else is evaluated with it.
 constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
               kStXS = 28, kStCnt = 37;
 
@@ -253,12 +255,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   const EdgeXf X = a.xf[e];
   const float4* __restrict__ src_pts = a.pts + a.frames[ed.m].pt_off;
   const int64_t end = ed.ent_off + ed.n_src;
-  const int64_t base = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads * a.per_thread;
+  const int64_t base = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads * ed.fin_pt;
   const int64_t N = a.n_entries;
   double st[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) st[k] = 0.0;
-  for (int j = 0; j < a.per_thread; ++j) {
+  for (int j = 0; j < ed.fin_pt; ++j) {
     const int64_t entry = base + (int64_t)j * kFinThreads + threadIdx.x;
     if (entry >= end) break;
     const double cnt = (double)a.cnt[entry];  // per-entry or per-pass pair counts

@@ -42,6 +42,7 @@ struct EdgeInfo {
   int32_t n_pass;
   int32_t fin_off;   // first finalize block of the edge
   int32_t n_fin;
+  int32_t fin_pt;    // entries per finalize thread (a block covers kFinThreads * fin_pt entries)
   int32_t prob;      // problem of the edge within the evaluated set (constants, system)
 };
 
@@ -150,7 +151,6 @@ struct FinArgs {
   int64_t n_entries;
   int32_t E;
   int32_t n_fin_total;
-  int32_t per_thread;     // entries per thread: a finalisation block covers kFinThreads * per_thread entries
 };
 constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
 constexpr int kFinThreads = 256;

@@ -37,6 +37,8 @@ def submit(srv, p):
 
 
 def test_alone_and_in_mix_agree(rk, requests):
+    # plus one request with frames large enough for several entries per finalisation thread
+    requests = requests + [scenes.request(7, k_range=(3, 3), n_range=(40000, 60000), n_iter=2)]
     say("[server] " + "; ".join(p.recipe[:60] for p in requests))
     with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
         alone = [srv.wait(submit(srv, p), timeout=120) for p in requests]
