@@ -201,8 +201,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--pass-points", type=int, default=16)
-    ap.add_argument("--cell-subdiv", type=int, default=8)
+    ap.add_argument("--pass-points", type=int, default=0, help="0: chosen at the build (or by the autotuner)")
+    ap.add_argument("--cell-subdiv", type=int, default=0, help="0: chosen at the build (or by the autotuner)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep --cell-subdiv/--pass-points instead of the autotuner's choice (made during warm-up)")
     ap.add_argument("--no-graphs", action="store_true", help="issue every launch eagerly (no HIP graph replay)")

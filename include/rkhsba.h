@@ -80,10 +80,12 @@ typedef struct {
   int fixed_frame;       /* gauge: this frame is not moved (default 0, Sec. V-A) */
   int clamp_negative_c;  /* use max(c_ij, 0) for dense features (default 1) */
   int device;            /* HIP device ordinal (default 0) */
-  int cell_subdiv;       /* voxel cells per truncation radius, 1..8, or 0 = chosen at each build from the
+  int cell_subdiv;       /* voxel cells per truncation radius, 1..8; 0 = chosen at each build from the
                             points per occupied r_c-cube (the table rkhsba_autotune fills, else a default
-                            rule) (default 8) */
-  int pass_points;       /* source points sharing one candidate sweep: 16, 32 or 64 (default 16) */
+                            rule) (default 0) */
+  int pass_points;       /* source points per candidate sweep: 16, 32 or 64 share one walk over the cells
+                            around their box; 1 = every point walks its own cells (sparse frames); 0 =
+                            chosen with cell_subdiv (default 0) */
   int moment_path;       /* 16-point sweep, Gauss-Newton moments accumulated on 0 = library choice,
                             1 = vector ALU, 2 = matrix cores (default 0) */
   int use_graphs;        /* 1 = capture one Gauss-Newton iteration in a HIP graph and replay it (default 1;
@@ -140,13 +142,13 @@ int rkhsba_gn_step(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* e
 
 /* Autotuner for the launch configuration.  Builds the frames (arguments as
  * rkhsba_build_neighbors) with every cell size in {1,2,3,4,6,8} cells per r_c
- * and every sweep size in {16,32,64} source points, times `trials` normal-
+ * and every sweep size in {1,16,32,64} source points, times `trials` normal-
  * equation evaluations of each at `poses` / `edges` (HIP events on the
  * context's stream, after one warm-up), and leaves the context built with the
  * fastest pair; outputs (nullable): that pair and its time per evaluation in
  * ms.  The choice is also recorded, for this feature layout and the frames'
  * points per occupied r_c-cube, in a process-wide table that builds with
- * cell_subdiv = 0 consult.  Results (pair sets, F, b, H) do not depend on the
+ * cell_subdiv = 0 / pass_points = 0 consult.  Results (pair sets, F, b, H) do not depend on the
  * configuration beyond FP32 summation order. */
 int rkhsba_autotune(rkhsba_ctx* ctx, int K, const int64_t* n_points, const float* const* xyz, int feat_kind, int D,
                     const void* const* feats, int is_device, const double* poses, int E, const int32_t* edges,
@@ -212,7 +214,7 @@ typedef struct {
   int D;                    /* dense feature dimension of every request */
   int max_active;           /* requests iterating together (default 64) */
   int64_t hbm_budget_bytes; /* admission limit on the estimated footprints (0: 80% of free memory) */
-  int pass_points;          /* sweep size (default 16) */
+  int pass_points;          /* sweep pass size for every request (0: chosen per request, default) */
   int use_graphs;           /* replay a batch iteration from a HIP graph while the active set is unchanged */
   void* stream;             /* hipStream_t for all work; NULL = a stream owned by the server */
 } rkhsba_server_options;

@@ -66,6 +66,7 @@ ProbParams params_of(const rkhsba_options& o) {
   p.fixed_frame = o.fixed_frame;
   p.clamp_negative_c = o.clamp_negative_c;
   p.cell_subdiv = o.cell_subdiv;
+  p.pass_points = o.pass_points;
   return p;
 }
 
@@ -83,8 +84,8 @@ void rkhsba_default_options(rkhsba_options* o) {
   o->fixed_frame = 0;
   o->clamp_negative_c = 1;
   o->device = 0;
-  o->cell_subdiv = 8;
-  o->pass_points = 16;
+  o->cell_subdiv = 0;
+  o->pass_points = 0;
   o->moment_path = 0;
   o->use_graphs = 1;
   o->stream = nullptr;
@@ -97,7 +98,9 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   if (!(opt->ell > 0.0) || !std::isfinite(opt->ell) || !(opt->cutoff_factor > 0.0) ||
       !std::isfinite(opt->cutoff_factor) || !std::isfinite(opt->sigma) || !(opt->damping_rel >= 0.0) ||
       opt->cell_subdiv < 0 || opt->cell_subdiv > 8 ||
-      (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) || opt->fixed_frame < 0 ||
+      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
+       opt->pass_points != 64) ||
+      opt->fixed_frame < 0 ||
       opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1)
     return RKHSBA_EINVAL;
   int ndev = 0;
@@ -118,7 +121,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
     }
     c->own_stream = true;
   }
-  c->eng.reset(new (std::nothrow) Engine(opt->device, c->stream, opt->pass_points, opt->moment_path));
+  c->eng.reset(new (std::nothrow) Engine(opt->device, c->stream, opt->moment_path));
   if (!c->eng) {
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -178,16 +181,16 @@ int rkhsba_autotune(rkhsba_ctx* c, int K, const int64_t* n_points, const float* 
       }
     } cleanup{ev, g, prof};
     const int subdivs[] = {1, 2, 3, 4, 6, 8};
-    const int passes[] = {16, 32, 64};
+    const int passes[] = {1, 16, 32, 64};
     double best = 1e300, occ_r = 0.0;
     int bestS = 0, bestP = 0;
     for (int P : passes) {
-      g.pass_points = P;
       for (int S : subdivs) {
         if (c->prob >= 0) g.remove_problem(c->prob);
         c->prob = -1;
         ProbParams par = params_of(c->opt);
         par.cell_subdiv = S;
+        par.pass_points = P;
         c->prob = g.add_problem(par, K, n_points, xyz, feat_kind, D, feats, is_device != 0);
         Problem* p = g.problem(c->prob);
         if (S == 1) occ_r = p->occupancy;
@@ -209,10 +212,9 @@ int rkhsba_autotune(rkhsba_ctx* c, int K, const int64_t* n_points, const float* 
       }
     }
     // leave the context on the best configuration
-    g.pass_points = bestP;
     c->opt.pass_points = bestP;
     c->opt.cell_subdiv = bestS;
-    g.tune_record(occ_r, bestS);
+    g.tune_record(occ_r, bestS, bestP);
     c->occ_r = occ_r;
     g.remove_problem(c->prob);
     c->prob = -1;
@@ -228,7 +230,7 @@ int rkhsba_get_config(rkhsba_ctx* c, int* cell_subdiv, int* pass_points, double*
   return guarded(c, [&]() -> int {
     Problem* p = resident(c);
     if (cell_subdiv) *cell_subdiv = p->par.cell_subdiv;
-    if (pass_points) *pass_points = c->eng->pass_points;
+    if (pass_points) *pass_points = p->par.pass_points;
     if (occupancy) *occupancy = p->occupancy_r > 0.0 ? p->occupancy_r : c->occ_r;
     return RKHSBA_OK;
   });

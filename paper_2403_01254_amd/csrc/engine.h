@@ -123,7 +123,8 @@ struct ProbParams {
   double damping_rel = 1e-10;
   int fixed_frame = 0;
   int clamp_negative_c = 1;
-  int cell_subdiv = 8;
+  int cell_subdiv = 8;   // cells per r_c, 1..8 (0: chosen at the build)
+  int pass_points = 16;  // sweep pass size: 1 (per-point walks), 16, 32, 64 (0: chosen at the build)
 };
 
 // One resident problem: its frames, their voxel structures and poses.
@@ -165,13 +166,18 @@ struct SetLayout {
   int n_prob = 0, n_max = 0, E = 0;
   int64_t n_entries = 0;
   int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, bin_bits = 3;
+  struct Group {
+    int pass_points, pass0, n_pass;
+  };
+  std::vector<Group> groups;        // contiguous runs of the pass table, one sweep launch each
   bool clamp = false;
   DBuf<EdgeInfo> d_edges;
   DBuf<int64_t> d_ent_off;
-  DBuf<int32_t> d_pass_off, d_fin_off;
+  DBuf<int32_t> d_fin_off;
   DBuf<SortTile> d_etiles;
   DBuf<SortSeg> d_esegs;
   DBuf<KConst> d_kcs;
+  DBuf<PassInfo> d_passes;
   DBuf<ProbSys> d_sys;
   DBuf<int32_t> d_blk_start, d_blk_list, d_vec_start, d_vec_list;
   std::vector<ProbSys> sys;         // host copy
@@ -187,14 +193,13 @@ struct SetLayout {
 
 class Engine {
  public:
-  Engine(int device, hipStream_t stream, int pass_points, int moment_path);
+  Engine(int device, hipStream_t stream, int moment_path);
   ~Engine();
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
 
   int device;
   hipStream_t st;
-  int pass_points;
   int moment_path;
   bool use_graphs = true;
 
@@ -209,8 +214,9 @@ class Engine {
   // of a first build with cells of edge r_c (tuned table, else a default rule).
   int add_problem_auto(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
                        int D, const void* const* feats, bool is_device);
-  int choose_subdiv(double occupancy_r) const;
-  void tune_record(double occupancy_r, int subdiv);  // process-wide tuned table
+  // (cell_subdiv, pass_points) for frames with this many points per occupied r_c-cube
+  std::pair<int, int> choose_config(double occupancy_r) const;
+  void tune_record(double occupancy_r, int subdiv, int pass_points);  // process-wide tuned table
   void remove_problem(int id);
   Problem* problem(int id);
   int n_problems() const { return (int)probs_.size(); }

@@ -133,8 +133,7 @@ SetLayout::~SetLayout() { drop_graph(); }
 
 // ---------------------------------------------------------------- Engine
 
-Engine::Engine(int dev, hipStream_t stream, int pp, int mp)
-    : device(dev), st(stream), pass_points(pp), moment_path(mp) {}
+Engine::Engine(int dev, hipStream_t stream, int mp) : device(dev), st(stream), moment_path(mp) {}
 
 Engine::~Engine() {
   for (auto& s : stages)
@@ -244,7 +243,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
   if (kind != RKHSBA_FEAT_CLASS_ID)
     RK_REQUIRE(Din >= 1 && Din <= kMaxDense, RKHSBA_EINVAL, "dense feature dimension must be in [1, 64]");
   RK_REQUIRE(par.ell > 0.0 && std::isfinite(par.ell) && par.cutoff_factor > 0.0 && std::isfinite(par.cutoff_factor) &&
-                 par.cell_subdiv >= 1 && par.cell_subdiv <= 8 && std::isfinite(par.sigma) && par.damping_rel >= 0.0,
+                 par.cell_subdiv >= 1 && par.cell_subdiv <= 8 && std::isfinite(par.sigma) && par.damping_rel >= 0.0 &&
+                 (par.pass_points == 1 || par.pass_points == 16 || par.pass_points == 32 || par.pass_points == 64),
              RKHSBA_EINVAL, "invalid problem parameters");
   const int Dk = kind == RKHSBA_FEAT_CLASS_ID ? 0 : Din;
   if (probs_.empty()) {
@@ -471,7 +471,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::vector<int>, int> g_tune;  // (feature kind, Dp, pass points, occupancy bucket) -> cell_subdiv
+// (feature kind, Dp, occupancy bucket) -> (cell_subdiv, pass_points)
+std::map<std::vector<int>, std::pair<int, int>> g_tune;
 }  // namespace
 
 int occupancy_bucket(double occ) {
@@ -479,36 +480,44 @@ int occupancy_bucket(double occ) {
   return (int)std::min(40.0, std::max(0.0, b));
 }
 
-void Engine::tune_record(double occ_r, int subdiv) {
+void Engine::tune_record(double occ_r, int subdiv, int pp) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[{feat_kind, Dp, pass_points, occupancy_bucket(occ_r)}] = subdiv;
+  g_tune[{feat_kind, Dp, occupancy_bucket(occ_r)}] = {subdiv, pp};
 }
 
-int Engine::choose_subdiv(double occ_r) const {
+std::pair<int, int> Engine::choose_config(double occ_r) const {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find({feat_kind, Dp, pass_points, occupancy_bucket(occ_r)});
+    auto it = g_tune.find({feat_kind, Dp, occupancy_bucket(occ_r)});
     if (it != g_tune.end()) return it->second;
   }
-  // Untuned default: finer cells as the points per truncation-radius cube grow.
-  if (occ_r < 3.0) return 1;
-  if (occ_r < 12.0) return 2;
-  if (occ_r < 48.0) return 4;
-  return 8;
+  // Untuned default: finer cells and shared 16-point walks as the points per
+  // truncation-radius cube grow; per-point walks for sparse frames.
+  if (occ_r < 3.0) return {1, 1};
+  if (occ_r < 12.0) return {2, 16};
+  if (occ_r < 48.0) return {4, 16};
+  return {8, 16};
 }
 
 int Engine::add_problem_auto(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
                              int Din, const void* const* feats, bool is_device) {
-  if (par.cell_subdiv != 0) return add_problem(par, K, n_points, xyz, kind, Din, feats, is_device);
+  if (par.cell_subdiv != 0 && par.pass_points != 0)
+    return add_problem(par, K, n_points, xyz, kind, Din, feats, is_device);
   ProbParams probe = par;
   probe.cell_subdiv = 1;  // cells of one truncation radius: occupancy probe
+  if (probe.pass_points == 0) probe.pass_points = 16;
   const int id = add_problem(probe, K, n_points, xyz, kind, Din, feats, is_device);
   const double occ = problem(id)->occupancy;
-  const int S = choose_subdiv(occ);
-  if (S == 1) return id;
-  remove_problem(id);
+  const std::pair<int, int> cfg = choose_config(occ);
   ProbParams fine = par;
-  fine.cell_subdiv = S;
+  if (fine.cell_subdiv == 0) fine.cell_subdiv = cfg.first;
+  if (fine.pass_points == 0) fine.pass_points = cfg.second;
+  if (fine.cell_subdiv == 1) {
+    Problem* p = problem(id);
+    p->par.pass_points = fine.pass_points;  // same grid; only the sweep choice changes
+    return id;
+  }
+  remove_problem(id);
   const int id2 = add_problem(fine, K, n_points, xyz, kind, Din, feats, is_device);
   problem(id2)->occupancy_r = occ;
   return id2;
@@ -589,7 +598,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     }
     ensure_history(it.p, it.n_iter);
   }
-  std::vector<int32_t> key{pass_points};  // (the finalisation split follows from the items)
+  std::vector<int32_t> key;  // (pass sizes and finalisation splits follow from the problems)
   std::vector<int> ids;
   for (const SetItem& it : items) {
     ids.push_back(it.p->id);
@@ -603,15 +612,16 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   if (key == lay.edge_key && !lay.sys.empty()) return;
   lay.drop_graph();
 
-  const int P = pass_points;
   int E_total = 0;
   for (const SetItem& it : items) E_total += it.E;
   std::vector<EdgeInfo> info(E_total);
   std::vector<int64_t> ent(E_total);
-  std::vector<int32_t> poff(E_total), foff(E_total);
+  std::vector<int32_t> foff(E_total);
   std::vector<SortTile> tiles;
   std::vector<SortSeg> segs(E_total);
   std::vector<KConst> kcs(items.size());
+  const int group_order[4] = {16, 1, 32, 64};
+  std::vector<PassInfo> gpass[4];
   std::vector<ProbSys> sys(items.size());
   std::vector<int32_t> bstart_all, blist, vstart_all, vlist;
   int64_t entries = 0, passes = 0, fins = 0, h_total = 0, v_total = 0;
@@ -651,15 +661,27 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       I.n = (int32_t)(p->slot0 + n);
       I.ent_off = entries;
       I.n_src = p->frames[m].n;
-      I.pass_off = (int32_t)passes;
+      const int pp = p->par.pass_points;
+      const int P = pp == 1 ? 64 : pp;  // per-point walks: 64 sources (one per lane) per pass
+      const int gi = pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : 3;
+      I.pass_size = pp;
       I.n_pass = (I.n_src + P - 1) / P;
       I.fin_off = (int32_t)fins;
       // finalisation split from the edge's own size: 1..16 entries per thread
       I.fin_pt = std::min(16, std::max(1, I.n_src / 16384));
       I.n_fin = (I.n_src + kFinThreads * I.fin_pt - 1) / (kFinThreads * I.fin_pt);
       I.prob = (int32_t)pi;
+      for (int k = 0; k < I.n_pass; ++k) {
+        PassInfo Q;
+        Q.entry0 = entries + (int64_t)k * P;
+        Q.src_off = p->frames[m].pt_off;
+        Q.e = e_glob;
+        Q.count = std::min(P, I.n_src - k * P);
+        Q.tgt = I.n;
+        Q.prob = (int32_t)pi;
+        gpass[gi].push_back(Q);
+      }
       ent[e_glob] = entries;
-      poff[e_glob] = I.pass_off;
       foff[e_glob] = I.fin_off;
       segs[e_glob].start = entries;
       segs[e_glob].count = I.n_src;
@@ -696,11 +718,18 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   if (vlist.empty()) vlist.push_back(0);
   RK_HIP(lay.d_edges.reserve(E_total));
   RK_HIP(lay.d_ent_off.reserve(E_total));
-  RK_HIP(lay.d_pass_off.reserve(E_total));
   RK_HIP(lay.d_fin_off.reserve(E_total));
   RK_HIP(lay.d_etiles.reserve(tiles.size()));
   RK_HIP(lay.d_esegs.reserve(E_total));
+  std::vector<PassInfo> pinfo;
+  std::vector<SetLayout::Group> groups;
+  for (int gi = 0; gi < 4; ++gi) {
+    if (gpass[gi].empty()) continue;
+    groups.push_back(SetLayout::Group{group_order[gi], (int)pinfo.size(), (int)gpass[gi].size()});
+    pinfo.insert(pinfo.end(), gpass[gi].begin(), gpass[gi].end());
+  }
   RK_HIP(lay.d_kcs.reserve(items.size()));
+  RK_HIP(lay.d_passes.reserve(pinfo.size()));
   RK_HIP(lay.d_sys.reserve(items.size()));
   RK_HIP(lay.d_blk_start.reserve(bstart_all.size()));
   RK_HIP(lay.d_blk_list.reserve(blist.size()));
@@ -711,11 +740,11 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   };
   up(lay.d_edges.p, info.data(), sizeof(EdgeInfo) * E_total);
   up(lay.d_ent_off.p, ent.data(), sizeof(int64_t) * E_total);
-  up(lay.d_pass_off.p, poff.data(), sizeof(int32_t) * E_total);
   up(lay.d_fin_off.p, foff.data(), sizeof(int32_t) * E_total);
   up(lay.d_etiles.p, tiles.data(), sizeof(SortTile) * tiles.size());
   up(lay.d_esegs.p, segs.data(), sizeof(SortSeg) * E_total);
   up(lay.d_kcs.p, kcs.data(), sizeof(KConst) * kcs.size());
+  up(lay.d_passes.p, pinfo.data(), sizeof(PassInfo) * pinfo.size());
   up(lay.d_sys.p, sys.data(), sizeof(ProbSys) * sys.size());
   up(lay.d_blk_start.p, bstart_all.data(), sizeof(int32_t) * bstart_all.size());
   up(lay.d_blk_list.p, blist.data(), sizeof(int32_t) * blist.size());
@@ -753,6 +782,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   lay.E = E_total;
   lay.n_entries = entries;
   lay.n_pass_total = (int)passes;
+  lay.groups = std::move(groups);
   lay.n_fin_total = (int)fins;
   lay.n_edge_tiles = (int)tiles.size();
   lay.bin_bits = bin_bits;
@@ -787,17 +817,22 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   pa.mom = mom_.p;
   pa.cnt = cnt_.p;
   pa.kcs = lay.d_kcs.p;
+  pa.passes = lay.d_passes.p;
   pa.n_entries = lay.n_entries;
   pa.E = lay.E;
-  pa.n_pass_total = lay.n_pass_total;
+
   pa.kc.Dp = Dp;
   pa.kc.clamp = lay.clamp ? 1 : 0;
   const int feat_path = feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
   hipEvent_t t1 = prof_begin();
-  if (pass_points == 16)
-    RK_HIP(launch_sweep16(pa, lay.d_pass_off.p, mode, feat_path, moment_path == 2, st));
-  else
-    RK_HIP(launch_pairs(pa, lay.d_pass_off.p, mode, feat_path, pass_points, st));
+  for (const SetLayout::Group& gr : lay.groups) {
+    pa.pass0 = gr.pass0;
+    pa.n_pass = gr.n_pass;
+    if (gr.pass_points == 16)
+      RK_HIP(launch_sweep16(pa, mode, feat_path, moment_path == 2, st));
+    else
+      RK_HIP(launch_pairs(pa, mode, feat_path, gr.pass_points, st));
+  }
   prof_end(mode == MODE_NORMAL ? RKHSBA_PROF_PAIRS : RKHSBA_PROF_PAIRS_LOSS, t1);
   FinArgs fa{};
   fa.pts = pts();

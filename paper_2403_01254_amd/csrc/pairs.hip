@@ -108,20 +108,25 @@ __global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts
 
 // ---------------------------------------------------------------- candidate sweep
 
-template <int MODE, int FEAT, int G, int DP>
-__global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* __restrict__ pass_off) {
+// Passes of 64/G source points.  SHARED: the pass's G candidate streams walk
+// the cells around the box of all its transformed source points, and every
+// source tests every candidate of the walk.  LOCAL (G = 1): each lane walks
+// the cells around its own transformed point only (for sparse frames, where
+// a shared box would be much larger than one point's neighbourhood).
+template <int MODE, int FEAT, int G, int DP, bool LOCAL>
+__global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
   constexpr int P = 64 / G;
   const int lane = threadIdx.x & 63;
   const int pass = (int)blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6);
-  if (pass >= a.n_pass_total) return;  // whole wavefront leaves; no block barrier below
-  const int e = upper_segment(pass_off, a.E, pass);
-  const EdgeInfo ed = a.edges[e];
-  const EdgeXf X = a.xf[e];
-  const FrameInfo Fm = a.frames[ed.m];
-  const FrameInfo Fn = a.frames[ed.n];
+  if (pass >= a.n_pass) return;  // whole wavefront leaves; no block barrier below
+  const PassInfo pi = a.passes[a.pass0 + pass];
+  const EdgeXf X = a.xf[pi.e];
+  const FrameInfo Fn = a.frames[pi.tgt];
+  const KConst kc = a.kcs[pi.prob];
   const int s = lane % P, g = lane / P;
-  const int64_t entry = ed.ent_off + (int64_t)(pass - ed.pass_off) * P + s;
-  bool valid = entry < ed.ent_off + ed.n_src;
+  const int64_t entry = pi.entry0 + s;
+  const bool in_range = s < pi.count;
+  bool valid = in_range;
   uint32_t src = 0;
   if (valid) {
     valid = a.keys[entry] != kInvalidKey;
@@ -131,11 +136,11 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
   uint32_t lbl = 0;
   float fs[DP > 0 ? DP : 1];
   if (valid) {
-    const float4 x = a.pts[Fm.pt_off + src];
+    const float4 x = a.pts[pi.src_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
     lbl = __float_as_uint(x.w);
     if constexpr (FEAT == FEAT_DENSE) {
-      const float4* f4 = reinterpret_cast<const float4*>(a.feat + (Fm.pt_off + src) * DP);
+      const float4* f4 = reinterpret_cast<const float4*>(a.feat + (pi.src_off + src) * DP);
 #pragma unroll
       for (int k = 0; k < DP / 4; ++k) {
         const float4 v = f4[k];
@@ -143,19 +148,20 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
       }
     }
   }
-  float3 lo, hi;
-  lo.x = wave_min(valid ? q.x : FLT_MAX);
-  lo.y = wave_min(valid ? q.y : FLT_MAX);
-  lo.z = wave_min(valid ? q.z : FLT_MAX);
-  hi.x = wave_max(valid ? q.x : -FLT_MAX);
-  hi.y = wave_max(valid ? q.y : -FLT_MAX);
-  hi.z = wave_max(valid ? q.z : -FLT_MAX);
-  if (lo.x > hi.x) {  // no valid source point in the pass (uniform)
-    if (g == 0 && entry < ed.ent_off + ed.n_src) a.cnt[entry] = 0u;
-    return;
+  float3 lo = q, hi = q;
+  if constexpr (!LOCAL) {
+    lo.x = wave_min(valid ? q.x : FLT_MAX);
+    lo.y = wave_min(valid ? q.y : FLT_MAX);
+    lo.z = wave_min(valid ? q.z : FLT_MAX);
+    hi.x = wave_max(valid ? q.x : -FLT_MAX);
+    hi.y = wave_max(valid ? q.y : -FLT_MAX);
+    hi.z = wave_max(valid ? q.z : -FLT_MAX);
+    if (lo.x > hi.x) {  // no valid source point in the pass (uniform)
+      if (g == 0 && in_range) a.cnt[entry] = 0u;
+      return;
+    }
   }
 
-  const KConst kc = a.kcs[ed.prob];
   const float rc2 = kc.rc2, alpha = kc.alpha;
   const bool clamp = a.kc.clamp != 0;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
@@ -164,6 +170,10 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
   const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
 
+  if (LOCAL && !valid) {  // empty walk for this lane
+    lo = make_float3(FLT_MAX, FLT_MAX, FLT_MAX);
+    hi = make_float3(-FLT_MAX, -FLT_MAX, -FLT_MAX);
+  }
   for_each_range(Fn, a.rows, a.xtab, kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0 + g; j < j1; j += G) {
       const float4 z = tp[j];
@@ -210,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a, const int32_t* _
       Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
     }
   }
-  if (g == 0 && entry < ed.ent_off + ed.n_src) a.cnt[entry] = valid ? cnt : 0u;
+  if (g == 0 && in_range) a.cnt[entry] = valid ? cnt : 0u;
   if (g == 0 && valid) {
     const int64_t N = a.n_entries;
     a.mom[entry] = A;
@@ -479,26 +489,25 @@ __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restr
 }
 
 template <int MODE, int FEAT>
-hipError_t dispatch_pairs(const PairArgs& a, const int32_t* pass_off, int G, int DP, hipStream_t st) {
-  const unsigned nb = (unsigned)((a.n_pass_total + 3) / 4);
+hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, int DP, hipStream_t st) {
+  const unsigned nb = (unsigned)((a.n_pass + 3) / 4);
   if (nb == 0) return hipSuccess;
-#define RKHSBA_LAUNCH(GG, DD) k_pairs<MODE, FEAT, GG, DD><<<nb, kThreads, 0, st>>>(a, pass_off)
+#define RKHSBA_LAUNCH(GG, DD, LL) k_pairs<MODE, FEAT, GG, DD, LL><<<nb, kThreads, 0, st>>>(a)
+#define RKHSBA_ANY(DD)                      \
+  if (local) RKHSBA_LAUNCH(1, DD, true);    \
+  else if (G == 1) RKHSBA_LAUNCH(1, DD, false); \
+  else if (G == 2) RKHSBA_LAUNCH(2, DD, false); \
+  else RKHSBA_LAUNCH(4, DD, false);
   if constexpr (FEAT == FEAT_CLASS) {
-    if (G == 1) RKHSBA_LAUNCH(1, 0);
-    else if (G == 2) RKHSBA_LAUNCH(2, 0);
-    else RKHSBA_LAUNCH(4, 0);
+    RKHSBA_ANY(0)
   } else {
-#define RKHSBA_DENSE(GG)                        \
-  if (DP <= 8) RKHSBA_LAUNCH(GG, 8);            \
-  else if (DP <= 16) RKHSBA_LAUNCH(GG, 16);     \
-  else if (DP <= 24) RKHSBA_LAUNCH(GG, 24);     \
-  else if (DP <= 32) RKHSBA_LAUNCH(GG, 32);     \
-  else RKHSBA_LAUNCH(GG, 64);
-    if (G == 1) { RKHSBA_DENSE(1) }
-    else if (G == 2) { RKHSBA_DENSE(2) }
-    else { RKHSBA_DENSE(4) }
-#undef RKHSBA_DENSE
+    if (DP <= 8) { RKHSBA_ANY(8) }
+    else if (DP <= 16) { RKHSBA_ANY(16) }
+    else if (DP <= 24) { RKHSBA_ANY(24) }
+    else if (DP <= 32) { RKHSBA_ANY(32) }
+    else { RKHSBA_ANY(64) }
   }
+#undef RKHSBA_ANY
 #undef RKHSBA_LAUNCH
   return hipGetLastError();
 }
@@ -522,15 +531,15 @@ hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const Edge
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
-                        hipStream_t st) {
-  const int G = 64 / pass_points;
+hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, hipStream_t st) {
+  const bool local = pass_points == 1;
+  const int G = local ? 1 : 64 / pass_points;
   const int DP = a.kc.Dp;
   if (mode == MODE_LOSS)
-    return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_LOSS, FEAT_CLASS>(a, d_pass_off, G, DP, st)
-                                   : dispatch_pairs<MODE_LOSS, FEAT_DENSE>(a, d_pass_off, G, DP, st);
-  return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_NORMAL, FEAT_CLASS>(a, d_pass_off, G, DP, st)
-                                 : dispatch_pairs<MODE_NORMAL, FEAT_DENSE>(a, d_pass_off, G, DP, st);
+    return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_LOSS, FEAT_CLASS>(a, G, local, DP, st)
+                                   : dispatch_pairs<MODE_LOSS, FEAT_DENSE>(a, G, local, DP, st);
+  return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_NORMAL, FEAT_CLASS>(a, G, local, DP, st)
+                                 : dispatch_pairs<MODE_NORMAL, FEAT_DENSE>(a, G, local, DP, st);
 }
 
 hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st) {

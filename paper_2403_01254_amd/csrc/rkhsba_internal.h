@@ -38,12 +38,22 @@ struct EdgeInfo {
   int32_t m, n;      // source frame, target frame
   int64_t ent_off;   // first binning entry (one per source point)
   int32_t n_src;     // source points (= frame m's count)
-  int32_t pass_off;  // first candidate-sweep pass of the edge
+  int32_t pass_size; // source points per sweep pass of the edge (its problem's choice)
   int32_t n_pass;
   int32_t fin_off;   // first finalize block of the edge
   int32_t n_fin;
   int32_t fin_pt;    // entries per finalize thread (a block covers kFinThreads * fin_pt entries)
   int32_t prob;      // problem of the edge within the evaluated set (constants, system)
+};
+
+// One sweep pass: up to pass-size consecutive binning entries of one edge.
+struct PassInfo {
+  int64_t entry0;    // first binning entry
+  int64_t src_off;   // pool offset of the source frame's points
+  int32_t e;         // edge (set-wide)
+  int32_t count;     // entries in the pass
+  int32_t tgt;       // target frame slot
+  int32_t prob;      // problem (constants)
 };
 
 // Relative transform of an edge, T_nm = T_n^-1 T_m (FP64), written on device.
@@ -127,16 +137,18 @@ struct PairArgs {
   float* mom;             // moments, component-major: mom[c * n_entries + entry]
   uint32_t* cnt;          // in-radius pair count per entry
   const KConst* kcs;      // per problem of the set, indexed by EdgeInfo::prob
+  const PassInfo* passes; // per sweep pass
   int64_t n_entries;
   int32_t E;
-  int32_t n_pass_total;
+  int32_t pass0;          // first pass of this launch in the pass table
+  int32_t n_pass;         // passes of this launch
   KConst kc;              // set-wide: Dp and clamp (clamping is exact for non-negative features)
 };
-hipError_t launch_pairs(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, int pass_points,
-                        hipStream_t st);
+// Passes of pass_points sources: 1 = each lane walks its own point's cells,
+// 16 (launch_sweep16), 32, 64 = shared walk over the pass's box.
+hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, hipStream_t st);
 
-hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, bool matrix_moments,
-                          hipStream_t st);
+hipError_t launch_sweep16(const PairArgs& a, int mode, int feat_path, bool matrix_moments, hipStream_t st);
 
 struct FinArgs {
   const float4* pts;

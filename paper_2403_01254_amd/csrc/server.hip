@@ -213,7 +213,7 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->D = 0;
   o->max_active = 64;
   o->hbm_budget_bytes = 0;
-  o->pass_points = 16;
+  o->pass_points = 0;
   o->use_graphs = 1;
   o->stream = nullptr;
 }
@@ -222,7 +222,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
   if (!out) return RKHSBA_EINVAL;
   *out = nullptr;
   if (!opt || opt->max_active < 1 || opt->hbm_budget_bytes < 0 ||
-      (opt->pass_points != 16 && opt->pass_points != 32 && opt->pass_points != 64) ||
+      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
+       opt->pass_points != 64) ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && opt->feat_kind != RKHSBA_FEAT_DENSE_F32) ||
       (opt->feat_kind == RKHSBA_FEAT_DENSE_F32 && (opt->D < 1 || opt->D > kMaxDense)))
     return RKHSBA_EINVAL;
@@ -249,7 +250,7 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
     }
     s->own_stream = true;
   }
-  s->eng.reset(new (std::nothrow) Engine(opt->device, s->stream, opt->pass_points, 0));
+  s->eng.reset(new (std::nothrow) Engine(opt->device, s->stream, 0));
   if (!s->eng) {
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -307,6 +308,7 @@ int rkhsba_server_submit(rkhsba_server* s, const rkhsba_request* r, int64_t* tic
     q->par.fixed_frame = r->fixed_frame;
     q->par.clamp_negative_c = r->clamp_negative_c;
     q->par.cell_subdiv = r->cell_subdiv;
+    q->par.pass_points = s->opt.pass_points;
     q->K = r->K;
     q->E = r->E;
     q->n_iter = r->n_iter;

@@ -71,7 +71,7 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
 // candidates), and A, B, C follow exactly from M and v = q - ref:
 //   A = M_1, B = A v - M_u, C = A v v^T - v M_u^T - M_u v^T + M_uu.
 template <int MODE, int FEAT, int DP, bool CLAMP, bool MM>
-__global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __restrict__ pass_off) {
+__global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   constexpr int P = 16;
   constexpr int FS = DP > 0 ? DP + 1 : 1;  // LDS feature row stride (odd: conflict-free column reads)
   constexpr int PHS = 20;                  // LDS Phi row stride (conflict-free B-operand reads)
@@ -84,14 +84,15 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
 
   const int lane = threadIdx.x;
   const int pass = blockIdx.x;
-  const int e = upper_segment(pass_off, a.E, pass);
-  const EdgeInfo ed = a.edges[e];
-  const EdgeXf X = a.xf[e];
-  const FrameInfo Fm = a.frames[ed.m];
-  const FrameInfo Fn = a.frames[ed.n];
+  // every per-pass index comes from one table entry, so the loads below do not wait on each other
+  const PassInfo pi = a.passes[a.pass0 + pass];
+  const EdgeXf X = a.xf[pi.e];
+  const FrameInfo Fn = a.frames[pi.tgt];
+  const KConst kc = a.kcs[pi.prob];
   const int s = lane & 15, g = lane >> 4;
-  const int64_t entry = ed.ent_off + (int64_t)(pass - ed.pass_off) * P + s;
-  bool valid = entry < ed.ent_off + ed.n_src;
+  const int64_t entry = pi.entry0 + s;
+  const bool in_range = s < pi.count;
+  bool valid = in_range;
   uint32_t src = 0;
   if (valid) {
     valid = a.keys[entry] != kInvalidKey;
@@ -101,12 +102,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   uint32_t lbl = 0;
   float fsrc[DP > 0 ? DP / 4 : 1] = {};
   if (valid) {
-    const float4 x = a.pts[Fm.pt_off + src];
+    const float4 x = a.pts[pi.src_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
     lbl = __float_as_uint(x.w);
     if constexpr (FEAT == FEAT_DENSE) {
       // B operand of the MFMA: feature 4k + g of this lane's source point
-      const float* f = a.feat + (Fm.pt_off + src) * DP;
+      const float* f = a.feat + (pi.src_off + src) * DP;
 #pragma unroll
       for (int k = 0; k < DP / 4; ++k) fsrc[k] = f[4 * k + g];
     }
@@ -118,7 +119,6 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
   hi.x = uniform_f(wave_max(valid ? q.x : -FLT_MAX));
   hi.y = uniform_f(wave_max(valid ? q.y : -FLT_MAX));
   hi.z = uniform_f(wave_max(valid ? q.z : -FLT_MAX));
-  const bool in_range = entry < ed.ent_off + ed.n_src;
   if (!(lo.x <= hi.x)) {  // no valid source point in this pass (uniform)
     if (g == 0 && in_range) a.cnt[entry] = 0u;
     return;
@@ -130,7 +130,6 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
     for (int k = 10; k < 16; ++k) tphi[lane * PHS + k] = 0.f;  // unused Phi columns stay zero
   }
 
-  const KConst kc = a.kcs[ed.prob];
   const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
   const int z0 = max(clamp_floor_d(((double)lo.z - reach) * inv - Fn.org[2], -1, Fn.dim[2]), 0);
   const int z1 = min(clamp_floor_d(((double)hi.z + reach) * inv - Fn.org[2], -1, Fn.dim[2]), Fn.dim[2] - 1);
@@ -326,37 +325,36 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a, const int32_t* __r
 }
 
 template <int MODE, int FEAT, bool CLAMP, bool MM>
-hipError_t dispatch(const PairArgs& a, const int32_t* pass_off, int DP, hipStream_t st) {
-  const unsigned nb = (unsigned)a.n_pass_total;
+hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
+  const unsigned nb = (unsigned)a.n_pass;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, false, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    k_sweep<MODE, FEAT, 0, false, MM><<<nb, kLanes, 0, st>>>(a);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
-    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a, pass_off);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
   }
   return hipGetLastError();
 }
 
 template <int MODE, bool MM>
-hipError_t dispatch_mode(const PairArgs& a, const int32_t* pass_off, int feat_path, hipStream_t st) {
-  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false, MM>(a, pass_off, 0, st);
-  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true, MM>(a, pass_off, a.kc.Dp, st);
-  return dispatch<MODE, FEAT_DENSE, false, MM>(a, pass_off, a.kc.Dp, st);
+hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
+  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false, MM>(a, 0, st);
+  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true, MM>(a, a.kc.Dp, st);
+  return dispatch<MODE, FEAT_DENSE, false, MM>(a, a.kc.Dp, st);
 }
 
 }  // namespace
 
 // Tiled sweep for passes of 16 source points.
 // Loss-only sums stay on the VALU; Gauss-Newton moments on the VALU or the matrix cores.
-hipError_t launch_sweep16(const PairArgs& a, const int32_t* d_pass_off, int mode, int feat_path, bool matrix_moments,
-                          hipStream_t st) {
-  if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, d_pass_off, feat_path, st);
-  return matrix_moments ? dispatch_mode<MODE_NORMAL, true>(a, d_pass_off, feat_path, st)
-                        : dispatch_mode<MODE_NORMAL, false>(a, d_pass_off, feat_path, st);
+hipError_t launch_sweep16(const PairArgs& a, int mode, int feat_path, bool matrix_moments, hipStream_t st) {
+  if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, feat_path, st);
+  return matrix_moments ? dispatch_mode<MODE_NORMAL, true>(a, feat_path, st)
+                        : dispatch_mode<MODE_NORMAL, false>(a, feat_path, st);
 }
 
 }  // namespace rkhsba

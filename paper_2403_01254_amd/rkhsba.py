@@ -145,8 +145,8 @@ class Context:
     """One rkhsba context (one stream, one set of resident frames)."""
 
     def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
-                 fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 8,
-                 pass_points: int = 16, moment_path: int = 0, use_graphs: bool = True, stream=None):
+                 fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 0,
+                 pass_points: int = 0, moment_path: int = 0, use_graphs: bool = True, stream=None):
         o = default_options()
         o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel
         o.fixed_frame, o.clamp_negative_c, o.device = fixed_frame, int(bool(clamp_negative_c)), device
@@ -316,7 +316,7 @@ class Server:
     """Request loop with continuous batching (rkhsba_server_*): submit() queues a whole
     solve and returns a ticket at once; wait() returns its result."""
 
-    def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=16,
+    def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
                  use_graphs=True, stream=None):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))

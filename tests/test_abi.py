@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_default_options_and_create_without_device(lib):
     from paper_2403_01254_amd import rkhsba
     o = rkhsba.default_options()
-    assert o.ell == 0.1 and o.cutoff_factor == 3.0 and o.sigma == 1.0 and o.cell_subdiv == 8 and o.pass_points == 16
+    assert o.ell == 0.1 and o.cutoff_factor == 3.0 and o.sigma == 1.0 and o.cell_subdiv == 0 and o.pass_points == 0
     h = ctypes.c_void_p()
     bad = rkhsba.default_options()
     bad.ell = -1.0

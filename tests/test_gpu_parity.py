@@ -125,12 +125,12 @@ def test_gauss_newton_parity(rk, scene):
     np.testing.assert_array_equal(poses[0], p.init_poses[0])  # the fixed frame does not move
 
 
-@pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1)])
+@pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1), (1, 1), (1, 3)])
 def test_launch_shapes_agree(rk, pass_points, subdiv):
     """Every sweep shape and cell size gives the same pair count and, up to
     FP32 summation order, the same F, b and H."""
     p = scenes.odometry(4, n_frames=3, n_points=3000)
-    ref = make_ctx(rk, p)
+    ref = make_ctx(rk, p, pass_points=16, cell_subdiv=8)
     H0, b0, F0, n0 = ref.accumulate_normal_eqs(p.init_poses, p.edges)
     ctx = make_ctx(rk, p, pass_points=pass_points, cell_subdiv=subdiv)
     H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
@@ -277,8 +277,8 @@ def test_autotune_and_auto_cell_size(rk):
     H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
     assert n == n0 and abs(F - F0) <= REL_TOL * abs(F0)
     assert normwise_rel(b, b0) <= REL_TOL and normwise_rel(H, H0) <= REL_TOL
-    auto = make_ctx(rk, p, cell_subdiv=0, pass_points=P)
+    auto = make_ctx(rk, p, cell_subdiv=0, pass_points=0)
     aS, aP, aocc = auto.config()
-    assert aS == S and aocc == occ
+    assert (aS, aP) == (S, P) and aocc == occ
     H2, b2, F2, n2 = auto.accumulate_normal_eqs(p.init_poses, p.edges)
     assert n2 == n0 and normwise_rel(H2, H0) <= REL_TOL
