@@ -68,8 +68,10 @@ typedef enum {
 typedef enum {
   RKHSBA_FEAT_CLASS_ID = 0,    /* one-hot labels passed as uint16 class ids (N_m values) */
   RKHSBA_FEAT_DENSE_F32 = 1,   /* dense float32 rows (N_m * D values), D <= 64 */
-  RKHSBA_FEAT_DENSE_BF16 = 2,  /* as DENSE_F32, inner products on MFMA in bfloat16 */
-  RKHSBA_FEAT_DENSE_FP8 = 3    /* as DENSE_F32, inner products on MFMA in fp8 e4m3 */
+  RKHSBA_FEAT_DENSE_BF16 = 2,  /* float32 rows as DENSE_F32, stored rounded to bfloat16 (nearest even); inner
+                                  products on the matrix cores with FP32 accumulation; per-edge sums of the
+                                  normal-equation terms in FP32 with Kahan compensation */
+  RKHSBA_FEAT_DENSE_FP8 = 3    /* as DENSE_BF16 with OCP fp8 e4m3 storage (nearest even, saturating at 448) */
 } rkhsba_feat_kind;
 
 typedef struct {
@@ -210,7 +212,7 @@ typedef struct rkhsba_server rkhsba_server;
 
 typedef struct {
   int device;
-  int feat_kind;            /* feature kind of every request (CLASS_ID or DENSE_F32) */
+  int feat_kind;            /* feature kind of every request */
   int D;                    /* dense feature dimension of every request */
   int max_active;           /* requests iterating together (default 64) */
   int64_t hbm_budget_bytes; /* admission limit on the estimated footprints (0: 80% of free memory) */

@@ -80,14 +80,40 @@ __global__ __launch_bounds__(kThreads) void k_cell_keys(const int32_t* __restric
   vals[i] = (uint32_t)l;
 }
 
+// Round to nearest even: float32 -> bfloat16 (finite inputs).
+__device__ inline uint16_t f32_to_bf16(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Round to nearest even: float32 -> OCP fp8 e4m3 (bias 7, 3 mantissa bits,
+// subnormal step 2^-9), saturating at the largest finite value 448.
+__device__ inline uint8_t f32_to_e4m3(float v) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t a = u & 0x7fffffffu;
+  uint32_t code;
+  if (a >= 0x43e00000u) {          // |v| >= 448
+    code = 0x7eu;
+  } else if (a < 0x3c800000u) {    // |v| < 2^-6: multiples of 2^-9
+    code = (uint32_t)rintf(__uint_as_float(a) * 512.0f);  // 0..8; 8 is the smallest normal, 2^-6
+  } else {
+    const uint32_t r = (a + 0x7ffffu + ((a >> 20) & 1u)) >> 20;  // biased exponent and 3 mantissa bits, rounded
+    code = r - (120u << 3);                                       // exponent bias 127 -> 7
+    if (code > 0x7eu) code = 0x7eu;
+  }
+  return (uint8_t)(sign | code);
+}
+
 // Gathers points (and features) into key order.  pts.w carries the class id
-// bits for one-hot features.
+// bits for one-hot features; dense rows are stored in the feature path's
+// element type, zero padded to Dp.
 __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restrict__ xyz,
                                                      const void* const* __restrict__ feats, int feat_kind, int D,
                                                      int Dp, const FrameInfo* __restrict__ frames,
                                                      const int64_t* __restrict__ off, int K, int64_t n_total,
                                                      const uint32_t* __restrict__ sorted_vals,
-                                                     float4* __restrict__ pts, float* __restrict__ feat,
+                                                     float4* __restrict__ pts, void* __restrict__ feat,
                                                      int32_t* __restrict__ perm, int32_t* __restrict__ neg_flag) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n_total) return;
@@ -102,12 +128,13 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restr
   perm[p] = (int32_t)o;
   if (feat_kind != 0) {
     const float* src = (const float*)feats[f] + o * D;
-    float* dst = feat + p * Dp;
     bool neg = false;
     for (int k = 0; k < Dp; ++k) {
       const float v = k < D ? src[k] : 0.0f;
       neg = neg || v < 0.0f;
-      dst[k] = v;
+      if (feat_kind == 1) static_cast<float*>(feat)[p * Dp + k] = v;
+      else if (feat_kind == 2) static_cast<uint16_t*>(feat)[p * Dp + k] = f32_to_bf16(v);
+      else static_cast<uint8_t*>(feat)[p * Dp + k] = f32_to_e4m3(v);
     }
     if (neg) atomicOr(neg_flag, 1);  // some inner products may be negative
   }
@@ -226,7 +253,7 @@ hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, cons
 
 hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
-                         const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
+                         const uint32_t* d_sorted_vals, float4* d_pts, void* d_feat, int32_t* d_perm,
                          int32_t* d_neg_flag, hipStream_t st) {
   if (n_total > 0)
     k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, D, Dp, d_frames, d_in_off, K,

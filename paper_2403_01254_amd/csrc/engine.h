@@ -251,7 +251,8 @@ class Engine {
 
   // device views
   const float4* pts() const { return static_cast<const float4*>(points_.ptr(0)); }
-  const float* feat() const { return static_cast<const float*>(points_.ptr(3)); }
+  const void* feat() const { return points_.ptr(3); }
+  int64_t feat_row_bytes() const { return feat_kind <= 0 ? 4 : (int64_t)feat_elem_bytes(feat_kind) * Dp; }
   const int32_t* perm() const { return static_cast<const int32_t*>(points_.ptr(1)); }
   const uint32_t* keys() const { return static_cast<const uint32_t*>(points_.ptr(2)); }
   const int4* rows() const { return static_cast<const int4*>(rows_.ptr(0)); }

@@ -212,7 +212,7 @@ int64_t Engine::estimate_problem_bytes(int K, const int64_t* n_points, int E) co
     N += n_points[f];
     nmax = std::max(nmax, n_points[f]);
   }
-  const int64_t per_point = 28 + 4 * std::max(Dp, 1) + 12;  // pools + cell tables (typical occupancy)
+  const int64_t per_point = 28 + feat_row_bytes() + 12;  // pools + cell tables (typical occupancy)
   const int64_t per_entry = 16 + 40 + 4 + 3;                // binning keys/values (x2), moments, count, partials
   const int64_t n = 6 * (int64_t)K;
   return N * per_point + (int64_t)E * nmax * per_entry + 2 * n * n * 8 + (int64_t)E * 2 * kEdgeVals * 8;
@@ -238,8 +238,9 @@ void Engine::compute_constants(Problem* p) {
 int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
                         int Din, const void* const* feats, bool is_device) {
   RK_REQUIRE(K >= 1 && n_points && xyz && feats, RKHSBA_EINVAL, "K >= 1 and non-NULL n_points/xyz/feats required");
-  RK_REQUIRE(kind == RKHSBA_FEAT_CLASS_ID || kind == RKHSBA_FEAT_DENSE_F32, RKHSBA_EINVAL,
-             "feature kind not supported by this build (class ids or dense float32)");
+  RK_REQUIRE(kind == RKHSBA_FEAT_CLASS_ID || kind == RKHSBA_FEAT_DENSE_F32 || kind == RKHSBA_FEAT_DENSE_BF16 ||
+                 kind == RKHSBA_FEAT_DENSE_FP8,
+             RKHSBA_EINVAL, "unknown feature kind");
   if (kind != RKHSBA_FEAT_CLASS_ID)
     RK_REQUIRE(Din >= 1 && Din <= kMaxDense, RKHSBA_EINVAL, "dense feature dimension must be in [1, 64]");
   RK_REQUIRE(par.ell > 0.0 && std::isfinite(par.ell) && par.cutoff_factor > 0.0 && std::isfinite(par.cutoff_factor) &&
@@ -250,8 +251,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
   if (probs_.empty()) {
     feat_kind = kind;
     D = Dk;
-    Dp = kind == RKHSBA_FEAT_CLASS_ID ? 0 : dense_pad(Din);
-    points_.set_elem_bytes(3, sizeof(float) * (size_t)std::max(Dp, 1));
+    Dp = kind == RKHSBA_FEAT_CLASS_ID ? 0 : dense_pad(Din, kind);
+    points_.set_elem_bytes(3, kind == RKHSBA_FEAT_CLASS_ID ? 4 : (size_t)feat_elem_bytes(kind) * Dp);
   } else {
     RK_REQUIRE(kind == feat_kind && Dk == D, RKHSBA_EINVAL,
                "all resident problems share one feature kind and dimension");
@@ -383,7 +384,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     float4* d_pts = static_cast<float4*>(points_.ptr(0)) + p->pbase;
     int32_t* d_perm = static_cast<int32_t*>(points_.ptr(1)) + p->pbase;
     uint32_t* d_keys = static_cast<uint32_t*>(points_.ptr(2)) + p->pbase;
-    float* d_feat = static_cast<float*>(points_.ptr(3)) + p->pbase * std::max(Dp, 1);
+    void* d_feat = static_cast<uint8_t*>(points_.ptr(3)) + p->pbase * feat_row_bytes();
     int4* d_rows = static_cast<int4*>(rows_.ptr(0)) + p->rbase;
 
     // keys, segmented sort by frame, gather
@@ -414,7 +415,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
                              key_bits, st, &in_tmp));
     uint32_t* sk = in_tmp ? k2_.p : k1_.p;
     uint32_t* sv = in_tmp ? v2_.p : v1_.p;
-    RK_HIP(launch_gather(d_xyz_ptrs_.p, d_feat_ptrs_.p, kind == RKHSBA_FEAT_CLASS_ID ? 0 : 1, D, std::max(Dp, 1),
+    RK_HIP(launch_gather(d_xyz_ptrs_.p, d_feat_ptrs_.p, kind, D, std::max(Dp, 1),
                          d_bframes_.p, d_in_off_.p, K, N, sv, d_pts, d_feat, d_perm, minmax_.p + 6 * K + 1, st));
     RK_HIP(hipMemcpyAsync(d_keys, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, st));
 
@@ -455,7 +456,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     prof_collect();
     p->frames = std::move(fr);
     p->occupancy = (double)N / std::max<uint32_t>(n_cells, 1u);
-    p->resident_bytes = N * (int64_t)(28 + 4 * std::max(Dp, 1)) + p->n_rows * 16 + p->n_xt * 4 +
+    p->resident_bytes = N * (int64_t)(28 + feat_row_bytes()) + p->n_rows * 16 + p->n_xt * 4 +
                         (int64_t)K * (int64_t)(sizeof(FrameInfo) + 96) + 8;
   } catch (...) {
     release();
@@ -823,7 +824,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
 
   pa.kc.Dp = Dp;
   pa.kc.clamp = lay.clamp ? 1 : 0;
-  const int feat_path = feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
+  const int feat_path = feat_kind;
   hipEvent_t t1 = prof_begin();
   for (const SetLayout::Group& gr : lay.groups) {
     pa.pass0 = gr.pass0;
@@ -848,8 +849,9 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   fa.E = lay.E;
   fa.n_fin_total = lay.n_fin_total;
   hipEvent_t t2 = prof_begin();
-  RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, st));
-  RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, xf_.p, lay.E, mode, edge_out_.p, st));
+  const bool fp32_sums = feat_low_precision(feat_kind);
+  RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, fp32_sums, st));
+  RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, xf_.p, lay.E, mode, fp32_sums, edge_out_.p, st));
   prof_end(RKHSBA_PROF_FINALIZE, t2);
 }
 

@@ -139,14 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     const float4 x = a.pts[pi.src_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
     lbl = __float_as_uint(x.w);
-    if constexpr (FEAT == FEAT_DENSE) {
-      const float4* f4 = reinterpret_cast<const float4*>(a.feat + (pi.src_off + src) * DP);
-#pragma unroll
-      for (int k = 0; k < DP / 4; ++k) {
-        const float4 v = f4[k];
-        fs[4 * k] = v.x; fs[4 * k + 1] = v.y; fs[4 * k + 2] = v.z; fs[4 * k + 3] = v.w;
-      }
-    }
+    if constexpr (FEAT != FEAT_CLASS) load_feature_row<FEAT, DP>(a.feat, pi.src_off + src, fs);
   }
   float3 lo = q, hi = q;
   if constexpr (!LOCAL) {
@@ -168,7 +161,6 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
   uint32_t cnt = 0;
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
-  const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
 
   if (LOCAL && !valid) {  // empty walk for this lane
     lo = make_float3(FLT_MAX, FLT_MAX, FLT_MAX);
@@ -183,17 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
       if constexpr (FEAT == FEAT_CLASS) in = in && (__float_as_uint(z.w) == lbl);
       if (in) {
         float c = 1.0f;
-        if constexpr (FEAT == FEAT_DENSE) {
-          const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
-          float acc = 0.f;
-#pragma unroll
-          for (int k = 0; k < DP / 4; ++k) {
-            const float4 v = f4[k];
-            acc = fmaf(fs[4 * k], v.x, acc);
-            acc = fmaf(fs[4 * k + 1], v.y, acc);
-            acc = fmaf(fs[4 * k + 2], v.z, acc);
-            acc = fmaf(fs[4 * k + 3], v.w, acc);
-          }
+        if constexpr (FEAT != FEAT_CLASS) {
+          const float acc = dot_feature_row<FEAT, DP>(a.feat, Fn.pt_off + j, fs);
           c = clamp ? fmaxf(acc, 0.f) : acc;
         }
         const float w = c * __builtin_amdgcn_exp2f(-alpha * s2);
@@ -255,10 +238,31 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
 constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
               kStXS = 28, kStCnt = 37;
 
-template <int MODE>
+// Running sums: FP64, or FP32 with Kahan compensation (low-precision feature paths).
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  double s = 0.0;
+  __device__ void add(double v) { s += v; }
+  __device__ double value() const { return s; }
+};
+template <>
+struct Acc<float> {
+  float s = 0.f, c = 0.f;
+  __device__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ float value() const { return s; }
+};
+
+template <int MODE, typename T>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32_t* __restrict__ fin_off) {
   constexpr int NS = MODE == MODE_LOSS ? 2 : kFinStats;
-  __shared__ double sh[(kFinThreads / 64) * kFinStats];
+  __shared__ T sh[(kFinThreads / 64) * kFinStats];
   const int blk = blockIdx.x;
   const int e = upper_segment(fin_off, a.E, blk);
   const EdgeInfo ed = a.edges[e];
@@ -267,71 +271,79 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   const int64_t end = ed.ent_off + ed.n_src;
   const int64_t base = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads * ed.fin_pt;
   const int64_t N = a.n_entries;
-  double st[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) st[k] = 0.0;
+  Acc<T> st[NS];
+  double cnt_sum = 0.0;  // pair counts: integers, exact in FP64
   for (int j = 0; j < ed.fin_pt; ++j) {
     const int64_t entry = base + (int64_t)j * kFinThreads + threadIdx.x;
     if (entry >= end) break;
-    const double cnt = (double)a.cnt[entry];  // per-entry or per-pass pair counts
+    cnt_sum += (double)a.cnt[entry];  // per-entry or per-pass pair counts
     if constexpr (MODE == MODE_LOSS) {
-      st[1] += cnt;
-      if (a.keys[entry] != kInvalidKey) st[0] += (double)a.mom[entry];
+      if (a.keys[entry] != kInvalidKey) st[0].add((T)a.mom[entry]);
     } else {
-      st[kStCnt] += cnt;
       if (a.keys[entry] == kInvalidKey) continue;
-      const double A = a.mom[entry];
-      double B[3], C[6], x[3], q[3];
+      const T A = a.mom[entry];
+      T B[3], C[6], x[3], q[3];
       for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
       for (int k = 0; k < 6; ++k) C[k] = a.mom[(4 + k) * N + entry];
       const float4 p = src_pts[a.vals[entry]];
       const float3 qq = rule_q32(X, p.x, p.y, p.z);
       x[0] = p.x; x[1] = p.y; x[2] = p.z;
       q[0] = qq.x; q[1] = qq.y; q[2] = qq.z;
-      double Bm[3];
-      for (int r = 0; r < 3; ++r) Bm[r] = X.R[r] * B[0] + X.R[3 + r] * B[1] + X.R[6 + r] * B[2];
-      st[kStA] += A;
-      for (int k = 0; k < 3; ++k) st[kStB + k] += B[k];
-      st[kStXBm + 0] += x[1] * Bm[2] - x[2] * Bm[1];
-      st[kStXBm + 1] += x[2] * Bm[0] - x[0] * Bm[2];
-      st[kStXBm + 2] += x[0] * Bm[1] - x[1] * Bm[0];
-      st[kStQB + 0] += q[1] * B[2] - q[2] * B[1];
-      st[kStQB + 1] += q[2] * B[0] - q[0] * B[2];
-      st[kStQB + 2] += q[0] * B[1] - q[1] * B[0];
-      double Ax[3], S[3];
+      T R[9];
+      for (int k = 0; k < 9; ++k) R[k] = (T)X.R[k];
+      T Bm[3];
+      for (int r = 0; r < 3; ++r) Bm[r] = R[r] * B[0] + R[3 + r] * B[1] + R[6 + r] * B[2];
+      st[kStA].add(A);
+      for (int k = 0; k < 3; ++k) st[kStB + k].add(B[k]);
+      st[kStXBm + 0].add(x[1] * Bm[2] - x[2] * Bm[1]);
+      st[kStXBm + 1].add(x[2] * Bm[0] - x[0] * Bm[2]);
+      st[kStXBm + 2].add(x[0] * Bm[1] - x[1] * Bm[0]);
+      st[kStQB + 0].add(q[1] * B[2] - q[2] * B[1]);
+      st[kStQB + 1].add(q[2] * B[0] - q[0] * B[2]);
+      st[kStQB + 2].add(q[0] * B[1] - q[1] * B[0]);
+      T Ax[3], S[3];
       for (int k = 0; k < 3; ++k) {
         Ax[k] = A * x[k];
-        st[kStAx + k] += Ax[k];
-        st[kStAq + k] += A * q[k];
+        st[kStAx + k].add(Ax[k]);
+        st[kStAq + k].add(A * q[k]);
         S[k] = A * q[k] - B[k];
       }
-      st[kStAxx + 0] += Ax[0] * x[0]; st[kStAxx + 1] += Ax[0] * x[1]; st[kStAxx + 2] += Ax[0] * x[2];
-      st[kStAxx + 3] += Ax[1] * x[1]; st[kStAxx + 4] += Ax[1] * x[2]; st[kStAxx + 5] += Ax[2] * x[2];
+      st[kStAxx + 0].add(Ax[0] * x[0]); st[kStAxx + 1].add(Ax[0] * x[1]); st[kStAxx + 2].add(Ax[0] * x[2]);
+      st[kStAxx + 3].add(Ax[1] * x[1]); st[kStAxx + 4].add(Ax[1] * x[2]); st[kStAxx + 5].add(Ax[2] * x[2]);
       // Szz (upper triangle xx, xy, xz, yy, yz, zz), C in the same order
       const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         const int r = ri[k], c = ci[k];
-        st[kStSzz + k] += A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + C[k];
+        st[kStSzz + k].add(A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + C[k]);
       }
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) st[kStXS + 3 * r + c] += x[r] * S[c];
+        for (int c = 0; c < 3; ++c) st[kStXS + 3 * r + c].add(x[r] * S[c]);
     }
   }
   // block sum in a fixed order: wavefront shuffles, then the four waves
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int KC = MODE == MODE_LOSS ? 1 : kStCnt;  // slot of the pair count (summed in FP64 below)
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const double t = wave_sum(st[k]);
+    const T t = wave_sum(st[k].value());
     if (lane == 0) sh[w * NS + k] = t;
   }
+  __shared__ double shc[kFinThreads / 64];
+  const double wc = wave_sum(cnt_sum);  // all lanes take part in the shuffles
+  if (lane == 0) shc[w] = wc;
   __syncthreads();
   if (threadIdx.x < NS) {
-    double t = 0.0;
-    for (int ww = 0; ww < kFinThreads / 64; ++ww) t += sh[ww * NS + threadIdx.x];
-    a.partial[(int64_t)blk * kFinStats + threadIdx.x] = t;
+    Acc<T> t;
+    for (int ww = 0; ww < kFinThreads / 64; ++ww) t.add(sh[ww * NS + threadIdx.x]);
+    double v = (double)t.value();
+    if ((int)threadIdx.x == KC) {
+      v = 0.0;
+      for (int ww = 0; ww < kFinThreads / 64; ++ww) v += shc[ww];
+    }
+    a.partial[(int64_t)blk * kFinStats + threadIdx.x] = v;
   }
 }
 
@@ -342,33 +354,44 @@ __device__ inline int sym_index(int r, int c) {  // upper triangle of a 6x6, row
 
 // One block per edge: deterministic sum of the edge's finalisation blocks,
 // then the expansion of the 37 sums into F, b_m, b_n, H_mm, H_nn, H_mn.
+template <typename TT>
 __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ partial,
                                                     const EdgeInfo* __restrict__ edges,
                                                     const EdgeXf* __restrict__ xf, int mode,
                                                     double* __restrict__ edge_out) {
-  __shared__ double T[kFinStats];
+  __shared__ TT T[kFinStats];
+  __shared__ double n_pairs;
   const EdgeInfo ed = edges[blockIdx.x];
   const int ns = mode == MODE_LOSS ? 2 : kFinStats;
+  const int kc = ns - 1;  // pair-count slot
   for (int t = threadIdx.x; t < kFinStats; t += blockDim.x) {
-    double s = 0.0;
+    if (t == kc) {
+      double c = 0.0;
+      for (int b = 0; b < ed.n_fin; ++b) c += partial[(int64_t)(ed.fin_off + b) * kFinStats + t];
+      n_pairs = c;
+      T[t] = (TT)0;
+      continue;
+    }
+    Acc<TT> s;
     if (t < ns)
-      for (int b = 0; b < ed.n_fin; ++b) s += partial[(int64_t)(ed.fin_off + b) * kFinStats + t];
-    T[t] = s;
+      for (int b = 0; b < ed.n_fin; ++b) s.add((TT)partial[(int64_t)(ed.fin_off + b) * kFinStats + t]);
+    T[t] = s.value();
   }
   __syncthreads();
   double* out = edge_out + (int64_t)blockIdx.x * kEdgeVals;
   if (mode == MODE_LOSS) {
-    for (int k = threadIdx.x; k < kEdgeVals; k += blockDim.x) out[k] = k == 0 ? T[0] : k == 91 ? T[1] : 0.0;
+    for (int k = threadIdx.x; k < kEdgeVals; k += blockDim.x)
+      out[k] = k == 0 ? (double)T[0] : k == 91 ? n_pairs : 0.0;
     return;
   }
   if (threadIdx.x != 0) return;
   const EdgeXf X = xf[blockIdx.x];
-  double Rmn[3][3];
+  TT Rmn[3][3];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) Rmn[r][c] = X.R[3 * c + r];
-  const double A = T[kStA];
-  const double* B = T + kStB;
-  double v[kEdgeVals];
+  const TT A = T[kStA];
+  const TT* B = T + kStB;
+  TT v[kEdgeVals];
   for (int k = 0; k < kEdgeVals; ++k) v[k] = 0.0;
   v[0] = A;
   for (int r = 0; r < 3; ++r) {
@@ -377,28 +400,28 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
     v[7 + r] = -B[r];
     v[10 + r] = -T[kStQB + r];
   }
-  auto skew = [](const double* a, double (&M)[3][3]) {
+  auto skew = [](const TT* a, TT (&M)[3][3]) {
     M[0][0] = 0.0;   M[0][1] = -a[2]; M[0][2] = a[1];
     M[1][0] = a[2];  M[1][1] = 0.0;   M[1][2] = -a[0];
     M[2][0] = -a[1]; M[2][1] = a[0];  M[2][2] = 0.0;
   };
   const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
-  double Axx[3][3], Szz[3][3];
+  TT Axx[3][3], Szz[3][3];
   for (int k = 0; k < 6; ++k) {
     Axx[ri[k]][ci[k]] = Axx[ci[k]][ri[k]] = T[kStAxx + k];
     Szz[ri[k]][ci[k]] = Szz[ci[k]][ri[k]] = T[kStSzz + k];
   }
-  double S[3];
+  TT S[3];
   for (int k = 0; k < 3; ++k) S[k] = T[kStAq + k] - B[k];
-  double Hmm[6][6], Hnn[6][6], Hmn[6][6];
-  double Kx[3][3], Ks[3][3];
+  TT Hmm[6][6], Hnn[6][6], Hmn[6][6];
+  TT Kx[3][3], Ks[3][3];
   skew(T + kStAx, Kx);
   skew(S, Ks);
-  const double trx = Axx[0][0] + Axx[1][1] + Axx[2][2];
-  const double trs = Szz[0][0] + Szz[1][1] + Szz[2][2];
+  const TT trx = Axx[0][0] + Axx[1][1] + Axx[2][2];
+  const TT trs = Szz[0][0] + Szz[1][1] + Szz[2][2];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
-      const double I = r == c ? 1.0 : 0.0;
+      const TT I = r == c ? 1.0 : 0.0;
       Hmm[r][c] = A * I;
       Hmm[r][3 + c] = -Kx[r][c];
       Hmm[3 + r][c] = Kx[r][c];
@@ -409,7 +432,7 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
       Hnn[3 + r][3 + c] = trs * I - Szz[r][c];
     }
   // H_mn: [[-A R_mn, R_mn [S]], [-[A x] R_mn, sum [x] R_mn [S]]]
-  double RKs[3][3], KxR[3][3], XRS[3][3];
+  TT RKs[3][3], KxR[3][3], XRS[3][3];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
       RKs[r][c] = Rmn[r][0] * Ks[0][c] + Rmn[r][1] * Ks[1][c] + Rmn[r][2] * Ks[2][c];
@@ -419,16 +442,16 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
   // sum_p [x_p] R_mn [S_p] = sum_{i,j} (sum_p x_i S_j) [e_i] R_mn [e_j]
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
-      const double mij = T[kStXS + 3 * i + j];
-      double ei[3] = {0, 0, 0}, ej[3] = {0, 0, 0};
+      const TT mij = T[kStXS + 3 * i + j];
+      TT ei[3] = {0, 0, 0}, ej[3] = {0, 0, 0};
       ei[i] = 1.0;
       ej[j] = 1.0;
-      double Ki[3][3], Kj[3][3];
+      TT Ki[3][3], Kj[3][3];
       skew(ei, Ki);
       skew(ej, Kj);
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {
-          double t = 0.0;
+          TT t = 0.0;
           for (int a0 = 0; a0 < 3; ++a0)
             for (int b0 = 0; b0 < 3; ++b0) t += Ki[r][a0] * Rmn[a0][b0] * Kj[b0][c];
           XRS[r][c] += mij * t;
@@ -448,8 +471,9 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
     }
   for (int r = 0; r < 6; ++r)
     for (int c = 0; c < 6; ++c) v[55 + 6 * r + c] = Hmn[r][c];
-  v[91] = T[kStCnt];
-  for (int k = 0; k < kEdgeVals; ++k) out[k] = v[k];
+  v[91] = (TT)0;
+  for (int k = 0; k < kEdgeVals; ++k) out[k] = (double)v[k];
+  out[91] = n_pairs;
 }
 
 // ---------------------------------------------------------------- pair export (parity)
@@ -500,6 +524,9 @@ hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, int DP, hipStrea
   else RKHSBA_LAUNCH(4, DD, false);
   if constexpr (FEAT == FEAT_CLASS) {
     RKHSBA_ANY(0)
+  } else if constexpr (feat_low_precision(FEAT)) {
+    if (DP <= 32) { RKHSBA_ANY(32) }
+    else { RKHSBA_ANY(64) }
   } else {
     if (DP <= 8) { RKHSBA_ANY(8) }
     else if (DP <= 16) { RKHSBA_ANY(16) }
@@ -514,7 +541,10 @@ hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, int DP, hipStrea
 
 }  // namespace
 
-int dense_pad(int D) { return D <= 8 ? 8 : D <= 16 ? 16 : D <= 24 ? 24 : D <= 32 ? 32 : 64; }
+int dense_pad(int D, int feat_path) {
+  if (feat_low_precision(feat_path)) return D <= 32 ? 32 : 64;
+  return D <= 8 ? 8 : D <= 16 ? 16 : D <= 24 ? 24 : D <= 32 ? 32 : 64;
+}
 
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st) {
   if (E > 0) k_edge_setup<<<(E + 63) / 64, 64, 0, st>>>(d_poses, d_edges, E, d_xf);
@@ -535,23 +565,36 @@ hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_poi
   const bool local = pass_points == 1;
   const int G = local ? 1 : 64 / pass_points;
   const int DP = a.kc.Dp;
-  if (mode == MODE_LOSS)
-    return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_LOSS, FEAT_CLASS>(a, G, local, DP, st)
-                                   : dispatch_pairs<MODE_LOSS, FEAT_DENSE>(a, G, local, DP, st);
-  return feat_path == FEAT_CLASS ? dispatch_pairs<MODE_NORMAL, FEAT_CLASS>(a, G, local, DP, st)
-                                 : dispatch_pairs<MODE_NORMAL, FEAT_DENSE>(a, G, local, DP, st);
+#define RKHSBA_FEATS(MM)                                                                 \
+  switch (feat_path) {                                                                   \
+    case FEAT_CLASS: return dispatch_pairs<MM, FEAT_CLASS>(a, G, local, DP, st);         \
+    case FEAT_DENSE: return dispatch_pairs<MM, FEAT_DENSE>(a, G, local, DP, st);         \
+    case FEAT_BF16: return dispatch_pairs<MM, FEAT_BF16>(a, G, local, DP, st);           \
+    default: return dispatch_pairs<MM, FEAT_FP8>(a, G, local, DP, st);                   \
+  }
+  if (mode == MODE_LOSS) { RKHSBA_FEATS(MODE_LOSS) }
+  RKHSBA_FEATS(MODE_NORMAL)
+#undef RKHSBA_FEATS
 }
 
-hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st) {
+hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, bool fp32_sums, hipStream_t st) {
   if (a.n_fin_total <= 0) return hipSuccess;
-  if (mode == MODE_LOSS) k_finalize<MODE_LOSS><<<a.n_fin_total, kFinThreads, 0, st>>>(a, d_fin_off);
-  else k_finalize<MODE_NORMAL><<<a.n_fin_total, kFinThreads, 0, st>>>(a, d_fin_off);
+  const unsigned nb = (unsigned)a.n_fin_total;
+  if (fp32_sums) {
+    if (mode == MODE_LOSS) k_finalize<MODE_LOSS, float><<<nb, kFinThreads, 0, st>>>(a, d_fin_off);
+    else k_finalize<MODE_NORMAL, float><<<nb, kFinThreads, 0, st>>>(a, d_fin_off);
+  } else {
+    if (mode == MODE_LOSS) k_finalize<MODE_LOSS, double><<<nb, kFinThreads, 0, st>>>(a, d_fin_off);
+    else k_finalize<MODE_NORMAL, double><<<nb, kFinThreads, 0, st>>>(a, d_fin_off);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, const EdgeXf* d_xf, int E, int mode,
-                              double* d_edge_out, hipStream_t st) {
-  if (E > 0) k_edge_reduce<<<E, 64, 0, st>>>(d_partial, d_edges, d_xf, mode, d_edge_out);
+                              bool fp32_sums, double* d_edge_out, hipStream_t st) {
+  if (E <= 0) return hipSuccess;
+  if (fp32_sums) k_edge_reduce<float><<<E, 64, 0, st>>>(d_partial, d_edges, d_xf, mode, d_edge_out);
+  else k_edge_reduce<double><<<E, 64, 0, st>>>(d_partial, d_edges, d_xf, mode, d_edge_out);
   return hipGetLastError();
 }
 

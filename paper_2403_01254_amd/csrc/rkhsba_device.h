@@ -30,6 +30,62 @@ __device__ inline float3 rule_q32(const EdgeXf& xf, float x0, float x1, float x2
   return q;
 }
 
+// Exact widening of the stored low-precision feature formats.
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// OCP e4m3 (bias 7; no infinities; the one NaN code is never stored).
+__device__ inline float fp8_to_f32(uint8_t b) {
+  const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  const float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;  // m * 2^-9
+  return (b & 0x80u) ? -v : v;
+}
+
+// Feature row `row` (DP elements of the feature path's type) widened to FP32.
+template <int FEAT, int DP>
+__device__ inline void load_feature_row(const void* __restrict__ base, int64_t row, float (&out)[DP]) {
+  if constexpr (FEAT == FEAT_DENSE) {
+    const float4* f4 = reinterpret_cast<const float4*>(static_cast<const float*>(base) + row * DP);
+#pragma unroll
+    for (int k = 0; k < DP / 4; ++k) {
+      const float4 v = f4[k];
+      out[4 * k] = v.x; out[4 * k + 1] = v.y; out[4 * k + 2] = v.z; out[4 * k + 3] = v.w;
+    }
+  } else if constexpr (FEAT == FEAT_BF16) {
+    const uint4* u4 = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + row * DP);
+#pragma unroll
+    for (int k = 0; k < DP / 8; ++k) {
+      const uint4 v = u4[k];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        out[8 * k + 2 * i] = bf16_to_f32((uint16_t)(w[i] & 0xffffu));
+        out[8 * k + 2 * i + 1] = bf16_to_f32((uint16_t)(w[i] >> 16));
+      }
+    }
+  } else {
+    const uint4* u4 = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(base) + row * DP);
+#pragma unroll
+    for (int k = 0; k < DP / 16; ++k) {
+      const uint4 v = u4[k];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) out[16 * k + 4 * i + b] = fp8_to_f32((uint8_t)(w[i] >> (8 * b)));
+    }
+  }
+}
+
+// <f_src, f_row> with FP32 fused multiply-adds in element order.
+template <int FEAT, int DP>
+__device__ inline float dot_feature_row(const void* __restrict__ base, int64_t row, const float (&fs)[DP]) {
+  float z[DP];
+  load_feature_row<FEAT, DP>(base, row, z);
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < DP; ++k) acc = fmaf(fs[k], z[k], acc);
+  return acc;
+}
+
 // The FP32 squared distance of the membership rule.
 __device__ inline float rule_s2(float3 q, float zx, float zy, float zz, float& dx, float& dy, float& dz) {
 #pragma clang fp contract(off)
@@ -64,6 +120,10 @@ __device__ inline float wave_max(float v) {
   return v;
 }
 __device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }

@@ -20,7 +20,13 @@ constexpr uint32_t kInvalidKey = 0xffffffffu;
 constexpr int kMaxDense = 64;
 
 enum Mode { MODE_LOSS = 0, MODE_NORMAL = 1 };
-enum FeatPath { FEAT_CLASS = 0, FEAT_DENSE = 1 };
+// Feature paths (values equal the public feature kinds): class ids, dense
+// FP32 rows, dense rows stored in bfloat16 or fp8 e4m3 (inner products on the
+// matrix cores with FP32 accumulation; moment-to-block sums in FP32 with
+// compensation).
+enum FeatPath { FEAT_CLASS = 0, FEAT_DENSE = 1, FEAT_BF16 = 2, FEAT_FP8 = 3 };
+__host__ __device__ constexpr bool feat_low_precision(int f) { return f == FEAT_BF16 || f == FEAT_FP8; }
+__host__ __device__ constexpr int feat_elem_bytes(int f) { return f == FEAT_DENSE ? 4 : f == FEAT_BF16 ? 2 : 1; }
 
 // Per-frame grid description (device and host copies).
 struct FrameInfo {
@@ -103,7 +109,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
                                  hipStream_t st);
 constexpr int kScanTileElems = 2048;
 
-int dense_pad(int D);
+// Padded feature row length: 8, 16, 24, 32 or 64 (FP32), 32 or 64 (bfloat16, fp8: whole 32-wide MFMA slices).
+int dense_pad(int D, int feat_path);
 
 hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
                               double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st);
@@ -111,7 +118,7 @@ hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, cons
                             int64_t n_total, uint32_t* d_keys, uint32_t* d_vals, hipStream_t st);
 hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
-                         const uint32_t* d_sorted_vals, float4* d_pts, float* d_feat, int32_t* d_perm,
+                         const uint32_t* d_sorted_vals, float4* d_pts, void* d_feat, int32_t* d_perm,
                          int32_t* d_neg_flag, hipStream_t st);
 hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
                        int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
@@ -126,7 +133,7 @@ hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const Edge
 
 struct PairArgs {
   const float4* pts;
-  const float* feat;
+  const void* feat;       // feature rows (element type by feature path), Dp elements per point
   const int4* rows;
   const uint32_t* xtab;
   const FrameInfo* frames;
@@ -167,9 +174,11 @@ struct FinArgs {
 constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
 constexpr int kFinThreads = 256;
 constexpr int kFinStats = 38;  // per-edge sums the normal-equation blocks are expanded from (+ pair count)
-hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, hipStream_t st);
+// fp32_sums: per-point terms and their sums in FP32 with Kahan compensation
+// (low-precision feature paths), else FP64.  Pair counts are summed in FP64.
+hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, bool fp32_sums, hipStream_t st);
 hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, const EdgeXf* d_xf, int E, int mode,
-                              double* d_edge_out, hipStream_t st);
+                              bool fp32_sums, double* d_edge_out, hipStream_t st);
 
 // One problem's Gauss-Newton system within an evaluated set.
 struct ProbSys {

@@ -224,8 +224,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
   if (!opt || opt->max_active < 1 || opt->hbm_budget_bytes < 0 ||
       (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
        opt->pass_points != 64) ||
-      (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && opt->feat_kind != RKHSBA_FEAT_DENSE_F32) ||
-      (opt->feat_kind == RKHSBA_FEAT_DENSE_F32 && (opt->D < 1 || opt->D > kMaxDense)))
+      opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
+      (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)))
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -289,7 +289,7 @@ int rkhsba_server_submit(rkhsba_server* s, const rkhsba_request* r, int64_t* tic
   if (!s || !r || !ticket) return RKHSBA_EINVAL;
   *ticket = 0;
   if (r->K < 1 || !r->n_points || !r->xyz || !r->feats || !r->poses || r->E < 1 || !r->edges || r->n_iter < 0 ||
-      r->feat_kind != s->opt.feat_kind || (r->feat_kind == RKHSBA_FEAT_DENSE_F32 && r->D != s->opt.D) ||
+      r->feat_kind != s->opt.feat_kind || (r->feat_kind != RKHSBA_FEAT_CLASS_ID && r->D != s->opt.D) ||
       !(r->ell > 0.0) || !(r->cutoff_factor > 0.0) || r->cell_subdiv < 0 || r->cell_subdiv > 8 ||
       r->fixed_frame < 0 || r->fixed_frame >= r->K)
     return RKHSBA_EINVAL;

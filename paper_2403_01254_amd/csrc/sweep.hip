@@ -64,6 +64,35 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
   return acc;
 }
 
+// The same products for feature rows stored in bfloat16 or fp8 e4m3: one
+// 16x16x32 MFMA (FP32 accumulation) per 32 feature dimensions.  Lane (s, g)
+// supplies elements 8g..8g+7 of the slice, of candidate 16 sub + s (A, from
+// the LDS tile, RB bytes per row) and of its own source point (B, registers).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+
+template <int FEAT, int DP, int RB>
+__device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s, int g, int sub,
+                                           const uint64_t (&src)[FEAT == FEAT_BF16 ? DP / 16 : DP / 32]) {
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  const uint8_t* row = tl + (16 * sub + s) * RB;
+#pragma unroll
+  for (int k = 0; k < DP / 32; ++k) {
+    if constexpr (FEAT == FEAT_BF16) {
+      const uint4 av = *reinterpret_cast<const uint4*>(row + 64 * k + 16 * g);
+      const uint4 bv = make_uint4((uint32_t)src[2 * k], (uint32_t)(src[2 * k] >> 32), (uint32_t)src[2 * k + 1],
+                                  (uint32_t)(src[2 * k + 1] >> 32));
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc,
+                                                    0, 0, 0);
+    } else {
+      const uint2 av = *reinterpret_cast<const uint2*>(row + 32 * k + 8 * g);
+      const long al = (long)(((uint64_t)av.y << 32) | av.x);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(al, (long)src[k], acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
 // MM: the moments are accumulated on the matrix core.  With u = z - ref (ref =
 // centre of the pass's box) and Phi(u) = [1, u, u u^T] (10 of 16 columns), the
 // sums M[s][f] = sum_j w_sj Phi_f(u_j) over all candidates are one MFMA chain
@@ -73,12 +102,19 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
 template <int MODE, int FEAT, int DP, bool CLAMP, bool MM>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   constexpr int P = 16;
-  constexpr int FS = DP > 0 ? DP + 1 : 1;  // LDS feature row stride (odd: conflict-free column reads)
+  constexpr bool LP = feat_low_precision(FEAT);
+  constexpr int FS = FEAT == FEAT_DENSE ? DP + 1 : 1;  // LDS FP32 feature row stride (odd: conflict-free column reads)
+  // LDS low-precision row: DP elements + 16 (bfloat16) or 8 (fp8) bytes, so that the 16 rows one MFMA
+  // operand read touches fall on disjoint banks
+  constexpr int RB = !LP ? 1 : FEAT == FEAT_BF16 ? 2 * DP + 16 : DP + 8;
+  constexpr int ROWB = !LP ? 1 : FEAT == FEAT_BF16 ? 2 * DP : DP;  // bytes of one stored row
+  constexpr int NSRC = !LP ? 1 : FEAT == FEAT_BF16 ? DP / 16 : DP / 32;
   constexpr int PHS = 20;                  // LDS Phi row stride (conflict-free B-operand reads)
   __shared__ uint32_t row_j0[kLanes];
   __shared__ uint32_t row_off[kLanes + 1];
   __shared__ float4 tpos[kTile];
-  __shared__ float tfeat[DP > 0 ? kTile * FS : 1];
+  __shared__ float tfeat[FEAT == FEAT_DENSE ? kTile * FS : 1];
+  __shared__ __align__(16) uint8_t tlp[LP ? kTile * RB : 16];
   __shared__ float tphi[MM ? kTile * PHS : 1];
   __shared__ float mt[MM ? 16 * 17 : 1];
 
@@ -100,16 +136,31 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   }
   float3 q = make_float3(0.f, 0.f, 0.f);
   uint32_t lbl = 0;
-  float fsrc[DP > 0 ? DP / 4 : 1] = {};
+  float fsrc[FEAT == FEAT_DENSE ? DP / 4 : 1] = {};
+  uint64_t slp[NSRC] = {};
   if (valid) {
     const float4 x = a.pts[pi.src_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
     lbl = __float_as_uint(x.w);
     if constexpr (FEAT == FEAT_DENSE) {
       // B operand of the MFMA: feature 4k + g of this lane's source point
-      const float* f = a.feat + (pi.src_off + src) * DP;
+      const float* f = static_cast<const float*>(a.feat) + (pi.src_off + src) * DP;
 #pragma unroll
       for (int k = 0; k < DP / 4; ++k) fsrc[k] = f[4 * k + g];
+    } else if constexpr (LP) {
+      // B operand: elements 32k + 8g .. 32k + 8g + 7 of this lane's source row
+      const uint8_t* f = static_cast<const uint8_t*>(a.feat) + (pi.src_off + src) * (int64_t)ROWB;
+#pragma unroll
+      for (int k = 0; k < DP / 32; ++k) {
+        if constexpr (FEAT == FEAT_BF16) {
+          const uint4 v = *reinterpret_cast<const uint4*>(f + 64 * k + 16 * g);
+          slp[2 * k] = ((uint64_t)v.y << 32) | v.x;
+          slp[2 * k + 1] = ((uint64_t)v.w << 32) | v.z;
+        } else {
+          const uint2 v = *reinterpret_cast<const uint2*>(f + 32 * k + 8 * g);
+          slp[k] = ((uint64_t)v.y << 32) | v.x;
+        }
+      }
     }
   }
   float3 lo, hi;
@@ -143,7 +194,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
   uint32_t cnt = 0;
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
-  const float* __restrict__ tf = a.feat + Fn.pt_off * (DP > 0 ? DP : 0);
+  const float* __restrict__ tf = static_cast<const float*>(a.feat) + Fn.pt_off * (FEAT == FEAT_DENSE ? DP : 0);
+  const uint8_t* __restrict__ tl = static_cast<const uint8_t*>(a.feat) + Fn.pt_off * (int64_t)(LP ? ROWB : 0);
   const float far_ = 1.0e30f;
 
   for (int rb = 0; rb < n_rows; rb += kLanes) {
@@ -181,7 +233,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     if (total == 0) continue;
 
     // ---- tiles of 64 candidates, next tile fetched while the current one is processed
-    auto fetch = [&](uint32_t c, float4& pos, float* fr, bool& pad) {
+    auto fetch = [&](uint32_t c, float4& pos, float* fr, uint4* lr, bool& pad) {
       pad = c >= total;
       if (c < total) {
         int lo_r = 0, hi_r = 63;  // largest row with row_off[row] <= c
@@ -198,19 +250,27 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
             const float4 v = f4[k];
             fr[4 * k] = v.x; fr[4 * k + 1] = v.y; fr[4 * k + 2] = v.z; fr[4 * k + 3] = v.w;
           }
+        } else if constexpr (LP) {
+          const uint4* r4 = reinterpret_cast<const uint4*>(tl + (int64_t)j * ROWB);
+#pragma unroll
+          for (int k = 0; k < ROWB / 16; ++k) lr[k] = r4[k];
         }
       } else {
         pos = make_float4(far_, far_, far_, 0.f);  // fails every membership test, keeps the products finite
         if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
           for (int k = 0; k < DP; ++k) fr[k] = 0.f;
+        } else if constexpr (LP) {
+#pragma unroll
+          for (int k = 0; k < ROWB / 16; ++k) lr[k] = make_uint4(0u, 0u, 0u, 0u);
         }
       }
     };
     float4 npos;
-    float nfeat[DP > 0 ? DP : 1];
+    float nfeat[FEAT == FEAT_DENSE ? DP : 1];
+    uint4 nlp[LP ? ROWB / 16 : 1];
     bool npad;
-    fetch((uint32_t)lane, npos, nfeat, npad);
+    fetch((uint32_t)lane, npos, nfeat, nlp, npad);
     for (uint32_t cb = 0; cb < total; cb += kTile) {
       tpos[lane] = npos;
       if constexpr (MM) {
@@ -226,13 +286,23 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
         for (int k = 0; k < DP; ++k) tfeat[lane * FS + k] = nfeat[k];
+      } else if constexpr (FEAT == FEAT_BF16) {
+#pragma unroll
+        for (int k = 0; k < ROWB / 16; ++k) *reinterpret_cast<uint4*>(tlp + lane * RB + 16 * k) = nlp[k];
+      } else if constexpr (FEAT == FEAT_FP8) {
+#pragma unroll
+        for (int k = 0; k < ROWB / 16; ++k) {  // RB is a multiple of 8 only: 8-byte stores
+          *reinterpret_cast<uint2*>(tlp + lane * RB + 16 * k) = make_uint2(nlp[k].x, nlp[k].y);
+          *reinterpret_cast<uint2*>(tlp + lane * RB + 16 * k + 8) = make_uint2(nlp[k].z, nlp[k].w);
+        }
       }
       __syncthreads();
-      if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, npad);
+      if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
       const uint32_t left = total - cb;
       const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
       floatx4 cv = {1.f, 1.f, 1.f, 1.f};
       if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
+      if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
       for (int sub = 0; sub < n_sub; ++sub) {
         // this lane's four candidates of the sub-tile, read before any use
         const float4* zp = tpos + 16 * sub + 4 * g;
@@ -246,6 +316,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         if constexpr (FEAT == FEAT_DENSE) {
           // issue the next sub-tile's products now: the matrix core works while the VALU runs below
           if (sub + 1 < n_sub) cv = tile_products<DP, FS>(tfeat, s, g, sub + 1, fsrc);
+        } else if constexpr (LP) {
+          if (sub + 1 < n_sub) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, sub + 1, slp);
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -330,6 +402,9 @@ hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
     k_sweep<MODE, FEAT, 0, false, MM><<<nb, kLanes, 0, st>>>(a);
+  } else if constexpr (feat_low_precision(FEAT)) {
+    if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
   } else {
     if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
     else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
@@ -340,11 +415,20 @@ hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int MODE, int FEAT, bool MM>
+hipError_t dispatch_clamp(const PairArgs& a, hipStream_t st) {
+  if (a.kc.clamp) return dispatch<MODE, FEAT, true, MM>(a, a.kc.Dp, st);
+  return dispatch<MODE, FEAT, false, MM>(a, a.kc.Dp, st);
+}
+
 template <int MODE, bool MM>
 hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
-  if (feat_path == FEAT_CLASS) return dispatch<MODE, FEAT_CLASS, false, MM>(a, 0, st);
-  if (a.kc.clamp) return dispatch<MODE, FEAT_DENSE, true, MM>(a, a.kc.Dp, st);
-  return dispatch<MODE, FEAT_DENSE, false, MM>(a, a.kc.Dp, st);
+  switch (feat_path) {
+    case FEAT_CLASS: return dispatch<MODE, FEAT_CLASS, false, MM>(a, 0, st);
+    case FEAT_DENSE: return dispatch_clamp<MODE, FEAT_DENSE, MM>(a, st);
+    case FEAT_BF16: return dispatch_clamp<MODE, FEAT_BF16, MM>(a, st);
+    default: return dispatch_clamp<MODE, FEAT_FP8, MM>(a, st);
+  }
 }
 
 }  // namespace

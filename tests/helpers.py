@@ -72,3 +72,28 @@ def pose_errors(P_hat, P):
 
 def ident():
     return np.concatenate([np.eye(3).reshape(9), np.zeros(3)])
+
+
+def _round_to_grid(x, exp_floor, mant_bits, max_abs):
+    """Round to nearest (ties to even) on a binary floating grid with `mant_bits`
+    fraction bits, exponents clamped below at `exp_floor` (subnormal step
+    2^(exp_floor - mant_bits)), saturating at max_abs.  Done in float64, where
+    every step is exact for float32 inputs."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0
+    e = np.maximum(np.floor(np.log2(np.abs(x[nz]))), exp_floor)
+    ulp = np.exp2(e - mant_bits)
+    out[nz] = np.round(x[nz] / ulp) * ulp          # numpy rounds halves to even
+    return np.clip(out, -max_abs, max_abs)
+
+
+def bf16_round(x):
+    """float32 -> bfloat16 (8 significant bits), nearest even, as float32."""
+    return _round_to_grid(x, -126, 7, 3.3895313892515355e38).astype(np.float32)
+
+
+def e4m3_round(x):
+    """float32 -> OCP fp8 e4m3 (bias 7: normal exponents -6..8, 3 fraction bits,
+    subnormal step 2^-9), nearest even, saturating at 448, as float32."""
+    return _round_to_grid(x, -6, 3, 448.0).astype(np.float32)
