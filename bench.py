@@ -42,6 +42,8 @@ WORKLOADS = {
              "flipped, 384 directed 6-nearest-pose pairs, ell=0.3 m, cutoff 3 ell, 10 Gauss-Newton iterations",
     "two_view": "two_view: 2 frames x 5,000 points, 10-class one-hot labels, ell=0.1 m, cutoff 3 ell, "
                 "10 Gauss-Newton iterations",
+    "dense64": "dense64: as odometry with 64-dim unit-vector features (per-class mean + N(0, 0.1) jitter, "
+               "renormalised; negative inner products clamped to 0)",
 }
 
 
@@ -119,13 +121,10 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
     log(f"[serving] one-at-a-time capacity {capacity:.2f} solves/s ({len(reqs)} requests in {cap_s:.2f} s)")
     rng = np.random.default_rng(seed)
     runs = []
-    max_pose_diff = 0.0
-    for frac in (0.5, 0.9):
-        qps = frac * capacity
-        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
-        arrivals -= arrivals[0]
-        # continuous batching
-        srv = rkhsba.Server(feat_kind="dense", D=D, max_active=64)
+    pose_diff = {}
+
+    def run_batched(kind, arrivals):
+        srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64)
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05
 
@@ -149,13 +148,20 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
         end = time.perf_counter()
         st = srv.stats()
         srv.close()
-        for r, q in zip(out, seq):
-            max_pose_diff = max(max_pose_diff, float(np.abs(r[0] - q[0]).max()))
-        served = {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
-                  "solves_per_s": len(reqs) / (end - start), "pair_evals_per_s": st["pair_evals"] / (end - start),
-                  "max_active": st["max_active"], "batch_iterations": st["batch_iterations"],
-                  "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out]))}
-        # one at a time, same arrivals
+        diff = max(float(np.abs(r[0] - q[0]).max()) for r, q in zip(out, seq))
+        pose_diff[kind] = max(pose_diff.get(kind, 0.0), diff)
+        return {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+                "solves_per_s": len(reqs) / (end - start), "pair_evals_per_s": st["pair_evals"] / (end - start),
+                "max_active": st["max_active"], "batch_iterations": st["batch_iterations"],
+                "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out])),
+                "max_pose_entry_diff_vs_one_at_a_time_f32": diff}
+
+    for frac in (0.5, 0.9):
+        qps = frac * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
+        arrivals -= arrivals[0]
+        batched = {k: run_batched(k, arrivals) for k in ("dense", "bf16")}
+        # one at a time, FP32, same arrivals
         lat1 = []
         start1 = time.perf_counter()
         for i in range(len(reqs)):
@@ -167,15 +173,17 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
         end1 = time.perf_counter()
         single = {"p50_ms": percentile_ms(lat1, 50), "p99_ms": percentile_ms(lat1, 99),
                   "solves_per_s": len(reqs) / (end1 - start1), "pair_evals_per_s": seq_pairs / (end1 - start1)}
-        log(f"[serving] {qps:.2f} req/s: batched p50 {served['p50_ms']:.1f} ms p99 {served['p99_ms']:.1f} ms "
-            f"({served['solves_per_s']:.2f} solves/s, up to {served['max_active']} active); one-at-a-time p50 "
-            f"{single['p50_ms']:.1f} ms p99 {single['p99_ms']:.1f} ms")
-        runs.append({"qps": qps, "load": frac, "batched": served, "one_at_a_time": single})
+        for k, v in batched.items():
+            log(f"[serving] {qps:.2f} req/s, batched {k}: p50 {v['p50_ms']:.1f} ms p99 {v['p99_ms']:.1f} ms "
+                f"({v['solves_per_s']:.2f} solves/s, up to {v['max_active']} active)")
+        log(f"[serving] {qps:.2f} req/s, one-at-a-time f32: p50 {single['p50_ms']:.1f} ms p99 {single['p99_ms']:.1f} ms")
+        runs.append({"qps": qps, "load": frac, "batched_f32": batched["dense"], "batched_bf16": batched["bf16"],
+                     "one_at_a_time_f32": single})
     for c in ctxs.values():
         c.close()
     return {"requests": len(reqs), "capacity_one_at_a_time_solves_per_s": capacity,
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
-            "max_pose_diff_batched_vs_one_at_a_time": max_pose_diff,
+            "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
                       "depth-camera trajectory (p = 1/2), 20-class Dirichlet(0.3) soft labels (D = 20), ell in "
                       "{0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs resident in HBM; Poisson "
@@ -207,7 +215,9 @@ def main():
                     help="keep --cell-subdiv/--pass-points instead of the autotuner's choice (made during warm-up)")
     ap.add_argument("--no-graphs", action="store_true", help="issue every launch eagerly (no HIP graph replay)")
     ap.add_argument("--moment-path", type=int, default=0, help="0 library choice, 1 vector ALU, 2 matrix cores")
-    ap.add_argument("--workload", default="odometry", choices=["odometry", "lidar", "two_view"],
+    ap.add_argument("--features", default="f32", choices=["f32", "bf16", "fp8"],
+                    help="storage / inner-product precision of dense features (bf16, fp8: matrix cores)")
+    ap.add_argument("--workload", default="odometry", choices=["odometry", "lidar", "two_view", "dense64"],
                     help="odometry is the headline configuration; the others are for kernel studies")
     ap.add_argument("--cpu-edges", type=int, default=8, help="frame pairs in the CPU oracle sample (0: skip)")
     ap.add_argument("--quiet", action="store_true")
@@ -241,7 +251,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p = {"odometry": scenes.odometry, "lidar": scenes.lidar, "two_view": scenes.two_view}[args.workload](0)
+    p = {"odometry": scenes.odometry, "lidar": scenes.lidar, "two_view": scenes.two_view,
+         "dense64": scenes.dense64}[args.workload](0)
+    kind = p.feat_kind
+    if kind == "dense" and args.features != "f32":
+        kind = args.features
     log(f"[bench] workload {p.recipe}: {len(p.edges)} edges, {p.n_iter} GN iterations")
     dev = torch.device("cuda:0")
     pts = [torch.from_numpy(x).to(dev) for x in p.points]
@@ -252,11 +266,11 @@ def main():
                          cell_subdiv=args.cell_subdiv, moment_path=args.moment_path,
                          use_graphs=not args.no_graphs)
     if not args.no_autotune:
-        S, P, ms = ctx.autotune(pts, feats, p.feat_kind, p.init_poses, p.edges, trials=2)
+        S, P, ms = ctx.autotune(pts, feats, kind, p.init_poses, p.edges, trials=2)
         log(f"[bench] autotuner: cell_subdiv {S}, pass_points {P} ({ms:.3f} ms per normal-equation evaluation)")
 
     def step():
-        ctx.build_neighbors(pts, feats, p.feat_kind)
+        ctx.build_neighbors(pts, feats, kind)
         return ctx.gn_step(p.init_poses, p.edges, p.n_iter)
 
     for w in range(args.warmup):
@@ -294,7 +308,10 @@ def main():
     # roofline of the sweep kernel (Gauss-Newton evaluations): algorithmic flops per launch / mean launch time
     pair_ms, pair_launches = prof["pairs"]
     gn_pairs_per_launch = float(np.mean(ppi[:-1])) if p.n_iter > 0 else 0.0
-    flops_per_pair = FLOPS_PER_PAIR_GEOM + (2 * p.D if p.feat_kind == "dense" else 0)
+    # FP32 features: the inner products run on the FP32 matrix cores, whose published peak equals the
+    # FP32 vector peak, and are counted in the same budget; bf16 / fp8 inner products run on the
+    # low-precision matrix cores and are not counted against the FP32 peak.
+    flops_per_pair = FLOPS_PER_PAIR_GEOM + (2 * p.D if kind == "dense" else 0)
     mean_launch_s = pair_ms / max(pair_launches, 1) / 1e3
     achieved = flops_per_pair * gn_pairs_per_launch / mean_launch_s / 1e12 if mean_launch_s > 0 else 0.0
     traffic = load_traffic()
@@ -310,12 +327,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if kind in ("class", "dense") else f"f32+{kind}",
         "data": "synthetic",
         "config": {
             "workload": WORKLOADS[args.workload],
             "frames": p.K, "points_per_frame": int(p.n_points[0]), "edges": int(len(p.edges)),
-            "gn_iterations": p.n_iter, "feature_dim": p.D, "ell": p.ell,
+            "gn_iterations": p.n_iter, "feature_dim": p.D, "feature_storage": kind, "ell": p.ell,
             "pass_points": cfg_pass, "cell_subdiv": cfg_subdiv, "moment_path": args.moment_path,
             "autotuned": not args.no_autotune, "points_per_rc_cube": cfg_occ,
         },

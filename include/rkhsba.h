@@ -69,8 +69,7 @@ typedef enum {
   RKHSBA_FEAT_CLASS_ID = 0,    /* one-hot labels passed as uint16 class ids (N_m values) */
   RKHSBA_FEAT_DENSE_F32 = 1,   /* dense float32 rows (N_m * D values), D <= 64 */
   RKHSBA_FEAT_DENSE_BF16 = 2,  /* float32 rows as DENSE_F32, stored rounded to bfloat16 (nearest even); inner
-                                  products on the matrix cores with FP32 accumulation; per-edge sums of the
-                                  normal-equation terms in FP32 with Kahan compensation */
+                                  products on the matrix cores with FP32 accumulation */
   RKHSBA_FEAT_DENSE_FP8 = 3    /* as DENSE_BF16 with OCP fp8 e4m3 storage (nearest even, saturating at 448) */
 } rkhsba_feat_kind;
 
@@ -92,6 +91,8 @@ typedef struct {
                             1 = vector ALU, 2 = matrix cores (default 0) */
   int use_graphs;        /* 1 = capture one Gauss-Newton iteration in a HIP graph and replay it (default 1;
                             stage timing, when enabled, runs the launches one by one instead) */
+  int hessian_fp32;      /* 1 = per-edge sums of the normal-equation terms in FP32 with Kahan compensation,
+                            0 = FP64 (default) */
   void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
 } rkhsba_options;
 
@@ -218,6 +219,7 @@ typedef struct {
   int64_t hbm_budget_bytes; /* admission limit on the estimated footprints (0: 80% of free memory) */
   int pass_points;          /* sweep pass size for every request (0: chosen per request, default) */
   int use_graphs;           /* replay a batch iteration from a HIP graph while the active set is unchanged */
+  int hessian_fp32;         /* as rkhsba_options.hessian_fp32 */
   void* stream;             /* hipStream_t for all work; NULL = a stream owned by the server */
 } rkhsba_server_options;
 

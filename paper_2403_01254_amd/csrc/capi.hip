@@ -88,6 +88,7 @@ void rkhsba_default_options(rkhsba_options* o) {
   o->pass_points = 0;
   o->moment_path = 0;
   o->use_graphs = 1;
+  o->hessian_fp32 = 0;
   o->stream = nullptr;
 }
 
@@ -101,7 +102,8 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
       (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
        opt->pass_points != 64) ||
       opt->fixed_frame < 0 ||
-      opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1)
+      opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1 ||
+      opt->hessian_fp32 < 0 || opt->hessian_fp32 > 1)
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -128,6 +130,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
     return RKHSBA_ENOMEM;
   }
   c->eng->use_graphs = opt->use_graphs != 0;
+  c->eng->fp32_sums = opt->hessian_fp32 != 0;
   *out = c;
   return RKHSBA_OK;
 }

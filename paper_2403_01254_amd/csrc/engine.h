@@ -202,6 +202,7 @@ class Engine {
   hipStream_t st;
   int moment_path;
   bool use_graphs = true;
+  bool fp32_sums = false;  // per-edge normal-equation sums in FP32 with Kahan compensation (else FP64)
 
   // feature layout shared by all resident problems
   int feat_kind = -1, D = 0, Dp = 0;

@@ -849,7 +849,6 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   fa.E = lay.E;
   fa.n_fin_total = lay.n_fin_total;
   hipEvent_t t2 = prof_begin();
-  const bool fp32_sums = feat_low_precision(feat_kind);
   RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, fp32_sums, st));
   RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, xf_.p, lay.E, mode, fp32_sums, edge_out_.p, st));
   prof_end(RKHSBA_PROF_FINALIZE, t2);

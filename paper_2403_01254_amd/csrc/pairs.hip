@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
 constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
               kStXS = 28, kStCnt = 37;
 
-// Running sums: FP64, or FP32 with Kahan compensation (low-precision feature paths).
+// Running sums: FP64, or FP32 with Kahan compensation (option).
 template <typename T>
 struct Acc;
 template <>

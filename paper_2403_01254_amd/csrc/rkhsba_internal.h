@@ -22,8 +22,7 @@ constexpr int kMaxDense = 64;
 enum Mode { MODE_LOSS = 0, MODE_NORMAL = 1 };
 // Feature paths (values equal the public feature kinds): class ids, dense
 // FP32 rows, dense rows stored in bfloat16 or fp8 e4m3 (inner products on the
-// matrix cores with FP32 accumulation; moment-to-block sums in FP32 with
-// compensation).
+// matrix cores with FP32 accumulation).
 enum FeatPath { FEAT_CLASS = 0, FEAT_DENSE = 1, FEAT_BF16 = 2, FEAT_FP8 = 3 };
 __host__ __device__ constexpr bool feat_low_precision(int f) { return f == FEAT_BF16 || f == FEAT_FP8; }
 __host__ __device__ constexpr int feat_elem_bytes(int f) { return f == FEAT_DENSE ? 4 : f == FEAT_BF16 ? 2 : 1; }
@@ -174,8 +173,8 @@ struct FinArgs {
 constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
 constexpr int kFinThreads = 256;
 constexpr int kFinStats = 38;  // per-edge sums the normal-equation blocks are expanded from (+ pair count)
-// fp32_sums: per-point terms and their sums in FP32 with Kahan compensation
-// (low-precision feature paths), else FP64.  Pair counts are summed in FP64.
+// fp32_sums: per-point terms and their sums in FP32 with Kahan compensation,
+// else FP64.  Pair counts are summed in FP64.
 hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, bool fp32_sums, hipStream_t st);
 hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, const EdgeXf* d_xf, int E, int mode,
                               bool fp32_sums, double* d_edge_out, hipStream_t st);

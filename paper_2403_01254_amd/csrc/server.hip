@@ -215,6 +215,7 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->hbm_budget_bytes = 0;
   o->pass_points = 0;
   o->use_graphs = 1;
+  o->hessian_fp32 = 0;
   o->stream = nullptr;
 }
 
@@ -257,6 +258,7 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
     return RKHSBA_ENOMEM;
   }
   s->eng->use_graphs = opt->use_graphs != 0;
+  s->eng->fp32_sums = opt->hessian_fp32 != 0;
   try {
     s->worker = std::thread([s] { s->run(); });
   } catch (...) {

@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("pass_points", ctypes.c_int),
         ("moment_path", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("hessian_fp32", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -55,6 +56,7 @@ class ServerOptions(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_int64),
         ("pass_points", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("hessian_fp32", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -146,12 +148,14 @@ class Context:
 
     def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
                  fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 0,
-                 pass_points: int = 0, moment_path: int = 0, use_graphs: bool = True, stream=None):
+                 pass_points: int = 0, moment_path: int = 0, use_graphs: bool = True, hessian_fp32: bool = False,
+                 stream=None):
         o = default_options()
         o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel
         o.fixed_frame, o.clamp_negative_c, o.device = fixed_frame, int(bool(clamp_negative_c)), device
         o.cell_subdiv, o.pass_points, o.moment_path = cell_subdiv, pass_points, moment_path
         o.use_graphs = int(bool(use_graphs))
+        o.hessian_fp32 = int(bool(hessian_fp32))
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_create(ctypes.byref(self._h), ctypes.byref(o))
@@ -317,13 +321,14 @@ class Server:
     solve and returns a ticket at once; wait() returns its result."""
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
-                 use_graphs=True, stream=None):
+                 use_graphs=True, hessian_fp32=False, stream=None):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
         o.feat_kind = _FEAT_NAMES[feat_kind] if isinstance(feat_kind, str) else int(feat_kind)
         o.D, o.max_active, o.hbm_budget_bytes = D, max_active, hbm_budget_bytes
         o.pass_points, o.use_graphs = pass_points, int(bool(use_graphs))
+        o.hessian_fp32 = int(bool(hessian_fp32))
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         self.opts = o
         self._h = ctypes.c_void_p()

@@ -61,16 +61,17 @@ def scene(request):
 
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
 @pytest.mark.parametrize("pass_points", [16, 1])
-def test_low_precision_normal_equations(rk, scene, kind, pass_points):
+@pytest.mark.parametrize("hessian_fp32", [False, True])
+def test_low_precision_normal_equations(rk, scene, kind, pass_points, hessian_fp32):
     name, p = scene
     rounded = [ROUND[kind](f) for f in p.feats]
     oq = oracle.Problem(p.points, rounded, "dense", p.ell, p.cutoff_factor)
     oF, ob, oH, _, on = oracle.normal_eqs(oq, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
-    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, pass_points=pass_points)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, pass_points=pass_points, hessian_fp32=hessian_fp32)
     ctx.build_neighbors(p.points, p.feats, kind)
     H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
     eF, eb, eH = abs(F - oF) / abs(oF), normwise_rel(b, ob), normwise_rel(H, oH)
-    say(f"[{kind}/{pass_points}] {name} vs oracle on rounded features: F {eF:.2e} b {eb:.2e} H {eH:.2e} "
+    say(f"[{kind}/{pass_points}/{'fp32k' if hessian_fp32 else 'fp64'}] {name} vs oracle on rounded features: F {eF:.2e} b {eb:.2e} H {eH:.2e} "
         f"pairs {n}/{on}")
     assert abs(n - on) <= max(2, 1e-5 * on)  # c exactly 0 after clamping may differ in the last bit
     tol = tolerance(kind, pass_points)
