@@ -231,8 +231,6 @@ def main():
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
-    gen_pool, gen_futures = start_request_generation(args.serving_requests, workers=8)
-
     import numpy as np
     import torch
 
@@ -353,15 +351,17 @@ def main():
             "mean_launch_ms": mean_launch_s * 1e3,
         },
     }
+    rank = int(os.environ.get("RANK", "0"))
+    if rank == 0 and args.cpu_edges > 0:
+        log(f"[bench] CPU oracle on {args.cpu_edges} frame pairs ...")
+        result["cpu_baseline"] = cpu_baseline(p, args.cpu_edges)
+    # serving requests are generated only now, so that no worker process competes with the timed regions above
+    gen_pool, gen_futures = start_request_generation(args.serving_requests, workers=8)
     if gen_futures:
         reqs = [f.result() for f in gen_futures]
         gen_pool.shutdown()
         log(f"[bench] serving: {len(reqs)} requests generated")
         result["serving"] = serving_benchmark(reqs, rkhsba, torch, log)
-    rank = int(os.environ.get("RANK", "0"))
-    if rank == 0 and args.cpu_edges > 0:
-        log(f"[bench] CPU oracle on {args.cpu_edges} frame pairs ...")
-        result["cpu_baseline"] = cpu_baseline(p, args.cpu_edges)
     if rank == 0:
         print(json.dumps(result), flush=True)
     ctx.close()
