@@ -161,6 +161,25 @@ int rkhsba_autotune(rkhsba_ctx* ctx, int K, const int64_t* n_points, const float
  * points per occupied r_c-cube (0 if that was not measured).  Nullable outputs. */
 int rkhsba_get_config(rkhsba_ctx* ctx, int* cell_subdiv, int* pass_points, double* occupancy);
 
+/* The 60 rotations of the icosahedral group (Sec. IV-A: the identity, 15
+ * half-turns about edge axes, 20 third-turns about face axes, 24 fifth-turns
+ * about vertex axes), 9 doubles each (row-major), in the library's order. */
+void rkhsba_icosahedral_rotations(double* out);
+
+/* Global rotation initialisation of frame n against frame m (Sec. IV-A):
+ * F of the edge (m, n) is evaluated with frame n's pose replaced by
+ * T_n G_k, G_k(x) = R_k (x - c) + c (c = centroid of frame n's points in its
+ * local coordinates), for every candidate rotation R_k -- all candidates in
+ * one batched evaluation.  The norms of the two point-cloud functions do not
+ * depend on the poses, so the largest F is the largest cosine alignment.
+ *   rotations: n_rot row-major 3x3 (1 <= n_rot <= 4096), or NULL with n_rot 0
+ *              or 60 for the icosahedral group (rkhsba_icosahedral_rotations).
+ *   scores:    n_rot doubles (nullable); best: index of the largest score (the
+ *              first one on ties; nullable); best_pose: 12 doubles (nullable).
+ * poses: K*12 as elsewhere; only frame m's and frame n's are used. */
+int rkhsba_rotation_search(rkhsba_ctx* ctx, const double* poses, int m, int n, int n_rot, const double* rotations,
+                           double* scores, int* best, double* best_pose);
+
 /* Debug/parity: the in-radius pairs of edge (m, n) at `poses` under the FP32
  * membership rule (and equal labels for class ids), as (i, j) original point
  * indices sorted by (i, j).  Writes min(total, cap) pairs to pairs (cap*2

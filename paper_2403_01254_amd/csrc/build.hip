@@ -233,9 +233,35 @@ __global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restri
   if (row_end) xt[R.y + 1 - R.x] = (uint32_t)(s + 1);
 }
 
+// Centroid of one frame: each thread sums a strided subset in FP64, then the
+// partial sums are added in thread order.
+__global__ __launch_bounds__(kThreads) void k_frame_centroid(const float4* __restrict__ pts, int n,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[3][kThreads];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const float4 p = pts[i];
+    s[0] += p.x;
+    s[1] += p.y;
+    s[2] += p.z;
+  }
+  for (int a = 0; a < 3; ++a) sh[a][threadIdx.x] = s[a];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int k = 0; k < kThreads; ++k) t += sh[threadIdx.x][k];
+    out[threadIdx.x] = n > 0 ? t / n : 0.0;
+  }
+}
+
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipStream_t st) {
+  k_frame_centroid<<<1, kThreads, 0, st>>>(d_pts, n, d_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
                               double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st) {

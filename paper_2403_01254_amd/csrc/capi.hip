@@ -2,6 +2,7 @@
 // argument validation, and the call sequences of build_neighbors /
 // eval_loss / accumulate_normal_eqs / gn_step.  No exception crosses the ABI.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -24,6 +25,7 @@ struct rkhsba_ctx {
   int prob = -1;         // the resident problem
   SetLayout lay_eval;    // evaluations without a fixed frame (loss, normal equations)
   SetLayout lay_gn;      // Gauss-Newton runs
+  SetLayout lay_rot;     // candidate-pose batches
   double occ_r = 0.0;    // points per occupied r_c-cube of the frames last measured
 };
 
@@ -55,6 +57,48 @@ Problem* resident(rkhsba_ctx* c) {
   Problem* p = c->prob >= 0 ? c->eng->problem(c->prob) : nullptr;
   RK_REQUIRE(p != nullptr, RKHSBA_ESTATE, "no frames: call rkhsba_build_neighbors first");
   return p;
+}
+
+// The rotation group of the icosahedron (Sec. IV-A): closure of the 3-fold
+// rotation about (1,1,1) (cyclic permutation of the axes) and the 5-fold
+// rotation about the vertex direction (0, 1, golden ratio), in breadth-first
+// order from the identity.
+std::vector<std::array<double, 9>> icosahedral_group() {
+  typedef std::array<double, 9> M;
+  auto mul = [](const M& A, const M& B) {
+    M C{};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+    return C;
+  };
+  const M P = {0, 0, 1, 1, 0, 0, 0, 1, 0};
+  const double phi = 0.5 * (1.0 + std::sqrt(5.0));
+  double ax[3] = {0.0, 1.0, phi};
+  const double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+  for (double& v : ax) v /= nrm;
+  const double th = 2.0 * M_PI / 5.0, cs = std::cos(th), sn = std::sin(th);
+  M Q{};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const double K[3][3] = {{0, -ax[2], ax[1]}, {ax[2], 0, -ax[0]}, {-ax[1], ax[0], 0}};
+      Q[3 * r + c] = (r == c ? cs : 0.0) + sn * K[r][c] + (1.0 - cs) * ax[r] * ax[c];
+    }
+  std::vector<M> G = {M{1, 0, 0, 0, 1, 0, 0, 0, 1}};
+  for (size_t i = 0; i < G.size() && G.size() < 64; ++i)
+    for (const M& g : {P, Q}) {
+      const M x = mul(G[i], g);
+      bool seen = false;
+      for (const M& y : G) {
+        double d = 0.0;
+        for (int k = 0; k < 9; ++k) d = std::max(d, std::fabs(x[k] - y[k]));
+        if (d < 1e-9) {
+          seen = true;
+          break;
+        }
+      }
+      if (!seen) G.push_back(x);
+    }
+  return G;
 }
 
 ProbParams params_of(const rkhsba_options& o) {
@@ -141,6 +185,7 @@ void rkhsba_destroy(rkhsba_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   c->lay_eval.drop_graph();
   c->lay_gn.drop_graph();
+  c->lay_rot.drop_graph();
   c->eng.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -315,6 +360,78 @@ int rkhsba_gn_step(rkhsba_ctx* c, double* poses, int E, const int32_t* edges, in
       c->err = "Cholesky pivot not positive in a Gauss-Newton step";
       return RKHSBA_ENOTPD;
     }
+    return RKHSBA_OK;
+  });
+}
+
+void rkhsba_icosahedral_rotations(double* out) {
+  if (!out) return;
+  const auto G = icosahedral_group();
+  for (size_t k = 0; k < G.size(); ++k)
+    for (int i = 0; i < 9; ++i) out[9 * k + i] = G[k][i];
+}
+
+int rkhsba_rotation_search(rkhsba_ctx* c, const double* poses, int m, int n, int n_rot, const double* rotations,
+                           double* scores, int* best, double* best_pose) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    Engine& g = *c->eng;
+    RK_REQUIRE(m >= 0 && n >= 0 && m < p->K && n < p->K && m != n, RKHSBA_EINVAL, "bad frame pair");
+    std::vector<std::array<double, 9>> R;
+    if (rotations) {
+      RK_REQUIRE(n_rot >= 1 && n_rot <= 4096, RKHSBA_EINVAL, "n_rot must be in [1, 4096]");
+      for (int k = 0; k < n_rot; ++k) {
+        std::array<double, 9> r;
+        for (int i = 0; i < 9; ++i) {
+          r[i] = rotations[9 * k + i];
+          RK_REQUIRE(std::isfinite(r[i]), RKHSBA_EINVAL, "non-finite rotation entry");
+        }
+        R.push_back(r);
+      }
+    } else {
+      R = icosahedral_group();
+      RK_REQUIRE(n_rot == 0 || n_rot == (int)R.size(), RKHSBA_EINVAL, "n_rot must be 0 or 60 without rotations");
+    }
+    const int nr = (int)R.size();
+    g.upload_poses(p, poses);
+    double ctr[3];
+    g.frame_centroid(p, n, ctr);
+    // candidate pose T_n G_k with G_k(x) = R_k (x - c) + c
+    const double* Tn = poses + 12 * n;
+    std::vector<double> cand((size_t)12 * nr);
+    for (int k = 0; k < nr; ++k) {
+      const auto& Rk = R[k];
+      double* T = &cand[(size_t)12 * k];
+      double gt[3];
+      for (int a = 0; a < 3; ++a) gt[a] = ctr[a] - (Rk[3 * a] * ctr[0] + Rk[3 * a + 1] * ctr[1] + Rk[3 * a + 2] * ctr[2]);
+      for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+          T[3 * a + b] = Tn[3 * a] * Rk[b] + Tn[3 * a + 1] * Rk[3 + b] + Tn[3 * a + 2] * Rk[6 + b];
+        T[9 + a] = Tn[3 * a] * gt[0] + Tn[3 * a + 1] * gt[1] + Tn[3 * a + 2] * gt[2] + Tn[9 + a];
+      }
+    }
+    g.set_aliases(p, n, nr, cand.data());
+    std::vector<int32_t> edges((size_t)2 * nr);
+    for (int k = 0; k < nr; ++k) {
+      edges[2 * k] = m;
+      edges[2 * k + 1] = p->K + k;
+    }
+    g.prepare(c->lay_rot, {SetItem{p, edges.data(), nr, -1, 0}});
+    g.evaluate(c->lay_rot, MODE_LOSS);
+    std::vector<double> eo((size_t)nr * kEdgeVals);
+    RK_HIP(hipMemcpyAsync(eo.data(), g.edge_out(), sizeof(double) * eo.size(), hipMemcpyDeviceToHost, c->stream));
+    RK_HIP(hipStreamSynchronize(c->stream));
+    g.prof_collect();
+    g.clear_aliases(p);
+    const double s2 = c->opt.sigma * c->opt.sigma;
+    int kb = 0;
+    for (int k = 0; k < nr; ++k) {
+      const double f = s2 * eo[(size_t)k * kEdgeVals];
+      if (scores) scores[k] = f;
+      if (f > s2 * eo[(size_t)kb * kEdgeVals]) kb = k;
+    }
+    if (best) *best = kb;
+    if (best_pose) std::copy(&cand[(size_t)12 * kb], &cand[(size_t)12 * kb] + 12, best_pose);
     return RKHSBA_OK;
   });
 }

@@ -145,6 +145,10 @@ struct Problem {
   std::vector<FrameInfo> frames;    // pool offsets
   std::vector<int64_t> n_points;
   int64_t resident_bytes = 0;       // pool bytes held by the problem
+  // aliases: extra frame slots sharing one frame's resident points, each with its own pose
+  // (local frame indices K .. K + n_alias - 1); used to evaluate a batch of candidate poses
+  int alias_of = -1, n_alias = 0;
+  int64_t alias_slot0 = -1;
   double occupancy = 0.0;           // points per occupied cell of the problem's grid
   double occupancy_r = 0.0;         // points per occupied cell of edge r_c (0: not measured)
 };
@@ -156,6 +160,7 @@ struct SetItem {
   int E;
   int fixed;             // frame removed from the system (-1: none)
   int n_iter;            // Gauss-Newton iterations (history length n_iter + 1)
+  bool allow_self = false;  // evaluation-only sets may pair a frame with itself (m == n)
 };
 
 // Work layout of a set (rebuilt when the set changes).
@@ -227,6 +232,11 @@ class Engine {
   int64_t estimate_problem_bytes(int K, const int64_t* n_points, int E) const;
 
   void upload_poses(Problem* p, const double* poses);   // host K*12
+  // count alias slots of `frame` with the given host poses (count*12); replaces earlier aliases
+  void set_aliases(Problem* p, int frame, int count, const double* poses);
+  void clear_aliases(Problem* p);
+  // FP64 centroid of a frame's local coordinates (fixed summation order)
+  void frame_centroid(Problem* p, int frame, double c[3]);
   void download_poses(Problem* p, double* poses);       // host K*12 (synchronises the stream)
   void ensure_history(Problem* p, int n_iter);
   void reset_state(Problem* p);                          // iter = 0, status = 0 (stream-ordered copy)

@@ -534,6 +534,7 @@ void Engine::remove_problem(int id) {
   slots_.free(p->slot0, p->K);
   state_.free(p->sbase, 1);
   if (p->hbase >= 0) hist_.free(p->hbase, p->n_hist);
+  clear_aliases(p);
   probs_.erase(it);
 }
 
@@ -541,6 +542,40 @@ void Engine::upload_poses(Problem* p, const double* poses) {
   RK_REQUIRE(poses != nullptr, RKHSBA_EINVAL, "poses is NULL");
   for (int i = 0; i < 12 * p->K; ++i) RK_REQUIRE(std::isfinite(poses[i]), RKHSBA_EINVAL, "non-finite pose entry");
   RK_HIP(hipMemcpyAsync(poses_ptr(p), poses, sizeof(double) * 12 * p->K, hipMemcpyHostToDevice, st));
+}
+
+void Engine::set_aliases(Problem* p, int frame, int count, const double* alias_poses) {
+  RK_REQUIRE(frame >= 0 && frame < p->K && count >= 1 && alias_poses, RKHSBA_EINVAL, "bad alias request");
+  for (int i = 0; i < 12 * count; ++i) RK_REQUIRE(std::isfinite(alias_poses[i]), RKHSBA_EINVAL, "non-finite pose entry");
+  if (p->n_alias != count) {
+    clear_aliases(p);
+    p->alias_slot0 = slots_.alloc(count, st);
+    p->n_alias = count;
+  }
+  p->alias_of = frame;
+  std::vector<FrameInfo> fr(count, p->frames[frame]);
+  RK_HIP(hipMemcpyAsync(static_cast<FrameInfo*>(slots_.ptr(0)) + p->alias_slot0, fr.data(), sizeof(FrameInfo) * count,
+                        hipMemcpyHostToDevice, st));
+  RK_HIP(hipMemcpyAsync(poses() + 12 * p->alias_slot0, alias_poses, sizeof(double) * 12 * count, hipMemcpyHostToDevice,
+                        st));
+  RK_HIP(hipStreamSynchronize(st));  // the host FrameInfo copies go out of scope
+}
+
+void Engine::clear_aliases(Problem* p) {
+  if (p->n_alias > 0) slots_.free(p->alias_slot0, p->n_alias);
+  p->alias_slot0 = -1;
+  p->n_alias = 0;
+  p->alias_of = -1;
+}
+
+void Engine::frame_centroid(Problem* p, int frame, double c[3]) {
+  RK_REQUIRE(frame >= 0 && frame < p->K, RKHSBA_EINVAL, "frame out of range");
+  DBuf<double> d;
+  RK_HIP(d.reserve(3));
+  const FrameInfo& F = p->frames[frame];
+  RK_HIP(launch_frame_centroid(pts() + F.pt_off, F.n, d.p, st));
+  RK_HIP(hipMemcpyAsync(c, d.p, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipStreamSynchronize(st));
 }
 
 void Engine::download_poses(Problem* p, double* poses) {
@@ -594,8 +629,9 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     RK_REQUIRE(it.n_iter >= 0, RKHSBA_EINVAL, "n_iter must be >= 0");
     for (int e = 0; e < it.E; ++e) {
       const int m = it.edges[2 * e], n = it.edges[2 * e + 1];
-      RK_REQUIRE(m >= 0 && n >= 0 && m < it.p->K && n < it.p->K, RKHSBA_EINVAL, "edge frame index out of range");
-      RK_REQUIRE(m != n, RKHSBA_EINVAL, "self-edge (m == n)");
+      const int Kx = it.p->K + it.p->n_alias;
+      RK_REQUIRE(m >= 0 && n >= 0 && m < Kx && n < Kx, RKHSBA_EINVAL, "edge frame index out of range");
+      RK_REQUIRE(m != n || it.allow_self, RKHSBA_EINVAL, "self-edge (m == n)");
     }
     ensure_history(it.p, it.n_iter);
   }
@@ -608,6 +644,8 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     key.push_back(it.fixed);
     key.push_back(it.n_iter);
     key.push_back((int32_t)it.p->hbase);
+    key.push_back((int32_t)it.p->alias_slot0);
+    key.push_back(it.allow_self ? 1 : 0);
     key.insert(key.end(), it.edges, it.edges + 2 * it.E);
   }
   if (key == lay.edge_key && !lay.sys.empty()) return;
@@ -658,10 +696,12 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     for (int e = 0; e < it.E; ++e, ++e_glob) {
       const int m = it.edges[2 * e], n = it.edges[2 * e + 1];
       EdgeInfo& I = info[e_glob];
-      I.m = (int32_t)(p->slot0 + m);
-      I.n = (int32_t)(p->slot0 + n);
+      auto slot_of = [&](int f) { return f < p->K ? p->slot0 + f : p->alias_slot0 + (f - p->K); };
+      auto frame_of = [&](int f) -> const FrameInfo& { return p->frames[f < p->K ? f : p->alias_of]; };
+      I.m = (int32_t)slot_of(m);
+      I.n = (int32_t)slot_of(n);
       I.ent_off = entries;
-      I.n_src = p->frames[m].n;
+      I.n_src = frame_of(m).n;
       const int pp = p->par.pass_points;
       const int P = pp == 1 ? 64 : pp;  // per-point walks: 64 sources (one per lane) per pass
       const int gi = pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : 3;
@@ -675,7 +715,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       for (int k = 0; k < I.n_pass; ++k) {
         PassInfo Q;
         Q.entry0 = entries + (int64_t)k * P;
-        Q.src_off = p->frames[m].pt_off;
+        Q.src_off = frame_of(m).pt_off;
         Q.e = e_glob;
         Q.count = std::min(P, I.n_src - k * P);
         Q.tgt = I.n;
@@ -693,12 +733,14 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       entries += I.n_src;
       passes += I.n_pass;
       fins += I.n_fin;
-      blk[(size_t)m * K + m].push_back(e_glob * 4 + 0);
-      blk[(size_t)n * K + n].push_back(e_glob * 4 + 1);
-      blk[(size_t)m * K + n].push_back(e_glob * 4 + 2);
-      blk[(size_t)n * K + m].push_back(e_glob * 4 + 3);
-      vec[m].push_back(e_glob * 2 + 0);
-      vec[n].push_back(e_glob * 2 + 1);
+      if (m != n && m < K && n < K) {  // self and alias edges are evaluated but never assembled
+        blk[(size_t)m * K + m].push_back(e_glob * 4 + 0);
+        blk[(size_t)n * K + n].push_back(e_glob * 4 + 1);
+        blk[(size_t)m * K + n].push_back(e_glob * 4 + 2);
+        blk[(size_t)n * K + m].push_back(e_glob * 4 + 3);
+        vec[m].push_back(e_glob * 2 + 0);
+        vec[n].push_back(e_glob * 2 + 1);
+      }
     }
     S.blk0 = (int32_t)bstart_all.size();
     for (size_t k = 0; k < blk.size(); ++k) {

@@ -125,6 +125,9 @@ hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
                        int64_t n_total, const int4* d_rows, uint32_t* d_xtab, uint32_t* d_n_cells, hipStream_t st);
 
+// Mean of n points' xyz in FP64 (one workgroup, fixed summation order) -> out[3].
+hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipStream_t st);
+
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
                       const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,

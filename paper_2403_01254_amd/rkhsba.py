@@ -127,6 +127,10 @@ def lib():
         L.rkhsba_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.rkhsba_server_last_error.argtypes = [vp]
         L.rkhsba_server_last_error.restype = ctypes.c_char_p
+        L.rkhsba_icosahedral_rotations.argtypes = [_dp]
+        L.rkhsba_icosahedral_rotations.restype = None
+        L.rkhsba_rotation_search.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                             ctypes.POINTER(ctypes.c_int), _dp]
         L.rkhsba_profile_enable.argtypes = [vp, ctypes.c_int]
         L.rkhsba_profile_read.argtypes = [vp, ctypes.c_int, _dp, _i64p, ctypes.c_int]
         _lib = L
@@ -305,6 +309,24 @@ class Context:
         return perm, keys, org, dims
 
 
+    # -- rkhsba_rotation_search
+    def rotation_search(self, poses, m, n, rotations=None):
+        """Scores of candidate rotations of frame n about its centroid against frame m.
+        Returns (scores, best index, best pose (12,))."""
+        p = self._poses(poses)
+        if rotations is None:
+            nr, rp = 60, None
+            rot = None
+        else:
+            rot = np.ascontiguousarray(rotations, dtype=np.float64).reshape(-1, 9)
+            nr, rp = len(rot), _p(rot)
+        scores = np.zeros(nr)
+        best = ctypes.c_int()
+        bp = np.zeros(12)
+        self._check(lib().rkhsba_rotation_search(self._h, _p(p), int(m), int(n), 0 if rot is None else nr, rp,
+                                                 _p(scores), ctypes.byref(best), _p(bp)))
+        return scores, best.value, bp
+
     # -- rkhsba_profile_enable / rkhsba_profile_read
     def profile_enable(self, on=True):
         self._check(lib().rkhsba_profile_enable(self._h, int(bool(on))))
@@ -399,6 +421,13 @@ class Server:
         if rc != OK:
             raise RkhsbaError(rc, "rkhsba_server_stats_get failed")
         return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+
+def icosahedral_rotations():
+    """The library's 60 icosahedral rotations, (60, 3, 3)."""
+    out = np.zeros(60 * 9)
+    lib().rkhsba_icosahedral_rotations(_p(out))
+    return out.reshape(60, 3, 3)
 
 
 PROF_BUILD, PROF_BIN, PROF_PAIRS, PROF_PAIRS_LOSS, PROF_FINALIZE, PROF_SOLVE = range(6)

@@ -1,0 +1,92 @@
+"""GPU path of the NEXT features against the oracle: global rotation
+initialisation (Sec. IV-A)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from helpers import REL_TOL, ident
+from oracle import global_init as gi
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_2403_01254_amd import rkhsba
+    rkhsba.lib()
+    return rkhsba
+
+
+def match(Ra, Rb):
+    """index map a -> b of two lists of rotations (each must match exactly one)."""
+    d = np.abs(Ra.reshape(-1, 1, 9) - Rb.reshape(1, -1, 9)).max(axis=2)
+    idx = d.argmin(axis=1)
+    assert np.all(d[np.arange(len(Ra)), idx] < 1e-12)
+    assert len(set(idx.tolist())) == len(Ra)
+    return idx
+
+
+def test_library_group_is_the_icosahedral_group(rk):
+    match(rk.icosahedral_rotations(), gi.icosahedral_rotations())
+
+
+@pytest.mark.parametrize("name", ["two_view", "odometry_small"])
+def test_rotation_search_scores_match_oracle(rk, name):
+    p = scenes.two_view(0, n_points=3000) if name == "two_view" else scenes.odometry(2, n_frames=2, n_points=3000)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    scores, best, best_pose = ctx.rotation_search(p.init_poses, 0, 1)
+    op = oracle.Problem.from_scene(p)
+    oscores, obest, oR = gi.rotation_search(lambda P, e: oracle.normal_eqs(op, P, e, oracle.MEMBER_FP32_RULE)[0],
+                                            p.points[1], p.init_poses, 0, 1)
+    idx = match(rk.icosahedral_rotations(), oR)
+    err = np.linalg.norm(scores - oscores[idx]) / np.linalg.norm(oscores)
+    say(f"[rotsearch] {name}: best {best} (oracle {obest}), score {scores[best]:.6g}, normwise score error {err:.2e}")
+    assert err <= REL_TOL
+    assert idx[best] == obest
+    np.testing.assert_allclose(best_pose, gi.candidate_pose(p.init_poses[1], oR[obest],
+                                                            np.asarray(p.points[1], np.float64).mean(axis=0)),
+                               atol=1e-6)
+
+
+def test_rotation_search_then_gauss_newton_recovers_large_rotation(rk):
+    """An object-sized two-view scene (the two-view generator scaled to a 1 m
+    cube, like the paper's object registration of Sec. VI-A): frame 1 is
+    turned about its centroid by a large rotation that lies 10 degrees from a
+    group element.  The search picks that element, and Gauss-Newton steps from
+    its pose reach the ground truth."""
+    p = scenes.two_view(4, n_points=4000)
+    scale = 0.05
+    pts0 = (np.asarray(p.points[0], np.float64) * scale).astype(np.float32)
+    x = np.asarray(p.points[1], np.float64) * scale
+    gt1 = p.gt_poses[1].copy()
+    gt1[9:] *= scale
+    c = x.mean(axis=0)
+    G = rk.icosahedral_rotations()
+    turn = G[41].T @ gi._axis_angle([0.3, -0.5, 0.8], np.radians(10.0))   # 10 deg from the inverse of G[41]
+    z = ((x - c) @ turn.T + c).astype(np.float32)
+    gt = np.stack([p.gt_poses[0], gi.candidate_pose(gt1, turn.T, c)])
+    ell = p.ell * scale * 5.0
+    ctx = rk.Context(ell=ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors([pts0, z], p.feats, p.feat_kind)
+    poses0 = np.stack([ident(), ident()])
+    scores, best, best_pose = ctx.rotation_search(poses0, 0, 1)
+    geo = [np.degrees(np.arccos(np.clip((np.trace(G[k] @ turn) - 1) / 2, -1, 1))) for k in range(60)]
+    say(f"[rotsearch] chosen candidate {best}: {geo[best]:.1f} deg from the inverse turn (best possible "
+        f"{min(geo):.1f} deg)")
+    assert geo[best] == min(geo)
+    poses = poses0.copy()
+    poses[1] = best_pose
+    out, lpi, ppi = ctx.gn_step(poses, p.edges, 20)
+    R = out[1][:9].reshape(3, 3) @ gt[1][:9].reshape(3, 3).T
+    rot = np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))
+    say(f"[rotsearch] after 20 Gauss-Newton steps: rotation error {rot:.3f} deg, F {lpi[0]:.4g} -> {lpi[-1]:.4g}")
+    assert rot < 1.0
