@@ -161,6 +161,41 @@ int rkhsba_autotune(rkhsba_ctx* ctx, int K, const int64_t* n_points, const float
  * points per occupied r_c-cube (0 if that was not measured).  Nullable outputs. */
 int rkhsba_get_config(rkhsba_ctx* ctx, int* cell_subdiv, int* pass_points, double* occupancy);
 
+/* Lengthscale outer loop (Sec. V-C).  The RKHS distance of the graph is
+ * d_H = sum over edges of <f_m,f_m> + <f_n,f_n> - 2 <f_m,f_n> (Eq. (eq:dist_rkhs),
+ * truncated inner products of Eq. (eq:double_sum)); its derivative in ell is
+ * sigma^2 / ell^3 times sum(W_mm + W_nn - 2 W_mn), W = sum over pairs of w r^2
+ * (the truncation radius moving with ell is not differentiated).
+ * rkhsba_ell_gradient returns both at `poses` and the context's lengthscale. */
+int rkhsba_ell_gradient(rkhsba_ctx* ctx, const double* poses, int E, const int32_t* edges, double* d,
+                        double* dd_dell);
+
+typedef struct {
+  double ell_init;     /* starting lengthscale (large: wide basin, Sec. VII) */
+  double ell_min;      /* lengthscale range */
+  double ell_max;
+  double step;         /* fixed fractional change per outer iteration (0 < step < 1) */
+  double elasticity;   /* ell shrinks when -ell (d d_H / d ell) / d_H >= elasticity, grows otherwise */
+  double tol;          /* an inner loop raising F by at most tol |F| counts as converged */
+  int inner_iter;      /* Gauss-Newton steps per lengthscale */
+  int max_outer;       /* bound on outer iterations */
+} rkhsba_ell_schedule;
+
+/* Defaults for a base lengthscale ell: ell_init 4 ell, range [ell, 8 ell], step 0.1, elasticity 1,
+ * tol 1e-6, 5 inner steps, at most 30 outer iterations. */
+void rkhsba_default_ell_schedule(rkhsba_ell_schedule* s, double ell);
+
+/* Inner-outer loop: at the current ell, inner_iter Gauss-Newton steps (as rkhsba_gn_step); then
+ * d_H and its derivative at the new poses decide the fixed-percentage update of ell (elasticity
+ * rule above), clamped to the range.  Stops when the clamped update leaves ell unchanged and the
+ * inner loop no longer increased F (tol), or after max_outer.  The cell grid of the build is kept
+ * (any lengthscale is correct on it).  poses_inout is updated; n_outer (nullable) receives the
+ * outer iterations run; trace (nullable, 5 * max_outer doubles) one row per outer iteration:
+ * ell, F entering and leaving its inner loop, d_H and d d_H / d ell after it.  The context's own
+ * lengthscale is unchanged afterwards. */
+int rkhsba_gn_lengthscale(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* edges,
+                          const rkhsba_ell_schedule* schedule, int* n_outer, double* trace);
+
 /* The 60 rotations of the icosahedral group (Sec. IV-A: the identity, 15
  * half-turns about edge axes, 20 third-turns about face axes, 24 fifth-turns
  * about vertex axes), 9 doubles each (row-major), in the library's order. */

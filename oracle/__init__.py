@@ -66,6 +66,7 @@ def lib():
                                         ctypes.POINTER(ctypes.c_int64)]
         L.oracle_gn.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_int, dp]
+        L.oracle_edge_sums.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp]
         L.oracle_pairs.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ip]
         L.oracle_pairs.restype = ctypes.c_int64
         L.oracle_voxels.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
@@ -95,6 +96,7 @@ class Problem:
             self.feats = [np.ascontiguousarray(f, dtype=np.float32) for f in feats]
             D = int(self.feats[0].shape[1])
         self.feat_kind = feat_kind
+        self.ell, self.cutoff_factor, self.sigma = float(ell), float(cutoff_factor), float(sigma)
         self.K = len(self.points)
         self._n = np.array([len(p) for p in self.points], dtype=np.int64)
         self._xyz = (ctypes.c_void_p * self.K)(*[p.ctypes.data for p in self.points])
@@ -142,6 +144,19 @@ def gn(prob: Problem, poses, edges, n_iter, fixed_frame=0, damping_rel=1e-10, me
     if rc != 0:
         raise ValueError(f"oracle_gn failed ({rc})")
     return poses, lpi
+
+
+def edge_sums(prob: Problem, poses, edges, membership=MEMBER_FP64):
+    """Per-edge F and W = sum w |u|^2 (self-pairs (m, m) allowed)."""
+    poses = np.ascontiguousarray(poses, dtype=np.float64).reshape(prob.K, 12)
+    e = _edges(edges)
+    Fe = np.zeros(max(len(e), 1))
+    We = np.zeros(max(len(e), 1))
+    rc = lib().oracle_edge_sums(ctypes.byref(prob.c), _ptr(poses), len(e), _ptr(e, ctypes.c_int32), membership,
+                                _ptr(Fe), _ptr(We))
+    if rc != 0:
+        raise ValueError("oracle_edge_sums failed")
+    return Fe[:len(e)], We[:len(e)]
 
 
 def pairs(prob: Problem, poses, m, n):

@@ -112,6 +112,7 @@ static double label_product(const oracle_problem* P, int m, int64_t i, int n, in
 
 typedef struct {
   double F, bm[6], bn[6], Hmm[36], Hnn[36], Hmn[36];
+  double W;  /* sum of w |u|^2: the ell-derivative of the factor is sigma^2 W / ell^3 */
   int64_t pairs;
 } edge_acc;
 
@@ -189,6 +190,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
         if (c == 0.0) continue;
         double w = c * exp(-r2 * inv_2l2);
         a.F += s2sig * w;
+        a.W += w * r2;
         a.pairs += 1;
         double z[3] = {Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
         double Jn[3][6];
@@ -221,6 +223,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
   memset(out, 0, sizeof(*out));
   for (int64_t ch = 0; ch < n_chunks; ++ch) {
     out->F += acc[ch].F;
+    out->W += acc[ch].W;
     out->pairs += acc[ch].pairs;
     for (int r = 0; r < 6; ++r) {
       out->bm[r] += acc[ch].bm[r];
@@ -234,6 +237,23 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
   }
   free(acc);
   free(Wz);
+}
+
+/* Per-edge F and W = sum w |u|^2 (no sigma^2).  An edge may pair a frame with
+ * itself: that is the self inner product <f_X, f_X> of the RKHS distance,
+ * Eq. (eq:dist_rkhs), whose pair (i, i) has u = 0. */
+int oracle_edge_sums(const oracle_problem* P, const double* poses, int E, const int32_t* edges, int membership,
+                     double* F_edge, double* W_edge) {
+  if (check_problem(P) || !poses || E < 0 || (E > 0 && !edges)) return -1;
+  for (int e = 0; e < E; ++e) {
+    const int m = edges[2 * e], n = edges[2 * e + 1];
+    if (m < 0 || n < 0 || m >= P->K || n >= P->K) return -1;
+    edge_acc a;
+    edge_terms(P, poses, m, n, membership, &a);
+    if (F_edge) F_edge[e] = a.F;
+    if (W_edge) W_edge[e] = a.W;
+  }
+  return 0;
 }
 
 int oracle_normal_eqs(const oracle_problem* P, const double* poses, int E, const int32_t* edges,

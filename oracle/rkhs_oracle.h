@@ -48,6 +48,12 @@ typedef struct {
 int oracle_normal_eqs(const oracle_problem* P, const double* poses, int E, const int32_t* edges,
                       int membership, double* F, double* b, double* H, double* F_edge, int64_t* n_pairs);
 
+/* Per-edge F and W = sum over the kept pairs of w |u|^2 (u the world residual,
+ * w = c exp(-|u|^2 / 2 ell^2), no sigma^2).  Edges may be self-pairs (m == n).
+ * F_edge, W_edge: E doubles (nullable).  Returns 0 or -1. */
+int oracle_edge_sums(const oracle_problem* P, const double* poses, int E, const int32_t* edges, int membership,
+                     double* F_edge, double* W_edge);
+
 /* n_iter Gauss-Newton / IRLS steps in place on poses (frame `fixed_frame`
  * untouched).  loss_per_iter (n_iter+1, nullable) receives F at the poses
  * entering each step and after the last one.  Returns 0, -1 invalid,

@@ -26,6 +26,7 @@ struct rkhsba_ctx {
   SetLayout lay_eval;    // evaluations without a fixed frame (loss, normal equations)
   SetLayout lay_gn;      // Gauss-Newton runs
   SetLayout lay_rot;     // candidate-pose batches
+  SetLayout lay_ell;     // RKHS distance terms (graph edges and self inner products)
   double occ_r = 0.0;    // points per occupied r_c-cube of the frames last measured
 };
 
@@ -186,6 +187,7 @@ void rkhsba_destroy(rkhsba_ctx* c) {
   c->lay_eval.drop_graph();
   c->lay_gn.drop_graph();
   c->lay_rot.drop_graph();
+  c->lay_ell.drop_graph();
   c->eng.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -356,6 +358,134 @@ int rkhsba_gn_step(rkhsba_ctx* c, double* poses, int E, const int32_t* edges, in
       if (loss_per_iter) loss_per_iter[i] = lh[i];
       if (pairs_per_iter) pairs_per_iter[i] = (int64_t)ph[i];
     }
+    if (status != 0) {
+      c->err = "Cholesky pivot not positive in a Gauss-Newton step";
+      return RKHSBA_ENOTPD;
+    }
+    return RKHSBA_OK;
+  });
+}
+
+// d_H = sum over edges of <f_m,f_m> + <f_n,f_n> - 2 <f_m,f_n> and its ell-derivative
+// sigma^2 / ell^3 * sum(W_mm + W_nn - 2 W_mn), at the device poses.
+static void distance_terms(rkhsba_ctx* c, Problem* p, int E, const int32_t* edges, double* d, double* g) {
+  Engine& eng = *c->eng;
+  std::vector<int> frames;
+  for (int e = 0; e < 2 * E; ++e) frames.push_back(edges[e]);
+  std::sort(frames.begin(), frames.end());
+  frames.erase(std::unique(frames.begin(), frames.end()), frames.end());
+  std::vector<int32_t> all(edges, edges + 2 * E);
+  for (int f : frames) {
+    all.push_back(f);
+    all.push_back(f);
+  }
+  const int Et = (int)all.size() / 2;
+  SetItem it{p, all.data(), Et, -1, 0};
+  it.allow_self = true;
+  eng.prepare(c->lay_ell, {it});
+  eng.evaluate(c->lay_ell, MODE_NORMAL);
+  std::vector<double> eo((size_t)Et * kEdgeVals);
+  RK_HIP(hipMemcpyAsync(eo.data(), eng.edge_out(), sizeof(double) * eo.size(), hipMemcpyDeviceToHost, c->stream));
+  RK_HIP(hipStreamSynchronize(c->stream));
+  eng.prof_collect();
+  std::vector<double> S(p->K, 0.0), SW(p->K, 0.0);
+  for (size_t k = 0; k < frames.size(); ++k) {
+    S[frames[k]] = eo[(size_t)(E + k) * kEdgeVals];
+    SW[frames[k]] = eo[(size_t)(E + k) * kEdgeVals + 92];
+  }
+  double dd = 0.0, gw = 0.0;
+  for (int e = 0; e < E; ++e) {
+    const int m = edges[2 * e], n = edges[2 * e + 1];
+    dd += S[m] + S[n] - 2.0 * eo[(size_t)e * kEdgeVals];
+    gw += SW[m] + SW[n] - 2.0 * eo[(size_t)e * kEdgeVals + 92];
+  }
+  const double s2 = p->par.sigma * p->par.sigma, ell = p->par.ell;
+  *d = s2 * dd;
+  *g = s2 * gw / (ell * ell * ell);
+}
+
+void rkhsba_default_ell_schedule(rkhsba_ell_schedule* s, double ell) {
+  if (!s) return;
+  s->ell_init = 4.0 * ell;
+  s->ell_min = ell;
+  s->ell_max = 8.0 * ell;
+  s->step = 0.1;
+  s->elasticity = 1.0;
+  s->tol = 1e-6;
+  s->inner_iter = 5;
+  s->max_outer = 30;
+}
+
+int rkhsba_ell_gradient(rkhsba_ctx* c, const double* poses, int E, const int32_t* edges, double* d, double* dd_dell) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    RK_REQUIRE(E >= 1 && edges, RKHSBA_EINVAL, "need at least one edge");
+    c->eng->upload_poses(p, poses);
+    double dv = 0.0, gv = 0.0;
+    distance_terms(c, p, E, edges, &dv, &gv);
+    if (d) *d = dv;
+    if (dd_dell) *dd_dell = gv;
+    return RKHSBA_OK;
+  });
+}
+
+int rkhsba_gn_lengthscale(rkhsba_ctx* c, double* poses, int E, const int32_t* edges, const rkhsba_ell_schedule* sc,
+                          int* n_outer, double* trace) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    Engine& g = *c->eng;
+    RK_REQUIRE(sc != nullptr, RKHSBA_EINVAL, "schedule is NULL");
+    RK_REQUIRE(sc->ell_min > 0.0 && sc->ell_max >= sc->ell_min && std::isfinite(sc->ell_max) && sc->step > 0.0 &&
+                   sc->step < 1.0 && sc->inner_iter >= 0 && sc->max_outer >= 1 && sc->tol >= 0.0,
+               RKHSBA_EINVAL, "invalid lengthscale schedule");
+    RK_REQUIRE(c->opt.fixed_frame < p->K, RKHSBA_EINVAL, "fixed_frame out of range");
+    const double ell_build = p->par.ell;
+    struct Restore {
+      Engine& g;
+      Problem* p;
+      double ell;
+      ~Restore() { g.set_ell(p, ell); }
+    } restore{g, p, ell_build};
+    double ell = std::min(std::max(sc->ell_init, sc->ell_min), sc->ell_max);
+    const int ni = sc->inner_iter;
+    std::vector<double> lh(ni + 1);
+    int outer = 0;
+    int status = 0;
+    for (; outer < sc->max_outer; ++outer) {
+      g.set_ell(p, ell);
+      g.prepare(c->lay_gn, {SetItem{p, edges, E, c->opt.fixed_frame, ni}});
+      g.upload_poses(p, poses);
+      g.reset_state(p);
+      g.iterate(c->lay_gn, ni);
+      g.evaluate(c->lay_gn, MODE_LOSS);
+      g.loss_only(c->lay_gn);
+      g.download_poses(p, poses);
+      g.read_history(p, ni + 1, lh.data(), nullptr);
+      status = g.read_status(p);
+      double d = 0.0, gr = 0.0;
+      distance_terms(c, p, E, edges, &d, &gr);
+      if (trace) {
+        double* t = trace + 5 * outer;
+        t[0] = ell;
+        t[1] = lh[0];
+        t[2] = lh[ni];
+        t[3] = d;
+        t[4] = gr;
+      }
+      if (status != 0) {
+        ++outer;
+        break;
+      }
+      const double eta = d > 0.0 ? -ell * gr / d : 0.0;
+      double nxt = eta >= sc->elasticity ? ell * (1.0 - sc->step) : ell * (1.0 + sc->step);
+      nxt = std::min(std::max(nxt, sc->ell_min), sc->ell_max);
+      if (nxt == ell && lh[ni] - lh[0] <= sc->tol * std::fabs(lh[0])) {
+        ++outer;
+        break;
+      }
+      ell = nxt;
+    }
+    if (n_outer) *n_outer = outer;
     if (status != 0) {
       c->err = "Cholesky pivot not positive in a Gauss-Newton step";
       return RKHSBA_ENOTPD;

@@ -147,6 +147,7 @@ struct Problem {
   int64_t resident_bytes = 0;       // pool bytes held by the problem
   // aliases: extra frame slots sharing one frame's resident points, each with its own pose
   // (local frame indices K .. K + n_alias - 1); used to evaluate a batch of candidate poses
+  int kc_version = 0;               // bumped when the constants change (lengthscale updates)
   int alias_of = -1, n_alias = 0;
   int64_t alias_slot0 = -1;
   double occupancy = 0.0;           // points per occupied cell of the problem's grid
@@ -235,6 +236,9 @@ class Engine {
   // count alias slots of `frame` with the given host poses (count*12); replaces earlier aliases
   void set_aliases(Problem* p, int frame, int count, const double* poses);
   void clear_aliases(Problem* p);
+  // New lengthscale on the existing grid: r_c, the reach (and the reach in cells) and the kernel
+  // scale follow ell; the cells keep their size (correct for any ell, fastest near the build's).
+  void set_ell(Problem* p, double ell);
   // FP64 centroid of a frame's local coordinates (fixed summation order)
   void frame_centroid(Problem* p, int frame, double c[3]);
   void download_poses(Problem* p, double* poses);       // host K*12 (synchronises the stream)

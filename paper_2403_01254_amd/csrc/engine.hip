@@ -561,6 +561,20 @@ void Engine::set_aliases(Problem* p, int frame, int count, const double* alias_p
   RK_HIP(hipStreamSynchronize(st));  // the host FrameInfo copies go out of scope
 }
 
+void Engine::set_ell(Problem* p, double ell) {
+  RK_REQUIRE(ell > 0.0 && std::isfinite(ell), RKHSBA_EINVAL, "lengthscale must be positive");
+  p->par.ell = ell;
+  KConst k = p->kc;
+  const double rc = p->par.cutoff_factor * ell;
+  k.reach = rc * (1.0 + std::ldexp(1.0, -12));
+  k.reach2 = k.reach * k.reach;
+  k.rc2 = (float)(rc * rc);
+  k.alpha = (float)(1.4426950408889634 / (2.0 * ell * ell));
+  k.reach_cells = (int)std::ceil(k.reach * k.inv_cell) + 1;
+  p->kc = k;
+  ++p->kc_version;
+}
+
 void Engine::clear_aliases(Problem* p) {
   if (p->n_alias > 0) slots_.free(p->alias_slot0, p->n_alias);
   p->alias_slot0 = -1;
@@ -646,6 +660,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     key.push_back((int32_t)it.p->hbase);
     key.push_back((int32_t)it.p->alias_slot0);
     key.push_back(it.allow_self ? 1 : 0);
+    key.push_back(it.p->kc_version);
     key.insert(key.end(), it.edges, it.edges + 2 * it.E);
   }
   if (key == lay.edge_key && !lay.sys.empty()) return;

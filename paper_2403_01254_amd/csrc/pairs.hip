@@ -230,13 +230,13 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
 //        = [[-A R_mn, R_mn [S]], [-[A x] R_mn, [x] R_mn [S]]]
 // so it suffices to sum, per edge, the 37 products
 //   A, B, x cross Bm, q cross B, A x, A x x^T (6), A q, Szz (6), x S^T (9)
-// (plus the pair count) and to expand the sums into the 91 values once per
+// (plus tr C = sum w |d|^2, the lengthscale derivative's term, and the pair count) and to expand the sums into the 91 values once per
 // edge.  Sums run in FP64: per thread over its entries, then per block in a
 // fixed order, then per edge over the blocks in order; the split into
 // blocks depends only on the edge's source count, so an edge's sums do not
 // depend on what else is evaluated with it.
 constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
-              kStXS = 28, kStCnt = 37;
+              kStXS = 28, kStWr2 = 37, kStCnt = 38;
 
 // Running sums: FP64, or FP32 with Kahan compensation (option).
 template <typename T>
@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st[kStXS + 3 * r + c].add(x[r] * S[c]);
+      st[kStWr2].add(C[0] + C[3] + C[5]);
     }
   }
   // block sum in a fixed order: wavefront shuffles, then the four waves
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
   double* out = edge_out + (int64_t)blockIdx.x * kEdgeVals;
   if (mode == MODE_LOSS) {
     for (int k = threadIdx.x; k < kEdgeVals; k += blockDim.x)
-      out[k] = k == 0 ? (double)T[0] : k == 91 ? n_pairs : 0.0;
+      out[k] = k == 0 ? (double)T[0] : k == 91 ? n_pairs : 0.0;  // (sum w r^2 needs the moments)
     return;
   }
   if (threadIdx.x != 0) return;
@@ -472,6 +473,7 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
   for (int r = 0; r < 6; ++r)
     for (int c = 0; c < 6; ++c) v[55 + 6 * r + c] = Hmn[r][c];
   v[91] = (TT)0;
+  v[92] = T[kStWr2];
   for (int k = 0; k < kEdgeVals; ++k) out[k] = (double)v[k];
   out[91] = n_pairs;
 }

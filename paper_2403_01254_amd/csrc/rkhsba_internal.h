@@ -173,9 +173,9 @@ struct FinArgs {
   int32_t E;
   int32_t n_fin_total;
 };
-constexpr int kEdgeVals = 92;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count
+constexpr int kEdgeVals = 93;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count, sum w r^2
 constexpr int kFinThreads = 256;
-constexpr int kFinStats = 38;  // per-edge sums the normal-equation blocks are expanded from (+ pair count)
+constexpr int kFinStats = 39;  // per-edge sums the normal-equation blocks are expanded from, sum w r^2, pair count
 // fp32_sums: per-point terms and their sums in FP32 with Kahan compensation,
 // else FP64.  Pair counts are summed in FP64.
 hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, bool fp32_sums, hipStream_t st);

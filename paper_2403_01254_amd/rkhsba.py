@@ -89,6 +89,11 @@ class ServerStats(ctypes.Structure):
                                                "max_active", "peak_device_bytes", "pair_evals")]
 
 
+class EllSchedule(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("ell_init", "ell_min", "ell_max", "step", "elasticity", "tol")] + \
+               [("inner_iter", ctypes.c_int), ("max_outer", ctypes.c_int)]
+
+
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -127,6 +132,11 @@ def lib():
         L.rkhsba_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.rkhsba_server_last_error.argtypes = [vp]
         L.rkhsba_server_last_error.restype = ctypes.c_char_p
+        L.rkhsba_ell_gradient.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp]
+        L.rkhsba_default_ell_schedule.argtypes = [ctypes.POINTER(EllSchedule), ctypes.c_double]
+        L.rkhsba_default_ell_schedule.restype = None
+        L.rkhsba_gn_lengthscale.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.POINTER(EllSchedule),
+                                            ctypes.POINTER(ctypes.c_int), _dp]
         L.rkhsba_icosahedral_rotations.argtypes = [_dp]
         L.rkhsba_icosahedral_rotations.restype = None
         L.rkhsba_rotation_search.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
@@ -308,6 +318,31 @@ class Context:
                                                _p(dims, ctypes.c_int32)))
         return perm, keys, org, dims
 
+
+    # -- rkhsba_ell_gradient
+    def ell_gradient(self, poses, edges):
+        """(d_H, d d_H / d ell) at the poses and the context's lengthscale."""
+        p, e = self._poses(poses), self._edges(edges)
+        d, g = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().rkhsba_ell_gradient(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(d),
+                                              ctypes.byref(g)))
+        return d.value, g.value
+
+    # -- rkhsba_gn_lengthscale
+    def gn_lengthscale(self, poses, edges, **schedule):
+        """Inner-outer loop; schedule fields as rkhsba_ell_schedule (defaults from the context's ell).
+        Returns (poses, trace rows (ell, F_start, F_end, d_H, g))."""
+        sc = EllSchedule()
+        lib().rkhsba_default_ell_schedule(ctypes.byref(sc), self.opts.ell)
+        for k, v in schedule.items():
+            setattr(sc, k, v)
+        p = self._poses(poses).copy()
+        e = self._edges(edges)
+        trace = np.zeros((sc.max_outer, 5))
+        n = ctypes.c_int()
+        self._check(lib().rkhsba_gn_lengthscale(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(sc),
+                                                ctypes.byref(n), _p(trace)))
+        return p, trace[:n.value]
 
     # -- rkhsba_rotation_search
     def rotation_search(self, poses, m, n, rotations=None):

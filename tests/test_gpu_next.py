@@ -90,3 +90,48 @@ def test_rotation_search_then_gauss_newton_recovers_large_rotation(rk):
     rot = np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))
     say(f"[rotsearch] after 20 Gauss-Newton steps: rotation error {rot:.3f} deg, F {lpi[0]:.4g} -> {lpi[-1]:.4g}")
     assert rot < 1.0
+
+
+# ---------------------------------------------------------------- lengthscale outer loop (Sec. V-C)
+
+from oracle import lengthscale as ls  # noqa: E402
+
+
+@pytest.mark.parametrize("name", ["two_view", "odometry_small"])
+def test_distance_and_derivative_match_oracle(rk, name):
+    p = scenes.two_view(1, n_points=2000) if name == "two_view" else scenes.odometry(3, n_frames=3, n_points=2500)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, sigma=1.3)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    d, g = ctx.ell_gradient(p.init_poses, p.edges)
+
+    def make(ell):
+        return oracle.Problem(p.points, p.feats, p.feat_kind, ell, p.cutoff_factor, sigma=1.3)
+
+    od, og = ls.distance_and_derivative(make, p.ell, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
+    say(f"[ell] {name}: d_H {d:.6g} / {od:.6g}, derivative {g:.6g} / {og:.6g}")
+    assert abs(d - od) <= REL_TOL * max(abs(od), 1.0) and abs(g - og) <= REL_TOL * abs(og)
+
+
+def test_lengthscale_loop_matches_oracle(rk):
+    p = scenes.two_view(1, n_points=1500)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    sched = dict(ell_init=0.4, ell_min=0.1, ell_max=0.8, inner_iter=3, max_outer=20)
+    poses, trace = ctx.gn_lengthscale(p.init_poses, p.edges, **sched)
+
+    def make(ell):
+        return oracle.Problem(p.points, p.feats, p.feat_kind, ell, p.cutoff_factor)
+
+    oposes, otrace = ls.gn_lengthscale(make, p.init_poses, p.edges, membership=oracle.MEMBER_FP32_RULE, **sched)
+    say(f"[ell] outer iterations {len(trace)} (oracle {len(otrace)}); ell {trace[0, 0]:.3g} -> {trace[-1, 0]:.3g}")
+    assert len(trace) == len(otrace)
+    np.testing.assert_allclose(trace[:, 0], otrace[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(trace[:, 1:3], otrace[:, 1:3], rtol=REL_TOL)
+    from helpers import ROT_TOL, TRANS_TOL, pose_errors
+    rot, tr = pose_errors(poses, oposes)
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    # the context's own lengthscale is back in place afterwards
+    F0 = ctx.eval_loss(p.init_poses, p.edges)[0]
+    ref = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    ref.build_neighbors(p.points, p.feats, p.feat_kind)
+    assert abs(F0 - ref.eval_loss(p.init_poses, p.edges)[0]) <= 1e-12 * abs(F0)

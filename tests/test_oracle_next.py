@@ -48,3 +48,69 @@ def test_rotation_search_recovers_a_group_rotation():
     F_same = oracle.normal_eqs(same, poses, [[0, 1]], oracle.MEMBER_FP32_RULE)[0]
     assert abs(scores[best] - F_same) <= 1e-5 * F_same            # the candidate re-aligns the copy
     assert np.partition(scores, -2)[-2] < 0.9 * scores[best]       # and is clearly the largest
+
+
+# ---------------------------------------------------------------- lengthscale (Sec. V-C)
+
+from oracle import lengthscale as ls  # noqa: E402
+
+
+def test_edge_sum_W_two_points():
+    """W of one pair is w |u|^2 (closed form)."""
+    x = np.array([[0.1, -0.2, 0.05]], np.float32)
+    z = np.array([[0.15, -0.1, 0.0]], np.float32)
+    feats = [np.array([[0.6, 0.8]], np.float32), np.array([[1.0, 0.5]], np.float32)]
+    prob = oracle.Problem([x, z], feats, "dense", 0.1, 3.0, sigma=1.7)
+    I = np.concatenate([np.eye(3).reshape(9), np.zeros(3)])
+    F, W = oracle.edge_sums(prob, np.stack([I, I]), [[0, 1]])
+    r2 = float(np.sum((x.astype(np.float64) - z) ** 2))
+    c = float(np.dot(feats[0][0].astype(np.float64), feats[1][0].astype(np.float64)))
+    w = c * np.exp(-r2 / (2 * 0.1 ** 2))
+    assert abs(W[0] - w * r2) <= 1e-14 * w * r2 and abs(F[0] - 1.7 ** 2 * w) <= 1e-14 * F[0]
+
+
+def test_distance_derivative_matches_finite_differences():
+    """d d_H / d ell = sigma^2 sum(W) / ell^3 against a central difference of
+    d_H (truncation at 12 ell, where the moving boundary carries < e^-72)."""
+    import scenes
+    p = scenes.odometry(7, n_frames=3, n_points=700)
+
+    def make(ell):
+        return oracle.Problem(p.points, p.feats, p.feat_kind, ell, 12.0, sigma=1.3)
+
+    for ell in (0.08, 0.2):
+        d, g = ls.distance_and_derivative(make, ell, p.init_poses, p.edges, oracle.MEMBER_FP64)
+        h = ell * 1e-4
+        dp, _ = ls.distance_and_derivative(make, ell + h, p.init_poses, p.edges, oracle.MEMBER_FP64)
+        dm, _ = ls.distance_and_derivative(make, ell - h, p.init_poses, p.edges, oracle.MEMBER_FP64)
+        fd = (dp - dm) / (2 * h)
+        assert abs(fd - g) <= 1e-6 * abs(g), (ell, fd, g)
+
+
+def test_distance_vanishes_for_identical_frames():
+    x = (np.random.default_rng(2).normal(size=(400, 3)) * 0.3).astype(np.float32)
+    ids = np.random.default_rng(3).integers(0, 4, size=400).astype(np.uint16)
+
+    def make(ell):
+        return oracle.Problem([x, x], [ids, ids], "class", ell)
+
+    I = np.concatenate([np.eye(3).reshape(9), np.zeros(3)])
+    d, g = ls.distance_and_derivative(make, 0.1, np.stack([I, I]), [[0, 1]], oracle.MEMBER_FP64)
+    assert abs(d) <= 1e-9 * make(0.1).K * 400 and abs(g) <= 1e-6
+
+
+def test_lengthscale_loop_refines_and_stops():
+    """From a coarse start the loop ends at the finest allowed lengthscale with
+    the objective no longer increasing, and the poses approach the ground truth."""
+    import scenes
+    p = scenes.two_view(1, n_points=800)
+
+    def make(ell):
+        return oracle.Problem(p.points, p.feats, p.feat_kind, ell, 3.0)
+
+    poses, trace = ls.gn_lengthscale(make, p.init_poses, p.edges, ell_init=0.4, ell_min=0.1, ell_max=0.8,
+                                     inner_iter=4, max_outer=25)
+    assert trace[-1, 0] == 0.1 and trace[:, 0].max() <= 0.8
+    assert trace[-1, 2] - trace[-1, 1] <= 1e-6 * abs(trace[-1, 1])
+    R = poses[1][:9].reshape(3, 3) @ p.gt_poses[1][:9].reshape(3, 3).T
+    assert np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))) < 0.5
