@@ -196,6 +196,23 @@ void rkhsba_default_ell_schedule(rkhsba_ell_schedule* s, double ell);
 int rkhsba_gn_lengthscale(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* edges,
                           const rkhsba_ell_schedule* schedule, int* n_outer, double* trace);
 
+/* Frame-to-frame tracking (Sec. III-A: the two-frame registration that
+ * initialises the graph, solved by gradient ascent on the inner product of
+ * Eq. (eq:double_sum)).  Frame m stays fixed; frame n moves by right
+ * perturbations along grad F = -(sigma^2/ell^2) b_n (normalised) with a step
+ * length s: a step is accepted when F increases (then s grows by 1.5),
+ * otherwise s halves and the step is retried; the run ends after max_iter
+ * accepted steps or when s drops below step_min.  step0: the first step
+ * length (e.g. ell).  poses_inout: K*12, frame n's pose is updated.
+ * iters (nullable): accepted steps; loss (nullable): the final F of the edge. */
+int rkhsba_track(rkhsba_ctx* ctx, double* poses_inout, int m, int n, int max_iter, double step0, double step_min,
+                 int* iters, double* loss);
+
+/* Cosine alignment of frames m and n at `poses`: <f_m, f_n> / sqrt(<f_m,f_m> <f_n,f_n>)
+ * (Sec. IV-A and the keyframe rule of Sec. VI-C: a new frame becomes a keyframe when
+ * its alignment with the latest keyframe falls below a threshold). */
+int rkhsba_cosine(rkhsba_ctx* ctx, const double* poses, int m, int n, double* cos_out);
+
 /* The 60 rotations of the icosahedral group (Sec. IV-A: the identity, 15
  * half-turns about edge axes, 20 third-turns about face axes, 24 fifth-turns
  * about vertex axes), 9 doubles each (row-major), in the library's order. */

@@ -404,6 +404,131 @@ static void distance_terms(rkhsba_ctx* c, Problem* p, int E, const int32_t* edge
   *g = s2 * gw / (ell * ell * ell);
 }
 
+// F of one edge and the 6-vector b of frame n (Gauss-Newton sums, no frame removed) at host poses.
+static double edge_value_and_b(rkhsba_ctx* c, Problem* p, const double* poses, int m, int n, double* bn) {
+  Engine& eng = *c->eng;
+  const int32_t edge[2] = {m, n};
+  eng.prepare(c->lay_eval, {SetItem{p, edge, 1, -1, 0}});
+  eng.upload_poses(p, poses);
+  std::vector<double> eo(kEdgeVals);
+  if (bn) {
+    eng.evaluate(c->lay_eval, MODE_NORMAL);
+  } else {
+    eng.evaluate(c->lay_eval, MODE_LOSS);
+  }
+  RK_HIP(hipMemcpyAsync(eo.data(), eng.edge_out(), sizeof(double) * kEdgeVals, hipMemcpyDeviceToHost, c->stream));
+  RK_HIP(hipStreamSynchronize(c->stream));
+  eng.prof_collect();
+  if (bn)
+    for (int r = 0; r < 6; ++r) bn[r] = eo[7 + r];  // b_n of the edge: the 6-vector of its second frame
+  return p->par.sigma * p->par.sigma * eo[0];
+}
+
+// T <- T exp(xi^), closed-form SE(3) exponential (host, FP64).
+static void host_right_update(double* T, const double* xi) {
+  const double* rho = xi;
+  const double* phi = xi + 3;
+  const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  const double th = std::sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    A = std::sin(th) / th;
+    B = (1.0 - std::cos(th)) / th2;
+    C = (th - std::sin(th)) / (th2 * th);
+  }
+  const double K[3][3] = {{0.0, -phi[2], phi[1]}, {phi[2], 0.0, -phi[0]}, {-phi[1], phi[0], 0.0}};
+  double K2[3][3], Re[3][3], V[3][3], te[3], R[3][3], t[3];
+  for (int r = 0; r < 3; ++r)
+    for (int c2 = 0; c2 < 3; ++c2) K2[r][c2] = K[r][0] * K[0][c2] + K[r][1] * K[1][c2] + K[r][2] * K[2][c2];
+  for (int r = 0; r < 3; ++r)
+    for (int c2 = 0; c2 < 3; ++c2) {
+      const double I = r == c2 ? 1.0 : 0.0;
+      Re[r][c2] = I + A * K[r][c2] + B * K2[r][c2];
+      V[r][c2] = I + B * K[r][c2] + C * K2[r][c2];
+    }
+  for (int r = 0; r < 3; ++r) te[r] = V[r][0] * rho[0] + V[r][1] * rho[1] + V[r][2] * rho[2];
+  for (int r = 0; r < 3; ++r) {
+    for (int c2 = 0; c2 < 3; ++c2) R[r][c2] = T[3 * r + c2];
+    t[r] = T[9 + r];
+  }
+  for (int r = 0; r < 3; ++r) {
+    for (int c2 = 0; c2 < 3; ++c2) T[3 * r + c2] = R[r][0] * Re[0][c2] + R[r][1] * Re[1][c2] + R[r][2] * Re[2][c2];
+    T[9 + r] = R[r][0] * te[0] + R[r][1] * te[1] + R[r][2] * te[2] + t[r];
+  }
+}
+
+int rkhsba_cosine(rkhsba_ctx* c, const double* poses, int m, int n, double* cos_out) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    RK_REQUIRE(m >= 0 && n >= 0 && m < p->K && n < p->K && m != n, RKHSBA_EINVAL, "bad frame pair");
+    c->eng->upload_poses(p, poses);
+    const int32_t e[6] = {m, n, m, m, n, n};
+    SetItem it{p, e, 3, -1, 0};
+    it.allow_self = true;
+    c->eng->prepare(c->lay_ell, {it});
+    c->eng->evaluate(c->lay_ell, MODE_LOSS);
+    std::vector<double> eo((size_t)3 * kEdgeVals);
+    RK_HIP(hipMemcpyAsync(eo.data(), c->eng->edge_out(), sizeof(double) * eo.size(), hipMemcpyDeviceToHost,
+                          c->stream));
+    RK_HIP(hipStreamSynchronize(c->stream));
+    c->eng->prof_collect();
+    const double Fmn = eo[0], Sm = eo[kEdgeVals], Sn = eo[2 * kEdgeVals];
+    if (cos_out) *cos_out = (Sm > 0.0 && Sn > 0.0) ? Fmn / std::sqrt(Sm * Sn) : 0.0;
+    return RKHSBA_OK;
+  });
+}
+
+int rkhsba_track(rkhsba_ctx* c, double* poses, int m, int n, int max_iter, double step0, double step_min,
+                 int* iters_out, double* loss_out) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    RK_REQUIRE(m >= 0 && n >= 0 && m < p->K && n < p->K && m != n, RKHSBA_EINVAL, "bad frame pair");
+    RK_REQUIRE(max_iter >= 0 && step0 > 0.0 && step_min > 0.0 && step_min <= step0, RKHSBA_EINVAL,
+               "bad tracking parameters");
+    for (int i = 0; i < 12 * p->K; ++i) RK_REQUIRE(std::isfinite(poses[i]), RKHSBA_EINVAL, "non-finite pose entry");
+    const double s2 = p->par.sigma * p->par.sigma, l2 = p->par.ell * p->par.ell;
+    std::vector<double> P(poses, poses + 12 * p->K), Pc;
+    double bn[6];
+    double F = edge_value_and_b(c, p, P.data(), m, n, bn);
+    double s = step0;
+    int it = 0;
+    for (; it < max_iter && s >= step_min; ++it) {
+      double g[6], gn = 0.0;
+      for (int r = 0; r < 6; ++r) {
+        g[r] = -(s2 / l2) * bn[r];  // grad of F w.r.t. the right perturbation of frame n
+        gn += g[r] * g[r];
+      }
+      gn = std::sqrt(gn);
+      if (!(gn > 0.0)) break;
+      bool accepted = false;
+      while (s >= step_min) {
+        double xi[6];
+        for (int r = 0; r < 6; ++r) xi[r] = s * g[r] / gn;
+        Pc = P;
+        host_right_update(&Pc[12 * n], xi);
+        const double Fc = edge_value_and_b(c, p, Pc.data(), m, n, nullptr);
+        if (Fc > F) {
+          P.swap(Pc);
+          s *= 1.5;
+          accepted = true;
+          break;
+        }
+        s *= 0.5;
+      }
+      if (!accepted) break;
+      F = edge_value_and_b(c, p, P.data(), m, n, bn);
+    }
+    std::copy(P.begin(), P.end(), poses);
+    if (iters_out) *iters_out = it;
+    if (loss_out) *loss_out = F;
+    return RKHSBA_OK;
+  });
+}
+
 void rkhsba_default_ell_schedule(rkhsba_ell_schedule* s, double ell) {
   if (!s) return;
   s->ell_init = 4.0 * ell;

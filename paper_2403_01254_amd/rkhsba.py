@@ -137,6 +137,9 @@ def lib():
         L.rkhsba_default_ell_schedule.restype = None
         L.rkhsba_gn_lengthscale.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.POINTER(EllSchedule),
                                             ctypes.POINTER(ctypes.c_int), _dp]
+        L.rkhsba_track.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double, ctypes.POINTER(ctypes.c_int), _dp]
+        L.rkhsba_cosine.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.rkhsba_icosahedral_rotations.argtypes = [_dp]
         L.rkhsba_icosahedral_rotations.restype = None
         L.rkhsba_rotation_search.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
@@ -343,6 +346,23 @@ class Context:
         self._check(lib().rkhsba_gn_lengthscale(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(sc),
                                                 ctypes.byref(n), _p(trace)))
         return p, trace[:n.value]
+
+    # -- rkhsba_track / rkhsba_cosine
+    def track(self, poses, m, n, max_iter=100, step0=None, step_min=None):
+        """Gradient-ascent registration of frame n to frame m.  Returns (poses, accepted steps, F)."""
+        p = self._poses(poses).copy()
+        s0 = self.opts.ell if step0 is None else step0
+        smin = 1e-4 * s0 if step_min is None else step_min
+        it, F = ctypes.c_int(), ctypes.c_double()
+        self._check(lib().rkhsba_track(self._h, _p(p), int(m), int(n), int(max_iter), float(s0), float(smin),
+                                       ctypes.byref(it), ctypes.byref(F)))
+        return p, it.value, F.value
+
+    def cosine(self, poses, m, n):
+        p = self._poses(poses)
+        v = ctypes.c_double()
+        self._check(lib().rkhsba_cosine(self._h, _p(p), int(m), int(n), ctypes.byref(v)))
+        return v.value
 
     # -- rkhsba_rotation_search
     def rotation_search(self, poses, m, n, rotations=None):

@@ -135,3 +135,44 @@ def test_lengthscale_loop_matches_oracle(rk):
     ref = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
     ref.build_neighbors(p.points, p.feats, p.feat_kind)
     assert abs(F0 - ref.eval_loss(p.init_poses, p.edges)[0]) <= 1e-12 * abs(F0)
+
+
+# ---------------------------------------------------------------- tracking and keyframe alignment
+
+from oracle import tracking as tk  # noqa: E402
+
+
+@pytest.mark.parametrize("name", ["two_view", "odometry_pair"])
+def test_tracking_matches_oracle(rk, name):
+    p = scenes.two_view(2, n_points=1500) if name == "two_view" else scenes.odometry(5, n_frames=2, n_points=2500)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    poses, it, F = ctx.track(p.init_poses, 0, 1, max_iter=40)
+    op = oracle.Problem.from_scene(p)
+    oposes, oit, oF = tk.track(op, p.init_poses, 0, 1, 40, p.ell, 1e-4 * p.ell, oracle.MEMBER_FP32_RULE)
+    from helpers import ROT_TOL, TRANS_TOL, pose_errors
+    rot, tr = pose_errors(poses, oposes)
+    say(f"[track] {name}: {it} accepted steps (oracle {oit}), F {F:.6g} / {oF:.6g}, rot {rot.max():.2e} "
+        f"trans {tr.max():.2e}")
+    assert it == oit
+    assert abs(F - oF) <= REL_TOL * abs(oF)
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+
+
+def test_cosine_matches_oracle_and_keyframe_rule(rk):
+    """Alignment of frame 0 with the later frames of a trajectory at the ground-
+    truth poses decreases as the views drift apart; with threshold 0.5 the
+    keyframe rule of Sec. VI-C selects the first frame whose alignment drops
+    below it."""
+    p = scenes.odometry(6, n_frames=6, n_points=2000)
+    ell = 0.3  # a scale above the point spacing of these 2,000-point views
+    ctx = rk.Context(ell=ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    op = oracle.Problem(p.points, p.feats, p.feat_kind, ell, p.cutoff_factor)
+    cos = [ctx.cosine(p.gt_poses, 0, k) for k in range(1, p.K)]
+    ocos = [tk.cosine(op, p.gt_poses, 0, k, oracle.MEMBER_FP32_RULE) for k in range(1, p.K)]
+    say(f"[cos] {np.round(cos, 4).tolist()}")
+    np.testing.assert_allclose(cos, ocos, rtol=REL_TOL)
+    key = next((k for k, c in enumerate(cos, start=1) if c < 0.5), None)
+    okey = next((k for k, c in enumerate(ocos, start=1) if c < 0.5), None)
+    assert key == okey and key is not None and key > 1

@@ -114,3 +114,34 @@ def test_lengthscale_loop_refines_and_stops():
     assert trace[-1, 2] - trace[-1, 1] <= 1e-6 * abs(trace[-1, 1])
     R = poses[1][:9].reshape(3, 3) @ p.gt_poses[1][:9].reshape(3, 3).T
     assert np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))) < 0.5
+
+
+# ---------------------------------------------------------------- tracking and keyframe alignment
+
+from oracle import tracking as tk  # noqa: E402
+
+
+def test_tracking_ascends_and_recovers_a_small_motion():
+    import scenes
+    p = scenes.two_view(2, n_points=600)
+    prob = oracle.Problem.from_scene(p)
+    F0 = oracle.normal_eqs(prob, p.init_poses, p.edges)[0]
+    poses, it, F = tk.track(prob, p.init_poses, 0, 1, 60, p.ell, 1e-4 * p.ell)
+    assert it > 0 and F > F0
+    R = poses[1][:9].reshape(3, 3) @ p.gt_poses[1][:9].reshape(3, 3).T
+    assert np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))) < 1.0
+    assert np.linalg.norm(poses[1][9:] - p.gt_poses[1][9:]) < 0.03
+
+
+def test_cosine_alignment():
+    x = (np.random.default_rng(4).normal(size=(300, 3)) * 0.4).astype(np.float32)
+    ids = np.random.default_rng(5).integers(0, 3, size=300).astype(np.uint16)
+    prob = oracle.Problem([x, x], [ids, ids], "class", 0.1)
+    I = np.concatenate([np.eye(3).reshape(9), np.zeros(3)])
+    assert abs(tk.cosine(prob, np.stack([I, I]), 0, 1) - 1.0) < 1e-14
+    far = I.copy()
+    far[9] = 100.0
+    assert tk.cosine(prob, np.stack([I, far]), 0, 1) == 0.0
+    near = I.copy()
+    near[9] = 0.05
+    assert 0.0 < tk.cosine(prob, np.stack([I, near]), 0, 1) < 1.0
