@@ -93,6 +93,12 @@ typedef struct {
                             stage timing, when enabled, runs the launches one by one instead) */
   int hessian_fp32;      /* 1 = per-edge sums of the normal-equation terms in FP32 with Kahan compensation,
                             0 = FP64 (default) */
+  int top_k;             /* 0 = every pair inside r_c (default); 1..8 = per source point and edge only the
+                            top_k pairs with the largest kernel values c exp(-r^2/2 ell^2) (Sec. VI-G: eight
+                            such neighbours sufficed on LiDAR), ranked in FP64 with ties broken by the
+                            smaller FP32 squared distance, then the smaller original index; class ids or
+                            float32 features; the per-point walks (pass_points 1) run the selection.
+                            rkhsba_export_pairs lists the selected pairs. */
   void* stream;          /* hipStream_t to run on; NULL = a stream owned by the context */
 } rkhsba_options;
 

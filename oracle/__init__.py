@@ -47,6 +47,7 @@ class _Problem(ctypes.Structure):
         ("cutoff_factor", ctypes.c_double),
         ("sigma", ctypes.c_double),
         ("clamp_negative_c", ctypes.c_int),
+        ("top_k", ctypes.c_int),
     ]
 
 
@@ -87,7 +88,8 @@ class Problem:
     points: list of (N_m, 3) float32; feats: list of (N_m,) uint16 class ids or
     (N_m, D) float32 rows; ell, cutoff_factor, sigma as in Eq. (eq:kernel)."""
 
-    def __init__(self, points, feats, feat_kind, ell, cutoff_factor=3.0, sigma=1.0, clamp_negative_c=True):
+    def __init__(self, points, feats, feat_kind, ell, cutoff_factor=3.0, sigma=1.0, clamp_negative_c=True,
+                 top_k=0):
         self.points = [np.ascontiguousarray(p, dtype=np.float32).reshape(-1, 3) for p in points]
         if feat_kind == "class":
             self.feats = [np.ascontiguousarray(f, dtype=np.uint16).reshape(-1) for f in feats]
@@ -102,7 +104,9 @@ class Problem:
         self._xyz = (ctypes.c_void_p * self.K)(*[p.ctypes.data for p in self.points])
         self._f = (ctypes.c_void_p * self.K)(*[f.ctypes.data for f in self.feats])
         self.c = _Problem(self.K, _ptr(self._n, ctypes.c_int64), self._xyz, 0 if feat_kind == "class" else 1, D,
-                          self._f, float(ell), float(cutoff_factor), float(sigma), int(bool(clamp_negative_c)))
+                          self._f, float(ell), float(cutoff_factor), float(sigma), int(bool(clamp_negative_c)),
+                          int(top_k))
+        self.top_k = int(top_k)
 
     @classmethod
     def from_scene(cls, p, **kw):

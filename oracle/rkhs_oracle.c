@@ -134,6 +134,100 @@ static int check_edges(const oracle_problem* P, int E, const int32_t* edges) {
 
 #define ORACLE_CHUNK 256
 
+/* One kept pair (i, j) of an edge: w = c exp(-r^2 / 2 ell^2) and the terms
+ * it adds to F, W, b and H (see edge_terms). */
+static void add_pair(edge_acc* a, double s2sig, double inv_2l2, const double Jm[3][6], const double Rn[3][3],
+                     const float* zj, const double u[3], double r2, double c) {
+  double w = c * exp(-r2 * inv_2l2);
+  a->F += s2sig * w;
+  a->W += w * r2;
+  a->pairs += 1;
+  double z[3] = {zj[0], zj[1], zj[2]};
+  double Jn[3][6];
+  jacobian(Rn, z, -1.0, Jn);
+  for (int r = 0; r < 6; ++r) {
+    double gm = 0.0, gn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      gm += Jm[k][r] * u[k];
+      gn += Jn[k][r] * u[k];
+    }
+    a->bm[r] += w * gm;
+    a->bn[r] += w * gn;
+    for (int s = 0; s < 6; ++s) {
+      double mm = 0.0, nn = 0.0, mn = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        mm += Jm[k][r] * Jm[k][s];
+        nn += Jn[k][r] * Jn[k][s];
+        mn += Jm[k][r] * Jn[k][s];
+      }
+      a->Hmm[6 * r + s] += w * mm;
+      a->Hnn[6 * r + s] += w * nn;
+      a->Hmn[6 * r + s] += w * mn;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ top-k truncation */
+
+/* Per-point truncation of the Time-Analysis paragraph of Sec. VI: each source
+ * point keeps only the top_k pairs with the largest kernel values.  The
+ * ranking value is the pair's weight c exp(-r^2 / 2 ell^2); only pairs inside
+ * the truncation radius with c > 0 are candidates.  Which pairs are kept is
+ * an integer decision, so with the FP32 membership rule it is taken on the
+ * rule's quantities: c rounded to float (class ids: 1; dense features: a
+ * float fused multiply-add chain in element order, clamped at 0 when
+ * negative c are clamped), s2 the rule's float squared distance, value
+ * (double)c * exp(-(double)s2 / 2 ell^2).  With FP64 membership the value
+ * uses the FP64 c and r^2.  Equal values: smaller squared distance first,
+ * then the smaller target index j. */
+typedef struct {
+  double key, s2;
+  int64_t j;
+} candidate;
+
+static int candidate_order(const void* pa, const void* pb) {
+  const candidate* a = (const candidate*)pa;
+  const candidate* b = (const candidate*)pb;
+  if (a->key != b->key) return a->key > b->key ? -1 : 1;
+  if (a->s2 != b->s2) return a->s2 < b->s2 ? -1 : 1;
+  return a->j < b->j ? -1 : (a->j > b->j ? 1 : 0);
+}
+
+static float label_product_f32(const oracle_problem* P, int m, int64_t i, int n, int64_t j) {
+  if (P->feat_kind == ORACLE_FEAT_CLASS) {
+    const uint16_t* lm = (const uint16_t*)P->feats[m];
+    const uint16_t* ln = (const uint16_t*)P->feats[n];
+    return lm[i] == ln[j] ? 1.0f : 0.0f;
+  }
+  const float* fm = (const float*)P->feats[m] + i * P->D;
+  const float* fn = (const float*)P->feats[n] + j * P->D;
+  float c = 0.0f;
+  for (int k = 0; k < P->D; ++k) c = fmaf(fm[k], fn[k], c);
+  if (P->clamp_negative_c) c = fmaxf(c, 0.0f);
+  return c;
+}
+
+/* Ranking candidate of pair (i, j); returns 0 when the pair is no candidate. */
+static int make_candidate(const oracle_problem* P, int m, int64_t i, int n, int64_t j, int membership,
+                          const float q32[3], double r2, double inv_2l2, candidate* out) {
+  if (membership == ORACLE_MEMBER_FP32_RULE) {
+    const float* z = P->xyz[n] + 3 * j;
+    float dx = q32[0] - z[0], dy = q32[1] - z[1], dz = q32[2] - z[2];
+    float s2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float c = label_product_f32(P, m, i, n, j);
+    if (!(c > 0.0f)) return 0;
+    out->key = (double)c * exp(-(double)s2 * inv_2l2);
+    out->s2 = (double)s2;
+  } else {
+    double c = label_product(P, m, i, n, j);
+    if (!(c > 0.0)) return 0;
+    out->key = c * exp(-r2 * inv_2l2);
+    out->s2 = r2;
+  }
+  out->j = j;
+  return 1;
+}
+
 /* One edge (m, n): the factor F^{mn} = sum_ij h(T_m x_i, T_n z_j) c_ij of
  * Eq. (eq:inner_product_actual_ba) over the pairs inside the truncation
  * radius (the sparsity remark of Sec. III-B), with
@@ -141,7 +235,8 @@ static int check_edges(const oracle_problem* P, int E, const int32_t* edges) {
  *   w = c_ij exp(-|u|^2 / (2 ell^2))             Eq. (eq:irls_weight)
  *   u = T_m x_i - T_n z_j                        residual d(.,.) of Sec. V-A
  * and the IRLS normal-equation terms of Eq. (eq:irls_final) with the weights
- * frozen: b += w J^T u, H += w J^T J, J = du/d[eps_m, eps_n]. */
+ * frozen: b += w J^T u, H += w J^T J, J = du/d[eps_m, eps_n].  With top_k > 0
+ * only each source point's top_k pairs (see make_candidate) are summed. */
 static void edge_terms(const oracle_problem* P, const double* poses, int m, int n, int membership,
                        edge_acc* out) {
   const int64_t Nm = P->n_points[m], Nn = P->n_points[n];
@@ -155,6 +250,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
   const float rc2_32 = (float)rc2;
   const double inv_2l2 = 1.0 / (2.0 * P->ell * P->ell);
   const double s2sig = P->sigma * P->sigma;
+  const int top_k = P->top_k;
   double Rnm[3][3], tnm[3];
   rule_relative(poses + 12 * m, poses + 12 * n, Rnm, tnm);
 
@@ -171,6 +267,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
   for (int64_t ch = 0; ch < n_chunks; ++ch) {
     edge_acc a;
     memset(&a, 0, sizeof(a));
+    candidate* cand = top_k > 0 ? (candidate*)malloc(sizeof(candidate) * (size_t)(Nn > 0 ? Nn : 1)) : NULL;
     const int64_t i1 = (ch + 1) * ORACLE_CHUNK < Nm ? (ch + 1) * ORACLE_CHUNK : Nm;
     for (int64_t i = ch * ORACLE_CHUNK; i < i1; ++i) {
       double x[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
@@ -180,43 +277,33 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
       rule_q32(Rnm, tnm, X + 3 * i, q32);
       double Jm[3][6];
       jacobian(Rm, x, +1.0, Jm);
+      int64_t nc = 0;
       for (int64_t j = 0; j < Nn; ++j) {
         const double* q = Wz + 3 * j;
         double u[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
         double r2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         int inside = membership == ORACLE_MEMBER_FP32_RULE ? rule_inside(q32, Z + 3 * j, rc2_32) : (r2 <= rc2);
         if (!inside) continue;
+        if (top_k > 0) {
+          nc += make_candidate(P, m, i, n, j, membership, q32, r2, inv_2l2, cand + nc);
+          continue;
+        }
         double c = label_product(P, m, i, n, j);
         if (c == 0.0) continue;
-        double w = c * exp(-r2 * inv_2l2);
-        a.F += s2sig * w;
-        a.W += w * r2;
-        a.pairs += 1;
-        double z[3] = {Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
-        double Jn[3][6];
-        jacobian(Rn, z, -1.0, Jn);
-        for (int r = 0; r < 6; ++r) {
-          double gm = 0.0, gn = 0.0;
-          for (int k = 0; k < 3; ++k) {
-            gm += Jm[k][r] * u[k];
-            gn += Jn[k][r] * u[k];
-          }
-          a.bm[r] += w * gm;
-          a.bn[r] += w * gn;
-          for (int s = 0; s < 6; ++s) {
-            double mm = 0.0, nn = 0.0, mn = 0.0;
-            for (int k = 0; k < 3; ++k) {
-              mm += Jm[k][r] * Jm[k][s];
-              nn += Jn[k][r] * Jn[k][s];
-              mn += Jm[k][r] * Jn[k][s];
-            }
-            a.Hmm[6 * r + s] += w * mm;
-            a.Hnn[6 * r + s] += w * nn;
-            a.Hmn[6 * r + s] += w * mn;
-          }
+        add_pair(&a, s2sig, inv_2l2, Jm, Rn, Z + 3 * j, u, r2, c);
+      }
+      if (top_k > 0) {
+        qsort(cand, (size_t)nc, sizeof(candidate), candidate_order);
+        for (int64_t t = 0; t < nc && t < top_k; ++t) {
+          const int64_t j = cand[t].j;
+          const double* q = Wz + 3 * j;
+          double u[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+          double r2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+          add_pair(&a, s2sig, inv_2l2, Jm, Rn, Z + 3 * j, u, r2, label_product(P, m, i, n, j));
         }
       }
     }
+    free(cand);
     acc[ch] = a;
   }
   /* chunks summed in a fixed order: the result does not depend on the thread count */
@@ -416,6 +503,11 @@ int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edge
 
 /* ------------------------------------------------------------------ neighbour list */
 
+static int cmp_i64(const void* pa, const void* pb) {
+  const int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
 int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n, int64_t cap, int32_t* pairs) {
   if (check_problem(P) || !poses || m < 0 || n < 0 || m >= P->K || n >= P->K || m == n || cap < 0) return -1;
   const int64_t Nm = P->n_points[m], Nn = P->n_points[n];
@@ -423,6 +515,7 @@ int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n,
   const float* Z = P->xyz[n];
   const double rc = P->cutoff_factor * P->ell;
   const float rc2_32 = (float)(rc * rc);
+  const double inv_2l2 = 1.0 / (2.0 * P->ell * P->ell);
   double Rnm[3][3], tnm[3];
   rule_relative(poses + 12 * m, poses + 12 * n, Rnm, tnm);
   int64_t* cnt = (int64_t*)calloc((size_t)(Nm + 1), sizeof(int64_t));
@@ -435,6 +528,26 @@ int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n,
       float q32[3];
       rule_q32(Rnm, tnm, X + 3 * i, q32);
       int64_t c = 0, o = pass ? cnt[i] : 0;
+      if (P->top_k > 0) { /* the top_k candidates of make_candidate, listed by j */
+        candidate* cand = (candidate*)malloc(sizeof(candidate) * (size_t)(Nn > 0 ? Nn : 1));
+        for (int64_t j = 0; j < Nn; ++j)
+          if (rule_inside(q32, Z + 3 * j, rc2_32))
+            c += make_candidate(P, m, i, n, j, ORACLE_MEMBER_FP32_RULE, q32, 0.0, inv_2l2, cand + c);
+        qsort(cand, (size_t)c, sizeof(candidate), candidate_order);
+        if (c > P->top_k) c = P->top_k;
+        int64_t* js = (int64_t*)malloc(sizeof(int64_t) * (size_t)(c > 0 ? c : 1));
+        for (int64_t t = 0; t < c; ++t) js[t] = cand[t].j;
+        qsort(js, (size_t)c, sizeof(int64_t), cmp_i64);
+        for (int64_t t = 0; pass && t < c; ++t)
+          if (o + t < cap) {
+            pairs[2 * (o + t)] = (int32_t)i;
+            pairs[2 * (o + t) + 1] = (int32_t)js[t];
+          }
+        free(js);
+        free(cand);
+        if (!pass) cnt[i] = c;
+        continue;
+      }
       for (int64_t j = 0; j < Nn; ++j) {
         if (!rule_inside(q32, Z + 3 * j, rc2_32)) continue;
         if (classes && lm[i] != ln[j]) continue;

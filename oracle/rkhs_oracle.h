@@ -38,6 +38,7 @@ typedef struct {
   double cutoff_factor;        /* truncation radius r_c = cutoff_factor * ell */
   double sigma;                /* kernel amplitude */
   int clamp_negative_c;        /* use max(c, 0) */
+  int top_k;                   /* > 0: each source point keeps its top_k largest-weight pairs */
 } oracle_problem;
 
 /* Loss F, b and H at `poses` (K*12), brute force over every point pair of
@@ -63,7 +64,8 @@ int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edge
 
 /* Point pairs (i, j) (original indices, i in frame m, j in frame n) kept by
  * the FP32 membership rule, in (i, j) order.  With class ids only pairs of
- * equal labels are listed.  Writes at most cap pairs, returns the total
+ * equal labels are listed; with top_k > 0 only each source point's top_k
+ * pairs (c > 0, ranked by weight).  Writes at most cap pairs, returns the total
  * count (or -1). */
 int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n, int64_t cap, int32_t* pairs);
 

@@ -112,6 +112,7 @@ ProbParams params_of(const rkhsba_options& o) {
   p.clamp_negative_c = o.clamp_negative_c;
   p.cell_subdiv = o.cell_subdiv;
   p.pass_points = o.pass_points;
+  p.top_k = o.top_k;
   return p;
 }
 
@@ -134,6 +135,7 @@ void rkhsba_default_options(rkhsba_options* o) {
   o->moment_path = 0;
   o->use_graphs = 1;
   o->hessian_fp32 = 0;
+  o->top_k = 0;
   o->stream = nullptr;
 }
 
@@ -148,7 +150,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
        opt->pass_points != 64) ||
       opt->fixed_frame < 0 ||
       opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1 ||
-      opt->hessian_fp32 < 0 || opt->hessian_fp32 > 1)
+      opt->hessian_fp32 < 0 || opt->hessian_fp32 > 1 || opt->top_k < 0 || opt->top_k > kMaxTopK)
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -714,7 +716,8 @@ int rkhsba_export_pairs(rkhsba_ctx* c, const double* poses, int m, int n, int64_
     RK_HIP(launch_edge_setup(g.poses(), d_one.p, 1, d_xf.p, st));
     const int fp = g.feat_kind == RKHSBA_FEAT_CLASS_ID ? FEAT_CLASS : FEAT_DENSE;
     RK_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(unsigned long long), st));
-    RK_HIP(launch_export_pairs(g.pts(), g.rows(), g.xtab(), g.frames(), p->frames[m].n, g.perm(), d_xf.p, mg, ng, fp,
+    RK_HIP(launch_export_pairs(g.pts(), g.rows(), g.xtab(), g.frames(), p->frames[m].n, g.perm(), g.feat(), d_xf.p, mg,
+                               ng, fp,
                                p->kc, 0, nullptr, d_cnt.p, st));
     unsigned long long total = 0;
     RK_HIP(hipMemcpyAsync(&total, d_cnt.p, sizeof(total), hipMemcpyDeviceToHost, st));
@@ -724,7 +727,8 @@ int rkhsba_export_pairs(rkhsba_ctx* c, const double* poses, int m, int n, int64_
     DBuf<int32_t> d_out;
     RK_HIP(d_out.reserve((size_t)total * 2));
     RK_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(unsigned long long), st));
-    RK_HIP(launch_export_pairs(g.pts(), g.rows(), g.xtab(), g.frames(), p->frames[m].n, g.perm(), d_xf.p, mg, ng, fp,
+    RK_HIP(launch_export_pairs(g.pts(), g.rows(), g.xtab(), g.frames(), p->frames[m].n, g.perm(), g.feat(), d_xf.p, mg,
+                               ng, fp,
                                p->kc, (int64_t)total, d_out.p, d_cnt.p, st));
     std::vector<int32_t> h((size_t)total * 2);
     RK_HIP(hipMemcpyAsync(h.data(), d_out.p, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, st));

@@ -125,6 +125,7 @@ struct ProbParams {
   int clamp_negative_c = 1;
   int cell_subdiv = 8;   // cells per r_c, 1..8 (0: chosen at the build)
   int pass_points = 16;  // sweep pass size: 1 (per-point walks), 16, 32, 64 (0: chosen at the build)
+  int top_k = 0;         // > 0: keep the top_k largest-kernel pairs per source point (per-point walks)
 };
 
 // One resident problem: its frames, their voxel structures and poses.
@@ -174,6 +175,7 @@ struct SetLayout {
   int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, bin_bits = 3;
   struct Group {
     int pass_points, pass0, n_pass;
+    bool topk;
   };
   std::vector<Group> groups;        // contiguous runs of the pass table, one sweep launch each
   bool clamp = false;

@@ -232,6 +232,8 @@ void Engine::compute_constants(Problem* p) {
   k.reach_cells = o.cell_subdiv + 1;
   k.clamp = (o.clamp_negative_c && p->negative_features) ? 1 : 0;
   k.Dp = Dp;
+  k.topk = o.top_k;
+  k.inv2l2 = 1.0 / (2.0 * o.ell * o.ell);
   p->kc = k;
 }
 
@@ -245,8 +247,12 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_REQUIRE(Din >= 1 && Din <= kMaxDense, RKHSBA_EINVAL, "dense feature dimension must be in [1, 64]");
   RK_REQUIRE(par.ell > 0.0 && std::isfinite(par.ell) && par.cutoff_factor > 0.0 && std::isfinite(par.cutoff_factor) &&
                  par.cell_subdiv >= 1 && par.cell_subdiv <= 8 && std::isfinite(par.sigma) && par.damping_rel >= 0.0 &&
-                 (par.pass_points == 1 || par.pass_points == 16 || par.pass_points == 32 || par.pass_points == 64),
+                 (par.pass_points == 1 || par.pass_points == 16 || par.pass_points == 32 || par.pass_points == 64) &&
+                 par.top_k >= 0 && par.top_k <= kMaxTopK,
              RKHSBA_EINVAL, "invalid problem parameters");
+  RK_REQUIRE(par.top_k == 0 || kind == RKHSBA_FEAT_CLASS_ID || kind == RKHSBA_FEAT_DENSE_F32, RKHSBA_EINVAL,
+             "top-k pair selection needs class ids or float32 dense features");
+  RK_REQUIRE(par.top_k == 0 || par.pass_points == 1, RKHSBA_EINVAL, "top-k pair selection needs per-point walks");
   const int Dk = kind == RKHSBA_FEAT_CLASS_ID ? 0 : Din;
   if (probs_.empty()) {
     feat_kind = kind;
@@ -500,8 +506,10 @@ std::pair<int, int> Engine::choose_config(double occ_r) const {
   return {8, 16};
 }
 
-int Engine::add_problem_auto(const ProbParams& par, int K, const int64_t* n_points, const float* const* xyz, int kind,
-                             int Din, const void* const* feats, bool is_device) {
+int Engine::add_problem_auto(const ProbParams& par_in, int K, const int64_t* n_points, const float* const* xyz,
+                             int kind, int Din, const void* const* feats, bool is_device) {
+  ProbParams par = par_in;
+  if (par.top_k > 0) par.pass_points = 1;  // the top-k selection runs in the per-point walks
   if (par.cell_subdiv != 0 && par.pass_points != 0)
     return add_problem(par, K, n_points, xyz, kind, Din, feats, is_device);
   ProbParams probe = par;
@@ -571,6 +579,7 @@ void Engine::set_ell(Problem* p, double ell) {
   k.rc2 = (float)(rc * rc);
   k.alpha = (float)(1.4426950408889634 / (2.0 * ell * ell));
   k.reach_cells = (int)std::ceil(k.reach * k.inv_cell) + 1;
+  k.inv2l2 = 1.0 / (2.0 * ell * ell);
   p->kc = k;
   ++p->kc_version;
 }
@@ -674,8 +683,8 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   std::vector<SortTile> tiles;
   std::vector<SortSeg> segs(E_total);
   std::vector<KConst> kcs(items.size());
-  const int group_order[4] = {16, 1, 32, 64};
-  std::vector<PassInfo> gpass[4];
+  const int group_order[5] = {16, 1, 32, 64, 1};  // the last group: per-point walks with top-k selection
+  std::vector<PassInfo> gpass[5];
   std::vector<ProbSys> sys(items.size());
   std::vector<int32_t> bstart_all, blist, vstart_all, vlist;
   int64_t entries = 0, passes = 0, fins = 0, h_total = 0, v_total = 0;
@@ -719,7 +728,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       I.n_src = frame_of(m).n;
       const int pp = p->par.pass_points;
       const int P = pp == 1 ? 64 : pp;  // per-point walks: 64 sources (one per lane) per pass
-      const int gi = pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : 3;
+      const int gi = p->par.top_k > 0 ? 4 : pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : 3;
       I.pass_size = pp;
       I.n_pass = (I.n_src + P - 1) / P;
       I.fin_off = (int32_t)fins;
@@ -781,9 +790,9 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   RK_HIP(lay.d_esegs.reserve(E_total));
   std::vector<PassInfo> pinfo;
   std::vector<SetLayout::Group> groups;
-  for (int gi = 0; gi < 4; ++gi) {
+  for (int gi = 0; gi < 5; ++gi) {
     if (gpass[gi].empty()) continue;
-    groups.push_back(SetLayout::Group{group_order[gi], (int)pinfo.size(), (int)gpass[gi].size()});
+    groups.push_back(SetLayout::Group{group_order[gi], (int)pinfo.size(), (int)gpass[gi].size(), gi == 4});
     pinfo.insert(pinfo.end(), gpass[gi].begin(), gpass[gi].end());
   }
   RK_HIP(lay.d_kcs.reserve(items.size()));
@@ -876,6 +885,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   pa.cnt = cnt_.p;
   pa.kcs = lay.d_kcs.p;
   pa.passes = lay.d_passes.p;
+  pa.perm = perm();
   pa.n_entries = lay.n_entries;
   pa.E = lay.E;
 
@@ -889,7 +899,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
     if (gr.pass_points == 16)
       RK_HIP(launch_sweep16(pa, mode, feat_path, moment_path == 2, st));
     else
-      RK_HIP(launch_pairs(pa, mode, feat_path, gr.pass_points, st));
+      RK_HIP(launch_pairs(pa, mode, feat_path, gr.pass_points, gr.topk, st));
   }
   prof_end(mode == MODE_NORMAL ? RKHSBA_PROF_PAIRS : RKHSBA_PROF_PAIRS_LOSS, t1);
   FinArgs fa{};

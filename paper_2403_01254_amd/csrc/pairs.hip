@@ -113,7 +113,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts
 // source tests every candidate of the walk.  LOCAL (G = 1): each lane walks
 // the cells around its own transformed point only (for sparse frames, where
 // a shared box would be much larger than one point's neighbourhood).
-template <int MODE, int FEAT, int G, int DP, bool LOCAL>
+// TOPK > 0 (with LOCAL): each source point keeps only its kc.topk (<= TOPK)
+// pairs with the largest kernel values c exp(-|d|^2 / 2 ell^2) (ranked in
+// FP64; ties: smaller squared distance, then smaller original index); the
+// moments and the pair count come from those pairs only.
+template <int MODE, int FEAT, int G, int DP, bool LOCAL, int TOPK>
 __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
   constexpr int P = 64 / G;
   const int lane = threadIdx.x & 63;
@@ -166,6 +170,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     lo = make_float3(FLT_MAX, FLT_MAX, FLT_MAX);
     hi = make_float3(-FLT_MAX, -FLT_MAX, -FLT_MAX);
   }
+  TopK<(TOPK > 0 ? TOPK : 1)> best;
+  if constexpr (TOPK > 0) best.clear();
+  const int topk = kc.topk;
   for_each_range(Fn, a.rows, a.xtab, kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0 + g; j < j1; j += G) {
       const float4 z = tp[j];
@@ -180,6 +187,13 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
           c = clamp ? fmaxf(acc, 0.f) : acc;
         }
         const float w = c * __builtin_amdgcn_exp2f(-alpha * s2);
+        if constexpr (TOPK > 0) {
+          if (c > 0.f) {
+            const double key = (double)c * exp(-(double)s2 * kc.inv2l2);
+            if (best.may_enter(topk, key, s2)) best.insert(topk, key, s2, a.perm[Fn.pt_off + j], w, dx, dy, dz);
+          }
+          continue;
+        }
         A += w;
         cnt += (c != 0.f) ? 1u : 0u;
         if constexpr (MODE == MODE_NORMAL) {
@@ -192,6 +206,21 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     }
   });
 
+  if constexpr (TOPK > 0) {  // moments of the kept pairs
+#pragma unroll
+    for (int t = 0; t < TOPK; ++t) {
+      if (!(best.key[t] > 0.0)) continue;
+      const float w = best.w[t], dx = best.dx[t], dy = best.dy[t], dz = best.dz[t];
+      A += w;
+      cnt += 1u;
+      if constexpr (MODE == MODE_NORMAL) {
+        const float wx = w * dx, wy = w * dy, wz = w * dz;
+        Bx += wx; By += wy; Bz += wz;
+        Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+        Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+      }
+    }
+  }
   // Sum the G lanes that share a source point (lanes s, s+P, s+2P, ...).
 #pragma unroll
   for (int o = P; o < 64; o <<= 1) {
@@ -480,11 +509,12 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
 
 // ---------------------------------------------------------------- pair export (parity)
 
-template <int FEAT>
+template <int FEAT, int DP, bool TOPK>
 __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restrict__ pts, const int4* __restrict__ rows,
                                                            const uint32_t* __restrict__ xtab,
                                                            const FrameInfo* __restrict__ frames,
                                                            const int32_t* __restrict__ perm,
+                                                           const void* __restrict__ feat,
                                                            const EdgeXf* __restrict__ xf, int m, int n, KConst kc,
                                                            int64_t cap, int32_t* __restrict__ out,
                                                            unsigned long long* __restrict__ count) {
@@ -496,6 +526,10 @@ __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restr
   const float3 q = rule_q32(xf[0], x.x, x.y, x.z);
   const uint32_t lbl = __float_as_uint(x.w);
   const int32_t oi = perm[Fm.pt_off + i];
+  float fs[DP > 0 ? DP : 1];
+  if constexpr (TOPK && FEAT != FEAT_CLASS) load_feature_row<FEAT, DP>(feat, Fm.pt_off + i, fs);
+  TopK<kMaxTopK> best;
+  if constexpr (TOPK) best.clear();
   for_each_range(Fn, rows, xtab, kc, q, q, [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0; j < j1; ++j) {
       const float4 z = pts[Fn.pt_off + j];
@@ -503,7 +537,18 @@ __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restr
       const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
       bool in = s2 <= kc.rc2;
       if constexpr (FEAT == FEAT_CLASS) in = in && __float_as_uint(z.w) == lbl;
-      if (in) {
+      if (!in) continue;
+      if constexpr (TOPK) {
+        float c = 1.0f;
+        if constexpr (FEAT != FEAT_CLASS) {
+          const float acc = dot_feature_row<FEAT, DP>(feat, Fn.pt_off + j, fs);
+          c = kc.clamp ? fmaxf(acc, 0.f) : acc;
+        }
+        if (c > 0.f) {
+          const double key = (double)c * exp(-(double)s2 * kc.inv2l2);
+          if (best.may_enter(kc.topk, key, s2)) best.insert(kc.topk, key, s2, perm[Fn.pt_off + j], 0.f, dx, dy, dz);
+        }
+      } else {
         const unsigned long long k = atomicAdd(count, 1ull);
         if ((int64_t)k < cap) {
           out[2 * k] = oi;
@@ -512,18 +557,31 @@ __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restr
       }
     }
   });
+  if constexpr (TOPK) {
+#pragma unroll
+    for (int t = 0; t < kMaxTopK; ++t) {
+      if (!(best.key[t] > 0.0)) continue;
+      const unsigned long long k = atomicAdd(count, 1ull);
+      if ((int64_t)k < cap) {
+        out[2 * k] = oi;
+        out[2 * k + 1] = best.jo[t];
+      }
+    }
+  }
 }
 
 template <int MODE, int FEAT>
-hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, int DP, hipStream_t st) {
+hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, bool topk, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)((a.n_pass + 3) / 4);
   if (nb == 0) return hipSuccess;
-#define RKHSBA_LAUNCH(GG, DD, LL) k_pairs<MODE, FEAT, GG, DD, LL><<<nb, kThreads, 0, st>>>(a)
-#define RKHSBA_ANY(DD)                      \
-  if (local) RKHSBA_LAUNCH(1, DD, true);    \
-  else if (G == 1) RKHSBA_LAUNCH(1, DD, false); \
-  else if (G == 2) RKHSBA_LAUNCH(2, DD, false); \
-  else RKHSBA_LAUNCH(4, DD, false);
+#define RKHSBA_LAUNCH(GG, DD, LL, TK) k_pairs<MODE, FEAT, GG, DD, LL, TK><<<nb, kThreads, 0, st>>>(a)
+#define RKHSBA_ANY(DD)                                                           \
+  if (topk) {                                                                    \
+    if constexpr (FEAT == FEAT_CLASS || FEAT == FEAT_DENSE) RKHSBA_LAUNCH(1, DD, true, kMaxTopK); \
+  } else if (local) RKHSBA_LAUNCH(1, DD, true, 0);                               \
+  else if (G == 1) RKHSBA_LAUNCH(1, DD, false, 0);                               \
+  else if (G == 2) RKHSBA_LAUNCH(2, DD, false, 0);                               \
+  else RKHSBA_LAUNCH(4, DD, false, 0);
   if constexpr (FEAT == FEAT_CLASS) {
     RKHSBA_ANY(0)
   } else if constexpr (feat_low_precision(FEAT)) {
@@ -563,16 +621,16 @@ hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const Edge
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, hipStream_t st) {
+hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, bool topk, hipStream_t st) {
   const bool local = pass_points == 1;
   const int G = local ? 1 : 64 / pass_points;
   const int DP = a.kc.Dp;
 #define RKHSBA_FEATS(MM)                                                                 \
   switch (feat_path) {                                                                   \
-    case FEAT_CLASS: return dispatch_pairs<MM, FEAT_CLASS>(a, G, local, DP, st);         \
-    case FEAT_DENSE: return dispatch_pairs<MM, FEAT_DENSE>(a, G, local, DP, st);         \
-    case FEAT_BF16: return dispatch_pairs<MM, FEAT_BF16>(a, G, local, DP, st);           \
-    default: return dispatch_pairs<MM, FEAT_FP8>(a, G, local, DP, st);                   \
+    case FEAT_CLASS: return dispatch_pairs<MM, FEAT_CLASS>(a, G, local, topk, DP, st);   \
+    case FEAT_DENSE: return dispatch_pairs<MM, FEAT_DENSE>(a, G, local, topk, DP, st);   \
+    case FEAT_BF16: return dispatch_pairs<MM, FEAT_BF16>(a, G, local, false, DP, st);    \
+    default: return dispatch_pairs<MM, FEAT_FP8>(a, G, local, false, DP, st);            \
   }
   if (mode == MODE_LOSS) { RKHSBA_FEATS(MODE_LOSS) }
   RKHSBA_FEATS(MODE_NORMAL)
@@ -601,17 +659,26 @@ hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, 
 }
 
 hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
-                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const EdgeXf* d_xf, int m,
-                               int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
+                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const void* d_feat,
+                               const EdgeXf* d_xf, int m, int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
                                unsigned long long* d_count, hipStream_t st) {
   if (n_src <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((n_src + kThreads - 1) / kThreads);
-  if (feat_path == FEAT_CLASS)
-    k_export_pairs<FEAT_CLASS><<<nb, kThreads, 0, st>>>(d_pts, d_rows, d_xtab, d_frames, d_perm, d_xf, m, n, kc, cap,
-                                                        d_out, d_count);
-  else
-    k_export_pairs<FEAT_DENSE><<<nb, kThreads, 0, st>>>(d_pts, d_rows, d_xtab, d_frames, d_perm, d_xf, m, n, kc, cap,
-                                                        d_out, d_count);
+#define RKHSBA_EXPORT(FF, DD, TK)                                                                               \
+  k_export_pairs<FF, DD, TK><<<nb, kThreads, 0, st>>>(d_pts, d_rows, d_xtab, d_frames, d_perm, d_feat, d_xf, m, n, kc, \
+                                                      cap, d_out, d_count)
+  if (kc.topk > 0) {
+    if (feat_path == FEAT_CLASS) RKHSBA_EXPORT(FEAT_CLASS, 0, true);
+    else if (kc.Dp <= 8) RKHSBA_EXPORT(FEAT_DENSE, 8, true);
+    else if (kc.Dp <= 16) RKHSBA_EXPORT(FEAT_DENSE, 16, true);
+    else if (kc.Dp <= 24) RKHSBA_EXPORT(FEAT_DENSE, 24, true);
+    else if (kc.Dp <= 32) RKHSBA_EXPORT(FEAT_DENSE, 32, true);
+    else RKHSBA_EXPORT(FEAT_DENSE, 64, true);
+  } else {
+    if (feat_path == FEAT_CLASS) RKHSBA_EXPORT(FEAT_CLASS, 0, false);
+    else RKHSBA_EXPORT(FEAT_DENSE, 0, false);
+  }
+#undef RKHSBA_EXPORT
   return hipGetLastError();
 }
 

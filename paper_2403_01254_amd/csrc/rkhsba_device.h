@@ -86,6 +86,59 @@ __device__ inline float dot_feature_row(const void* __restrict__ base, int64_t r
   return acc;
 }
 
+// The K best pairs of one source point: larger ranking key c exp(-s2 / 2 ell^2)
+// (FP64), then smaller FP32 squared distance s2, then smaller original index j.
+// Entries are kept best first; unused entries hold a sentinel (key -1) that
+// every real pair (key > 0) beats.  All indexing is static (registers).
+template <int K>
+struct TopK {
+  double key[K];
+  float s2[K], w[K], dx[K], dy[K], dz[K];
+  int32_t jo[K];
+  __device__ void clear() {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      key[t] = -1.0;
+      s2[t] = 3.0e38f;
+      jo[t] = 0x7fffffff;
+      w[t] = dx[t] = dy[t] = dz[t] = 0.f;
+    }
+  }
+  __device__ static bool better(double k1, float a1, int32_t j1, double k2, float a2, int32_t j2) {
+    return k1 > k2 || (k1 == k2 && (a1 < a2 || (a1 == a2 && j1 < j2)));
+  }
+  // Could (key, s2) enter a list of the first k entries?  (The index tie-break is decided in insert.)
+  __device__ bool may_enter(int k, double kk, float ss) const {
+    double lk = -1.0;
+    float ls = 3.0e38f;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if (t == k - 1) {
+        lk = key[t];
+        ls = s2[t];
+      }
+    return kk > lk || (kk == lk && ss <= ls);
+  }
+  __device__ void insert(int k, double kk, float ss, int32_t j, float ww, float ax, float ay, float az) {
+    bool placed = false;
+#pragma unroll
+    for (int t = K - 1; t >= 0; --t) {
+      if (t >= k || placed) continue;
+      if (t == k - 1 && !better(kk, ss, j, key[t], s2[t], jo[t])) {  // not better than the last kept pair
+        placed = true;
+        continue;
+      }
+      if (t > 0 && better(kk, ss, j, key[t - 1], s2[t - 1], jo[t - 1])) {
+        key[t] = key[t - 1]; s2[t] = s2[t - 1]; jo[t] = jo[t - 1];
+        w[t] = w[t - 1]; dx[t] = dx[t - 1]; dy[t] = dy[t - 1]; dz[t] = dz[t - 1];
+      } else {
+        key[t] = kk; s2[t] = ss; jo[t] = j; w[t] = ww; dx[t] = ax; dy[t] = ay; dz[t] = az;
+        placed = true;
+      }
+    }
+  }
+};
+
 // The FP32 squared distance of the membership rule.
 __device__ inline float rule_s2(float3 q, float zx, float zy, float zz, float& dx, float& dy, float& dz) {
 #pragma clang fp contract(off)

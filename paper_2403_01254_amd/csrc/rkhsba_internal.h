@@ -78,8 +78,10 @@ struct KConst {
   int reach_cells;   // cell_subdiv + 1
   int clamp;         // clamp negative c to 0 (only set when some feature value is negative)
   int Dp;            // padded dense feature width (0 for class ids)
-  int pad;
+  int topk;          // > 0: only the topk pairs with the largest kernel values per source point (per edge)
+  double inv2l2;     // 1 / (2 ell^2), for the FP64 ranking key of the topk selection
 };
+constexpr int kMaxTopK = 8;
 
 // Segmented LSD radix sort: tiles never straddle a segment.
 struct SortTile {
@@ -146,6 +148,7 @@ struct PairArgs {
   float* mom;             // moments, component-major: mom[c * n_entries + entry]
   uint32_t* cnt;          // in-radius pair count per entry
   const KConst* kcs;      // per problem of the set, indexed by EdgeInfo::prob
+  const int32_t* perm;    // sorted position -> original index (ties of the topk selection)
   const PassInfo* passes; // per sweep pass
   int64_t n_entries;
   int32_t E;
@@ -155,7 +158,7 @@ struct PairArgs {
 };
 // Passes of pass_points sources: 1 = each lane walks its own point's cells,
 // 16 (launch_sweep16), 32, 64 = shared walk over the pass's box.
-hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, hipStream_t st);
+hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, bool topk, hipStream_t st);
 
 hipError_t launch_sweep16(const PairArgs& a, int mode, int feat_path, bool matrix_moments, hipStream_t st);
 
@@ -230,8 +233,8 @@ hipError_t launch_loss_only(const SolveArgs& a, hipStream_t st);
 hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);
 
 hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
-                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const EdgeXf* d_xf, int m,
-                               int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
+                               const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const void* d_feat,
+                               const EdgeXf* d_xf, int m, int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,
                                unsigned long long* d_count, hipStream_t st);
 
 }  // namespace rkhsba

@@ -43,6 +43,7 @@ class Options(ctypes.Structure):
         ("moment_path", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
         ("hessian_fp32", ctypes.c_int),
+        ("top_k", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -166,13 +167,14 @@ class Context:
     def __init__(self, ell: float, cutoff_factor: float = 3.0, sigma: float = 1.0, damping_rel: float = 1e-10,
                  fixed_frame: int = 0, clamp_negative_c: bool = True, device: int = 0, cell_subdiv: int = 0,
                  pass_points: int = 0, moment_path: int = 0, use_graphs: bool = True, hessian_fp32: bool = False,
-                 stream=None):
+                 top_k: int = 0, stream=None):
         o = default_options()
         o.ell, o.cutoff_factor, o.sigma, o.damping_rel = ell, cutoff_factor, sigma, damping_rel
         o.fixed_frame, o.clamp_negative_c, o.device = fixed_frame, int(bool(clamp_negative_c)), device
         o.cell_subdiv, o.pass_points, o.moment_path = cell_subdiv, pass_points, moment_path
         o.use_graphs = int(bool(use_graphs))
         o.hessian_fp32 = int(bool(hessian_fp32))
+        o.top_k = int(top_k)
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_create(ctypes.byref(self._h), ctypes.byref(o))
