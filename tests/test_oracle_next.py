@@ -20,9 +20,34 @@ def test_icosahedral_group_structure():
     for a in R[::7]:                                            # closed under composition
         for b in R[::5]:
             assert np.abs(flat - (a @ b).reshape(9)).max(axis=1).min() < 1e-9
-    ang = np.degrees(np.arccos(np.clip((np.trace(R, axis1=1, axis2=2) - 1) / 2, -1, 1)))
-    classes = {a: int(np.sum(np.abs(ang - a) < 1e-6)) for a in (0, 72, 120, 144, 180)}
-    assert classes == {0: 1, 72: 12, 120: 20, 144: 12, 180: 15}  # 1 + 15 + 20 + 24 (Sec. IV-A)
+    # rotation angles (in [0, pi]) against the element classes the paper lists (tests/golden)
+    ang = np.arccos(np.clip((np.trace(R, axis1=1, axis2=2) - 1) / 2, -1, 1)) / np.pi
+    want, total = golden_icosahedral_classes()
+    assert total == 60 == sum(want.values())
+    got = {a: int(np.sum(np.abs(ang - a) < 1e-9)) for a in want}
+    assert got == want
+
+
+def golden_icosahedral_classes():
+    """{rotation angle / pi: number of group elements} and the stated total."""
+    from fractions import Fraction
+    import os
+    want, total = {}, None
+    path = os.path.join(os.path.dirname(__file__), "golden", "icosahedral_group.txt")
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "total":
+            total = int(f[1])
+        if f[0] != "class":
+            continue
+        axes = int(f[2].split("=")[1])
+        for t in f[3].split("=")[1].split(","):
+            a = Fraction(t)
+            a = float(min(a, 2 - a))          # a turn by a pi is a rotation by min(a, 2 - a) pi
+            want[a] = want.get(a, 0) + axes
+    return want, total
 
 
 def test_rotation_search_recovers_a_group_rotation():
