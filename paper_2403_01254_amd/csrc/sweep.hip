@@ -28,6 +28,8 @@ namespace rkhsba {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kLanes = 64;
 constexpr int kTile = 64;
@@ -49,6 +51,22 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v, int lane) {
     if (lane >= o) v += t;
   }
   return v;
+}
+
+// Inclusive max-scan of unsigned values over the wavefront's 64 lanes: four
+// row shifts within each row of 16 lanes, then the last lane of a row
+// broadcast to the rows after it.  Lanes a shift leaves without a source read
+// the identity 0.
+__device__ inline uint32_t wave_inclusive_max(uint32_t v) {
+  const int x = (int)v;
+  int m = x;
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x111, 0xf, 0xf, true));  // row_shr:1
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x112, 0xf, 0xf, true));  // row_shr:2
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x114, 0xf, 0xf, true));  // row_shr:4
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x118, 0xf, 0xf, true));  // row_shr:8
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  m = (int)max((uint32_t)m, (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (uint32_t)m;
 }
 
 // Feature inner products of one 16-candidate sub-tile with the pass's 16
@@ -111,7 +129,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   constexpr int NSRC = !LP ? 1 : FEAT == FEAT_BF16 ? DP / 16 : DP / 32;
   constexpr int PHS = 20;                  // LDS Phi row stride (conflict-free B-operand reads)
   __shared__ uint32_t row_j0[kLanes];
-  __shared__ uint32_t row_off[kLanes + 1];
+  __shared__ uint32_t row_off[kLanes];
+  __shared__ uint32_t marker[kLanes];
   __shared__ float4 tpos[kTile];
   __shared__ float tfeat[FEAT == FEAT_DENSE ? kTile * FS : 1];
   __shared__ __align__(16) uint8_t tlp[LP ? kTile * RB : 16];
@@ -175,6 +194,9 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     return;
   }
   const float3 ref = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
+  // A lane without a valid source point gets q at -1e30 (padding candidates sit at +1e30): its squared
+  // distance to every candidate overflows to +inf and fails the membership test.
+  if (!valid) q = make_float3(-1.0e30f, -1.0e30f, -1.0e30f);
   floatx4 macc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
   if constexpr (MM) {
 #pragma unroll
@@ -228,48 +250,49 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     __syncthreads();  // previous users of row_j0/row_off are done
     row_j0[lane] = j0;
     row_off[lane] = incl - cntr;
-    if (lane == 63) row_off[64] = incl;
     __syncthreads();
     if (total == 0) continue;
 
     // ---- tiles of 64 candidates, next tile fetched while the current one is processed
-    auto fetch = [&](uint32_t c, float4& pos, float* fr, uint4* lr, bool& pad) {
-      pad = c >= total;
-      if (c < total) {
-        int lo_r = 0, hi_r = 63;  // largest row with row_off[row] <= c
-        while (lo_r < hi_r) {
-          const int mid = (lo_r + hi_r + 1) >> 1;
-          if (row_off[mid] <= c) lo_r = mid; else hi_r = mid - 1;
+    // The row of every candidate of a tile: each non-empty row marks the first tile position it
+    // covers, and the candidate at position p belongs to the last row marked at or before p.
+    const uint32_t my_off = incl - cntr;
+    auto tile_rows = [&](uint32_t base) __attribute__((always_inline)) -> int {
+      marker[lane] = 0u;  // 0: no row starts here; row r is marked r + 1
+      __syncthreads();
+      if (cntr > 0 && my_off < base + (uint32_t)kTile && my_off + cntr > base)
+        marker[my_off > base ? my_off - base : 0u] = (uint32_t)lane + 1u;
+      __syncthreads();
+      const uint32_t r = wave_inclusive_max(marker[lane]);
+      __syncthreads();  // markers are rewritten by the next call
+      return (int)min(max(r, 1u), (uint32_t)kLanes) - 1;
+    };
+    auto fetch = [&](uint32_t c, float4& pos, float* fr, u32x4* lr, bool& pad) __attribute__((always_inline)) {
+      const int rid = tile_rows(c - (uint32_t)lane);
+      const uint32_t jc = row_j0[rid] + (c - row_off[rid]);
+      pad = c >= total || jc >= (uint32_t)Fn.n;  // the second test only bounds the reads below
+      // padding lanes read the frame's first point (always present when there are candidates) and
+      // move it far away: it fails every membership test and its products stay finite
+      const uint32_t j = pad ? 0u : jc;
+      pos = tp[j];
+      if (pad) pos = make_float4(far_, far_, far_, 0.f);
+      if constexpr (FEAT == FEAT_DENSE) {
+        const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 4; ++k) {
+          const float4 v = f4[k];
+          fr[4 * k] = v.x; fr[4 * k + 1] = v.y; fr[4 * k + 2] = v.z; fr[4 * k + 3] = v.w;
         }
-        const uint32_t j = row_j0[lo_r] + (c - row_off[lo_r]);
-        pos = tp[j];
-        if constexpr (FEAT == FEAT_DENSE) {
-          const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
+      } else if constexpr (LP) {
+        const u32x4* r4 = reinterpret_cast<const u32x4*>(tl + (int64_t)j * ROWB);
 #pragma unroll
-          for (int k = 0; k < DP / 4; ++k) {
-            const float4 v = f4[k];
-            fr[4 * k] = v.x; fr[4 * k + 1] = v.y; fr[4 * k + 2] = v.z; fr[4 * k + 3] = v.w;
-          }
-        } else if constexpr (LP) {
-          const uint4* r4 = reinterpret_cast<const uint4*>(tl + (int64_t)j * ROWB);
-#pragma unroll
-          for (int k = 0; k < ROWB / 16; ++k) lr[k] = r4[k];
-        }
-      } else {
-        pos = make_float4(far_, far_, far_, 0.f);  // fails every membership test, keeps the products finite
-        if constexpr (FEAT == FEAT_DENSE) {
-#pragma unroll
-          for (int k = 0; k < DP; ++k) fr[k] = 0.f;
-        } else if constexpr (LP) {
-#pragma unroll
-          for (int k = 0; k < ROWB / 16; ++k) lr[k] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        for (int k = 0; k < ROWB / 16; ++k) lr[k] = r4[k];
       }
     };
     float4 npos;
-    float nfeat[FEAT == FEAT_DENSE ? DP : 1];
-    uint4 nlp[LP ? ROWB / 16 : 1];
     bool npad;
+    float nfeat[FEAT == FEAT_DENSE ? DP : 1];
+    u32x4 nlp[LP ? ROWB / 16 : 1];
     fetch((uint32_t)lane, npos, nfeat, nlp, npad);
     for (uint32_t cb = 0; cb < total; cb += kTile) {
       tpos[lane] = npos;
@@ -288,12 +311,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         for (int k = 0; k < DP; ++k) tfeat[lane * FS + k] = nfeat[k];
       } else if constexpr (FEAT == FEAT_BF16) {
 #pragma unroll
-        for (int k = 0; k < ROWB / 16; ++k) *reinterpret_cast<uint4*>(tlp + lane * RB + 16 * k) = nlp[k];
+        for (int k = 0; k < ROWB / 16; ++k) *reinterpret_cast<u32x4*>(tlp + lane * RB + 16 * k) = nlp[k];
       } else if constexpr (FEAT == FEAT_FP8) {
 #pragma unroll
         for (int k = 0; k < ROWB / 16; ++k) {  // RB is a multiple of 8 only: 8-byte stores
-          *reinterpret_cast<uint2*>(tlp + lane * RB + 16 * k) = make_uint2(nlp[k].x, nlp[k].y);
-          *reinterpret_cast<uint2*>(tlp + lane * RB + 16 * k + 8) = make_uint2(nlp[k].z, nlp[k].w);
+          *reinterpret_cast<u32x2*>(tlp + lane * RB + 16 * k) = nlp[k].xy;
+          *reinterpret_cast<u32x2*>(tlp + lane * RB + 16 * k + 8) = nlp[k].zw;
         }
       }
       __syncthreads();
@@ -324,7 +347,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           const float4 z = z4[rr];
           float dx, dy, dz;
           const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
-          bool in = valid && s2 <= rc2;
+          bool in = s2 <= rc2;
           float c = 1.f;
           if constexpr (FEAT == FEAT_CLASS) {
             in = in && (__float_as_uint(z.w) == lbl);
@@ -333,9 +356,9 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           }
           const float k = __builtin_amdgcn_exp2f(-alpha * s2);
           const float w = in ? c * k : 0.f;
-          // pairs counted per pass from the wavefront's lane mask (scalar unit)
-          if constexpr (FEAT == FEAT_CLASS) cnt += (uint32_t)__popcll(__ballot(in));
-          else cnt += (uint32_t)__popcll(__ballot(in && c != 0.f));
+          // pairs counted per pass from the wavefront's lane masks (scalar unit)
+          if constexpr (FEAT == FEAT_CLASS) cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
+          else cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
           if constexpr (MM) {
             macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
           } else {
