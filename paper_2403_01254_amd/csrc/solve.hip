@@ -5,16 +5,15 @@
 //
 // Assembly is one thread per entry of the system, summing that entry's
 // contributing edge blocks in edge order (host-built lists, deterministic).
-// The solve is one workgroup: blocked right-looking Cholesky with 16-wide
-// panels, each diagonal block factored in one wavefront's registers, panel
-// rows solved one per thread, and the trailing update in 4x4 register tiles.
+// The solve is one workgroup per problem: systems up to 128 unknowns are
+// eliminated in LDS (one barrier per column, no square roots) and solved in
+// one wavefront; larger ones run a blocked right-looking Cholesky with
+// 32-wide panels, the panel kept in LDS for the trailing update.
 #include "rkhsba_device.h"
 
 namespace rkhsba {
 namespace {
 
-constexpr int kSolveThreads = 1024;
-constexpr int NB = 16;
 
 __device__ inline int sym_index(int r, int c) {
   if (r > c) { const int t = r; r = c; c = t; }
@@ -133,222 +132,277 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Factors the nb x nb diagonal block at (kb, kb) of the n x n matrix H in
-// wavefront 0: lane i holds row i in registers; column j's pivot and entries
-// are broadcast with shuffles.  Writes L11 to H and to Ld.  Returns false (in
-// every lane of wave 0) on a non-positive pivot.
-__device__ __noinline__ bool factor_diag(double* H, int n, int kb, int nb, double (*Ld)[NB + 1]) {
-  const int i = threadIdx.x;  // wave 0 only
-  double r[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) r[k] = (i < nb && k <= i) ? H[(int64_t)(kb + i) * n + kb + k] : 0.0;
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j < nb) {
-      const double d = __shfl(r[j], j, 64);
-      ok = ok && d > 0.0;
-      const double ljj = sqrt(d > 0.0 ? d : 1.0);
-      if (i == j) r[j] = ljj;
-      else if (i > j) r[j] /= ljj;
-#pragma unroll
-      for (int k = j + 1; k < NB; ++k) {
-        const double lkj = __shfl(r[j], k, 64);
-        if (k < nb && i >= k) r[k] -= r[j] * lkj;
-      }
-    }
-  }
-  if (i < nb) {
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k <= i) {
-        H[(int64_t)(kb + i) * n + kb + k] = r[k];
-        Ld[i][k] = r[k];
-      }
-  }
-  return ok;
+// A double read from one lane of the wavefront (lane index uniform).
+__device__ inline double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// Panel below the diagonal block: L21 = A21 L11^-T, one row per thread.
-__device__ __noinline__ void panel_solve(double* H, int n, int kb, int nb, const double (*Ld)[NB + 1]) {
-  const int t = threadIdx.x, T = blockDim.x;
-    const int m0 = kb + nb;
-    for (int i = m0 + t; i < n; i += T) {
-      double* row = H + (int64_t)i * n + kb;
-      double x[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-          double v = row[j];
-#pragma unroll
-          for (int k = 0; k < NB; ++k)
-            if (k < j) v -= x[k] * Ld[j][k];
-          x[j] = v / Ld[j][j];
-        } else {
-          x[j] = 0.0;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < nb) row[j] = x[j];
+// Right-looking elimination of an n x n symmetric block held in LDS (row
+// stride ld, lower triangle used), without square roots: step j subtracts
+// a_ij a_kj / d_j from every trailing entry (j < k <= i), d_j the pivot of
+// step j.  Afterwards the block holds M (unit-free lower factor: A = M D^-1 M^T
+// with D = diag(d)), and rd[j] = 1 / d_j.  One barrier per step; threads form a
+// 32 x 32 grid over the trailing rows and columns.  Returns false (in every
+// thread) when a pivot is not positive.
+__device__ bool eliminate_lds(double* A, int n, int ld, double* rd) {
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  for (int j = 0; j < n; ++j) {
+    const double d = A[j * ld + j];
+    if (!(d > 0.0)) return false;  // every thread read the same pivot
+    const double inv = 1.0 / d;
+    if (t == 0) rd[j] = inv;
+    for (int i = j + 1 + ty; i < n; i += 32) {
+      const double aij = A[i * ld + j] * inv;
+      for (int k = j + 1 + tx; k <= i; k += 32) A[i * ld + k] -= aij * A[k * ld + j];
     }
+    __syncthreads();
+  }
+  return true;
 }
 
-// Trailing update of the lower triangle: A22 -= L21 L21^T in 4x4 register
-// tiles.  The panel L21 is read from LDS (P, row stride NB) when it fits, else
-// from global memory.
-constexpr int kPanelRows = 896;  // LDS panel capacity: 896 x 16 doubles = 112 KB
-__device__ __noinline__ void trailing_update(double* H, int n, int kb, int nb, const double* P) {
-  const int t = threadIdx.x, T = blockDim.x;
-  const int m0 = kb + nb;
-  const int m = n - m0;
-  const bool lds = m <= kPanelRows;
-  const int tiles = (m + 3) / 4;
-  const int n_tiles = tiles * (tiles + 1) / 2;
-  for (int tt = t; tt < n_tiles; tt += T) {
-    // tile (ti, tk) with ti >= tk, enumerated row by row of the tile triangle
-    int ti = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
-    while (ti * (ti + 1) / 2 > tt) --ti;
-    const int tk = tt - ti * (ti + 1) / 2;
-    const int i0 = 4 * ti, k0 = 4 * tk;  // panel-relative rows
-    double acc[4][4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-    for (int j0 = 0; j0 < nb; j0 += 4) {
-      double li[4][4], lk[4][4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool okj = j0 + j < nb;
-          const int ri = i0 + p, rk = k0 + p;
-          li[p][j] = (okj && ri < m) ? (lds ? P[ri * NB + j0 + j] : H[(int64_t)(m0 + ri) * n + kb + j0 + j]) : 0.0;
-          lk[p][j] = (okj && rk < m) ? (lds ? P[rk * NB + j0 + j] : H[(int64_t)(m0 + rk) * n + kb + j0 + j]) : 0.0;
-        }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[p][q] = fma(li[p][j], lk[q][j], acc[p][q]);
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = m0 + i0 + p, k = m0 + k0 + q;
-        if (i < n && k <= i) H[(int64_t)i * n + k] -= acc[p][q];
-      }
-  }
-}
+// ---- systems that fit in LDS (n <= kLdsSystem)
+//
+// (H + mu I) delta = -b as M D^-1 M^T delta = -b: forward M u = -b, then
+// M^T delta = D u, both in wavefront 0 with two rows per lane.
+constexpr int kSolveThreads = 1024;
+constexpr int kLdsSystem = 128;
+constexpr int kLdsDoubles = kLdsSystem * (kLdsSystem + 1);  // shared buffer of both paths
 
-// Damped Cholesky solve of one problem's system and its pose update.  Every
-// return is block-uniform.
-__device__ __noinline__ void solve_one(const ProbSys& S, const SolveArgs& a, double* Ld, double* P, double* sh,
-                                       int* fail_flag, int32_t* status) {
-  const int n = S.n;
-  const int t = threadIdx.x, T = blockDim.x;
-  double* H = a.H + S.h_off;
-  double* y = a.delta + S.v_off;
-  const double* b = a.b + S.v_off;
-  double tr = 0.0;
-  for (int i = t; i < n; i += T) tr += H[(int64_t)i * n + i];
-  tr = block_sum(tr, sh);
-  if (!(tr > 0.0)) return;  // no pair touches a free frame: nothing moves
-  const double mu = S.damping_rel * tr / n;
-  for (int i = t; i < n; i += T) {
-    H[(int64_t)i * n + i] += mu;
-    y[i] = -b[i];
+__device__ void solve_lds(const ProbSys& S, const SolveArgs& a, double mu, double* A, double* rd, int32_t* status) {
+  const int n = S.n, ld = n + 1;  // odd stride: column reads spread over the banks
+  const int t = threadIdx.x;
+  const double* H = a.H + S.h_off;
+  for (int idx = t; idx < n * n; idx += kSolveThreads) {
+    const int i = idx / n, k = idx - i * n;
+    if (k <= i) A[i * ld + k] = H[idx] + (i == k ? mu : 0.0);
   }
-  if (t == 0) *fail_flag = 0;
   __syncthreads();
-
-  // ---- blocked Cholesky, lower triangle in place
-  for (int kb = 0; kb < n; kb += NB) {
-    const int nb = min(NB, n - kb);
-    if (t < 64) {
-      const bool ok = factor_diag(H, n, kb, nb, reinterpret_cast<double(*)[NB + 1]>(Ld));
-      if (t == 0 && !ok) *fail_flag = 1;
-    }
-    __syncthreads();
-    if (*fail_flag) break;
-    panel_solve(H, n, kb, nb, reinterpret_cast<double(*)[NB + 1]>(Ld));
-    __syncthreads();
-    if (n - (kb + nb) <= kPanelRows) {  // stage the panel in LDS for the trailing update
-      for (int idx = threadIdx.x; idx < (n - kb - nb) * NB; idx += blockDim.x) {
-        const int r = idx / NB, j = idx % NB;
-        P[idx] = j < nb ? H[(int64_t)(kb + nb + r) * n + kb + j] : 0.0;
-      }
-      __syncthreads();
-    }
-    trailing_update(H, n, kb, nb, P);
-    __syncthreads();
-  }
-  if (*fail_flag) {
+  const bool ok = eliminate_lds(A, n, ld, rd);
+  if (!ok) {
     if (t == 0) *status = -4;
     return;
   }
+  if (t < 64) {
+    const double* b = a.b + S.v_off;
+    double u0 = t < n ? -b[t] : 0.0, u1 = t + 64 < n ? -b[t + 64] : 0.0;
+    // forward: u_j = (r_j - sum_{k<j} M_jk u_k) / d_j
+    for (int j = 0; j < n; ++j) {
+      const double uj = lane_value(j < 64 ? u0 : u1, j & 63) * rd[j];
+      if (t == (j & 63)) {
+        if (j < 64) u0 = uj; else u1 = uj;
+      }
+      if (t > j && t < n) u0 -= A[t * ld + j] * uj;
+      if (t + 64 > j && t + 64 < n) u1 -= A[(t + 64) * ld + j] * uj;
+    }
+    // backward: x_j = u_j - (1/d_j) sum_{k>j} M_kj x_k, columns from the last
+    for (int j = n - 1; j >= 0; --j) {
+      const double xj = lane_value(j < 64 ? u0 : u1, j & 63);
+      if (t < j) u0 -= rd[t] * A[j * ld + t] * xj;
+      if (t + 64 < j) u1 -= rd[t + 64] * A[j * ld + t + 64] * xj;
+    }
+    double* y = a.delta + S.v_off;
+    if (t < n) y[t] = u0;
+    if (t + 64 < n) y[t + 64] = u1;
+  }
+  __syncthreads();
+}
 
-  // ---- L y' = -b: diagonal blocks in wave 0, off-diagonal updates by all threads
+// ---- larger systems: blocked right-looking Cholesky in global memory
+//
+// Panels of NB columns: the diagonal block is eliminated in LDS and scaled to
+// L11; the rows below solve L21 = A21 L11^-T (one row per thread, in
+// registers) and are kept in LDS for the trailing update A22 -= L21 L21^T
+// (4 x 4 register tiles on a 32 x 32 thread grid; from global memory when the
+// panel does not fit).  Then L y = -b and L^T delta = y, panel by panel.
+constexpr int NB = 32;
+constexpr int PS = NB + 1;  // LDS panel row stride (odd: rows of different threads fall on different banks)
+constexpr int kPanelRows = (kLdsDoubles - NB * (NB + 1) - 2 * NB) / PS;
+
+__device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, double* buf, int32_t* status) {
+  const int n = S.n, t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  double* H = a.H + S.h_off;
+  double* Dg = buf;                       // NB x (NB + 1) diagonal block
+  double* rd = buf + NB * (NB + 1);       // NB reciprocal pivots / diagonal
+  double* yb = rd + NB;                   // NB solution entries of a panel
+  double* P = yb + NB;                    // panel rows, stride PS
+  for (int i = t; i < n; i += kSolveThreads) H[(int64_t)i * n + i] += mu;
+  __syncthreads();
+  for (int kb = 0; kb < n; kb += NB) {
+    const int nb = min(NB, n - kb), m0 = kb + nb, m = n - m0;
+    for (int idx = t; idx < nb * nb; idx += kSolveThreads) {
+      const int i = idx / nb, k = idx - i * nb;
+      if (k <= i) Dg[i * (NB + 1) + k] = H[(int64_t)(kb + i) * n + kb + k];
+    }
+    __syncthreads();
+    if (!eliminate_lds(Dg, nb, NB + 1, rd)) {
+      if (t == 0) *status = -4;
+      return;
+    }
+    // scale to L11: L_jj = sqrt(d_j), L_ij = M_ij / sqrt(d_j); rd <- 1 / L_jj
+    for (int idx = t; idx < nb * nb; idx += kSolveThreads) {
+      const int i = idx / nb, k = idx - i * nb;
+      if (k <= i) {
+        const double sk = sqrt(rd[k]);  // 1 / sqrt(d_k)
+        const double v = (i == k) ? 1.0 / sk : Dg[i * (NB + 1) + k] * sk;
+        Dg[i * (NB + 1) + k] = v;
+        H[(int64_t)(kb + i) * n + kb + k] = v;
+      }
+    }
+    __syncthreads();
+    if (t < nb) rd[t] = 1.0 / Dg[t * (NB + 1) + t];
+    __syncthreads();
+    // panel rows: x L11^T = a (forward substitution per row, in LDS when the panel fits)
+    const bool in_lds = m <= kPanelRows;
+    for (int r = t; r < m; r += kSolveThreads) {
+      double* row = H + (int64_t)(m0 + r) * n + kb;
+      double* x = in_lds ? P + r * PS : row;
+      if (in_lds)
+        for (int j = 0; j < nb; ++j) x[j] = row[j];
+      for (int j = 0; j < nb; ++j) {
+        const double* Lj = Dg + j * (NB + 1);
+        double s0 = x[j], s1 = 0.0;
+        int k = 0;
+        for (; k + 1 < j; k += 2) {
+          s0 -= Lj[k] * x[k];
+          s1 -= Lj[k + 1] * x[k + 1];
+        }
+        if (k < j) s0 -= Lj[k] * x[k];
+        x[j] = (s0 + s1) * rd[j];
+      }
+      if (in_lds)
+        for (int j = 0; j < nb; ++j) row[j] = x[j];
+    }
+    __syncthreads();
+    // trailing update of the lower triangle of A22
+    const int tiles = (m + 3) / 4;
+    for (int ti = ty; ti < tiles; ti += 32) {
+      for (int tk = tx; tk <= ti; tk += 32) {
+        double acc[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+        for (int j = 0; j < nb; ++j) {
+          double li[4], lk[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const int ri = 4 * ti + p, rk = 4 * tk + p;
+            li[p] = ri < m ? (in_lds ? P[ri * PS + j] : H[(int64_t)(m0 + ri) * n + kb + j]) : 0.0;
+            lk[p] = rk < m ? (in_lds ? P[rk * PS + j] : H[(int64_t)(m0 + rk) * n + kb + j]) : 0.0;
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = fma(li[p], lk[q], acc[p][q]);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = 4 * ti + p, k = 4 * tk + q;
+            if (i < m && k <= i) H[(int64_t)(m0 + i) * n + m0 + k] -= acc[p][q];
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  double* y = a.delta + S.v_off;
+  const double* b = a.b + S.v_off;
+  for (int i = t; i < n; i += kSolveThreads) y[i] = -b[i];
+  __syncthreads();
+  // L y = -b: each diagonal block staged in LDS (with the reciprocals of its diagonal) and solved in
+  // wavefront 0, then the rows below updated by all threads
+  auto stage_diag = [&](int kb, int nb) {
+    for (int idx = t; idx < nb * nb; idx += kSolveThreads) {
+      const int i = idx / nb, k = idx - i * nb;
+      if (k <= i) Dg[i * (NB + 1) + k] = H[(int64_t)(kb + i) * n + kb + k];
+    }
+    if (t < nb) rd[t] = 1.0 / H[(int64_t)(kb + t) * n + kb + t];
+    __syncthreads();
+  };
   for (int kb = 0; kb < n; kb += NB) {
     const int nb = min(NB, n - kb);
+    stage_diag(kb, nb);
     if (t < 64) {
       double v = t < nb ? y[kb + t] : 0.0;
       for (int j = 0; j < nb; ++j) {
-        const double yj = __shfl(v, j, 64) / H[(int64_t)(kb + j) * n + kb + j];
+        const double yj = lane_value(v, j) * rd[j];
         if (t == j) v = yj;
-        else if (t > j && t < nb) v -= H[(int64_t)(kb + t) * n + kb + j] * yj;
+        else if (t > j && t < nb) v -= Dg[t * (NB + 1) + j] * yj;
       }
-      if (t < nb) y[kb + t] = v;
+      if (t < nb) {
+        y[kb + t] = v;
+        yb[t] = v;
+      }
     }
     __syncthreads();
-    for (int i = kb + nb + t; i < n; i += T) {
+    for (int i = kb + nb + t; i < n; i += kSolveThreads) {
+      const double* row = H + (int64_t)i * n + kb;
       double v = y[i];
-      for (int j = 0; j < nb; ++j) v -= H[(int64_t)i * n + kb + j] * y[kb + j];
+      for (int j = 0; j < nb; ++j) v -= row[j] * yb[j];
       y[i] = v;
     }
     __syncthreads();
   }
-  // ---- L^T delta = y'
+  // L^T delta = y
   for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
     const int nb = min(NB, n - kb);
+    stage_diag(kb, nb);
     if (t < 64) {
       double v = t < nb ? y[kb + t] : 0.0;
       for (int j = nb - 1; j >= 0; --j) {
-        const double xj = __shfl(v, j, 64) / H[(int64_t)(kb + j) * n + kb + j];
+        const double xj = lane_value(v, j) * rd[j];
         if (t == j) v = xj;
-        else if (t < j) v -= H[(int64_t)(kb + j) * n + kb + t] * xj;
+        else if (t < j) v -= Dg[j * (NB + 1) + t] * xj;
       }
-      if (t < nb) y[kb + t] = v;
+      if (t < nb) {
+        y[kb + t] = v;
+        yb[t] = v;
+      }
     }
     __syncthreads();
-    for (int i = t; i < kb; i += T) {
+    for (int i = t; i < kb; i += kSolveThreads) {
       double v = y[i];
-      for (int j = 0; j < nb; ++j) v -= H[(int64_t)(kb + j) * n + i] * y[kb + j];
+      for (int j = 0; j < nb; ++j) v -= H[(int64_t)(kb + j) * n + i] * yb[j];
       y[i] = v;
     }
     __syncthreads();
   }
-  for (int k = t; k < n / 6; k += T)
-    right_update(a.poses + 12 * (S.slot0 + frame_of_reduced(k, S.fixed)), y + 6 * k);
 }
 
-// One workgroup per problem.  A problem whose iteration count has reached
-// n_iter (its last evaluation gave the final loss) is left unchanged.
+// One workgroup per problem: damped solve and pose update.  A problem whose
+// iteration count has reached n_iter (its last evaluation gave the final
+// loss) is left unchanged.  Every branch below is block-uniform.
 __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
-  __shared__ double Ld[NB * (NB + 1)];
-  __shared__ double P[kPanelRows * NB];
+  __shared__ double buf[kLdsDoubles];
+  __shared__ double rd[kLdsSystem];
   __shared__ double sh[kSolveThreads / 64];
-  __shared__ int fail;
   const ProbSys S = a.sys[blockIdx.x];
   int32_t* st = a.state + S.state_off;
   const int iter = st[0];
   const bool run = iter < S.n_iter && st[1] == 0 && S.n > 0;
   __syncthreads();
-  if (run) solve_one(S, a, Ld, P, sh, &fail, st + 1);
+  if (run) {
+    const int n = S.n;
+    const double* H = a.H + S.h_off;
+    double tr = 0.0;
+    for (int i = threadIdx.x; i < n; i += kSolveThreads) tr += H[(int64_t)i * n + i];
+    tr = block_sum(tr, sh);
+    if (tr > 0.0) {  // otherwise no pair touches a free frame: nothing moves
+      const double mu = S.damping_rel * tr / n;
+      if (n <= kLdsSystem) solve_lds(S, a, mu, buf, rd, st + 1);
+      else solve_blocked(S, a, mu, buf, st + 1);
+      __syncthreads();
+      if (st[1] == 0) {
+        const double* y = a.delta + S.v_off;
+        for (int k = threadIdx.x; k < n / 6; k += kSolveThreads)
+          right_update(a.poses + 12 * (S.slot0 + frame_of_reduced(k, S.fixed)), y + 6 * k);
+      }
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0 && iter <= S.n_iter) st[0] = iter + 1;
 }
