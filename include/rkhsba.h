@@ -84,9 +84,9 @@ typedef struct {
   int cell_subdiv;       /* voxel cells per truncation radius, 1..8; 0 = chosen at each build from the
                             points per occupied r_c-cube (the table rkhsba_autotune fills, else a default
                             rule) (default 0) */
-  int pass_points;       /* source points per candidate sweep: 16, 32 or 64 share one walk over the cells
-                            around their box; 1 = every point walks its own cells (sparse frames); 0 =
-                            chosen with cell_subdiv (default 0) */
+  int pass_points;       /* source points per candidate sweep: 16, 32 or 64 (8 with class ids) share one
+                            walk over the cells around their box; 1 = every point walks its own cells
+                            (sparse frames); 0 = chosen with cell_subdiv (default 0) */
   int moment_path;       /* 16-point sweep, Gauss-Newton moments accumulated on 0 = library choice,
                             1 = vector ALU, 2 = matrix cores (default 0) */
   int use_graphs;        /* 1 = capture one Gauss-Newton iteration in a HIP graph and replay it (default 1;
@@ -151,7 +151,7 @@ int rkhsba_gn_step(rkhsba_ctx* ctx, double* poses_inout, int E, const int32_t* e
 
 /* Autotuner for the launch configuration.  Builds the frames (arguments as
  * rkhsba_build_neighbors) with every cell size in {1,2,3,4,6,8} cells per r_c
- * and every sweep size in {1,16,32,64} source points, times `trials` normal-
+ * and every sweep size in {1,16,32,64} source points (and 8 with class ids), times `trials` normal-
  * equation evaluations of each at `poses` / `edges` (HIP events on the
  * context's stream, after one warm-up), and leaves the context built with the
  * fastest pair; outputs (nullable): that pair and its time per evaluation in

@@ -146,8 +146,8 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   if (!(opt->ell > 0.0) || !std::isfinite(opt->ell) || !(opt->cutoff_factor > 0.0) ||
       !std::isfinite(opt->cutoff_factor) || !std::isfinite(opt->sigma) || !(opt->damping_rel >= 0.0) ||
       opt->cell_subdiv < 0 || opt->cell_subdiv > 8 ||
-      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
-       opt->pass_points != 64) ||
+      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 8 && opt->pass_points != 16 &&
+       opt->pass_points != 32 && opt->pass_points != 64) ||
       opt->fixed_frame < 0 ||
       opt->moment_path < 0 || opt->moment_path > 2 || opt->use_graphs < 0 || opt->use_graphs > 1 ||
       opt->hessian_fp32 < 0 || opt->hessian_fp32 > 1 || opt->top_k < 0 || opt->top_k > kMaxTopK)
@@ -233,10 +233,11 @@ int rkhsba_autotune(rkhsba_ctx* c, int K, const int64_t* n_points, const float* 
       }
     } cleanup{ev, g, prof};
     const int subdivs[] = {1, 2, 3, 4, 6, 8};
-    const int passes[] = {1, 16, 32, 64};
+    const int passes[] = {1, 8, 16, 32, 64};
     double best = 1e300, occ_r = 0.0;
     int bestS = 0, bestP = 0;
     for (int P : passes) {
+      if (P == 8 && feat_kind != RKHSBA_FEAT_CLASS_ID) continue;  // 8-point passes: class ids only
       for (int S : subdivs) {
         if (c->prob >= 0) g.remove_problem(c->prob);
         c->prob = -1;

@@ -247,12 +247,14 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_REQUIRE(Din >= 1 && Din <= kMaxDense, RKHSBA_EINVAL, "dense feature dimension must be in [1, 64]");
   RK_REQUIRE(par.ell > 0.0 && std::isfinite(par.ell) && par.cutoff_factor > 0.0 && std::isfinite(par.cutoff_factor) &&
                  par.cell_subdiv >= 1 && par.cell_subdiv <= 8 && std::isfinite(par.sigma) && par.damping_rel >= 0.0 &&
-                 (par.pass_points == 1 || par.pass_points == 16 || par.pass_points == 32 || par.pass_points == 64) &&
+                 (par.pass_points == 1 || par.pass_points == 8 || par.pass_points == 16 || par.pass_points == 32 ||
+                  par.pass_points == 64) &&
                  par.top_k >= 0 && par.top_k <= kMaxTopK,
              RKHSBA_EINVAL, "invalid problem parameters");
   RK_REQUIRE(par.top_k == 0 || kind == RKHSBA_FEAT_CLASS_ID || kind == RKHSBA_FEAT_DENSE_F32, RKHSBA_EINVAL,
              "top-k pair selection needs class ids or float32 dense features");
   RK_REQUIRE(par.top_k == 0 || par.pass_points == 1, RKHSBA_EINVAL, "top-k pair selection needs per-point walks");
+  RK_REQUIRE(par.pass_points != 8 || kind == RKHSBA_FEAT_CLASS_ID, RKHSBA_EINVAL, "8-point passes need class ids");
   const int Dk = kind == RKHSBA_FEAT_CLASS_ID ? 0 : Din;
   if (probs_.empty()) {
     feat_kind = kind;
@@ -683,8 +685,10 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   std::vector<SortTile> tiles;
   std::vector<SortSeg> segs(E_total);
   std::vector<KConst> kcs(items.size());
-  const int group_order[5] = {16, 1, 32, 64, 1};  // the last group: per-point walks with top-k selection
-  std::vector<PassInfo> gpass[5];
+  // one launch per group of equal pass size; group 4: per-point walks with top-k selection
+  const int group_order[6] = {16, 1, 32, 64, 1, 8};
+  int64_t gcount[6] = {0, 0, 0, 0, 0, 0};  // passes per group
+  std::vector<int8_t> egroup(E_total);
   std::vector<ProbSys> sys(items.size());
   std::vector<int32_t> bstart_all, blist, vstart_all, vlist;
   int64_t entries = 0, passes = 0, fins = 0, h_total = 0, v_total = 0;
@@ -728,24 +732,17 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       I.n_src = frame_of(m).n;
       const int pp = p->par.pass_points;
       const int P = pp == 1 ? 64 : pp;  // per-point walks: 64 sources (one per lane) per pass
-      const int gi = p->par.top_k > 0 ? 4 : pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : 3;
+      const int gi = p->par.top_k > 0 ? 4 : pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : pp == 64 ? 3 : 5;
       I.pass_size = pp;
       I.n_pass = (I.n_src + P - 1) / P;
       I.fin_off = (int32_t)fins;
       // finalisation split from the edge's own size: 1..16 entries per thread
-      I.fin_pt = std::min(16, std::max(1, I.n_src / 16384));
+      I.fin_pt = std::min(16, std::max(1, I.n_src / 4096));
       I.n_fin = (I.n_src + kFinThreads * I.fin_pt - 1) / (kFinThreads * I.fin_pt);
       I.prob = (int32_t)pi;
-      for (int k = 0; k < I.n_pass; ++k) {
-        PassInfo Q;
-        Q.entry0 = entries + (int64_t)k * P;
-        Q.src_off = frame_of(m).pt_off;
-        Q.e = e_glob;
-        Q.count = std::min(P, I.n_src - k * P);
-        Q.tgt = I.n;
-        Q.prob = (int32_t)pi;
-        gpass[gi].push_back(Q);
-      }
+      I.pass0 = (int32_t)gcount[gi];  // within its group; the group's base is added below
+      gcount[gi] += I.n_pass;
+      egroup[e_glob] = (int8_t)gi;
       ent[e_glob] = entries;
       foff[e_glob] = I.fin_off;
       segs[e_glob].start = entries;
@@ -788,15 +785,18 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   RK_HIP(lay.d_fin_off.reserve(E_total));
   RK_HIP(lay.d_etiles.reserve(tiles.size()));
   RK_HIP(lay.d_esegs.reserve(E_total));
-  std::vector<PassInfo> pinfo;
+  // the pass table: the groups one after another, each edge's passes contiguous (filled on the device)
   std::vector<SetLayout::Group> groups;
-  for (int gi = 0; gi < 5; ++gi) {
-    if (gpass[gi].empty()) continue;
-    groups.push_back(SetLayout::Group{group_order[gi], (int)pinfo.size(), (int)gpass[gi].size(), gi == 4});
-    pinfo.insert(pinfo.end(), gpass[gi].begin(), gpass[gi].end());
+  int64_t gbase[6], n_pass_table = 0;
+  for (int gi = 0; gi < 6; ++gi) {
+    gbase[gi] = n_pass_table;
+    if (gcount[gi] == 0) continue;
+    groups.push_back(SetLayout::Group{group_order[gi], (int)n_pass_table, (int)gcount[gi], gi == 4});
+    n_pass_table += gcount[gi];
   }
+  for (int e = 0; e < E_total; ++e) info[e].pass0 += (int32_t)gbase[egroup[e]];
   RK_HIP(lay.d_kcs.reserve(items.size()));
-  RK_HIP(lay.d_passes.reserve(pinfo.size()));
+  RK_HIP(lay.d_passes.reserve((size_t)n_pass_table));
   RK_HIP(lay.d_sys.reserve(items.size()));
   RK_HIP(lay.d_blk_start.reserve(bstart_all.size()));
   RK_HIP(lay.d_blk_list.reserve(blist.size()));
@@ -811,7 +811,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   up(lay.d_etiles.p, tiles.data(), sizeof(SortTile) * tiles.size());
   up(lay.d_esegs.p, segs.data(), sizeof(SortSeg) * E_total);
   up(lay.d_kcs.p, kcs.data(), sizeof(KConst) * kcs.size());
-  up(lay.d_passes.p, pinfo.data(), sizeof(PassInfo) * pinfo.size());
+  RK_HIP(launch_fill_passes(lay.d_edges.p, E_total, frames(), lay.d_passes.p, st));
   up(lay.d_sys.p, sys.data(), sizeof(ProbSys) * sys.size());
   up(lay.d_blk_start.p, bstart_all.data(), sizeof(int32_t) * bstart_all.size());
   up(lay.d_blk_list.p, blist.data(), sizeof(int32_t) * blist.size());
@@ -896,8 +896,8 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   for (const SetLayout::Group& gr : lay.groups) {
     pa.pass0 = gr.pass0;
     pa.n_pass = gr.n_pass;
-    if (gr.pass_points == 16)
-      RK_HIP(launch_sweep16(pa, mode, feat_path, moment_path == 2, st));
+    if (gr.pass_points == 16 || gr.pass_points == 8)
+      RK_HIP(launch_sweep(pa, mode, feat_path, gr.pass_points, moment_path == 2, st));
     else
       RK_HIP(launch_pairs(pa, mode, feat_path, gr.pass_points, gr.topk, st));
   }

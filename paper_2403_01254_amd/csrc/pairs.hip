@@ -106,6 +106,28 @@ __global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts
   vals[i] = src;
 }
 
+// ---------------------------------------------------------------- pass table
+
+// One block per edge: the edge's passes, in entry order.
+__global__ __launch_bounds__(256) void k_fill_passes(const EdgeInfo* __restrict__ edges,
+                                                     const FrameInfo* __restrict__ frames,
+                                                     PassInfo* __restrict__ passes) {
+  const int e = blockIdx.x;
+  const EdgeInfo ed = edges[e];
+  const int P = ed.pass_size == 1 ? 64 : ed.pass_size;  // per-point walks: one source per lane
+  const int64_t src_off = frames[ed.m].pt_off;
+  for (int k = threadIdx.x; k < ed.n_pass; k += blockDim.x) {
+    PassInfo Q;
+    Q.entry0 = ed.ent_off + (int64_t)k * P;
+    Q.src_off = src_off;
+    Q.e = e;
+    Q.count = min(P, ed.n_src - k * P);
+    Q.tgt = ed.n;
+    Q.prob = ed.prob;
+    passes[(int64_t)ed.pass0 + k] = Q;
+  }
+}
+
 // ---------------------------------------------------------------- candidate sweep
 
 // Passes of 64/G source points.  SHARED: the pass's G candidate streams walk
@@ -604,6 +626,12 @@ hipError_t dispatch_pairs(const PairArgs& a, int G, bool local, bool topk, int D
 int dense_pad(int D, int feat_path) {
   if (feat_low_precision(feat_path)) return D <= 32 ? 32 : 64;
   return D <= 8 ? 8 : D <= 16 ? 16 : D <= 24 ? 24 : D <= 32 ? 32 : 64;
+}
+
+hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, PassInfo* d_passes,
+                              hipStream_t st) {
+  if (E > 0) k_fill_passes<<<E, 256, 0, st>>>(d_edges, d_frames, d_passes);
+  return hipGetLastError();
 }
 
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st) {

@@ -49,6 +49,7 @@ struct EdgeInfo {
   int32_t n_fin;
   int32_t fin_pt;    // entries per finalize thread (a block covers kFinThreads * fin_pt entries)
   int32_t prob;      // problem of the edge within the evaluated set (constants, system)
+  int32_t pass0;     // first pass of the edge in the set's pass table
 };
 
 // One sweep pass: up to pass-size consecutive binning entries of one edge.
@@ -130,6 +131,10 @@ hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 // Mean of n points' xyz in FP64 (one workgroup, fixed summation order) -> out[3].
 hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipStream_t st);
 
+// The pass table of a set from its edge table: passes pass0 .. pass0 + n_pass - 1
+// of each edge cover its entries in runs of pass_size (64 for per-point walks).
+hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, PassInfo* d_passes,
+                              hipStream_t st);
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
                       const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,
@@ -157,10 +162,12 @@ struct PairArgs {
   KConst kc;              // set-wide: Dp and clamp (clamping is exact for non-negative features)
 };
 // Passes of pass_points sources: 1 = each lane walks its own point's cells,
-// 16 (launch_sweep16), 32, 64 = shared walk over the pass's box.
+// 8 (class ids) and 16 (launch_sweep), 32, 64 = shared walk over the pass's box.
 hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, bool topk, hipStream_t st);
 
-hipError_t launch_sweep16(const PairArgs& a, int mode, int feat_path, bool matrix_moments, hipStream_t st);
+// Tiled sweep for passes of 16 sources, or 8 with class ids.
+hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_points, bool matrix_moments,
+                        hipStream_t st);
 
 struct FinArgs {
   const float4* pts;

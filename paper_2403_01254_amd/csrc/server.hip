@@ -223,8 +223,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
   if (!out) return RKHSBA_EINVAL;
   *out = nullptr;
   if (!opt || opt->max_active < 1 || opt->hbm_budget_bytes < 0 ||
-      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 16 && opt->pass_points != 32 &&
-       opt->pass_points != 64) ||
+      (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 8 && opt->pass_points != 16 &&
+       opt->pass_points != 32 && opt->pass_points != 64) ||
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)))
     return RKHSBA_EINVAL;

@@ -117,9 +117,12 @@ __device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s
 // (A operand = the weights the lanes just computed, B = Phi of the same
 // candidates), and A, B, C follow exactly from M and v = q - ref:
 //   A = M_1, B = A v - M_u, C = A v v^T - v M_u^T - M_u v^T + M_uu.
-template <int MODE, int FEAT, int DP, bool CLAMP, bool MM>
+template <int MODE, int FEAT, int DP, bool CLAMP, bool MM, int P>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
-  constexpr int P = 16;
+  // P source points per pass (16, or 8 for class ids); lane (s, g) takes CPL candidates of every
+  // 16-candidate sub-tile
+  static_assert(P == 16 || (P == 8 && FEAT == FEAT_CLASS && !MM), "8-point passes: class ids only");
+  constexpr int CPL = P / 4;
   constexpr bool LP = feat_low_precision(FEAT);
   constexpr int FS = FEAT == FEAT_DENSE ? DP + 1 : 1;  // LDS FP32 feature row stride (odd: conflict-free column reads)
   // LDS low-precision row: DP elements + 16 (bfloat16) or 8 (fp8) bytes, so that the 16 rows one MFMA
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   const EdgeXf X = a.xf[pi.e];
   const FrameInfo Fn = a.frames[pi.tgt];
   const KConst kc = a.kcs[pi.prob];
-  const int s = lane & 15, g = lane >> 4;
+  const int s = lane & (P - 1), g = lane / P;
   const int64_t entry = pi.entry0 + s;
   const bool in_range = s < pi.count;
   bool valid = in_range;
@@ -328,8 +331,10 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
       for (int sub = 0; sub < n_sub; ++sub) {
         // this lane's four candidates of the sub-tile, read before any use
-        const float4* zp = tpos + 16 * sub + 4 * g;
-        const float4 z4[4] = {zp[0], zp[1], zp[2], zp[3]};
+        const float4* zp = tpos + 16 * sub + CPL * g;
+        float4 z4[CPL];
+#pragma unroll
+        for (int rr = 0; rr < CPL; ++rr) z4[rr] = zp[rr];
         float phi4[4] = {0.f, 0.f, 0.f, 0.f};
         if constexpr (MM) {
 #pragma unroll
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           if (sub + 1 < n_sub) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, sub + 1, slp);
         }
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
+        for (int rr = 0; rr < CPL; ++rr) {
           const float4 z = z4[rr];
           float dx, dy, dz;
           const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
@@ -398,7 +403,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   }
   // sum the four candidate streams of each source point
 #pragma unroll
-  for (int o = 16; o < 64 && !MM; o <<= 1) {
+  for (int o = P; o < 64 && !MM; o <<= 1) {
     A += __shfl_xor(A, o, 64);
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
@@ -424,16 +429,16 @@ hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, false, MM><<<nb, kLanes, 0, st>>>(a);
+    k_sweep<MODE, FEAT, 0, false, MM, 16><<<nb, kLanes, 0, st>>>(a);
   } else if constexpr (feat_low_precision(FEAT)) {
-    if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CLAMP, MM><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
   }
   return hipGetLastError();
 }
@@ -456,9 +461,16 @@ hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
 
 }  // namespace
 
-// Tiled sweep for passes of 16 source points.
+// Tiled sweep for passes of 16 source points (8 for class ids on request).
 // Loss-only sums stay on the VALU; Gauss-Newton moments on the VALU or the matrix cores.
-hipError_t launch_sweep16(const PairArgs& a, int mode, int feat_path, bool matrix_moments, hipStream_t st) {
+hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_points, bool matrix_moments,
+                        hipStream_t st) {
+  if (pass_points == 8) {
+    if (feat_path != FEAT_CLASS || a.n_pass == 0) return feat_path != FEAT_CLASS ? hipErrorInvalidValue : hipSuccess;
+    if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, false, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, false, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    return hipGetLastError();
+  }
   if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, feat_path, st);
   return matrix_moments ? dispatch_mode<MODE_NORMAL, true>(a, feat_path, st)
                         : dispatch_mode<MODE_NORMAL, false>(a, feat_path, st);

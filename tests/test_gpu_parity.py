@@ -125,11 +125,17 @@ def test_gauss_newton_parity(rk, scene):
     np.testing.assert_array_equal(poses[0], p.init_poses[0])  # the fixed frame does not move
 
 
-@pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1), (1, 1), (1, 3)])
+@pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1), (1, 1), (1, 3), (8, 1),
+                                                (8, 3)])
 def test_launch_shapes_agree(rk, pass_points, subdiv):
     """Every sweep shape and cell size gives the same pair count and, up to
-    FP32 summation order, the same F, b and H."""
-    p = scenes.odometry(4, n_frames=3, n_points=3000)
+    FP32 summation order, the same F, b and H (8-point passes: class ids)."""
+    if pass_points == 8:
+        p = scenes.lidar(2, n_frames=3, n_points=4000, n_neighbours=2, n_iter=1, spacing=3.125)
+        with pytest.raises(rk.RkhsbaError):
+            make_ctx(rk, scenes.odometry(4, n_frames=2, n_points=500), pass_points=8, cell_subdiv=subdiv)
+    else:
+        p = scenes.odometry(4, n_frames=3, n_points=3000)
     ref = make_ctx(rk, p, pass_points=16, cell_subdiv=8)
     H0, b0, F0, n0 = ref.accumulate_normal_eqs(p.init_poses, p.edges)
     ctx = make_ctx(rk, p, pass_points=pass_points, cell_subdiv=subdiv)
