@@ -863,7 +863,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
 void Engine::evaluate(SetLayout& lay, int mode) {
   hipEvent_t t0 = prof_begin();
   RK_HIP(launch_edge_setup(poses(), lay.d_edges.p, lay.E, xf_.p, st));
-  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_ent_off.p, xf_.p, lay.E, lay.n_entries, lay.d_kcs.p, bk_.p,
+  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, xf_.p, lay.d_kcs.p, bk_.p,
                     bv_.p, st));
   bool in_tmp = false;
   RK_HIP(launch_radix_sort(bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,

@@ -79,31 +79,38 @@ __global__ void k_edge_setup(const double* __restrict__ poses, const EdgeInfo* _
   xf[e] = o;
 }
 
-__global__ __launch_bounds__(kThreads) void k_bin(const float4* __restrict__ pts, const FrameInfo* __restrict__ frames,
-                                                  const EdgeInfo* __restrict__ edges,
-                                                  const int64_t* __restrict__ ent_off, const EdgeXf* __restrict__ xf,
-                                                  int E, int64_t n_entries, const KConst* __restrict__ kcs,
-                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n_entries) return;
-  const int e = upper_segment(ent_off, E, i);
-  const EdgeInfo& ed = edges[e];
+// One block per sort tile (kSortTile consecutive entries of one edge): the
+// Morton code of each source point's target-frame cell, or kInvalidKey when
+// the point falls outside the target grid (it has no pair).
+__global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__ pts,
+                                                      const FrameInfo* __restrict__ frames,
+                                                      const EdgeInfo* __restrict__ edges,
+                                                      const SortTile* __restrict__ tiles,
+                                                      const EdgeXf* __restrict__ xf, const KConst* __restrict__ kcs,
+                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const SortTile t = tiles[blockIdx.x];
+  const int e = t.seg;
+  const EdgeInfo ed = edges[e];
   const KConst kc = kcs[ed.prob];
-  const uint32_t src = (uint32_t)(i - ed.ent_off);
-  const FrameInfo& Fm = frames[ed.m];
-  const FrameInfo& Fn = frames[ed.n];
-  const float4 x = pts[Fm.pt_off + src];
-  const float3 q = rule_q32(xf[e], x.x, x.y, x.z);
+  const FrameInfo Fm = frames[ed.m];
+  const FrameInfo Fn = frames[ed.n];
+  const EdgeXf X = xf[e];
   const int r = kc.reach_cells;
   const int lim = 1 << 30;
-  const int cx = clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r;
-  const int cy = clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r;
-  const int cz = clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r;
-  uint32_t key = kInvalidKey;
-  if (cx >= 0 && cy >= 0 && cz >= 0 && cx < Fn.dim[0] + 2 * r && cy < Fn.dim[1] + 2 * r && cz < Fn.dim[2] + 2 * r)
-    key = morton3((uint32_t)cx >> Fn.mort_shift, (uint32_t)cy >> Fn.mort_shift, (uint32_t)cz >> Fn.mort_shift);
-  keys[i] = key;
-  vals[i] = src;
+  for (int k = threadIdx.x; k < t.count; k += kSortThreads) {
+    const int64_t i = t.start + k;
+    const uint32_t src = (uint32_t)(i - ed.ent_off);
+    const float4 x = pts[Fm.pt_off + src];
+    const float3 q = rule_q32(X, x.x, x.y, x.z);
+    const int cx = clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r;
+    const int cy = clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r;
+    const int cz = clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r;
+    uint32_t key = kInvalidKey;
+    if (cx >= 0 && cy >= 0 && cz >= 0 && cx < Fn.dim[0] + 2 * r && cy < Fn.dim[1] + 2 * r && cz < Fn.dim[2] + 2 * r)
+      key = morton3((uint32_t)cx >> Fn.mort_shift, (uint32_t)cy >> Fn.mort_shift, (uint32_t)cz >> Fn.mort_shift);
+    keys[i] = key;
+    vals[i] = src;
+  }
 }
 
 // ---------------------------------------------------------------- pass table
@@ -639,13 +646,11 @@ hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
-                      const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,
+hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges,
+                      const SortTile* d_tiles, int n_tiles, const EdgeXf* d_xf, const KConst* d_kcs, uint32_t* d_keys,
                       uint32_t* d_vals, hipStream_t st) {
-  if (n_entries > 0)
-    k_bin<<<(unsigned)((n_entries + kThreads - 1) / kThreads), kThreads, 0, st>>>(d_pts, d_frames, d_edges, d_ent_off,
-                                                                                d_xf, E, n_entries, d_kcs, d_keys,
-                                                                                d_vals);
+  if (n_tiles > 0)
+    k_bin<<<(unsigned)n_tiles, kSortThreads, 0, st>>>(d_pts, d_frames, d_edges, d_tiles, d_xf, d_kcs, d_keys, d_vals);
   return hipGetLastError();
 }
 

@@ -82,10 +82,12 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
       val = vin[t.start + k];
       d = (key >> shift) & 0xffu;
     }
-    uint64_t peers = __ballot(valid);
+    uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
+#pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-      const uint64_t bl = __ballot((d >> bit) & 1u);
-      peers &= ((d >> bit) & 1u) ? bl : ~bl;
+      const bool b = ((d >> bit) & 1u) != 0u;
+      const uint64_t bl = __builtin_amdgcn_ballot_w64(b);
+      peers &= b ? bl : ~bl;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);

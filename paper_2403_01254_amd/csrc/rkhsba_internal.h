@@ -136,8 +136,9 @@ hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipS
 hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, PassInfo* d_passes,
                               hipStream_t st);
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
-hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges, const int64_t* d_ent_off,
-                      const EdgeXf* d_xf, int E, int64_t n_entries, const KConst* d_kcs, uint32_t* d_keys,
+// Binning keys and source indices of every entry, one block per sort tile of an edge.
+hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges,
+                      const SortTile* d_tiles, int n_tiles, const EdgeXf* d_xf, const KConst* d_kcs, uint32_t* d_keys,
                       uint32_t* d_vals, hipStream_t st);
 
 struct PairArgs {
