@@ -86,7 +86,7 @@ def percentile_ms(lat, q):
     return float(np.percentile(np.asarray(lat) * 1e3, q)) if len(lat) else None
 
 
-def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
+def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
     """Seeded Poisson stream of whole solves: capacity of the one-at-a-time
     FP32 form, then, at 0.5x and 0.9x of it, latency percentiles and
     throughput of the continuous-batching request loop and of the
@@ -124,7 +124,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
     pose_diff = {}
 
     def run_batched(kind, arrivals):
-        srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64)
+        srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64, lanes=lanes)
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05
 
@@ -181,7 +181,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0):
                      "one_at_a_time_f32": single})
     for c in ctxs.values():
         c.close()
-    return {"requests": len(reqs), "capacity_one_at_a_time_solves_per_s": capacity,
+    return {"requests": len(reqs), "lanes": lanes, "capacity_one_at_a_time_solves_per_s": capacity,
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
             "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48,
                     help="requests in the serving measurement (0: skip); the serving workload's full stream is 512")
+    ap.add_argument("--serving-lanes", type=int, default=2, choices=[1, 2],
+                    help="concurrent batches of the request server (large requests in the second)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -373,7 +375,7 @@ def main():
         reqs = [f.result() for f in gen_futures]
         gen_pool.shutdown()
         log(f"[bench] serving: {len(reqs)} requests generated")
-        result["serving"] = serving_benchmark(reqs, rkhsba, torch, log)
+        result["serving"] = serving_benchmark(reqs, rkhsba, torch, log, lanes=args.serving_lanes)
     if rank == 0:
         print(json.dumps(result), flush=True)
     ctx.close()

@@ -270,12 +270,15 @@ int rkhsba_profile_read(rkhsba_ctx* ctx, int stage, double* total_ms, int64_t* l
 /* ------------------------------------------------------------------------
  * Request loop (continuous batching of whole solves).
  *
- * A server owns one device stream and a worker thread.  Each request is one
- * multi-frame problem (its own frames, edge list, ell, n_iter and initial
- * poses) solved exactly as rkhsba_gn_step solves it.  Requests wait in FIFO
- * order and are admitted while fewer than max_active are active and the sum
- * of their estimated device footprints stays within hbm_budget_bytes (one
- * request is always admitted when none is active).  Admission builds the
+ * A server runs one or two lanes, each a worker thread with its own engine
+ * and device stream.  Each request is one multi-frame problem (its own
+ * frames, edge list, ell, n_iter and initial poses) solved exactly as
+ * rkhsba_gn_step solves it; with two lanes, large requests (by their
+ * (edge, source point) entries) go to the second lane, so that small ones do
+ * not wait for their iterations.  In a lane, requests wait in FIFO order and
+ * are admitted while fewer than max_active are active in the lane and the sum
+ * of the estimated device footprints of all admitted requests stays within
+ * hbm_budget_bytes (one request is always admitted when its lane is idle).  Admission builds the
  * request's voxel structures into memory that stays resident until it
  * finishes; every batch iteration then advances every active request by one
  * Gauss-Newton step in shared launches (one edge table over all requests, one
@@ -297,7 +300,11 @@ typedef struct {
   int pass_points;          /* sweep pass size for every request (0: chosen per request, default) */
   int use_graphs;           /* replay a batch iteration from a HIP graph while the active set is unchanged */
   int hessian_fp32;         /* as rkhsba_options.hessian_fp32 */
-  void* stream;             /* hipStream_t for all work; NULL = a stream owned by the server */
+  void* stream;             /* hipStream_t of lane 0; NULL = a stream owned by the server (lane 1 always runs
+                               on a stream of its own) */
+  int lanes;                /* 1 or 2 concurrent batches, each with its own engine and stream (default 1) */
+  int64_t lane_split_entries; /* with 2 lanes: requests with more (edge, source point) entries (sum over the edges
+                               of the source frame's points) go to lane 1 (default 2,000,000) */
 } rkhsba_server_options;
 
 typedef struct {

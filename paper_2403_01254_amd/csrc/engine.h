@@ -232,7 +232,11 @@ class Engine {
   // Bytes the engine holds in HBM (pools, set buffers, build scratch).
   int64_t device_bytes() const;
   // Resident pool bytes a problem of this shape is expected to hold (admission estimate).
-  int64_t estimate_problem_bytes(int K, const int64_t* n_points, int E) const;
+  int64_t estimate_problem_bytes(int K, const int64_t* n_points, int E) const {
+    return estimate_bytes(K, n_points, E, feat_row_bytes());
+  }
+  // The same estimate for a given feature row size (bytes per point), without engine state.
+  static int64_t estimate_bytes(int K, const int64_t* n_points, int E, int64_t row_bytes);
 
   void upload_poses(Problem* p, const double* poses);   // host K*12
   // count alias slots of `frame` with the given host poses (count*12); replaces earlier aliases

@@ -206,13 +206,13 @@ int64_t Engine::device_bytes() const {
   return b;
 }
 
-int64_t Engine::estimate_problem_bytes(int K, const int64_t* n_points, int E) const {
+int64_t Engine::estimate_bytes(int K, const int64_t* n_points, int E, int64_t row_bytes) {
   int64_t N = 0, nmax = 0;
   for (int f = 0; f < K; ++f) {
     N += n_points[f];
     nmax = std::max(nmax, n_points[f]);
   }
-  const int64_t per_point = 28 + feat_row_bytes() + 12;  // pools + cell tables (typical occupancy)
+  const int64_t per_point = 28 + row_bytes + 12;  // pools + cell tables (typical occupancy)
   const int64_t per_entry = 16 + 40 + 4 + 3;                // binning keys/values (x2), moments, count, partials
   const int64_t n = 6 * (int64_t)K;
   return N * per_point + (int64_t)E * nmax * per_entry + 2 * n * n * 8 + (int64_t)E * 2 * kEdgeVals * 8;

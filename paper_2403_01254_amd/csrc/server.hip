@@ -1,16 +1,20 @@
 // Request loop: continuous batching of whole solves (each request = the
 // multi-frame Gauss-Newton problem of Sec. V-A on its own frames, graph and
-// length scale).  A worker thread owns one engine; requests wait in a FIFO
-// queue and are admitted while the number of active requests and the sum of
-// their estimated device footprints stay within the limits (a request is
-// always admitted when nothing is active).  Admission builds the request's
-// voxel structures into the engine's resident pools; then every active
-// request advances by one Gauss-Newton iteration per batch iteration, all of
-// them in the same launches (one edge table, one system per request).  A
-// request that has taken its n_iter steps gets its final loss evaluation in
-// the next batch iteration and is retired: poses and histories are copied
-// out, its pools are freed and its waiter is woken.  Requests that arrive
-// meanwhile join at the next batch iteration.
+// length scale).  The server runs one or two lanes; a lane is a worker thread
+// with its own engine and stream.  With two lanes, requests with many
+// (edge, source point) entries go to lane 1 and the others to lane 0, so small
+// requests do not wait for the iterations of large ones, and the two lanes'
+// launches overlap on the device.  In a lane, requests wait in a FIFO queue
+// and are admitted while the number of active requests and the sum of the
+// estimated device footprints of all admitted requests stay within the limits
+// (a request is always admitted when its lane is idle).  Admission builds the
+// request's voxel structures into the lane engine's resident pools; then every
+// active request of the lane advances by one Gauss-Newton iteration per batch
+// iteration, all of them in the same launches (one edge table, one system per
+// request).  A request that has taken its n_iter steps gets its final loss
+// evaluation in the next batch iteration and is retired: poses and histories
+// are copied out, its pools are freed and its waiter is woken.  Requests that
+// arrive meanwhile join at the next batch iteration.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -56,21 +60,32 @@ struct Req {
 
 }  // namespace
 
-struct rkhsba_server {
-  rkhsba_server_options opt{};
+namespace {
+
+struct Lane {
+  int id = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::unique_ptr<Engine> eng;
   SetLayout lay;
   std::thread worker;
+  std::deque<std::shared_ptr<Req>> queue;    // guarded by the server mutex
+  std::vector<std::shared_ptr<Req>> active;  // worker thread only
+  int64_t dev_bytes = 0;                     // the engine's device memory, guarded by the server mutex
+};
+
+}  // namespace
+
+struct rkhsba_server {
+  rkhsba_server_options opt{};
+  std::vector<std::unique_ptr<Lane>> lanes;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Req>> queue;
   std::map<int64_t, std::shared_ptr<Req>> tickets;
-  std::vector<std::shared_ptr<Req>> active;  // worker thread only
   bool stop = false;
   int64_t next_ticket = 1;
-  int64_t committed = 0;  // estimated bytes of admitted requests
+  int64_t committed = 0;  // estimated bytes of admitted requests (all lanes)
+  int64_t row_bytes = 4;  // stored feature bytes per point (admission estimates)
   rkhsba_server_stats stats{};
   std::string err;
 
@@ -85,18 +100,19 @@ struct rkhsba_server {
     if (q->admitted) committed -= q->est_bytes;
     q->admitted = false;
     cv_done.notify_all();
+    cv_work.notify_all();  // memory was released: other lanes may admit
   }
 
-  void retire(const std::shared_ptr<Req>& q) {
-    Problem* p = eng->problem(q->prob);
+  void retire(Lane& L, const std::shared_ptr<Req>& q) {
+    Problem* p = L.eng->problem(q->prob);
     int status = RKHSBA_OK;
     std::string msg;
     try {
       q->loss.assign(q->n_iter + 1, 0.0);
       q->pairs.assign(q->n_iter + 1, 0.0);
-      eng->download_poses(p, q->poses.data());
-      eng->read_history(p, q->n_iter + 1, q->loss.data(), q->pairs.data());
-      if (eng->read_status(p) != 0) {
+      L.eng->download_poses(p, q->poses.data());
+      L.eng->read_history(p, q->n_iter + 1, q->loss.data(), q->pairs.data());
+      if (L.eng->read_status(p) != 0) {
         status = RKHSBA_ENOTPD;
         msg = "Cholesky pivot not positive in a Gauss-Newton step";
       }
@@ -104,7 +120,7 @@ struct rkhsba_server {
       status = f.code;
       msg = f.msg;
     }
-    eng->remove_problem(q->prob);
+    L.eng->remove_problem(q->prob);
     q->prob = -1;
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -113,93 +129,109 @@ struct rkhsba_server {
     finish(q, status, msg);
   }
 
-  void run() {
+  void drop(Lane& L, const std::shared_ptr<Req>& q, int code, const std::string& msg) {
+    if (q->prob >= 0) L.eng->remove_problem(q->prob);
+    q->prob = -1;
+    finish(q, code, msg);
+  }
+
+  void run(Lane& L) {
     (void)hipSetDevice(opt.device);
     for (;;) {
       std::vector<std::shared_ptr<Req>> admit;
       {
         std::unique_lock<std::mutex> lk(mu);
-        if (active.empty()) cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        if (L.active.empty()) cv_work.wait(lk, [&] { return stop || !L.queue.empty(); });
         if (stop) break;
-        while (!queue.empty() && (int)(active.size() + admit.size()) < opt.max_active) {
-          const std::shared_ptr<Req>& q = queue.front();
-          const bool idle = active.empty() && admit.empty();
+        while (!L.queue.empty() && (int)(L.active.size() + admit.size()) < opt.max_active) {
+          const std::shared_ptr<Req>& q = L.queue.front();
+          const bool idle = L.active.empty() && admit.empty();
           if (!idle && committed + q->est_bytes > opt.hbm_budget_bytes) break;
           committed += q->est_bytes;
           q->admitted = true;
           admit.push_back(q);
-          queue.pop_front();
+          L.queue.pop_front();
         }
       }
       for (auto& q : admit) {
         try {
-          q->prob = eng->add_problem_auto(q->par, q->K, q->n_points.data(), q->xyz.data(), q->feat_kind, q->D,
-                                          q->feats.data(), q->is_device != 0);
-          Problem* p = eng->problem(q->prob);
-          eng->upload_poses(p, q->poses.data());
-          eng->reset_state(p);
+          q->prob = L.eng->add_problem_auto(q->par, q->K, q->n_points.data(), q->xyz.data(), q->feat_kind, q->D,
+                                            q->feats.data(), q->is_device != 0);
+          Problem* p = L.eng->problem(q->prob);
+          L.eng->upload_poses(p, q->poses.data());
+          L.eng->reset_state(p);
           q->t_admit = Clock::now();
-          active.push_back(q);
+          L.active.push_back(q);
         } catch (const Fail& f) {
-          if (q->prob >= 0) eng->remove_problem(q->prob);
-          q->prob = -1;
-          finish(q, f.code, f.msg);
+          drop(L, q, f.code, f.msg);
         } catch (...) {
-          if (q->prob >= 0) eng->remove_problem(q->prob);
-          q->prob = -1;
-          finish(q, RKHSBA_EDEVICE, "unexpected exception at admission");
+          drop(L, q, RKHSBA_EDEVICE, "unexpected exception at admission");
         }
       }
-      if (active.empty()) continue;
+      if (L.active.empty()) continue;
       try {
         std::vector<SetItem> items;
         bool all_final = true;
-        for (auto& q : active) {
-          items.push_back(SetItem{eng->problem(q->prob), q->edges.data(), q->E, q->par.fixed_frame, q->n_iter});
+        for (auto& q : L.active) {
+          items.push_back(SetItem{L.eng->problem(q->prob), q->edges.data(), q->E, q->par.fixed_frame, q->n_iter});
           all_final = all_final && q->evals == q->n_iter;
         }
-        eng->prepare(lay, items);
+        L.eng->prepare(L.lay, items);
         if (all_final) {
-          eng->evaluate(lay, MODE_LOSS);
-          eng->loss_only(lay);
+          L.eng->evaluate(L.lay, MODE_LOSS);
+          L.eng->loss_only(L.lay);
         } else {
-          eng->iterate(lay, 1);
+          L.eng->iterate(L.lay, 1);
         }
+        const int64_t mine = L.eng->device_bytes();
         {
           std::lock_guard<std::mutex> lk(mu);
           stats.batch_iterations += 1;
-          stats.max_active = std::max<int64_t>(stats.max_active, (int64_t)active.size());
-          stats.peak_device_bytes = std::max<int64_t>(stats.peak_device_bytes, eng->device_bytes());
+          stats.max_active = std::max<int64_t>(stats.max_active, (int64_t)L.active.size());
+          L.dev_bytes = mine;
+          int64_t dev = 0;
+          for (const auto& l : lanes) dev += l->dev_bytes;
+          stats.peak_device_bytes = std::max<int64_t>(stats.peak_device_bytes, dev);
         }
         std::vector<std::shared_ptr<Req>> still;
-        for (auto& q : active) {
+        for (auto& q : L.active) {
           q->evals += 1;
-          if (q->evals > q->n_iter) retire(q);
+          if (q->evals > q->n_iter) retire(L, q);
           else still.push_back(q);
         }
-        active.swap(still);
+        L.active.swap(still);
       } catch (const Fail& f) {
-        for (auto& q : active) {
-          if (q->prob >= 0) eng->remove_problem(q->prob);
-          q->prob = -1;
-          finish(q, f.code, f.msg);
-        }
-        active.clear();
+        for (auto& q : L.active) drop(L, q, f.code, f.msg);
+        L.active.clear();
       }
     }
-    // shutting down: drop what is active or queued
-    for (auto& q : active) {
-      if (q->prob >= 0) eng->remove_problem(q->prob);
-      q->prob = -1;
-      finish(q, RKHSBA_ESTATE, "server shut down");
-    }
-    active.clear();
+    // shutting down: drop what is active or queued in this lane
+    for (auto& q : L.active) drop(L, q, RKHSBA_ESTATE, "server shut down");
+    L.active.clear();
     std::deque<std::shared_ptr<Req>> rest;
     {
       std::lock_guard<std::mutex> lk(mu);
-      rest.swap(queue);
+      rest.swap(L.queue);
     }
     for (auto& q : rest) finish(q, RKHSBA_ESTATE, "server shut down");
+  }
+
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv_work.notify_all();
+    for (auto& L : lanes)
+      if (L->worker.joinable()) L->worker.join();
+    (void)hipSetDevice(opt.device);
+    for (auto& L : lanes) {
+      if (L->stream) (void)hipStreamSynchronize(L->stream);
+      L->lay.drop_graph();
+      L->eng.reset();
+      if (L->own_stream) (void)hipStreamDestroy(L->stream);
+    }
+    lanes.clear();
   }
 };
 
@@ -217,6 +249,8 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->use_graphs = 1;
   o->hessian_fp32 = 0;
   o->stream = nullptr;
+  o->lanes = 1;
+  o->lane_split_entries = 2000000;
 }
 
 int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
@@ -226,7 +260,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
       (opt->pass_points != 0 && opt->pass_points != 1 && opt->pass_points != 8 && opt->pass_points != 16 &&
        opt->pass_points != 32 && opt->pass_points != 64) ||
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
-      (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)))
+      (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)) || opt->lanes < 1 ||
+      opt->lanes > 2 || opt->lane_split_entries < 0)
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -242,30 +277,39 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
     }
     s->opt.hbm_budget_bytes = (int64_t)(0.8 * (double)free_b);
   }
-  if (opt->stream) {
-    s->stream = static_cast<hipStream_t>(opt->stream);
-  } else {
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete s;
-      return RKHSBA_EDEVICE;
-    }
-    s->own_stream = true;
-  }
-  s->eng.reset(new (std::nothrow) Engine(opt->device, s->stream, 0));
-  if (!s->eng) {
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
-    delete s;
-    return RKHSBA_ENOMEM;
-  }
-  s->eng->use_graphs = opt->use_graphs != 0;
-  s->eng->fp32_sums = opt->hessian_fp32 != 0;
+  s->row_bytes = opt->feat_kind == RKHSBA_FEAT_CLASS_ID
+                     ? 4
+                     : (int64_t)feat_elem_bytes(opt->feat_kind) * dense_pad(opt->D, opt->feat_kind);
+  int rc = RKHSBA_OK;
   try {
-    s->worker = std::thread([s] { s->run(); });
+    for (int i = 0; i < opt->lanes && rc == RKHSBA_OK; ++i) {
+      std::unique_ptr<Lane> L(new Lane());
+      L->id = i;
+      if (i == 0 && opt->stream) {
+        L->stream = static_cast<hipStream_t>(opt->stream);
+      } else if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) == hipSuccess) {
+        L->own_stream = true;
+      } else {
+        rc = RKHSBA_EDEVICE;
+        break;
+      }
+      L->eng.reset(new Engine(opt->device, L->stream, 0));
+      L->eng->use_graphs = opt->use_graphs != 0;
+      L->eng->fp32_sums = opt->hessian_fp32 != 0;
+      s->lanes.push_back(std::move(L));
+    }
+    if (rc == RKHSBA_OK)
+      for (auto& L : s->lanes) {
+        Lane* lp = L.get();
+        L->worker = std::thread([s, lp] { s->run(*lp); });
+      }
   } catch (...) {
-    s->eng.reset();
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    rc = RKHSBA_EDEVICE;
+  }
+  if (rc != RKHSBA_OK) {
+    s->shutdown();
     delete s;
-    return RKHSBA_EDEVICE;
+    return rc;
   }
   *out = s;
   return RKHSBA_OK;
@@ -273,17 +317,7 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
 
 void rkhsba_server_destroy(rkhsba_server* s) {
   if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-  }
-  s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  (void)hipSetDevice(s->opt.device);
-  (void)hipStreamSynchronize(s->stream);
-  s->lay.drop_graph();
-  s->eng.reset();
-  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  s->shutdown();
   delete s;
 }
 
@@ -322,17 +356,20 @@ int rkhsba_server_submit(rkhsba_server* s, const rkhsba_request* r, int64_t* tic
     q->feats.assign(r->feats, r->feats + r->K);
     q->poses.assign(r->poses, r->poses + 12 * (size_t)r->K);
     q->edges.assign(r->edges, r->edges + 2 * (size_t)r->E);
-    q->est_bytes = s->eng->estimate_problem_bytes(r->K, r->n_points, r->E);
+    q->est_bytes = Engine::estimate_bytes(r->K, r->n_points, r->E, s->row_bytes);
+    int64_t entries = 0;  // (edge, source point) entries: the request's share of every launch
+    for (int e = 0; e < r->E; ++e) entries += r->n_points[r->edges[2 * e]];
+    const size_t lane = (s->lanes.size() > 1 && entries > s->opt.lane_split_entries) ? 1 : 0;
     q->t_submit = Clock::now();
     {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->stop) return RKHSBA_ESTATE;
       q->ticket = s->next_ticket++;
       s->tickets[q->ticket] = q;
-      s->queue.push_back(q);
+      s->lanes[lane]->queue.push_back(q);
       s->stats.submitted += 1;
     }
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     *ticket = q->ticket;
     return RKHSBA_OK;
   } catch (const std::bad_alloc&) {
@@ -374,7 +411,8 @@ int rkhsba_server_stats_get(rkhsba_server* s, rkhsba_server_stats* out) {
   if (!s || !out) return RKHSBA_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->stats;
-  out->queued = (int64_t)s->queue.size();
+  out->queued = 0;
+  for (const auto& L : s->lanes) out->queued += (int64_t)L->queue.size();
   return RKHSBA_OK;
 }
 

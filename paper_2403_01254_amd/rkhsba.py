@@ -59,6 +59,8 @@ class ServerOptions(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("hessian_fp32", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("lanes", ctypes.c_int),
+        ("lane_split_entries", ctypes.c_int64),
     ]
 
 
@@ -400,7 +402,7 @@ class Server:
     solve and returns a ticket at once; wait() returns its result."""
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
-                 use_graphs=True, hessian_fp32=False, stream=None):
+                 use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
@@ -409,6 +411,7 @@ class Server:
         o.pass_points, o.use_graphs = pass_points, int(bool(use_graphs))
         o.hessian_fp32 = int(bool(hessian_fp32))
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
+        o.lanes, o.lane_split_entries = int(lanes), int(lane_split_entries)
         self.opts = o
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))

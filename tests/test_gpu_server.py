@@ -36,11 +36,13 @@ def submit(srv, p):
     return srv.submit(p.points, p.feats, p.init_poses, p.edges, p.ell, p.n_iter)
 
 
-def test_alone_and_in_mix_agree(rk, requests):
-    # plus one request with frames large enough for several entries per finalisation thread
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_alone_and_in_mix_agree(rk, requests, lanes):
+    # plus one request with frames large enough for several entries per finalisation thread (with two
+    # lanes it is the only one above the split and runs in the second lane, beside the others)
     requests = requests + [scenes.request(7, k_range=(3, 3), n_range=(40000, 60000), n_iter=2)]
-    say("[server] " + "; ".join(p.recipe[:60] for p in requests))
-    with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
+    say(f"[server] lanes {lanes}: " + "; ".join(p.recipe[:60] for p in requests))
+    with rk.Server(feat_kind="dense", D=20, max_active=8, lanes=lanes, lane_split_entries=60000) as srv:
         alone = [srv.wait(submit(srv, p), timeout=120) for p in requests]
         assert srv.stats()["max_active"] == 1
         tickets = [submit(srv, p) for p in requests]       # all in flight together
@@ -106,3 +108,6 @@ def test_invalid_requests(rk, requests):
         # the server still works after rejected submissions
         poses, lpi, ppi, lat, qs = srv.wait(submit(srv, p), timeout=120)
         assert np.all(np.isfinite(poses))
+    for bad in (0, 3):
+        with pytest.raises(rk.RkhsbaError):
+            rk.Server(feat_kind="dense", D=20, lanes=bad)
