@@ -160,7 +160,10 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
         qps = frac * capacity
         arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
         arrivals -= arrivals[0]
-        batched = {k: run_batched(k, arrivals) for k in ("dense", "bf16")}
+        batched = {}
+        for k in ("dense", "bf16"):
+            batched[k] = run_batched(k, arrivals)
+            log(f"[serving] {qps:.2f} req/s: batched {k} done")
         # one at a time, FP32, same arrivals
         lat1 = []
         start1 = time.perf_counter()
