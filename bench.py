@@ -107,17 +107,27 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
         return ctxs[ell]
 
     def solve_one(i):
+        """One request on its own context; None if a Gauss-Newton step met a non-positive Cholesky pivot."""
         p = reqs[i]
         c = ctx_for(p.ell)
         c.build_neighbors(staged[i][0], staged[i][1], p.feat_kind)
-        return c.gn_step(p.init_poses, p.edges, p.n_iter)
+        try:
+            return c.gn_step(p.init_poses, p.edges, p.n_iter)
+        except rkhsba.RkhsbaError as e:
+            if e.code != rkhsba.ENOTPD:
+                raise
+            return None
 
     solve_one(0)  # warm-up (library load, first allocations)
     t0 = time.perf_counter()
     seq = [solve_one(i) for i in range(len(reqs))]
     cap_s = time.perf_counter() - t0
     capacity = len(reqs) / cap_s
-    seq_pairs = sum(int(r[2].sum()) for r in seq)
+    seq_pairs = sum(int(r[2].sum()) for r in seq if r is not None)
+    not_pd = [i for i, r in enumerate(seq) if r is None]
+    if not_pd:
+        log(f"[serving] {len(not_pd)} request(s) met a non-positive Cholesky pivot: " +
+            "; ".join(reqs[i].recipe for i in not_pd))
     log(f"[serving] one-at-a-time capacity {capacity:.2f} solves/s ({len(reqs)} requests in {cap_s:.2f} s)")
     rng = np.random.default_rng(seed)
     runs = []
@@ -141,19 +151,21 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
         for i in range(len(reqs)):
             while tickets[i] is None:
                 time.sleep(1e-4)
-            r = srv.wait(tickets[i])
+            r = srv.wait(tickets[i], with_status=True)
             out.append(r)
             lat.append(r[3])
         th.join()
         end = time.perf_counter()
         st = srv.stats()
         srv.close()
-        diff = max(float(np.abs(r[0] - q[0]).max()) for r, q in zip(out, seq))
+        diff = max(float(np.abs(r[0] - q[0]).max()) for r, q in zip(out, seq)
+                   if q is not None and r[5] == rkhsba.OK)
+        not_pd_batched = sum(1 for r in out if r[5] != rkhsba.OK)
         pose_diff[kind] = max(pose_diff.get(kind, 0.0), diff)
         return {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
                 "solves_per_s": len(reqs) / (end - start), "pair_evals_per_s": st["pair_evals"] / (end - start),
                 "max_active": st["max_active"], "batch_iterations": st["batch_iterations"],
-                "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out])),
+                "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out])), "not_pd_requests": not_pd_batched,
                 "max_pose_entry_diff_vs_one_at_a_time_f32": diff}
 
     for frac in (0.5, 0.9):
@@ -185,6 +197,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
     for c in ctxs.values():
         c.close()
     return {"requests": len(reqs), "lanes": lanes, "capacity_one_at_a_time_solves_per_s": capacity,
+            "not_pd_requests_one_at_a_time": len(not_pd),
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
             "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "

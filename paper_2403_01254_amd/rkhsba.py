@@ -458,8 +458,10 @@ class Server:
         self._keep[t.value] = (keep, n, xarr, farr, points, feats, K, n_iter)
         return t.value
 
-    def wait(self, ticket, timeout=-1.0):
-        """(poses (K,12), loss per evaluation, pairs per evaluation, latency s, queued s)."""
+    def wait(self, ticket, timeout=-1.0, with_status=False):
+        """(poses (K,12), loss per evaluation, pairs per evaluation, latency s, queued s); with_status: the same
+        plus the request's status, and RKHSBA_ENOTPD (a non-positive Cholesky pivot, outputs still written) is
+        returned instead of raised."""
         keep = self._keep[ticket]
         K, n_iter = keep[6], keep[7]
         poses = np.zeros((K, 12))
@@ -471,8 +473,10 @@ class Server:
         if rc == EBUSY:
             raise TimeoutError(f"request {ticket} not finished within {timeout} s")
         del self._keep[ticket]
-        if rc != OK:
+        if rc != OK and not (with_status and rc == ENOTPD):
             raise RkhsbaError(rc, lib().rkhsba_server_last_error(self._h).decode())
+        if with_status:
+            return poses, lpi, ppi, lat.value, qs.value, rc
         return poses, lpi, ppi, lat.value, qs.value
 
     def stats(self):
