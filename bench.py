@@ -201,9 +201,9 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
             "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
-                      "depth-camera trajectory (p = 1/2), 20-class Dirichlet(0.3) soft labels (D = 20), ell in "
-                      "{0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs resident in HBM; Poisson "
-                      "arrivals at 0.5x and 0.9x of the measured one-at-a-time capacity"}
+                      "depth-camera trajectory with a 0.3 m minimum range (p = 1/2), 20-class Dirichlet(0.3) soft "
+                      "labels (D = 20), ell in {0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs "
+                      "resident in HBM; Poisson arrivals at 0.5x and 0.9x of the measured one-at-a-time capacity"}
 
 
 def cpu_baseline(p, n_edges, min_seconds=10.0, max_repeats=5):

@@ -235,9 +235,11 @@ def _cast(scene: _Scene, o: np.ndarray, dirs: np.ndarray, max_range: float):
     return best_t, best_p
 
 
-def _depth_view(rng, scene, pose, n_pts, fov_h=60.0, fov_v=45.0, grid=(200, 150), max_range=8.0, max_rounds=60):
+def _depth_view(rng, scene, pose, n_pts, fov_h=60.0, fov_v=45.0, grid=(200, 150), max_range=8.0, max_rounds=60,
+                min_range=0.0):
     """Jittered depth-camera ray grid (x forward, y left, z up) from a camera pose;
-    misses are re-drawn inside the field of view until n_pts hits are collected."""
+    misses are re-drawn inside the field of view until n_pts hits are collected.  Hits nearer than
+    min_range count as misses (a depth camera's minimum range)."""
     R, t = pose_rt(pose)
     gw, gh = grid
     hits_t, hits_d, hits_p = [], [], []
@@ -254,7 +256,7 @@ def _depth_view(rng, scene, pose, n_pts, fov_h=60.0, fov_v=45.0, grid=(200, 150)
         d_loc = np.stack([np.cos(e) * np.cos(a), np.cos(e) * np.sin(a), np.sin(e)], axis=1)
         d_w = d_loc @ R.T
         tt, pp = _cast(scene, t, d_w, max_range)
-        ok = np.isfinite(tt)
+        ok = np.isfinite(tt) & (tt >= min_range)
         hits_t.append(tt[ok]); hits_d.append(d_loc[ok]); hits_p.append(pp[ok])
         got += int(ok.sum())
         if got >= n_pts:
@@ -583,7 +585,7 @@ def request(seed: int, k_range=(2, 16), n_range=(5000, 120_000), ells=(0.08, 0.3
     else:
         for _attempt in range(50):
             gt = _trajectory(rng, K)
-            views = [_depth_view(rng, scene, gt[k], Ns[k]) for k in range(K)]
+            views = [_depth_view(rng, scene, gt[k], Ns[k], min_range=0.3) for k in range(K)]
             if all(v is not None for v in views):
                 break
         pts = [v[0].astype(np.float32) for v in views]
