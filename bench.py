@@ -32,7 +32,8 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 # Algorithmic work per in-radius pair of the sweep (FMA = 2 flops, exp = 1):
 # residual 3 + squared distance 5 + scale 1 + exp 1 + weight 1 + A 1 + w*d 3 + B 3 + C 12
 FLOPS_PER_PAIR_GEOM = 30
-PAIR_KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_01254_amd", "csrc", "sweep.hip")
+# the sweep kernel and the engine that lays out its pass table (the pass order changes the kernel's traffic)
+PAIR_KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_01254_amd", "csrc", f) for f in ("sweep.hip", "engine.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_odometry_traffic.json")
 WORKLOADS = {
     "odometry": "odometry: 8 depth-camera frames x 30,000 points, 23-dim soft-label+RGB features, all 28 frame "
@@ -48,8 +49,11 @@ WORKLOADS = {
 
 
 def kernel_source_hash():
-    with open(PAIR_KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in PAIR_KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():

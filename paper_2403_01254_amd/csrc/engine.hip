@@ -740,8 +740,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       I.fin_pt = std::min(16, std::max(1, I.n_src / 4096));
       I.n_fin = (I.n_src + kFinThreads * I.fin_pt - 1) / (kFinThreads * I.fin_pt);
       I.prob = (int32_t)pi;
-      I.pass0 = (int32_t)gcount[gi];  // within its group; the group's base is added below
-      gcount[gi] += I.n_pass;
+      gcount[gi] += I.n_pass;  // pass0 is assigned below, once every edge's target is known
       egroup[e_glob] = (int8_t)gi;
       ent[e_glob] = entries;
       foff[e_glob] = I.fin_off;
@@ -794,7 +793,22 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     groups.push_back(SetLayout::Group{group_order[gi], (int)n_pass_table, (int)gcount[gi], gi == 4});
     n_pass_table += gcount[gi];
   }
-  for (int e = 0; e < E_total; ++e) info[e].pass0 += (int32_t)gbase[egroup[e]];
+  // Inside a group, the passes of edges that share a target frame are placed next to each other: the
+  // passes in flight at one time then read candidates from the same frame, which stays in the L2.  The
+  // results do not depend on this order (every pass writes its own entries).
+  {
+    std::vector<int> order(E_total);
+    for (int e = 0; e < E_total; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return egroup[x] != egroup[y] ? egroup[x] < egroup[y] : info[x].n < info[y].n;
+    });
+    int64_t run[6] = {0, 0, 0, 0, 0, 0};
+    for (int e : order) {
+      const int gi = egroup[e];
+      info[e].pass0 = (int32_t)(gbase[gi] + run[gi]);
+      run[gi] += info[e].n_pass;
+    }
+  }
   RK_HIP(lay.d_kcs.reserve(items.size()));
   RK_HIP(lay.d_passes.reserve((size_t)n_pass_table));
   RK_HIP(lay.d_sys.reserve(items.size()));
