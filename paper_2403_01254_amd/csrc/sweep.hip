@@ -329,7 +329,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       floatx4 cv = {1.f, 1.f, 1.f, 1.f};
       if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
       if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
-      for (int sub = 0; sub < n_sub; ++sub) {
+      // unrolled over the four sub-tiles: the products and the LDS offsets of each sub-tile get registers
+      // and immediates of their own (no register copies or address updates between sub-tiles)
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub) {
+        if (sub >= n_sub) break;  // uniform
         // this lane's four candidates of the sub-tile, read before any use
         const float4* zp = tpos + 16 * sub + CPL * g;
         float4 z4[CPL];
