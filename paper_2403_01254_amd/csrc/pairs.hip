@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
   const float rc2 = kc.rc2, alpha = kc.alpha;
   const bool clamp = a.kc.clamp != 0;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
-  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
+  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Wr2 = 0.f;  // Wr2 = sum w |d|^2 (in place of C_zz)
   uint32_t cnt = 0;
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
 
@@ -226,10 +226,10 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
         A += w;
         cnt += (c != 0.f) ? 1u : 0u;
         if constexpr (MODE == MODE_NORMAL) {
-          const float wx = w * dx, wy = w * dy, wz = w * dz;
-          Bx += wx; By += wy; Bz += wz;
+          const float wx = w * dx, wy = w * dy;
+          Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
           Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-          Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+          Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
         }
       }
     }
@@ -243,10 +243,10 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
       A += w;
       cnt += 1u;
       if constexpr (MODE == MODE_NORMAL) {
-        const float wx = w * dx, wy = w * dy, wz = w * dz;
-        Bx += wx; By += wy; Bz += wz;
+        const float wx = w * dx, wy = w * dy;
+        Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
         Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-        Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+        Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, best.s2[t], Wr2);
       }
     }
   }
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
       Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
-      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
+      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Wr2 += __shfl_xor(Wr2, o, 64);
     }
   }
   if (g == 0 && in_range) a.cnt[entry] = valid ? cnt : 0u;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     if constexpr (MODE == MODE_NORMAL) {
       a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
       a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
-      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Czz;
+      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Wr2;
     }
   }
 }
@@ -342,7 +342,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
       const T A = a.mom[entry];
       T B[3], C[6], x[3], q[3];
       for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
-      for (int k = 0; k < 6; ++k) C[k] = a.mom[(4 + k) * N + entry];
+      for (int k = 0; k < 5; ++k) C[k] = a.mom[(4 + k) * N + entry];
+      const T Wr2 = a.mom[9 * N + entry];  // the sweeps store sum w |d|^2 in place of C_zz
+      C[5] = Wr2 - C[0] - C[3];
       const float4 p = src_pts[a.vals[entry]];
       const float3 qq = rule_q32(X, p.x, p.y, p.z);
       x[0] = p.x; x[1] = p.y; x[2] = p.z;
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st[kStXS + 3 * r + c].add(x[r] * S[c]);
-      st[kStWr2].add(C[0] + C[3] + C[5]);
+      st[kStWr2].add(Wr2);
     }
   }
   // block sum in a fixed order: wavefront shuffles, then the four waves

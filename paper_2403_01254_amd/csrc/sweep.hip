@@ -18,8 +18,10 @@
 //      16x16x4 FP32 MFMA per 4 feature dimensions; its accumulator layout
 //      (row 4(l/16)+r, column l%16) is exactly candidate 4g+r for source s.
 //   4. Inside the FP32 membership rule the pair adds w = c exp(-|d|^2/2l^2)
-//      to the moments A, B = sum w d, C = sum w d d^T (d = q - z); the four
-//      streams of each source are summed with cross-lane shuffles at the end.
+//      to the moments A, B = sum w d, C = sum w d d^T (d = q - z) and
+//      W = sum w |d|^2; C_zz is not summed (the finaliser takes it from the
+//      trace, C_zz = W - C_xx - C_yy), which saves w d_z.  The four streams of
+//      each source are summed with cross-lane shuffles at the end.
 #include <cfloat>
 
 #include "rkhsba_device.h"
@@ -197,9 +199,10 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     return;
   }
   const float3 ref = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
-  // A lane without a valid source point gets q at -1e30 (padding candidates sit at +1e30): its squared
-  // distance to every candidate overflows to +inf and fails the membership test.
-  if (!valid) q = make_float3(-1.0e30f, -1.0e30f, -1.0e30f);
+  // A lane without a valid source point gets q at -1e18 (padding candidates sit at +1e18): its squared
+  // distance to every candidate is at least ~1e36, still finite (so w * |d|^2 = 0 * s2 stays 0), and fails
+  // the membership test.
+  if (!valid) q = make_float3(-1.0e18f, -1.0e18f, -1.0e18f);
   floatx4 macc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
   if constexpr (MM) {
 #pragma unroll
@@ -216,12 +219,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
 
   const float rc2 = kc.rc2, alpha = kc.alpha;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
-  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Czz = 0.f;
+  float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Wr2 = 0.f;
   uint32_t cnt = 0;
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
   const float* __restrict__ tf = static_cast<const float*>(a.feat) + Fn.pt_off * (FEAT == FEAT_DENSE ? DP : 0);
   const uint8_t* __restrict__ tl = static_cast<const uint8_t*>(a.feat) + Fn.pt_off * (int64_t)(LP ? ROWB : 0);
-  const float far_ = 1.0e30f;
+  const float far_ = 1.0e18f;
 
   for (int rb = 0; rb < n_rows; rb += kLanes) {
     // ---- one row per lane: its contiguous candidate range
@@ -374,10 +377,10 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
             A += w;
           }
           if constexpr (MODE == MODE_NORMAL && !MM) {
-            const float wx = w * dx, wy = w * dy, wz = w * dz;
-            Bx += wx; By += wy; Bz += wz;
+            const float wx = w * dx, wy = w * dy;
+            Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
             Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Czz = fmaf(wz, dz, Czz);
+            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
           }
         }
       }
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       Cxz = A * vx * vz - vx * mz - mx * vz + m[6];
       Cyy = A * vy * vy - 2.f * vy * my + m[7];
       Cyz = A * vy * vz - vy * mz - my * vz + m[8];
-      Czz = A * vz * vz - 2.f * vz * mz + m[9];
+      Wr2 = Cxx + Cyy + (A * vz * vz - 2.f * vz * mz + m[9]);
     }
   }
   // sum the four candidate streams of each source point
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
       Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
-      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Czz += __shfl_xor(Czz, o, 64);
+      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Wr2 += __shfl_xor(Wr2, o, 64);
     }
   }
   // the pass's pair count goes to its first entry, zeros to the others
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     if constexpr (MODE == MODE_NORMAL) {
       a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
       a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
-      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Czz;
+      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Wr2;
     }
   }
 }
