@@ -90,7 +90,7 @@ def percentile_ms(lat, q):
     return float(np.percentile(np.asarray(lat) * 1e3, q)) if len(lat) else None
 
 
-def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
+def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_000_000):
     """Seeded Poisson stream of whole solves: capacity of the one-at-a-time
     FP32 form, then, at 0.5x and 0.9x of it, latency percentiles and
     throughput of the continuous-batching request loop and of the
@@ -138,7 +138,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
     pose_diff = {}
 
     def run_batched(kind, arrivals):
-        srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64, lanes=lanes)
+        srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64, lanes=lanes, lane_work_entries=work_entries)
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05
 
@@ -172,6 +172,12 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
                 "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out])), "not_pd_requests": not_pd_batched,
                 "max_pose_entry_diff_vs_one_at_a_time_f32": diff}
 
+    # capacity of the batched forms: every request submitted at once
+    saturated = {}
+    for k in ("dense", "bf16"):
+        saturated[k] = run_batched(k, np.zeros(len(reqs)))
+        log(f"[serving] all at once, batched {k}: {saturated[k]['solves_per_s']:.2f} solves/s "
+            f"(up to {saturated[k]['max_active']} active, {saturated[k]['batch_iterations']} batch iterations)")
     for frac in (0.5, 0.9):
         qps = frac * capacity
         arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
@@ -200,8 +206,11 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2):
                      "one_at_a_time_f32": single})
     for c in ctxs.values():
         c.close()
-    return {"requests": len(reqs), "lanes": lanes, "capacity_one_at_a_time_solves_per_s": capacity,
+    return {"requests": len(reqs), "lanes": lanes, "lane_work_entries": work_entries,
+            "capacity_one_at_a_time_solves_per_s": capacity,
             "not_pd_requests_one_at_a_time": len(not_pd),
+            "capacity_batched_f32_solves_per_s": saturated["dense"]["solves_per_s"],
+            "capacity_batched_bf16_solves_per_s": saturated["bf16"]["solves_per_s"],
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
             "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
@@ -253,6 +262,8 @@ def main():
                     help="requests in the serving measurement (0: skip); the serving workload's full stream is 512")
     ap.add_argument("--serving-lanes", type=int, default=2, choices=[1, 2],
                     help="concurrent batches of the request server (large requests in the second)")
+    ap.add_argument("--serving-work-entries", type=int, default=8_000_000,
+                    help="request server: most (edge, source point) entries active in one lane (0: no limit)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -395,7 +406,8 @@ def main():
         reqs = [f.result() for f in gen_futures]
         gen_pool.shutdown()
         log(f"[bench] serving: {len(reqs)} requests generated")
-        result["serving"] = serving_benchmark(reqs, rkhsba, torch, log, lanes=args.serving_lanes)
+        result["serving"] = serving_benchmark(reqs, rkhsba, torch, log, lanes=args.serving_lanes,
+                                              work_entries=args.serving_work_entries)
     if rank == 0:
         print(json.dumps(result), flush=True)
     ctx.close()

@@ -305,6 +305,10 @@ typedef struct {
   int lanes;                /* 1 or 2 concurrent batches, each with its own engine and stream (default 1) */
   int64_t lane_split_entries; /* with 2 lanes: requests with more (edge, source point) entries (sum over the edges
                                of the source frame's points) go to lane 1 (default 2,000,000) */
+  int64_t lane_work_entries;  /* a lane admits the request at the head of its queue only while the entries of its
+                               active requests plus the request's stay within this (0: no limit, the default; a
+                               request is always admitted into an idle lane).  It bounds the work of one batch
+                               iteration, which every active request of the lane waits for. */
 } rkhsba_server_options;
 
 typedef struct {

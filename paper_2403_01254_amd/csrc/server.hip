@@ -5,7 +5,9 @@
 // (edge, source point) entries go to lane 1 and the others to lane 0, so small
 // requests do not wait for the iterations of large ones, and the two lanes'
 // launches overlap on the device.  In a lane, requests wait in a FIFO queue
-// and are admitted while the number of active requests and the sum of the
+// and are admitted while the number of active requests, the sum of their
+// (edge, source point) entries (a bound on one batch iteration's work, and so
+// on the time every active request waits per iteration) and the sum of the
 // estimated device footprints of all admitted requests stay within the limits
 // (a request is always admitted when its lane is idle).  Admission builds the
 // request's voxel structures into the lane engine's resident pools; then every
@@ -46,6 +48,7 @@ struct Req {
   std::vector<double> poses;
   std::vector<int32_t> edges;
   int64_t est_bytes = 0;
+  int64_t entries = 0;    // (edge, source point) entries: the request's share of every launch
   bool admitted = false;  // est_bytes counted in the server's committed total
   // progress (worker thread)
   int prob = -1;
@@ -143,10 +146,14 @@ struct rkhsba_server {
         std::unique_lock<std::mutex> lk(mu);
         if (L.active.empty()) cv_work.wait(lk, [&] { return stop || !L.queue.empty(); });
         if (stop) break;
+        int64_t work = 0;
+        for (const auto& a : L.active) work += a->entries;
         while (!L.queue.empty() && (int)(L.active.size() + admit.size()) < opt.max_active) {
           const std::shared_ptr<Req>& q = L.queue.front();
           const bool idle = L.active.empty() && admit.empty();
           if (!idle && committed + q->est_bytes > opt.hbm_budget_bytes) break;
+          if (!idle && opt.lane_work_entries > 0 && work + q->entries > opt.lane_work_entries) break;
+          work += q->entries;
           committed += q->est_bytes;
           q->admitted = true;
           admit.push_back(q);
@@ -251,6 +258,7 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->stream = nullptr;
   o->lanes = 1;
   o->lane_split_entries = 2000000;
+  o->lane_work_entries = 0;
 }
 
 int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
@@ -261,7 +269,7 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
        opt->pass_points != 32 && opt->pass_points != 64) ||
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)) || opt->lanes < 1 ||
-      opt->lanes > 2 || opt->lane_split_entries < 0)
+      opt->lanes > 2 || opt->lane_split_entries < 0 || opt->lane_work_entries < 0)
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -357,8 +365,9 @@ int rkhsba_server_submit(rkhsba_server* s, const rkhsba_request* r, int64_t* tic
     q->poses.assign(r->poses, r->poses + 12 * (size_t)r->K);
     q->edges.assign(r->edges, r->edges + 2 * (size_t)r->E);
     q->est_bytes = Engine::estimate_bytes(r->K, r->n_points, r->E, s->row_bytes);
-    int64_t entries = 0;  // (edge, source point) entries: the request's share of every launch
+    int64_t entries = 0;
     for (int e = 0; e < r->E; ++e) entries += r->n_points[r->edges[2 * e]];
+    q->entries = entries;
     const size_t lane = (s->lanes.size() > 1 && entries > s->opt.lane_split_entries) ? 1 : 0;
     q->t_submit = Clock::now();
     {

@@ -61,6 +61,7 @@ class ServerOptions(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("lanes", ctypes.c_int),
         ("lane_split_entries", ctypes.c_int64),
+        ("lane_work_entries", ctypes.c_int64),
     ]
 
 
@@ -402,7 +403,8 @@ class Server:
     solve and returns a ticket at once; wait() returns its result."""
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
-                 use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000):
+                 use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000,
+                 lane_work_entries=0):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
@@ -412,6 +414,7 @@ class Server:
         o.hessian_fp32 = int(bool(hessian_fp32))
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         o.lanes, o.lane_split_entries = int(lanes), int(lane_split_entries)
+        o.lane_work_entries = int(lane_work_entries)
         self.opts = o
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))

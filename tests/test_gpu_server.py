@@ -93,6 +93,27 @@ def test_admission_by_footprint(rk, requests):
         assert b[4] >= 0.0
 
 
+def test_admission_by_work(rk, requests):
+    """A lane admits the request at the head of its queue only while the active requests' entries plus its own
+    stay within the work limit: with a limit of one entry, requests run one at a time (an idle lane always
+    admits), with the same results; with a larger limit, never more requests than the limit can hold."""
+    with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
+        ref = [srv.wait(submit(srv, p), timeout=120) for p in requests]
+    entries = sorted(sum(len(p.points[m]) for m, _ in p.edges) for p in requests)
+    limit2 = entries[-1] + entries[-2]
+    most2 = max(k for k in range(1, len(entries) + 1) if k == 1 or sum(entries[:k]) <= limit2)
+    for limit, most in ((1, 1), (limit2, most2)):
+        with rk.Server(feat_kind="dense", D=20, max_active=8, lane_work_entries=limit) as srv:
+            tickets = [submit(srv, p) for p in requests]
+            got = [srv.wait(t, timeout=120) for t in tickets]
+            st = srv.stats()
+        say(f"[server] work limit {limit}: max_active {st['max_active']}, {st['batch_iterations']} batch iterations")
+        assert 1 <= st["max_active"] <= most and st["completed"] == len(requests)
+        for a, b in zip(ref, got):
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[2], b[2])
+
+
 def test_invalid_requests(rk, requests):
     p = requests[0]
     with rk.Server(feat_kind="dense", D=20) as srv:
@@ -111,3 +132,5 @@ def test_invalid_requests(rk, requests):
     for bad in (0, 3):
         with pytest.raises(rk.RkhsbaError):
             rk.Server(feat_kind="dense", D=20, lanes=bad)
+    with pytest.raises(rk.RkhsbaError):
+        rk.Server(feat_kind="dense", D=20, lane_work_entries=-1)
