@@ -403,7 +403,11 @@ def main():
     # serving requests are generated only now, so that no worker process competes with the timed regions above
     gen_pool, gen_futures = start_request_generation(args.serving_requests, workers=8)
     if gen_futures:
-        reqs = [f.result() for f in gen_futures]
+        reqs = []
+        for i, f in enumerate(gen_futures):
+            reqs.append(f.result())
+            if (i + 1) % 32 == 0 and i + 1 < len(gen_futures):
+                log(f"[bench] serving: {i + 1} of {len(gen_futures)} requests generated")
         gen_pool.shutdown()
         log(f"[bench] serving: {len(reqs)} requests generated")
         result["serving"] = serving_benchmark(reqs, rkhsba, torch, log, lanes=args.serving_lanes,
