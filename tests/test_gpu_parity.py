@@ -171,6 +171,32 @@ def test_degenerate_inputs(rk):
     np.testing.assert_array_equal(out[2], poses[2])
 
 
+def test_frame_of_coincident_points(rk):
+    """A frame whose points all lie at one location (a depth camera placed on a
+    surface returns such a view): a zero-extent voxel grid, passes of identical
+    points, and exactly zero rotational terms in the oracle.  Pair counts are
+    exact; F, b and H agree with the oracle within the tolerance."""
+    rng = np.random.default_rng(11)
+    x = (rng.normal(size=(400, 3)) * 0.1).astype(np.float32)
+    spot = np.repeat(np.array([[0.02, -0.01, 0.03]], np.float32), 300, axis=0)
+    pts = [x, spot]
+    feats = [rng.dirichlet(np.full(6, 0.5), size=len(a)).astype(np.float32) for a in pts]
+    poses = np.stack([ident(), ident()])
+    poses[1, 9:] = [0.01, 0.0, -0.02]
+    op = oracle.Problem(pts, feats, "dense", 0.08)
+    for subdiv in (1, 8):
+        ctx = rk.Context(ell=0.08, cell_subdiv=subdiv, pass_points=16)
+        ctx.build_neighbors(pts, feats, "dense")
+        for edges in ([[0, 1]], [[1, 0]], [[0, 1], [1, 0]]):
+            H, b, F, n = ctx.accumulate_normal_eqs(poses, edges)
+            oF, ob, oH, _, on = oracle.normal_eqs(op, poses, edges, oracle.MEMBER_FP32_RULE)
+            say(f"[coincident] subdiv {subdiv} edges {edges}: pairs {n} / {on}, F {F:.9g} / {oF:.9g}")
+            assert n == on > 0 and abs(F - oF) <= REL_TOL * oF
+            assert_blocks_close(b, ob, 6, what="coincident b")
+            assert_blocks_close(H, oH, 6, what="coincident H")
+        ctx.close()
+
+
 def test_common_rigid_motion_invariance_gpu(rk):
     p = scenes.odometry(6, n_frames=3, n_points=3000)
     ctx = make_ctx(rk, p)
