@@ -212,13 +212,17 @@ __device__ void solve_lds(const ProbSys& S, const SolveArgs& a, double mu, doubl
 // ---- larger systems: blocked right-looking Cholesky in global memory
 //
 // Panels of NB columns: the diagonal block is eliminated in LDS and scaled to
-// L11; the rows below solve L21 = A21 L11^-T (one row per thread, in
-// registers) and are kept in LDS for the trailing update A22 -= L21 L21^T
-// (4 x 4 register tiles on a 32 x 32 thread grid; from global memory when the
-// panel does not fit).  Then L y = -b and L^T delta = y, panel by panel.
+// L11; the rows below solve L21 = A21 L11^-T and are kept in LDS for the
+// trailing update A22 -= L21 L21^T.  While the panel has at most kPanelCols
+// rows (every system up to ~500 unknowns), each row is solved in registers
+// (one row per thread, the 32 steps unrolled) and the panel is stored column
+// by column, so that the trailing update's 4 x 4 register tiles, whose rows
+// and columns are 32 apart, read it without bank conflicts and write A22 with
+// consecutive threads on consecutive columns.  Larger panels are solved and
+// read in place in global memory, with contiguous tiles.  Then L y = -b and
+// L^T delta = y, panel by panel.
 constexpr int NB = 32;
-constexpr int PS = NB + 1;  // LDS panel row stride (odd: rows of different threads fall on different banks)
-constexpr int kPanelRows = (kLdsDoubles - NB * (NB + 1) - 2 * NB) / PS;
+constexpr int kPanelCols = (kLdsDoubles - NB * (NB + 1) - 2 * NB) / NB;  // rows of a column-major panel
 
 __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, double* buf, int32_t* status) {
   const int n = S.n, t = threadIdx.x, tx = t & 31, ty = t >> 5;
@@ -226,7 +230,7 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
   double* Dg = buf;                       // NB x (NB + 1) diagonal block
   double* rd = buf + NB * (NB + 1);       // NB reciprocal pivots / diagonal
   double* yb = rd + NB;                   // NB solution entries of a panel
-  double* P = yb + NB;                    // panel rows, stride PS
+  double* P = yb + NB;                    // the panel L21, column-major (P[j * m + r])
   for (int i = t; i < n; i += kSolveThreads) H[(int64_t)i * n + i] += mu;
   __syncthreads();
   for (int kb = 0; kb < n; kb += NB) {
@@ -253,13 +257,72 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
     __syncthreads();
     if (t < nb) rd[t] = 1.0 / Dg[t * (NB + 1) + t];
     __syncthreads();
-    // panel rows: x L11^T = a (forward substitution per row, in LDS when the panel fits)
-    const bool in_lds = m <= kPanelRows;
+    if (m <= kPanelCols) {
+      // panel rows in registers, stored column-major: P[j * m + r] = L21[r][j]
+      for (int r = t; r < m; r += kSolveThreads) {
+        double* row = H + (int64_t)(m0 + r) * n + kb;
+        double x[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) x[j] = j < nb ? row[j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j < nb) {
+            const double* Lj = Dg + j * (NB + 1);
+            double s0 = x[j], s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k + 1 < j; k += 2) {
+              s0 -= Lj[k] * x[k];
+              s1 -= Lj[k + 1] * x[k + 1];
+            }
+            if (j & 1) s0 -= Lj[j - 1] * x[j - 1];
+            x[j] = (s0 + s1) * rd[j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) {
+            row[j] = x[j];
+            P[j * m + r] = x[j];
+          }
+      }
+      __syncthreads();
+      // A22 -= L21 L21^T over 128 x 128 blocks on or below the diagonal; thread (tx, ty) takes rows
+      // a0 + ty + 32p and columns b0 + tx + 32q
+      for (int a0 = 0; a0 < m; a0 += 128)
+        for (int b0 = 0; b0 <= a0; b0 += 128) {
+          double acc[4][4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+          for (int j = 0; j < nb; ++j) {
+            const double* Pj = P + j * m;
+            double li[4], lk[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const int i = a0 + ty + 32 * p, k = b0 + tx + 32 * p;
+              li[p] = i < m ? Pj[i] : 0.0;
+              lk[p] = k < m ? Pj[k] : 0.0;
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[p][q] = fma(li[p], lk[q], acc[p][q]);
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int i = a0 + ty + 32 * p, k = b0 + tx + 32 * q;
+              if (i < m && k <= i) H[(int64_t)(m0 + i) * n + m0 + k] -= acc[p][q];
+            }
+        }
+      __syncthreads();
+      continue;
+    }
+    // larger panels: rows solved and read in place in global memory
     for (int r = t; r < m; r += kSolveThreads) {
-      double* row = H + (int64_t)(m0 + r) * n + kb;
-      double* x = in_lds ? P + r * PS : row;
-      if (in_lds)
-        for (int j = 0; j < nb; ++j) x[j] = row[j];
+      double* x = H + (int64_t)(m0 + r) * n + kb;
       for (int j = 0; j < nb; ++j) {
         const double* Lj = Dg + j * (NB + 1);
         double s0 = x[j], s1 = 0.0;
@@ -271,8 +334,6 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
         if (k < j) s0 -= Lj[k] * x[k];
         x[j] = (s0 + s1) * rd[j];
       }
-      if (in_lds)
-        for (int j = 0; j < nb; ++j) row[j] = x[j];
     }
     __syncthreads();
     // trailing update of the lower triangle of A22
@@ -289,8 +350,8 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
             const int ri = 4 * ti + p, rk = 4 * tk + p;
-            li[p] = ri < m ? (in_lds ? P[ri * PS + j] : H[(int64_t)(m0 + ri) * n + kb + j]) : 0.0;
-            lk[p] = rk < m ? (in_lds ? P[rk * PS + j] : H[(int64_t)(m0 + rk) * n + kb + j]) : 0.0;
+            li[p] = ri < m ? H[(int64_t)(m0 + ri) * n + kb + j] : 0.0;
+            lk[p] = rk < m ? H[(int64_t)(m0 + rk) * n + kb + j] : 0.0;
           }
 #pragma unroll
           for (int p = 0; p < 4; ++p)

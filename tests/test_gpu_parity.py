@@ -242,12 +242,36 @@ def test_invalid_arguments(rk):
     assert e.value.code == rk.ESTATE
 
 
-def test_gauss_newton_step_matches_host_solve_large_system(rk):
+def chain_of_copies(n_frames, n_points=400, seed=9):
+    """n_frames noisy copies of one small cloud of class-labelled points, each frame paired with the next two:
+    a quick way to a large reduced system."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(seed)
+    base = rng.uniform(-1.0, 1.0, size=(n_points, 3))
+    labels = rng.integers(0, 4, size=n_points).astype(np.uint16)
+    pts, poses = [], []
+    for _ in range(n_frames):
+        pts.append((base + rng.normal(scale=0.01, size=base.shape)).astype(np.float32))
+        T = np.concatenate([Rotation.from_rotvec(rng.normal(scale=0.01, size=3)).as_matrix().reshape(9),
+                            rng.normal(scale=0.02, size=3)])
+        poses.append(T)
+    edges = np.array([(k, k + d) for k in range(n_frames) for d in (1, 2) if k + d < n_frames], np.int32)
+    return scenes.Problem(name=f"chain{n_frames}", points=pts, feat_kind="class", feats=[labels] * n_frames, D=4,
+                          gt_poses=np.stack(poses), init_poses=np.stack(poses), edges=edges, ell=0.1)
+
+
+@pytest.mark.parametrize("n_frames", [40, 90])
+def test_gauss_newton_step_matches_host_solve_large_system(rk, n_frames):
     """One Gauss-Newton step on 40 frames (a 234-unknown system, several
-    Cholesky panels with a ragged last one) equals the step computed on the
-    host from the library's own H and b (numpy solve, scipy SE(3) exp)."""
+    Cholesky panels with a ragged last one) or 90 frames (534 unknowns: the
+    first panels too tall for the column-major panel in LDS) equals the step
+    computed on the host from the library's own H and b (numpy solve, scipy
+    SE(3) exp)."""
     import scipy.linalg
-    p = scenes.lidar(4, n_frames=40, n_points=2000, n_neighbours=4, spacing=3.125)
+    if n_frames == 40:
+        p = scenes.lidar(4, n_frames=40, n_points=2000, n_neighbours=4, spacing=3.125)
+    else:
+        p = chain_of_copies(n_frames)
     ctx = make_ctx(rk, p)
     H, b, F, n = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
     Hr, br = H[6:, 6:], b[6:]
