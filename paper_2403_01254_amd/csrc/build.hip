@@ -2,6 +2,8 @@
 // and the per-row cell tables used by the candidate sweeps.  Runs once per
 // set of frames; each frame is hashed in its own local coordinates, so the
 // structure does not depend on the poses.
+#include <algorithm>
+#include <cfloat>
 #include <climits>
 
 #include "rkhsba_device.h"
@@ -148,6 +150,25 @@ __device__ inline void decode(uint32_t key, const FrameInfo& F, int& kx, int& ky
   kz = (int)(r / ny);
 }
 
+// Smallest value of each feature dimension over n rows of Dp FP32 values: the
+// block size and the grid stride are multiples of Dp, so every thread sees
+// one dimension (threadIdx.x % Dp) and reads the rows' values coalesced.
+// out[d] (bit patterns of non-negative floats, ordered as integers) must hold
+// +inf or a larger earlier minimum; negative values count as 0.
+__global__ __launch_bounds__(kThreads) void k_feature_min(const float* __restrict__ feat, int64_t total, int Dp,
+                                                          uint32_t* __restrict__ out) {
+  __shared__ uint32_t sm[64];
+  const int t = threadIdx.x;
+  if (t < Dp) sm[t] = 0x7f800000u;
+  __syncthreads();
+  float m = FLT_MAX;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + t; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    m = fminf(m, feat[e]);
+  atomicMin(&sm[t % Dp], __float_as_uint(fmaxf(m, 0.0f)));
+  __syncthreads();
+  if (t < Dp) atomicMin(&out[t], sm[t]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_row_init(int4* __restrict__ rows, int64_t n_rows) {
   const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (r < n_rows) rows[r] = make_int4(INT_MAX, INT_MIN, 0, 0);
@@ -284,6 +305,15 @@ hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_fe
   if (n_total > 0)
     k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, D, Dp, d_frames, d_in_off, K,
                                                    n_total, d_sorted_vals, d_pts, d_feat, d_perm, d_neg_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_feature_min(const float* d_feat, int64_t n, int Dp, uint32_t* d_min, hipStream_t st) {
+  if (Dp <= 0 || Dp > 64 || n <= 0) return Dp > 64 ? hipErrorInvalidValue : hipSuccess;
+  const int threads = Dp * (kThreads / Dp);
+  const int64_t total = n * Dp;
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (total + threads - 1) / threads);
+  k_feature_min<<<blocks, threads, 0, st>>>(d_feat, total, Dp, d_min);
   return hipGetLastError();
 }
 

@@ -134,6 +134,7 @@ struct Problem {
   ProbParams par;
   KConst kc{};
   bool negative_features = false;
+  bool c_positive = false;  // every inner product of the features is > 0 (KConst::c_positive)
   int K = 0;
   int64_t N = 0;
   int64_t slot0 = -1;   // frame slots (frame table and poses)
@@ -179,6 +180,7 @@ struct SetLayout {
   };
   std::vector<Group> groups;        // contiguous runs of the pass table, one sweep launch each
   bool clamp = false;
+  bool c_positive = false;          // every problem's inner products are > 0 (pair counts need no c != 0 test)
   DBuf<EdgeInfo> d_edges;
   DBuf<int64_t> d_ent_off;
   DBuf<int32_t> d_fin_off;

@@ -231,6 +231,7 @@ void Engine::compute_constants(Problem* p) {
   k.alpha = (float)(1.4426950408889634 / (2.0 * o.ell * o.ell));
   k.reach_cells = o.cell_subdiv + 1;
   k.clamp = (o.clamp_negative_c && p->negative_features) ? 1 : 0;
+  k.c_positive = p->c_positive ? 1 : 0;
   k.Dp = Dp;
   k.topk = o.top_k;
   k.inv2l2 = 1.0 / (2.0 * o.ell * o.ell);
@@ -330,7 +331,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
 
     // cell coordinates and per-frame bounds
-    std::vector<int32_t> mm(6 * K + 3);
+    const int n_dmin = kind == RKHSBA_FEAT_DENSE_F32 ? Dp : 0;  // per-dimension minima of FP32 features
+    std::vector<int32_t> mm(6 * K + 3 + n_dmin);
     for (int f = 0; f < K; ++f)
       for (int a = 0; a < 3; ++a) {
         mm[6 * f + a] = INT_MAX;
@@ -339,6 +341,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     mm[6 * K] = 0;      // bad coordinate flag
     mm[6 * K + 1] = 0;  // negative feature flag
     mm[6 * K + 2] = 0;  // occupied cells
+    for (int d = 0; d < n_dmin; ++d) mm[6 * K + 3 + d] = 0x7f800000;  // feature minima (+inf until the build)
     RK_HIP(cell_.reserve((size_t)N * 3));
     RK_HIP(minmax_.reserve(mm.size()));
     RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, st));
@@ -426,6 +429,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(launch_gather(d_xyz_ptrs_.p, d_feat_ptrs_.p, kind, D, std::max(Dp, 1),
                          d_bframes_.p, d_in_off_.p, K, N, sv, d_pts, d_feat, d_perm, minmax_.p + 6 * K + 1, st));
     RK_HIP(hipMemcpyAsync(d_keys, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, st));
+    RK_HIP(launch_feature_min(static_cast<const float*>(d_feat), N, n_dmin,
+                              reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 3), st));
 
     // cell-row tables
     RK_HIP(row_sizes_.reserve(rows_total));
@@ -437,8 +442,18 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     int32_t neg = 0;
     RK_HIP(hipMemcpyAsync(&xt_total, d_total_.p, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     RK_HIP(hipMemcpyAsync(&neg, minmax_.p + 6 * K + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> dmin(std::max(n_dmin, 1));
+    if (n_dmin > 0)
+      RK_HIP(hipMemcpyAsync(dmin.data(), minmax_.p + 6 * K + 3, sizeof(uint32_t) * n_dmin, hipMemcpyDeviceToHost, st));
     RK_HIP(hipStreamSynchronize(st));
     p->negative_features = neg != 0;
+    p->c_positive = false;
+    if (!p->negative_features)
+      for (int d = 0; d < n_dmin; ++d) {
+        float v;
+        std::memcpy(&v, &dmin[d], sizeof(v));
+        p->c_positive = p->c_positive || v >= 1e-18f;
+      }
     compute_constants(p);
     RK_REQUIRE(xt_total < (1ull << 31), RKHSBA_ENOMEM, "cell table too large");
     p->n_xt = std::max<int64_t>((int64_t)xt_total, 1);
@@ -693,7 +708,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   std::vector<int32_t> bstart_all, blist, vstart_all, vlist;
   int64_t entries = 0, passes = 0, fins = 0, h_total = 0, v_total = 0;
   int bin_bits = 3, n_max = 0;
-  bool clamp = false;
+  bool clamp = false, positive = true;
   int e_glob = 0;
   for (size_t pi = 0; pi < items.size(); ++pi) {
     const SetItem& it = items[pi];
@@ -701,6 +716,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     kcs[pi] = p->kc;
     kcs[pi].Dp = Dp;
     clamp = clamp || p->kc.clamp;
+    positive = positive && p->kc.c_positive;
     bin_bits = std::max(bin_bits, p->bin_bits);
     ProbSys& S = sys[pi];
     S.K = p->K;
@@ -868,6 +884,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   lay.n_edge_tiles = (int)tiles.size();
   lay.bin_bits = bin_bits;
   lay.clamp = clamp;
+  lay.c_positive = positive && !items.empty();
   lay.h_total = h_total;
   lay.v_total = v_total;
 }
@@ -905,6 +922,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
 
   pa.kc.Dp = Dp;
   pa.kc.clamp = lay.clamp ? 1 : 0;
+  pa.kc.c_positive = lay.c_positive ? 1 : 0;
   const int feat_path = feat_kind;
   hipEvent_t t1 = prof_begin();
   for (const SetLayout::Group& gr : lay.groups) {

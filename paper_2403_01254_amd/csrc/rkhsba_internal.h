@@ -81,6 +81,8 @@ struct KConst {
   int Dp;            // padded dense feature width (0 for class ids)
   int topk;          // > 0: only the topk pairs with the largest kernel values per source point (per edge)
   double inv2l2;     // 1 / (2 ell^2), for the FP64 ranking key of the topk selection
+  int c_positive;    // FP32 dense features, none negative, and one dimension >= 1e-18 in every row: every
+                     // inner product is > 0 (its term in that dimension is >= 1e-36, above FLT_MIN)
 };
 constexpr int kMaxTopK = 8;
 
@@ -122,6 +124,9 @@ hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_fe
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
                          const uint32_t* d_sorted_vals, float4* d_pts, void* d_feat, int32_t* d_perm,
                          int32_t* d_neg_flag, hipStream_t st);
+// Per feature dimension d < Dp (<= 64), the smallest stored FP32 value over n rows, as its bit pattern (values
+// >= 0; negative values count as 0), min-combined into d_min[d], which the caller sets to +inf first.
+hipError_t launch_feature_min(const float* d_feat, int64_t n, int Dp, uint32_t* d_min, hipStream_t st);
 hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
                        int64_t n_total, int4* d_rows, int64_t n_rows, uint32_t* d_sizes, uint32_t* d_scan_tmp,
                        uint64_t* d_total, hipStream_t st);

@@ -119,7 +119,9 @@ __device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s
 // (A operand = the weights the lanes just computed, B = Phi of the same
 // candidates), and A, B, C follow exactly from M and v = q - ref:
 //   A = M_1, B = A v - M_u, C = A v v^T - v M_u^T - M_u v^T + M_uu.
-template <int MODE, int FEAT, int DP, bool CLAMP, bool MM, int P>
+// CM: the inner products as computed (0), negative ones clamped to 0 (1), or
+// known to be positive (2: the pair count then needs no c != 0 test).
+template <int MODE, int FEAT, int DP, int CM, bool MM, int P>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // P source points per pass (16, or 8 for class ids); lane (s, g) takes CPL candidates of every
   // 16-candidate sub-tile
@@ -364,12 +366,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           if constexpr (FEAT == FEAT_CLASS) {
             in = in && (__float_as_uint(z.w) == lbl);
           } else {
-            c = CLAMP ? fmaxf(cur[rr], 0.f) : cur[rr];
+            c = CM == 1 ? fmaxf(cur[rr], 0.f) : cur[rr];
           }
           const float k = __builtin_amdgcn_exp2f(-alpha * s2);
           const float w = in ? c * k : 0.f;
           // pairs counted per pass from the wavefront's lane masks (scalar unit)
-          if constexpr (FEAT == FEAT_CLASS) cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
+          if constexpr (FEAT == FEAT_CLASS || CM == 2) cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
           else cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
           if constexpr (MM) {
             macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
@@ -431,35 +433,38 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   }
 }
 
-template <int MODE, int FEAT, bool CLAMP, bool MM>
+template <int MODE, int FEAT, int CM, bool MM>
 hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, false, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    k_sweep<MODE, FEAT, 0, 0, MM, 16><<<nb, kLanes, 0, st>>>(a);
   } else if constexpr (feat_low_precision(FEAT)) {
-    if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CLAMP, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
   }
   return hipGetLastError();
 }
 
+// clamped, known-positive (FP32 features, VALU moments) or plain inner products
 template <int MODE, int FEAT, bool MM>
 hipError_t dispatch_clamp(const PairArgs& a, hipStream_t st) {
-  if (a.kc.clamp) return dispatch<MODE, FEAT, true, MM>(a, a.kc.Dp, st);
-  return dispatch<MODE, FEAT, false, MM>(a, a.kc.Dp, st);
+  if (a.kc.clamp) return dispatch<MODE, FEAT, 1, MM>(a, a.kc.Dp, st);
+  if constexpr (FEAT == FEAT_DENSE && !MM)
+    if (a.kc.c_positive) return dispatch<MODE, FEAT, 2, MM>(a, a.kc.Dp, st);
+  return dispatch<MODE, FEAT, 0, MM>(a, a.kc.Dp, st);
 }
 
 template <int MODE, bool MM>
 hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
   switch (feat_path) {
-    case FEAT_CLASS: return dispatch<MODE, FEAT_CLASS, false, MM>(a, 0, st);
+    case FEAT_CLASS: return dispatch<MODE, FEAT_CLASS, 0, MM>(a, 0, st);
     case FEAT_DENSE: return dispatch_clamp<MODE, FEAT_DENSE, MM>(a, st);
     case FEAT_BF16: return dispatch_clamp<MODE, FEAT_BF16, MM>(a, st);
     default: return dispatch_clamp<MODE, FEAT_FP8, MM>(a, st);
@@ -474,8 +479,8 @@ hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_poi
                         hipStream_t st) {
   if (pass_points == 8) {
     if (feat_path != FEAT_CLASS || a.n_pass == 0) return feat_path != FEAT_CLASS ? hipErrorInvalidValue : hipSuccess;
-    if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, false, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
-    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, false, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
     return hipGetLastError();
   }
   if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, feat_path, st);
