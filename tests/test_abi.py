@@ -53,6 +53,24 @@ def test_default_options_and_create_without_device(lib):
         assert not h.value
 
 
+def test_server_default_options_and_validation_without_device(lib):
+    """The server's defaults as documented in the header, and argument checks that come before any device
+    call (lane count, work limit, split threshold)."""
+    from paper_2403_01254_amd import rkhsba
+    o = rkhsba.ServerOptions()
+    rkhsba.lib().rkhsba_server_default_options(ctypes.byref(o))
+    assert (o.max_active, o.hbm_budget_bytes, o.pass_points, o.use_graphs, o.lanes) == (64, 0, 0, 1, 1)
+    assert o.lane_split_entries == 2_000_000 and o.lane_work_entries == 0
+    h = ctypes.c_void_p()
+    for field, value in (("lanes", 0), ("lanes", 3), ("lane_work_entries", -1), ("lane_split_entries", -1),
+                         ("max_active", 0)):
+        bad = rkhsba.ServerOptions()
+        rkhsba.lib().rkhsba_server_default_options(ctypes.byref(bad))
+        setattr(bad, field, value)
+        assert rkhsba.lib().rkhsba_server_create(ctypes.byref(h), ctypes.byref(bad)) == rkhsba.EINVAL, field
+        assert not h.value
+
+
 def test_product_code_never_touches_the_oracle():
     pkg = os.path.join(ROOT, "paper_2403_01254_amd")
     for dirpath, _, files in os.walk(pkg):
