@@ -197,6 +197,34 @@ def test_frame_of_coincident_points(rk):
         ctx.close()
 
 
+def test_zero_feature_rows_are_not_pairs(rk):
+    """Pairs whose feature inner product is exactly 0 are not pairs (skipped by
+    the oracle).  With strictly positive soft labels every product is > 0 and
+    the sweep counts pairs from the membership mask alone; one all-zero row
+    (or a zero in every row of each dimension) must switch that off: the counts
+    stay equal to the oracle's."""
+    rng = np.random.default_rng(12)
+    x = (rng.normal(size=(600, 3)) * 0.1).astype(np.float32)
+    y = (x[:500] + rng.normal(scale=0.01, size=(500, 3))).astype(np.float32)
+    base = [rng.dirichlet(np.full(5, 0.5), size=len(a)).astype(np.float32) for a in (x, y)]
+    poses = np.stack([ident(), ident()])
+    zero_row = [f.copy() for f in base]
+    zero_row[1][7] = 0.0
+    staggered = [f.copy() for f in base]
+    for d in range(5):
+        staggered[0][d, d] = 0.0
+    for name, feats in (("positive", base), ("zero row", zero_row), ("a zero per dimension", staggered)):
+        op = oracle.Problem([x, y], feats, "dense", 0.08)
+        ctx = rk.Context(ell=0.08, cell_subdiv=4, pass_points=16)
+        ctx.build_neighbors([x, y], feats, "dense")
+        H, b, F, n = ctx.accumulate_normal_eqs(poses, [[0, 1], [1, 0]])
+        oF, ob, oH, _, on = oracle.normal_eqs(op, poses, [[0, 1], [1, 0]], oracle.MEMBER_FP32_RULE)
+        say(f"[zero rows] {name}: pairs {n} / {on}")
+        assert n == on and abs(F - oF) <= REL_TOL * oF
+        assert_blocks_close(H, oH, 6, what=f"{name} H")
+        ctx.close()
+
+
 def test_common_rigid_motion_invariance_gpu(rk):
     p = scenes.odometry(6, n_frames=3, n_points=3000)
     ctx = make_ctx(rk, p)
