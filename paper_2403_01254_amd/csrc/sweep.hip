@@ -84,6 +84,15 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
   return acc;
 }
 
+// Orders LDS accesses between the lanes of the workgroup, which is one
+// wavefront: its LDS operations are carried out in issue order, so only the
+// compiler must not move them across this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The same products for feature rows stored in bfloat16 or fp8 e4m3: one
 // 16x16x32 MFMA (FP32 accumulation) per 32 feature dimensions.  Lane (s, g)
 // supplies elements 8g..8g+7 of the slice, of candidate 16 sub + s (A, from
@@ -255,10 +264,10 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     }
     const uint32_t incl = wave_inclusive_scan(cntr, lane);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    __syncthreads();  // previous users of row_j0/row_off are done
+    wave_sync();  // previous users of row_j0/row_off are done
     row_j0[lane] = j0;
     row_off[lane] = incl - cntr;
-    __syncthreads();
+    wave_sync();
     if (total == 0) continue;
 
     // ---- tiles of 64 candidates, next tile fetched while the current one is processed
@@ -267,12 +276,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     const uint32_t my_off = incl - cntr;
     auto tile_rows = [&](uint32_t base) __attribute__((always_inline)) -> int {
       marker[lane] = 0u;  // 0: no row starts here; row r is marked r + 1
-      __syncthreads();
+      wave_sync();
       if (cntr > 0 && my_off < base + (uint32_t)kTile && my_off + cntr > base)
         marker[my_off > base ? my_off - base : 0u] = (uint32_t)lane + 1u;
-      __syncthreads();
+      wave_sync();
       const uint32_t r = wave_inclusive_max(marker[lane]);
-      __syncthreads();  // markers are rewritten by the next call
+      wave_sync();  // markers are rewritten by the next call
       return (int)min(max(r, 1u), (uint32_t)kLanes) - 1;
     };
     auto fetch = [&](uint32_t c, float4& pos, float* fr, u32x4* lr, bool& pad) __attribute__((always_inline)) {
@@ -327,7 +336,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           *reinterpret_cast<u32x2*>(tlp + lane * RB + 16 * k + 8) = nlp[k].zw;
         }
       }
-      __syncthreads();
+      wave_sync();
       if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
       const uint32_t left = total - cb;
       const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
@@ -386,16 +395,16 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           }
         }
       }
-      __syncthreads();  // the tile buffer is rewritten next
+      wave_sync();  // the tile buffer is rewritten next
     }
   }
 
   if constexpr (MM) {
     // lane (s, g) holds M[source 4g + r][column s]; regroup per source through LDS
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int r = 0; r < 4; ++r) mt[(4 * g + r) * 17 + s] = macc[0][r] + macc[1][r];
-    __syncthreads();
+    wave_sync();
     if (g == 0) {
       const float* m = mt + s * 17;
       const float vx = q.x - ref.x, vy = q.y - ref.y, vz = q.z - ref.z;
