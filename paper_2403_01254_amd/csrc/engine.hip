@@ -943,6 +943,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   fa.vals = sorted_v_;
   fa.mom = mom_.p;
   fa.cnt = cnt_.p;
+  fa.kcs = lay.d_kcs.p;
   fa.partial = partial_.p;
   fa.n_entries = lay.n_entries;
   fa.E = lay.E;

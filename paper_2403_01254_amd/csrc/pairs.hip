@@ -288,13 +288,23 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
 //        = [[-A R_mn, R_mn [S]], [-[A x] R_mn, [x] R_mn [S]]]
 // so it suffices to sum, per edge, the 37 products
 //   A, B, x cross Bm, q cross B, A x, A x x^T (6), A q, Szz (6), x S^T (9)
-// (plus tr C = sum w |d|^2, the lengthscale derivative's term, and the pair count) and to expand the sums into the 91 values once per
-// edge.  Sums run in FP64: per thread over its entries, then per block in a
+// (plus tr C = sum w |d|^2, the lengthscale derivative's term, F and the
+// pair count) and to expand the sums into the 91 values once per edge.
+//
+// The sweeps form d = q32 - z from q rounded to FP32 (the membership rule's
+// value).  Far from a frame's origin that rounding, up to half an FP32 ulp of
+// |q|, is no longer small next to d, and it is the same for every pair of one
+// source point.  The per-point terms therefore use q in FP64 and moments
+// moved to d + dl (dl = q64 - q32) to first order in dl, which needs only the
+// moments at hand; F itself is left as the plain sum of the kernel values, so
+// that it is the same number the loss-only evaluation gives.
+//
+// Sums run in FP64: per thread over its entries, then per block in a
 // fixed order, then per edge over the blocks in order; the split into
 // blocks depends only on the edge's source count, so an edge's sums do not
 // depend on what else is evaluated with it.
 constexpr int kStA = 0, kStB = 1, kStXBm = 4, kStQB = 7, kStAx = 10, kStAxx = 13, kStAq = 19, kStSzz = 22,
-              kStXS = 28, kStWr2 = 37, kStCnt = 38;
+              kStXS = 28, kStWr2 = 37, kStF = 38, kStCnt = 39;
 
 // Running sums: FP64, or FP32 with Kahan compensation (option).
 template <typename T>
@@ -325,6 +335,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   const int e = upper_segment(fin_off, a.E, blk);
   const EdgeInfo ed = a.edges[e];
   const EdgeXf X = a.xf[e];
+  const KConst& kc = a.kcs[ed.prob];
   const float4* __restrict__ src_pts = a.pts + a.frames[ed.m].pt_off;
   const int64_t end = ed.ent_off + ed.n_src;
   const int64_t base = ed.ent_off + (int64_t)(blk - ed.fin_off) * kFinThreads * ed.fin_pt;
@@ -343,17 +354,37 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
       T B[3], C[6], x[3], q[3];
       for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
       for (int k = 0; k < 5; ++k) C[k] = a.mom[(4 + k) * N + entry];
-      const T Wr2 = a.mom[9 * N + entry];  // the sweeps store sum w |d|^2 in place of C_zz
+      T Wr2 = a.mom[9 * N + entry];  // the sweeps store sum w |d|^2 in place of C_zz
       C[5] = Wr2 - C[0] - C[3];
       const float4 p = src_pts[a.vals[entry]];
-      const float3 qq = rule_q32(X, p.x, p.y, p.z);
+      const double3 q64 = rule_q64(X, p.x, p.y, p.z);
       x[0] = p.x; x[1] = p.y; x[2] = p.z;
-      q[0] = qq.x; q[1] = qq.y; q[2] = qq.z;
+      q[0] = (T)q64.x; q[1] = (T)q64.y; q[2] = (T)q64.z;
+      // The sweeps formed d = q32 - z from the rounded q32; every pair of this
+      // point has d64 = d + dl.  First-order update of the moments in dl:
+      // w64 = w (1 - d.g), g = dl / ell^2 (third moments dropped).
+      const T dl[3] = {(T)(q64.x - (double)(float)q64.x), (T)(q64.y - (double)(float)q64.y),
+                       (T)(q64.z - (double)(float)q64.z)};
+      const T two_a = (T)(2.0 * kc.inv2l2);
+      const T g[3] = {dl[0] * two_a, dl[1] * two_a, dl[2] * two_a};
+      const T Bg = B[0] * g[0] + B[1] * g[1] + B[2] * g[2];
+      const T Bdl = B[0] * dl[0] + B[1] * dl[1] + B[2] * dl[2];
+      const T Cg[3] = {C[0] * g[0] + C[1] * g[1] + C[2] * g[2], C[1] * g[0] + C[3] * g[1] + C[4] * g[2],
+                       C[2] * g[0] + C[4] * g[1] + C[5] * g[2]};
+      {
+        const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C[k] += B[ri[k]] * dl[ci[k]] + dl[ri[k]] * B[ci[k]];
+      }
+      for (int k = 0; k < 3; ++k) B[k] += A * dl[k] - Cg[k] - Bg * dl[k];
+      Wr2 += (T)2 * Bdl;
+      const T A1 = A - Bg;
       T R[9];
       for (int k = 0; k < 9; ++k) R[k] = (T)X.R[k];
       T Bm[3];
       for (int r = 0; r < 3; ++r) Bm[r] = R[r] * B[0] + R[3 + r] * B[1] + R[6 + r] * B[2];
-      st[kStA].add(A);
+      st[kStF].add(A);  // F as the loss-only evaluation forms it
+      st[kStA].add(A1);
       for (int k = 0; k < 3; ++k) st[kStB + k].add(B[k]);
       st[kStXBm + 0].add(x[1] * Bm[2] - x[2] * Bm[1]);
       st[kStXBm + 1].add(x[2] * Bm[0] - x[0] * Bm[2]);
@@ -363,10 +394,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
       st[kStQB + 2].add(q[0] * B[1] - q[1] * B[0]);
       T Ax[3], S[3];
       for (int k = 0; k < 3; ++k) {
-        Ax[k] = A * x[k];
+        Ax[k] = A1 * x[k];
         st[kStAx + k].add(Ax[k]);
-        st[kStAq + k].add(A * q[k]);
-        S[k] = A * q[k] - B[k];
+        st[kStAq + k].add(A1 * q[k]);
+        S[k] = A1 * q[k] - B[k];
       }
       st[kStAxx + 0].add(Ax[0] * x[0]); st[kStAxx + 1].add(Ax[0] * x[1]); st[kStAxx + 2].add(Ax[0] * x[2]);
       st[kStAxx + 3].add(Ax[1] * x[1]); st[kStAxx + 4].add(Ax[1] * x[2]); st[kStAxx + 5].add(Ax[2] * x[2]);
@@ -375,7 +406,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         const int r = ri[k], c = ci[k];
-        st[kStSzz + k].add(A * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + C[k]);
+        st[kStSzz + k].add(A1 * q[r] * q[c] - q[r] * B[c] - B[r] * q[c] + C[k]);
       }
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -454,7 +485,7 @@ __global__ __launch_bounds__(64) void k_edge_reduce(const double* __restrict__ p
   const TT* B = T + kStB;
   TT v[kEdgeVals];
   for (int k = 0; k < kEdgeVals; ++k) v[k] = 0.0;
-  v[0] = A;
+  v[0] = T[kStF];
   for (int r = 0; r < 3; ++r) {
     v[1 + r] = Rmn[r][0] * B[0] + Rmn[r][1] * B[1] + Rmn[r][2] * B[2];
     v[4 + r] = T[kStXBm + r];

@@ -18,16 +18,22 @@ __device__ inline void rule_relative(const double* __restrict__ Tm, const double
   for (int a = 0; a < 3; ++a) t[a] = fma(Tn[6 + a], d2, fma(Tn[3 + a], d1, Tn[a] * d0));
 }
 
+// T_nm x in FP64: the source point in the target frame before rounding.
+__device__ inline double3 rule_q64(const EdgeXf& xf, float x0, float x1, float x2) {
+#pragma clang fp contract(off)
+  const double a = x0, b = x1, c = x2;
+  double3 q;
+  q.x = fma(xf.R[2], c, fma(xf.R[1], b, fma(xf.R[0], a, xf.t[0])));
+  q.y = fma(xf.R[5], c, fma(xf.R[4], b, fma(xf.R[3], a, xf.t[1])));
+  q.z = fma(xf.R[8], c, fma(xf.R[7], b, fma(xf.R[6], a, xf.t[2])));
+  return q;
+}
+
 // q32 = float(T_nm x): the source point in the target frame, computed in FP64
 // and rounded once.
 __device__ inline float3 rule_q32(const EdgeXf& xf, float x0, float x1, float x2) {
-#pragma clang fp contract(off)
-  const double a = x0, b = x1, c = x2;
-  float3 q;
-  q.x = (float)fma(xf.R[2], c, fma(xf.R[1], b, fma(xf.R[0], a, xf.t[0])));
-  q.y = (float)fma(xf.R[5], c, fma(xf.R[4], b, fma(xf.R[3], a, xf.t[1])));
-  q.z = (float)fma(xf.R[8], c, fma(xf.R[7], b, fma(xf.R[6], a, xf.t[2])));
-  return q;
+  const double3 q = rule_q64(xf, x0, x1, x2);
+  return make_float3((float)q.x, (float)q.y, (float)q.z);
 }
 
 // Exact widening of the stored low-precision feature formats.

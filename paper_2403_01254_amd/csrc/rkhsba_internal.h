@@ -184,6 +184,7 @@ struct FinArgs {
   const uint32_t* vals;
   const float* mom;
   const uint32_t* cnt;
+  const KConst* kcs;      // per problem of the set, indexed by EdgeInfo::prob
   double* partial;        // [n_fin_total][kFinStats]
   int64_t n_entries;
   int32_t E;
@@ -191,7 +192,7 @@ struct FinArgs {
 };
 constexpr int kEdgeVals = 93;  // F, b_m(6), b_n(6), H_mm(21), H_nn(21), H_mn(36), pair count, sum w r^2
 constexpr int kFinThreads = 256;
-constexpr int kFinStats = 39;  // per-edge sums the normal-equation blocks are expanded from, sum w r^2, pair count
+constexpr int kFinStats = 40;  // per-edge sums the normal-equation blocks are expanded from, sum w r^2, F, pair count
 // fp32_sums: per-point terms and their sums in FP32 with Kahan compensation,
 // else FP64.  Pair counts are summed in FP64.
 hipError_t launch_finalize(const FinArgs& a, const int32_t* d_fin_off, int mode, bool fp32_sums, hipStream_t st);

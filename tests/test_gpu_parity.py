@@ -225,6 +225,49 @@ def test_zero_feature_rows_are_not_pairs(rk):
         ctx.close()
 
 
+def test_frame_above_2_24_points(rk):
+    """A frame of 2^24 + 250,000 points (more than FP32 counts exactly), against
+    a small frame at a rotated pose: the pair lists of both directions must be
+    bit-exact, with indices above 2^24 on the large side, and F, b and H within
+    the usual tolerance.  The points near the small frame are the last ones of
+    the large frame, so most pairs use its highest indices."""
+    rng = np.random.default_rng(21)
+    n_far, n_tail, n_small = 1 << 24, 250_000, 150
+    big = np.empty((n_far + n_tail, 3), np.float32)
+    big[:n_far, :2] = rng.uniform(-200.0, 200.0, size=(n_far, 2))
+    big[n_far:, :2] = rng.uniform(-20.0, 20.0, size=(n_tail, 2)) + np.array([3.0, 150.0])
+    big[:, 2] = rng.normal(scale=0.01, size=len(big))
+    small = np.empty((n_small, 3), np.float32)
+    small[:, 0] = rng.uniform(-2.0, 2.0, n_small)
+    small[:, 1] = rng.uniform(-1.75, 1.75, n_small)
+    small[:, 2] = rng.normal(scale=0.01, size=n_small)
+    labels = [rng.integers(0, 3, len(a)).astype(np.uint16) for a in (big, small)]
+    pose1 = ident()
+    c, s = np.cos(0.2), np.sin(0.2)
+    pose1[:9] = [c, -s, 0.0, s, c, 0.0, 0.0, 0.0, 1.0]
+    pose1[9:] = [3.0, 150.0, 0.0]
+    poses = np.stack([ident(), pose1])
+    edges = [[0, 1], [1, 0]]
+    say(f"[2^24] building {len(big)} + {n_small} points")
+    ctx = rk.Context(ell=0.1, cell_subdiv=2, pass_points=16)
+    ctx.build_neighbors([big, small], labels, "class")
+    op = oracle.Problem([big, small], labels, "class", 0.1)
+    for m, n in edges:
+        got = ctx.export_pairs(poses, m, n)
+        ref = oracle.pairs(op, poses, m, n)
+        big_side = got[:, 0] if m == 0 else got[:, 1]
+        say(f"[2^24] edge ({m},{n}) gpu {len(got)} oracle {len(ref)}, above 2^24: {(big_side >= n_far).sum()}")
+        assert len(ref) > 1000 and (big_side >= n_far).sum() > len(ref) // 2
+        np.testing.assert_array_equal(got, ref)
+    H, b, F, npairs = ctx.accumulate_normal_eqs(poses, edges)
+    oF, ob, oH, _, onp = oracle.normal_eqs(op, poses, edges, oracle.MEMBER_FP32_RULE)
+    say(f"[2^24] F gpu {F:.9g} oracle {oF:.9g} pairs {npairs} / {onp}")
+    assert npairs == onp and abs(F - oF) <= REL_TOL * oF
+    assert_blocks_close(b, ob, 6, what="2^24 b")
+    assert_blocks_close(H, oH, 6, what="2^24 H")
+    ctx.close()
+
+
 def test_common_rigid_motion_invariance_gpu(rk):
     p = scenes.odometry(6, n_frames=3, n_points=3000)
     ctx = make_ctx(rk, p)
