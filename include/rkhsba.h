@@ -28,6 +28,11 @@
  *     last failure on that context.  Calls on one context must not overlap.
  *   - Membership in the truncation radius is decided by the FP32 rule below,
  *     so the pair set is exactly reproducible on a CPU.
+ *   - Values: the pair terms are FP32, from d = q32 - z of the rule.  F is
+ *     their sum.  b and H take q in FP64 and move each source point's sums to
+ *     d = q - z to first order in q - q32 (q32 is off by up to half an FP32
+ *     ulp of |q|, which matters for points far from their frame's origin).
+ *     Sums past the per-point stage run in FP64 (or Kahan FP32, option).
  *
  * FP32 membership rule (pair (i in frame m, j in frame n)):
  *   R_nm[a][b] = fma(Rn[2][a], Rm[2][b], fma(Rn[1][a], Rm[1][b], Rn[0][a]*Rm[0][b]))
