@@ -265,6 +265,12 @@ def test_frame_above_2_24_points(rk):
     assert npairs == onp and abs(F - oF) <= REL_TOL * oF
     assert_blocks_close(b, ob, 6, what="2^24 b")
     assert_blocks_close(H, oH, 6, what="2^24 H")
+    # F is the plain sum of the pair terms in both evaluations (only b and H
+    # take the correction for the rounding of q), so the two agree far below
+    # the size of that correction here (2e-7 of F)
+    F_loss, _, n_loss = ctx.eval_loss(poses, edges)
+    say(f"[2^24] F loss-only {F_loss:.12g} normal equations {F:.12g}")
+    assert n_loss == npairs and abs(F_loss - F) <= 1e-8 * F
     ctx.close()
 
 
