@@ -274,6 +274,40 @@ def test_frame_above_2_24_points(rk):
     ctx.close()
 
 
+def test_points_far_from_frame_origins(rk):
+    """The same world geometry with every frame's points stored about 300 m
+    from the frame's origin (poses compensate): the FP32 transformed points
+    then carry rounding up to 2^-17 m, which the finalisation corrects to first
+    order.  Pair counts are exact; F, b, H and Gauss-Newton poses agree with
+    the oracle within the usual tolerances."""
+    p = scenes.odometry(1, n_frames=4, n_points=4000, n_iter=3)
+    shift = np.array([200.0, -150.0, 160.0])
+    pts = [(a.astype(np.float64) + shift).astype(np.float32) for a in p.points]
+    def moved(poses):
+        out = np.array(poses, dtype=np.float64).copy()
+        for q in out:
+            q[9:] -= q[:9].reshape(3, 3) @ shift
+        return out
+    init = moved(p.init_poses)
+    op = oracle.Problem(pts, p.feats, p.feat_kind, p.ell, p.cutoff_factor)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor)
+    ctx.build_neighbors(pts, p.feats, p.feat_kind)
+    H, b, F, n = ctx.accumulate_normal_eqs(init, p.edges)
+    oF, ob, oH, _, on = oracle.normal_eqs(op, init, p.edges, oracle.MEMBER_FP32_RULE)
+    say(f"[far] pairs {n} / {on}, F rel {abs(F - oF) / oF:.3g}, b rel {normwise_rel(b, ob):.3g}, "
+        f"H rel {normwise_rel(H, oH):.3g}")
+    assert n == on and abs(F - oF) <= REL_TOL * oF
+    assert_blocks_close(b, ob, 6, what="far b")
+    assert_blocks_close(H, oH, 6, what="far H")
+    poses, lpi, _ = ctx.gn_step(init, p.edges, 3)
+    oposes, olpi = oracle.gn(op, init, p.edges, 3, membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(poses, oposes)
+    say(f"[far] gn rot err {rot.max():.3g} trans err {tr.max():.3g}")
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+    ctx.close()
+
+
 def test_common_rigid_motion_invariance_gpu(rk):
     p = scenes.odometry(6, n_frames=3, n_points=3000)
     ctx = make_ctx(rk, p)
