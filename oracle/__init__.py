@@ -1,9 +1,11 @@
 """FP64 CPU oracle for the RKHS-BA hot path -- TEST INFRASTRUCTURE ONLY.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
-``bench.py`` may import this package.  It is a plain brute-force C
-restatement of the paper's definitions (arXiv 2403.01254, Sec. III and
-Sec. V-A) loaded through ctypes; it shares no code with the GPU library.
+``bench.py`` may import this package.  It is a plain C restatement of the
+paper's definitions (arXiv 2403.01254, Sec. III and Sec. V-A), loaded
+through ctypes: brute force over all point pairs, or an independent
+cell-list search over the same pairs.  It shares no code with the GPU
+library.
 
 Every function here follows a passage of the paper; see ``rkhs_oracle.c``
 for the per-function citations.  Pins live in ``tests/test_oracle_*.py``.
@@ -22,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MEMBER_FP64 = 0
 MEMBER_FP32_RULE = 1
+SEARCH = {"brute": 0, "cells": 1}
 
 
 def build(force: bool = True) -> str:
@@ -48,6 +51,7 @@ class _Problem(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("clamp_negative_c", ctypes.c_int),
         ("top_k", ctypes.c_int),
+        ("search", ctypes.c_int),
     ]
 
 
@@ -86,10 +90,13 @@ class Problem:
     """Frames, features and kernel parameters in the layout the C oracle reads.
 
     points: list of (N_m, 3) float32; feats: list of (N_m,) uint16 class ids or
-    (N_m, D) float32 rows; ell, cutoff_factor, sigma as in Eq. (eq:kernel)."""
+    (N_m, D) float32 rows; ell, cutoff_factor, sigma as in Eq. (eq:kernel).
+    search: "brute" (every point pair, the definition) or "cells" (the targets
+    of the 27 world-coordinate cells around each source point: the same pairs,
+    summed in another order)."""
 
     def __init__(self, points, feats, feat_kind, ell, cutoff_factor=3.0, sigma=1.0, clamp_negative_c=True,
-                 top_k=0):
+                 top_k=0, search="brute"):
         self.points = [np.ascontiguousarray(p, dtype=np.float32).reshape(-1, 3) for p in points]
         if feat_kind == "class":
             self.feats = [np.ascontiguousarray(f, dtype=np.uint16).reshape(-1) for f in feats]
@@ -105,12 +112,18 @@ class Problem:
         self._f = (ctypes.c_void_p * self.K)(*[f.ctypes.data for f in self.feats])
         self.c = _Problem(self.K, _ptr(self._n, ctypes.c_int64), self._xyz, 0 if feat_kind == "class" else 1, D,
                           self._f, float(ell), float(cutoff_factor), float(sigma), int(bool(clamp_negative_c)),
-                          int(top_k))
+                          int(top_k), SEARCH[search])
         self.top_k = int(top_k)
+        self.search = search
 
     @classmethod
     def from_scene(cls, p, **kw):
         return cls(p.points, p.feats, p.feat_kind, p.ell, p.cutoff_factor, **kw)
+
+    def with_search(self, search):
+        """The same frames and parameters with another neighbour search."""
+        return Problem(self.points, self.feats, self.feat_kind, self.ell, self.cutoff_factor, self.sigma,
+                       bool(self.c.clamp_negative_c), self.top_k, search)
 
 
 def _edges(edges):

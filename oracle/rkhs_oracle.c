@@ -1,8 +1,10 @@
 /*
  * FP64 CPU oracle for the RKHS-BA hot path -- TEST INFRASTRUCTURE ONLY.
  *
- * Plain, slow, brute-force restatement of the paper's definitions, written to
- * be checked by eye against the paper.  Only tests/, the smoke check and the
+ * Plain, slow restatement of the paper's definitions, written to be checked
+ * by eye against the paper: brute force over every point pair, or (search
+ * mode) a world-coordinate cell list that visits a superset of the pairs
+ * inside the truncation radius.  Only tests/, the smoke check and the
  * benchmark's CPU-baseline leg use it; it shares no code with the GPU library.
  * Build: gcc -O2 -fopenmp -ffp-contract=off (no fast-math).
  *
@@ -108,6 +110,142 @@ static double label_product(const oracle_problem* P, int m, int64_t i, int n, in
   return c;
 }
 
+/* ------------------------------------------------------------------ cell-list neighbour search */
+
+/* The truncation radius makes the double sum of Eq. (eq:double_sum) sparse
+ * (Sec. III-B): a pair farther apart than r_c adds nothing.  With search =
+ * ORACLE_SEARCH_CELLS an edge's target points are hashed, in WORLD
+ * coordinates at the current poses, into cubic cells of edge h slightly above
+ * r_c, and each source point visits only the targets of the 27 cells around
+ * its own.  Every pair the membership test can accept is among them, so the
+ * sums are those of the brute-force search up to the order of summation
+ * (cells in a fixed order, targets by ascending index within a cell).
+ *
+ * h = r_c (1 + 2^-10) + 2^-20 (M + r_c), M the largest absolute local
+ * coordinate of the target frame: the FP32 rule's rounding of q and of the
+ * squared distance moves a pair's decision by at most ~2^-22 r_c + 2^-23 (M + r_c),
+ * and the FP64 world coordinates by far less, so an accepted pair is always
+ * less than h apart in every axis and its cells differ by at most one. */
+#define CELL_BITS 21
+#define CELL_HALF (1LL << (CELL_BITS - 1))
+
+typedef struct {
+  double inv_h;
+  int64_t n_runs;
+  int64_t* order;  /* target indices sorted by (cell key, index) */
+  int64_t* start;  /* n_runs + 1: first position of each cell's run in order */
+  uint64_t* key;   /* cell key of each run */
+  int64_t* slot;   /* open addressing table: run index, or -1 */
+  uint64_t mask;
+} cell_list;
+
+typedef struct {
+  uint64_t key;
+  int64_t j;
+} keyed_index;
+
+static int cmp_keyed_index(const void* pa, const void* pb) {
+  const keyed_index* a = (const keyed_index*)pa;
+  const keyed_index* b = (const keyed_index*)pb;
+  if (a->key != b->key) return a->key < b->key ? -1 : 1;
+  return a->j < b->j ? -1 : (a->j > b->j ? 1 : 0);
+}
+
+/* 1 and the packed key of cell (cx, cy, cz) if every coordinate fits CELL_BITS bits, else 0. */
+static int cell_key(int64_t cx, int64_t cy, int64_t cz, uint64_t* key) {
+  if (cx < -CELL_HALF || cx >= CELL_HALF || cy < -CELL_HALF || cy >= CELL_HALF || cz < -CELL_HALF ||
+      cz >= CELL_HALF)
+    return 0;
+  *key = ((uint64_t)(cx + CELL_HALF) << (2 * CELL_BITS)) | ((uint64_t)(cy + CELL_HALF) << CELL_BITS) |
+         (uint64_t)(cz + CELL_HALF);
+  return 1;
+}
+
+static uint64_t mix64(uint64_t x) { /* splitmix64 finaliser */
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ULL;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebULL;
+  return x ^ (x >> 31);
+}
+
+static void cell_of_point(const cell_list* cl, const double w[3], int64_t c[3]) {
+  for (int a = 0; a < 3; ++a) c[a] = (int64_t)floor(w[a] * cl->inv_h);
+}
+
+/* Cell list of the world points Wz (N rows of 3); h from r_c and the target's local coordinates Z.
+ * Returns 0, or -1 when a cell coordinate does not fit the key. */
+static int cell_list_build(cell_list* cl, const double* Wz, const float* Z, int64_t N, double rc) {
+  double M = 0.0;
+  for (int64_t i = 0; i < 3 * N; ++i) M = fmax(M, fabs((double)Z[i]));
+  const double h = rc * (1.0 + ldexp(1.0, -10)) + ldexp(M + rc, -20);
+  cl->inv_h = 1.0 / h;
+  keyed_index* ki = (keyed_index*)malloc(sizeof(keyed_index) * (size_t)(N > 0 ? N : 1));
+  for (int64_t j = 0; j < N; ++j) {
+    int64_t c[3];
+    cell_of_point(cl, Wz + 3 * j, c);
+    if (!cell_key(c[0], c[1], c[2], &ki[j].key)) {
+      free(ki);
+      return -1;
+    }
+    ki[j].j = j;
+  }
+  qsort(ki, (size_t)N, sizeof(keyed_index), cmp_keyed_index);
+  cl->order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+  cl->start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N + 1));
+  cl->key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(N > 0 ? N : 1));
+  int64_t runs = 0;
+  for (int64_t p = 0; p < N; ++p) {
+    cl->order[p] = ki[p].j;
+    if (p == 0 || ki[p].key != ki[p - 1].key) {
+      cl->start[runs] = p;
+      cl->key[runs] = ki[p].key;
+      ++runs;
+    }
+  }
+  cl->start[runs] = N;
+  cl->n_runs = runs;
+  uint64_t size = 16;
+  while (size < 2 * (uint64_t)runs) size <<= 1;
+  cl->mask = size - 1;
+  cl->slot = (int64_t*)malloc(sizeof(int64_t) * size);
+  for (uint64_t s = 0; s < size; ++s) cl->slot[s] = -1;
+  for (int64_t r = 0; r < runs; ++r) {
+    uint64_t s = mix64(cl->key[r]) & cl->mask;
+    while (cl->slot[s] >= 0) s = (s + 1) & cl->mask;
+    cl->slot[s] = r;
+  }
+  free(ki);
+  return 0;
+}
+
+static void cell_list_free(cell_list* cl) {
+  free(cl->order);
+  free(cl->start);
+  free(cl->key);
+  free(cl->slot);
+}
+
+/* Targets in the 27 cells around world point w, appended to out (capacity N); returns their count. */
+static int64_t cell_list_gather(const cell_list* cl, const double w[3], int64_t* out) {
+  int64_t c[3], n = 0;
+  cell_of_point(cl, w, c);
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        uint64_t key;
+        if (!cell_key(c[0] + dx, c[1] + dy, c[2] + dz, &key)) continue;
+        uint64_t s = mix64(key) & cl->mask;
+        for (; cl->slot[s] >= 0; s = (s + 1) & cl->mask) {
+          const int64_t r = cl->slot[s];
+          if (cl->key[r] != key) continue;
+          for (int64_t p = cl->start[r]; p < cl->start[r + 1]; ++p) out[n++] = cl->order[p];
+          break;
+        }
+      }
+  return n;
+}
+
 /* ------------------------------------------------------------------ loss, gradient, GN matrix */
 
 typedef struct {
@@ -120,6 +258,7 @@ static int check_problem(const oracle_problem* P) {
   if (!P || P->K < 1 || !P->n_points || !P->xyz || !P->feats) return -1;
   if (!(P->ell > 0.0) || !(P->cutoff_factor > 0.0)) return -1;
   if (P->feat_kind != ORACLE_FEAT_CLASS && (P->feat_kind != ORACLE_FEAT_DENSE || P->D < 1)) return -1;
+  if (P->search != ORACLE_SEARCH_BRUTE && P->search != ORACLE_SEARCH_CELLS) return -1;
   return 0;
 }
 
@@ -237,8 +376,8 @@ static int make_candidate(const oracle_problem* P, int m, int64_t i, int n, int6
  * and the IRLS normal-equation terms of Eq. (eq:irls_final) with the weights
  * frozen: b += w J^T u, H += w J^T J, J = du/d[eps_m, eps_n].  With top_k > 0
  * only each source point's top_k pairs (see make_candidate) are summed. */
-static void edge_terms(const oracle_problem* P, const double* poses, int m, int n, int membership,
-                       edge_acc* out) {
+static int edge_terms(const oracle_problem* P, const double* poses, int m, int n, int membership,
+                      edge_acc* out) {
   const int64_t Nm = P->n_points[m], Nn = P->n_points[n];
   const float* X = P->xyz[m];
   const float* Z = P->xyz[n];
@@ -260,6 +399,12 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
     double z[3] = {Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
     apply(Rn, tn, z, Wz + 3 * j);
   }
+  const int cells = P->search == ORACLE_SEARCH_CELLS;
+  cell_list cl;
+  if (cells && cell_list_build(&cl, Wz, Z, Nn, rc)) {
+    free(Wz);
+    return -1;
+  }
   const int64_t n_chunks = (Nm + ORACLE_CHUNK - 1) / ORACLE_CHUNK;
   edge_acc* acc = (edge_acc*)calloc((size_t)(n_chunks > 0 ? n_chunks : 1), sizeof(edge_acc));
 
@@ -268,6 +413,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
     edge_acc a;
     memset(&a, 0, sizeof(a));
     candidate* cand = top_k > 0 ? (candidate*)malloc(sizeof(candidate) * (size_t)(Nn > 0 ? Nn : 1)) : NULL;
+    int64_t* near = cells ? (int64_t*)malloc(sizeof(int64_t) * (size_t)(Nn > 0 ? Nn : 1)) : NULL;
     const int64_t i1 = (ch + 1) * ORACLE_CHUNK < Nm ? (ch + 1) * ORACLE_CHUNK : Nm;
     for (int64_t i = ch * ORACLE_CHUNK; i < i1; ++i) {
       double x[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
@@ -278,7 +424,10 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
       double Jm[3][6];
       jacobian(Rm, x, +1.0, Jm);
       int64_t nc = 0;
-      for (int64_t j = 0; j < Nn; ++j) {
+      /* brute force: every target point; cell list: the targets of the 27 cells around p */
+      const int64_t n_near = cells ? cell_list_gather(&cl, p, near) : Nn;
+      for (int64_t t = 0; t < n_near; ++t) {
+        const int64_t j = cells ? near[t] : t;
         const double* q = Wz + 3 * j;
         double u[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
         double r2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -304,8 +453,10 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
       }
     }
     free(cand);
+    free(near);
     acc[ch] = a;
   }
+  if (cells) cell_list_free(&cl);
   /* chunks summed in a fixed order: the result does not depend on the thread count */
   memset(out, 0, sizeof(*out));
   for (int64_t ch = 0; ch < n_chunks; ++ch) {
@@ -324,6 +475,7 @@ static void edge_terms(const oracle_problem* P, const double* poses, int m, int 
   }
   free(acc);
   free(Wz);
+  return 0;
 }
 
 /* Per-edge F and W = sum w |u|^2 (no sigma^2).  An edge may pair a frame with
@@ -336,7 +488,7 @@ int oracle_edge_sums(const oracle_problem* P, const double* poses, int E, const 
     const int m = edges[2 * e], n = edges[2 * e + 1];
     if (m < 0 || n < 0 || m >= P->K || n >= P->K) return -1;
     edge_acc a;
-    edge_terms(P, poses, m, n, membership, &a);
+    if (edge_terms(P, poses, m, n, membership, &a)) return -2;
     if (F_edge) F_edge[e] = a.F;
     if (W_edge) W_edge[e] = a.W;
   }
@@ -354,7 +506,7 @@ int oracle_normal_eqs(const oracle_problem* P, const double* poses, int E, const
   for (int e = 0; e < E; ++e) {
     const int m = edges[2 * e], n = edges[2 * e + 1];
     edge_acc a;
-    edge_terms(P, poses, m, n, membership, &a);
+    if (edge_terms(P, poses, m, n, membership, &a)) return -2;
     Ftot += a.F;
     ptot += a.pairs;
     if (F_edge) F_edge[e] = a.F;
@@ -467,7 +619,8 @@ int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edge
   int status = 0;
   for (int it = 0; it <= n_iter; ++it) {
     double F;
-    oracle_normal_eqs(P, poses, E, edges, membership, &F, b, H, NULL, NULL);
+    status = oracle_normal_eqs(P, poses, E, edges, membership, &F, b, H, NULL, NULL);
+    if (status) break;
     if (loss_per_iter) loss_per_iter[it] = F;
     if (it == n_iter || nr == 0) continue;
     double tr = 0.0;
@@ -518,46 +671,70 @@ int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n,
   const double inv_2l2 = 1.0 / (2.0 * P->ell * P->ell);
   double Rnm[3][3], tnm[3];
   rule_relative(poses + 12 * m, poses + 12 * n, Rnm, tnm);
+  /* cell search: the targets' world coordinates at the given poses */
+  const int cells = P->search == ORACLE_SEARCH_CELLS;
+  double Rm[3][3], tm[3], Rn[3][3], tn[3];
+  pose_split(poses + 12 * m, Rm, tm);
+  pose_split(poses + 12 * n, Rn, tn);
+  cell_list cl;
+  if (cells) {
+    double* Wz = (double*)malloc(sizeof(double) * 3 * (size_t)(Nn > 0 ? Nn : 1));
+    for (int64_t j = 0; j < Nn; ++j) {
+      double z[3] = {Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
+      apply(Rn, tn, z, Wz + 3 * j);
+    }
+    const int bad = cell_list_build(&cl, Wz, Z, Nn, rc);
+    free(Wz);
+    if (bad) return -1;
+  }
   int64_t* cnt = (int64_t*)calloc((size_t)(Nm + 1), sizeof(int64_t));
   const uint16_t* lm = (const uint16_t*)P->feats[m];
   const uint16_t* ln = (const uint16_t*)P->feats[n];
   const int classes = P->feat_kind == ORACLE_FEAT_CLASS;
   for (int pass = 0; pass < 2; ++pass) {
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < Nm; ++i) {
-      float q32[3];
-      rule_q32(Rnm, tnm, X + 3 * i, q32);
-      int64_t c = 0, o = pass ? cnt[i] : 0;
-      if (P->top_k > 0) { /* the top_k candidates of make_candidate, listed by j */
-        candidate* cand = (candidate*)malloc(sizeof(candidate) * (size_t)(Nn > 0 ? Nn : 1));
-        for (int64_t j = 0; j < Nn; ++j)
-          if (rule_inside(q32, Z + 3 * j, rc2_32))
-            c += make_candidate(P, m, i, n, j, ORACLE_MEMBER_FP32_RULE, q32, 0.0, inv_2l2, cand + c);
-        qsort(cand, (size_t)c, sizeof(candidate), candidate_order);
-        if (c > P->top_k) c = P->top_k;
-        int64_t* js = (int64_t*)malloc(sizeof(int64_t) * (size_t)(c > 0 ? c : 1));
-        for (int64_t t = 0; t < c; ++t) js[t] = cand[t].j;
-        qsort(js, (size_t)c, sizeof(int64_t), cmp_i64);
+#pragma omp parallel
+    {
+      int64_t* near = (int64_t*)malloc(sizeof(int64_t) * (size_t)(Nn > 0 ? Nn : 1));
+      candidate* cand = P->top_k > 0 ? (candidate*)malloc(sizeof(candidate) * (size_t)(Nn > 0 ? Nn : 1)) : NULL;
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t i = 0; i < Nm; ++i) {
+        float q32[3];
+        rule_q32(Rnm, tnm, X + 3 * i, q32);
+        /* candidate targets: all of them, or those of the 27 cells around the source's world point */
+        int64_t n_near = Nn;
+        if (cells) {
+          double x[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]}, p[3];
+          apply(Rm, tm, x, p);
+          n_near = cell_list_gather(&cl, p, near);
+        }
+        int64_t c = 0, o = pass ? cnt[i] : 0;
+        if (P->top_k > 0) { /* the top_k candidates of make_candidate, listed by j */
+          for (int64_t t = 0; t < n_near; ++t) {
+            const int64_t j = cells ? near[t] : t;
+            if (rule_inside(q32, Z + 3 * j, rc2_32))
+              c += make_candidate(P, m, i, n, j, ORACLE_MEMBER_FP32_RULE, q32, 0.0, inv_2l2, cand + c);
+          }
+          qsort(cand, (size_t)c, sizeof(candidate), candidate_order);
+          if (c > P->top_k) c = P->top_k;
+          for (int64_t t = 0; t < c; ++t) near[t] = cand[t].j;
+        } else {
+          for (int64_t t = 0; t < n_near; ++t) {
+            const int64_t j = cells ? near[t] : t;
+            if (!rule_inside(q32, Z + 3 * j, rc2_32)) continue;
+            if (classes && lm[i] != ln[j]) continue;
+            near[c++] = j; /* c <= t: overwrites only entries already read */
+          }
+        }
+        qsort(near, (size_t)c, sizeof(int64_t), cmp_i64);
         for (int64_t t = 0; pass && t < c; ++t)
           if (o + t < cap) {
             pairs[2 * (o + t)] = (int32_t)i;
-            pairs[2 * (o + t) + 1] = (int32_t)js[t];
+            pairs[2 * (o + t) + 1] = (int32_t)near[t];
           }
-        free(js);
-        free(cand);
         if (!pass) cnt[i] = c;
-        continue;
       }
-      for (int64_t j = 0; j < Nn; ++j) {
-        if (!rule_inside(q32, Z + 3 * j, rc2_32)) continue;
-        if (classes && lm[i] != ln[j]) continue;
-        if (pass && o + c < cap) {
-          pairs[2 * (o + c)] = (int32_t)i;
-          pairs[2 * (o + c) + 1] = (int32_t)j;
-        }
-        ++c;
-      }
-      if (!pass) cnt[i] = c;
+      free(cand);
+      free(near);
     }
     if (!pass) { /* exclusive prefix sum: output offset of each source point */
       int64_t s = 0;
@@ -569,6 +746,7 @@ int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n,
       cnt[Nm] = s;
     }
   }
+  if (cells) cell_list_free(&cl);
   const int64_t total = cnt[Nm];
   free(cnt);
   return total;

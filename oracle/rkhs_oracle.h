@@ -26,6 +26,10 @@ extern "C" {
 
 enum { ORACLE_FEAT_CLASS = 0, ORACLE_FEAT_DENSE = 1 };
 enum { ORACLE_MEMBER_FP64 = 0, ORACLE_MEMBER_FP32_RULE = 1 };
+/* Neighbour search: every point pair (the definition), or the targets of the
+ * 27 world-coordinate cells around each source point (same pairs, sums in
+ * another order; see rkhs_oracle.c). */
+enum { ORACLE_SEARCH_BRUTE = 0, ORACLE_SEARCH_CELLS = 1 };
 
 typedef struct {
   int K;                       /* frames */
@@ -39,26 +43,28 @@ typedef struct {
   double sigma;                /* kernel amplitude */
   int clamp_negative_c;        /* use max(c, 0) */
   int top_k;                   /* > 0: each source point keeps its top_k largest-weight pairs */
+  int search;                  /* ORACLE_SEARCH_* */
 } oracle_problem;
 
-/* Loss F, b and H at `poses` (K*12), brute force over every point pair of
- * every edge.  membership: ORACLE_MEMBER_FP64 keeps pairs with r^2 <= r_c^2
+/* Loss F, b and H at `poses` (K*12), over every point pair of every edge
+ * (or, with the cell search, over each source point's 27 nearby cells).  membership: ORACLE_MEMBER_FP64 keeps pairs with r^2 <= r_c^2
  * in FP64 (the definition); ORACLE_MEMBER_FP32_RULE keeps the pairs of the
  * documented FP32 membership rule.  b, H, F_edge, n_pairs may be NULL.
- * Returns 0, or -1 on invalid arguments. */
+ * Returns 0, -1 on invalid arguments, or -2 when a world coordinate is too
+ * far out for the cell list's keys (cell search only). */
 int oracle_normal_eqs(const oracle_problem* P, const double* poses, int E, const int32_t* edges,
                       int membership, double* F, double* b, double* H, double* F_edge, int64_t* n_pairs);
 
 /* Per-edge F and W = sum over the kept pairs of w |u|^2 (u the world residual,
  * w = c exp(-|u|^2 / 2 ell^2), no sigma^2).  Edges may be self-pairs (m == n).
- * F_edge, W_edge: E doubles (nullable).  Returns 0 or -1. */
+ * F_edge, W_edge: E doubles (nullable).  Returns 0, -1, or -2 (as oracle_normal_eqs). */
 int oracle_edge_sums(const oracle_problem* P, const double* poses, int E, const int32_t* edges, int membership,
                      double* F_edge, double* W_edge);
 
 /* n_iter Gauss-Newton / IRLS steps in place on poses (frame `fixed_frame`
  * untouched).  loss_per_iter (n_iter+1, nullable) receives F at the poses
  * entering each step and after the last one.  Returns 0, -1 invalid,
- * -4 Cholesky failure. */
+ * -2 (as oracle_normal_eqs), -4 Cholesky failure. */
 int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edges, int n_iter,
               int fixed_frame, double damping_rel, int membership, double* loss_per_iter);
 
@@ -66,7 +72,7 @@ int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edge
  * the FP32 membership rule, in (i, j) order.  With class ids only pairs of
  * equal labels are listed; with top_k > 0 only each source point's top_k
  * pairs (c > 0, ranked by weight).  Writes at most cap pairs, returns the total
- * count (or -1). */
+ * count (or -1).  The list does not depend on the search mode. */
 int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n, int64_t cap, int32_t* pairs);
 
 /* Voxel structure of one frame: cell coordinates k = floor(x * inv_cell)

@@ -394,3 +394,107 @@ def test_voxel_sort_properties():
     kz = keys // (dims[0] * dims[1])
     np.testing.assert_array_equal(np.stack([kx, ky, kz], 1) + origin, k)
     assert np.all(k.min(0) - origin == 1) and np.all(dims - (k.max(0) - origin) - 1 == 1)
+
+
+# ----------------------------------------------------------------------------- one Gauss-Newton step
+
+def test_gn_step_is_the_damped_solve_with_right_update():
+    """One oracle step (Sec. V-A) equals, rebuilt from its own normal
+    equations with textbook routines: drop the fixed frame's rows and columns,
+    add mu I with mu = damping_rel tr(H_red) / dim(H_red), solve with numpy,
+    and move every other frame by T <- T expm(delta^) (right perturbation,
+    scipy expm).  Frame 1 is the fixed one and the damping is large enough to
+    matter; a left update, an undamped solve or the wrong fixed frame each
+    miss the result by far more than the tolerance."""
+    rng = np.random.default_rng(16)
+    P, pts, feats = dense_problem(rng, [60, 50, 40], ell=0.3, cutoff=3.0)
+    poses = np.stack([rand_pose(rng, 0.1, 0.1) for _ in range(3)])
+    edges = [[0, 1], [0, 2], [1, 2]]
+    fixed, damping = 1, 1e-2
+    F, b, H, _, _ = oracle.normal_eqs(P, poses, edges)
+    free = [0, 2]
+    idx = np.concatenate([np.arange(6 * f, 6 * f + 6) for f in free])
+    Hr, br = H[np.ix_(idx, idx)], b[idx]
+    mu = damping * np.trace(Hr) / len(idx)
+
+    def step(delta, right=True):
+        out = poses.copy()
+        for k, f in enumerate(free):
+            E = scipy.linalg.expm(wedge(delta[6 * k:6 * k + 6]))
+            out[f] = from44(to44(poses[f]) @ E if right else E @ to44(poses[f]))
+        return out
+
+    delta = np.linalg.solve(Hr + mu * np.eye(len(idx)), -br)
+    expect = step(delta)
+    got, lpi = oracle.gn(P, poses, edges, 1, fixed_frame=fixed, damping_rel=damping)
+    assert lpi[0] == pytest.approx(F, rel=1e-14)
+    assert lpi[1] == pytest.approx(oracle.loss(P, got, edges), rel=1e-14)
+    np.testing.assert_array_equal(got[fixed], poses[fixed])
+    np.testing.assert_allclose(got, expect, atol=1e-12)
+    assert np.abs(delta).max() > 1e-3  # a real step
+    # what a plausible mistake would give instead
+    wrong = {
+        "left update": step(delta, right=False),
+        "undamped": step(np.linalg.solve(Hr, -br)),
+    }
+    for what, alt in wrong.items():
+        assert np.abs(alt - got).max() > 1e-6, what
+    other, _ = oracle.gn(P, poses, edges, 1, fixed_frame=0, damping_rel=damping)
+    assert np.abs(other - got).max() > 1e-3
+
+
+def test_gn_step_frame_without_pairs_stays():
+    """A frame with no pair inside the radius gets delta = 0 (only the damping
+    sees its rows); the other frames still move."""
+    rng = np.random.default_rng(20)
+    P, pts, feats = dense_problem(rng, [50, 40, 30], ell=0.3, cutoff=3.0)
+    far = pts[2] + np.float32(100.0)
+    P = oracle.Problem([pts[0], pts[1], far], feats, "dense", 0.3, 3.0)
+    poses = np.stack([rand_pose(rng, 0.1, 0.1) for _ in range(3)])
+    got, _ = oracle.gn(P, poses, [[0, 1], [0, 2]], 1, fixed_frame=0, damping_rel=1e-6)
+    np.testing.assert_array_equal(got[2], poses[2])
+    assert np.abs(got[1] - poses[1]).max() > 1e-4
+
+
+def test_sigma_scales_the_loss_only():
+    """F carries sigma^2 (Eq. (eq:kernel)); b and H are defined with the
+    weights w = c k of Eq. (eq:irls_weight) and do not; the step is the same."""
+    rng = np.random.default_rng(21)
+    P1, pts, feats = dense_problem(rng, [60, 50, 40], ell=0.3, cutoff=3.0)
+    P2 = oracle.Problem(pts, feats, "dense", 0.3, 3.0, 1.7)
+    poses = np.stack([rand_pose(rng, 0.1, 0.1) for _ in range(3)])
+    edges = [[0, 1], [0, 2], [1, 2]]
+    F1, b1, H1, Fe1, n1 = oracle.normal_eqs(P1, poses, edges)
+    F2, b2, H2, Fe2, n2 = oracle.normal_eqs(P2, poses, edges)
+    assert n1 == n2 > 0
+    assert F2 == pytest.approx(1.7 ** 2 * F1, rel=1e-14)
+    np.testing.assert_allclose(Fe2, 1.7 ** 2 * Fe1, rtol=1e-14)
+    np.testing.assert_array_equal(b2, b1)
+    np.testing.assert_array_equal(H2, H1)
+    g1, _ = oracle.gn(P1, poses, edges, 2)
+    g2, l2 = oracle.gn(P2, poses, edges, 2)
+    np.testing.assert_array_equal(g2, g1)
+
+
+def test_gradient_matches_central_differences_with_sigma():
+    """grad_eps F = -(sigma^2/l^2) b with sigma = 1.7: central differences of
+    the loss against b of the normal equations."""
+    rng = np.random.default_rng(22)
+    pts = [rng.normal(size=(n, 3)).astype(np.float32) * 0.6 for n in (30, 25)]
+    feats = [rng.uniform(0.1, 1.0, size=(n, 4)).astype(np.float32) for n in (30, 25)]
+    sigma, ell = 1.7, 0.4
+    P = oracle.Problem(pts, feats, "dense", ell, 20.0, sigma)
+    poses = np.stack([rand_pose(rng, 0.1, 0.1) for _ in range(2)])
+    F, b, H, _, _ = oracle.normal_eqs(P, poses, [[0, 1]])
+    h = 1e-6
+    g = np.zeros(12)
+    for m in range(2):
+        for k in range(6):
+            xi = np.zeros(6)
+            xi[k] = h
+            pp, pm = poses.copy(), poses.copy()
+            pp[m] = right_perturb(poses[m], xi)
+            pm[m] = right_perturb(poses[m], -xi)
+            g[6 * m + k] = (oracle.loss(P, pp, [[0, 1]]) - oracle.loss(P, pm, [[0, 1]])) / (2 * h)
+    expect = -(sigma ** 2 / ell ** 2) * b
+    np.testing.assert_allclose(g, expect, rtol=2e-6, atol=2e-6 * np.abs(expect).max())
