@@ -70,7 +70,7 @@ def lib():
         L.oracle_normal_eqs.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp, dp, dp,
                                         ctypes.POINTER(ctypes.c_int64)]
         L.oracle_gn.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                ctypes.c_int, dp]
+                                ctypes.c_int, dp, dp]
         L.oracle_edge_sums.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp]
         L.oracle_pairs.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ip]
         L.oracle_pairs.restype = ctypes.c_int64
@@ -151,16 +151,20 @@ def loss(prob: Problem, poses, edges, membership=MEMBER_FP64):
     return normal_eqs(prob, poses, edges, membership)[0]
 
 
-def gn(prob: Problem, poses, edges, n_iter, fixed_frame=0, damping_rel=1e-10, membership=MEMBER_FP64):
-    """n_iter Gauss-Newton/IRLS steps (Sec. V-A); returns (poses, F per iteration)."""
+def gn(prob: Problem, poses, edges, n_iter, fixed_frame=0, damping_rel=1e-10, membership=MEMBER_FP64,
+       trace=False):
+    """n_iter Gauss-Newton/IRLS steps (Sec. V-A); returns (poses, F per iteration), and with trace=True
+    also the poses entering each step and after the last ((n_iter + 1, K, 12))."""
     poses = np.ascontiguousarray(poses, dtype=np.float64).reshape(prob.K, 12).copy()
     e = _edges(edges)
     lpi = np.zeros(n_iter + 1)
+    tr = np.zeros((n_iter + 1, prob.K, 12)) if trace else None
     rc = lib().oracle_gn(ctypes.byref(prob.c), _ptr(poses), len(e), _ptr(e, ctypes.c_int32), int(n_iter),
-                         int(fixed_frame), float(damping_rel), membership, _ptr(lpi))
+                         int(fixed_frame), float(damping_rel), membership, _ptr(lpi),
+                         _ptr(tr) if trace else ctypes.cast(None, ctypes.POINTER(ctypes.c_double)))
     if rc != 0:
         raise ValueError(f"oracle_gn failed ({rc})")
-    return poses, lpi
+    return (poses, lpi, tr) if trace else (poses, lpi)
 
 
 def edge_sums(prob: Problem, poses, edges, membership=MEMBER_FP64):

@@ -604,7 +604,7 @@ int oracle_cholesky_solve(int n, const double* A, const double* b, double* x) {
  * fixed one and moves T_m <- T_m exp(delta_m^).  The weights are recomputed
  * from the new poses before the next step. */
 int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edges, int n_iter,
-              int fixed_frame, double damping_rel, int membership, double* loss_per_iter) {
+              int fixed_frame, double damping_rel, int membership, double* loss_per_iter, double* pose_trace) {
   if (check_problem(P) || !poses || check_edges(P, E, edges) || n_iter < 0) return -1;
   if (fixed_frame < 0 || fixed_frame >= P->K || damping_rel < 0.0) return -1;
   const int K = P->K, n6 = 6 * K, nr = 6 * (K - 1);
@@ -622,6 +622,7 @@ int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edge
     status = oracle_normal_eqs(P, poses, E, edges, membership, &F, b, H, NULL, NULL);
     if (status) break;
     if (loss_per_iter) loss_per_iter[it] = F;
+    if (pose_trace) memcpy(pose_trace + (size_t)it * 12 * K, poses, sizeof(double) * 12 * K);
     if (it == n_iter || nr == 0) continue;
     double tr = 0.0;
     for (int r = 0; r < nr; ++r) {

@@ -63,10 +63,11 @@ int oracle_edge_sums(const oracle_problem* P, const double* poses, int E, const 
 
 /* n_iter Gauss-Newton / IRLS steps in place on poses (frame `fixed_frame`
  * untouched).  loss_per_iter (n_iter+1, nullable) receives F at the poses
- * entering each step and after the last one.  Returns 0, -1 invalid,
+ * entering each step and after the last one; pose_trace ((n_iter+1)*K*12,
+ * nullable) the poses at the same points.  Returns 0, -1 invalid,
  * -2 (as oracle_normal_eqs), -4 Cholesky failure. */
 int oracle_gn(const oracle_problem* P, double* poses, int E, const int32_t* edges, int n_iter,
-              int fixed_frame, double damping_rel, int membership, double* loss_per_iter);
+              int fixed_frame, double damping_rel, int membership, double* loss_per_iter, double* pose_trace);
 
 /* Point pairs (i, j) (original indices, i in frame m, j in frame n) kept by
  * the FP32 membership rule, in (i, j) order.  With class ids only pairs of

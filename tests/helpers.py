@@ -97,3 +97,15 @@ def e4m3_round(x):
     """float32 -> OCP fp8 e4m3 (bias 7: normal exponents -6..8, 3 fraction bits,
     subnormal step 2^-9), nearest even, saturating at 448, as float32."""
     return _round_to_grid(x, -6, 3, 448.0).astype(np.float32)
+
+
+def scene_digest(points, feats, poses, edges):
+    """SHA-256 of a workload's inputs (points, features, initial poses, edges), so that stored
+    expected values are only compared on the inputs they were computed from."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in list(points) + list(feats) + [poses, edges]:
+        a = np.ascontiguousarray(a)
+        h.update(str(a.dtype).encode() + str(a.shape).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()

@@ -305,6 +305,48 @@ def test_points_far_from_frame_origins(rk):
     say(f"[far] gn rot err {rot.max():.3g} trans err {tr.max():.3g}")
     assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
     np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+    # the RKHS distance and its lengthscale derivative (Sec. V-C), whose W = sum w |d|^2 also takes the
+    # first-order correction for the FP32 rounding of the transformed points
+    from oracle import lengthscale as ls
+    d, g = ctx.ell_gradient(init, p.edges)
+    od, og = ls.distance_and_derivative(lambda ell: oracle.Problem(pts, p.feats, p.feat_kind, ell, p.cutoff_factor),
+                                        p.ell, init, p.edges, oracle.MEMBER_FP32_RULE)
+    say(f"[far] d_H {d:.9g} / {od:.9g}, derivative {g:.9g} / {og:.9g} (rel {abs(g - og) / abs(og):.3g})")
+    assert abs(d - od) <= REL_TOL * abs(od) and abs(g - og) <= REL_TOL * abs(og)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,fixed,sigma,damping", [("odometry_small", 2, 1.7, 1e-3), ("two_view", 1, 0.6, 1e-10),
+                                                      ("lidar_k12", 5, 2.5, 1e-6)])
+def test_fixed_frame_sigma_and_damping_parity(rk, name, fixed, sigma, damping):
+    """Options the default parity cases leave at their defaults: the gauge
+    frame (Sec. V-A keeps the first frame fixed; any frame may be chosen), the
+    kernel amplitude sigma of Eq. (eq:kernel) (it scales F, not b or H) and the
+    relative damping of the step.  Loss, normal equations and Gauss-Newton
+    poses against the oracle run with the same options."""
+    p = SCENES[name]()
+    op = oracle.Problem(p.points, p.feats, p.feat_kind, p.ell, p.cutoff_factor, sigma)
+    ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, sigma=sigma, fixed_frame=fixed, damping_rel=damping)
+    ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+    F, Fe, npairs = ctx.eval_loss(p.init_poses, p.edges)
+    oF, ob, oH, oFe, onp = oracle.normal_eqs(op, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
+    assert npairs == onp and abs(F - oF) <= REL_TOL * abs(oF) and normwise_rel(Fe, oFe) <= REL_TOL
+    H, b, F2, n2 = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+    assert n2 == onp and abs(F2 - oF) <= REL_TOL * abs(oF)
+    assert_blocks_close(b, ob, 6, what=f"{name} b (sigma {sigma})")
+    assert_blocks_close(H, oH, 6, what=f"{name} H (sigma {sigma})")
+    n_iter = 3
+    poses, lpi, _ = ctx.gn_step(p.init_poses, p.edges, n_iter)
+    oposes, olpi = oracle.gn(op, p.init_poses, p.edges, n_iter, fixed_frame=fixed, damping_rel=damping,
+                             membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(poses, oposes)
+    moved = max(np.abs(oposes[k] - p.init_poses[k]).max() for k in range(p.K) if k != fixed)
+    say(f"[options] {name} fixed {fixed} sigma {sigma} damping {damping}: rot err {rot.max():.3g} "
+        f"trans err {tr.max():.3g}, F {lpi[-1]:.9g} / {olpi[-1]:.9g}, largest move {moved:.3g}")
+    np.testing.assert_array_equal(poses[fixed], p.init_poses[fixed])
+    assert moved > 1e-4
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
     ctx.close()
 
 
