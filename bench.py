@@ -1,26 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the RKHS-BA hot path on one MI355X.
 
-One step = one whole solve of the odometry workload: the voxel build of all
-frames from device-resident clouds (rkhsba_build_neighbors) followed by the
-Gauss-Newton / IRLS iterations (rkhsba_gn_step: per iteration, transforms,
+One step = one whole solve of the LiDAR-mapping workload: the voxel build of
+all frames from device-resident clouds (rkhsba_build_neighbors) followed by
+the Gauss-Newton / IRLS iterations (rkhsba_gn_step: per iteration, transforms,
 binning, candidate sweep, finalisation, assembly, Cholesky and pose update,
-plus the final loss evaluation).  Workload: 8 depth-camera frames x 30,000
-points, 23-dim features (20-class Dirichlet(0.3) soft label + RGB), all 28
-frame pairs, ell = 0.08 m, cutoff 3 ell, 15 iterations (seeded synthetic
-scene).
+plus the final loss evaluation).  Workload: 64 spinning-LiDAR frames x
+100,000 points over a 200 m street loop, 20% uniform outliers, 20-class
+one-hot labels with 10% flipped, each frame paired with its 6 nearest poses
+(384 directed pairs), ell = 0.3 m, cutoff 3 ell, 10 iterations (seeded
+synthetic scene).  --workload selects the other configurations (odometry,
+dense64, two_view) for kernel studies.
 
 The printed JSON line reports pair evaluations per second (in-radius pairs
 with c != 0, summed over every evaluation of the step), Gauss-Newton
 iterations per second, the roofline position of the candidate-sweep kernel
-measured with HIP events on the library's stream, and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+measured with HIP events on the library's stream, the voxel build's
+bandwidth, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
 import json
 import os
-import re
 import sys
 import time
 
@@ -34,7 +36,8 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 FLOPS_PER_PAIR_GEOM = 30
 # the sweep kernel and the engine that lays out its pass table (the pass order changes the kernel's traffic)
 PAIR_KERNEL_SOURCES = [os.path.join(ROOT, "paper_2403_01254_amd", "csrc", f) for f in ("sweep.hip", "engine.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_odometry_traffic.json")
+# calibrated HBM bytes per sweep launch from rocprofv3 counters, per workload (profiles/)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_{workload}_traffic.json")
 WORKLOADS = {
     "odometry": "odometry: 8 depth-camera frames x 30,000 points, 23-dim soft-label+RGB features, all 28 frame "
                 "pairs, ell=0.08 m, cutoff 3 ell, 15 Gauss-Newton iterations (one step = voxel build + 15 "
@@ -56,17 +59,52 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(workload, config):
     """HBM bytes per launch of the sweep kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary of this workload, if it was taken on the current kernel
+    source in the same launch configuration."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload=workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("config") != list(config):
         return None
     return t.get("bytes_per_launch")
+
+
+def cpu_info():
+    """Host description for the CPU baseline: CPUs this process may use and the model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def build_bytes_per_point(p, cell_subdiv, kind, Dp):
+    """Bytes the voxel build's kernels read and write per point, by design: cell coordinates (read xyz
+    12, write 12), keys and values (read 12, write 8), each 8-bit digit pass of the radix sort (histogram
+    read 4, scatter read 8 + write 8), the gather into key order (read value 4 + xyz 12 + feature, write
+    point 16 + index 4 + stored feature), the key copy (8), and the row extents and cell tables (read
+    keys 4 + 4).  Digit passes: ceil(key bits / 8) of the largest frame grid."""
+    import math
+    import numpy as np
+    inv = 1.0 / ((p.cutoff_factor * p.ell) / cell_subdiv)
+    cells = 1
+    for x in p.points:
+        k = np.floor(x.astype(np.float64) * inv)
+        cells = max(cells, int(np.prod(k.max(0) - k.min(0) + 1)))
+    key_bits = max(1, math.ceil(math.log2(cells)))
+    passes = math.ceil(key_bits / 8)
+    feat_in = 2 if kind == "class" else 4 * p.D
+    feat_out = 0 if kind == "class" else {"dense": 4, "bf16": 2, "fp8": 1}[kind] * Dp
+    return 24 + 20 + 20 * passes + (4 + 12 + feat_in + 16 + 4 + feat_out) + 8 + 8, passes
 
 
 def _make_request(seed):
@@ -83,6 +121,17 @@ def start_request_generation(n, workers):
         return None, []
     ex = concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn"))
     return ex, [ex.submit(_make_request, 1000 + i) for i in range(n)]
+
+
+def stop_request_generation(ex):
+    """Joins the worker pool and the resource-tracker process that multiprocessing starts for its queues
+    (it would otherwise outlive the pool until this process exits)."""
+    ex.shutdown(wait=True)
+    try:
+        from multiprocessing import resource_tracker
+        resource_tracker._resource_tracker._stop()
+    except (ImportError, AttributeError, OSError):
+        pass
 
 
 def percentile_ms(lat, q):
@@ -219,24 +268,32 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
                       "resident in HBM; Poisson arrivals at 0.5x and 0.9x of the measured one-at-a-time capacity"}
 
 
-def cpu_baseline(p, n_edges, min_seconds=10.0, max_repeats=5):
-    """The oracle timed on the host cores: normal-equation evaluations (loss, b, H; brute force over all point
-    pairs, FP64) of the first n_edges frame pairs at the initial poses, repeated until min_seconds have passed."""
+def cpu_baseline(p, workload, reps=5):
+    """The oracle timed on the host cores: normal-equation evaluations (loss, b, H; FP64) of a fixed sample
+    of the workload's frame pairs at the initial poses, one warm-up then `reps` timed runs; the value is
+    the pairs of one evaluation over the median time.  Brute force over all point pairs (the definition)
+    where that finishes in seconds, else the oracle's cell-list search (the same pairs and sums)."""
+    import numpy as np
     import oracle
-    op = oracle.Problem.from_scene(p)
-    edges = p.edges[:n_edges]
-    t0 = time.perf_counter()
-    pairs, reps = 0, 0
-    while reps < max_repeats and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+    stride, search = {"lidar": (48, "cells"), "dense64": (4, "cells"), "odometry": (4, "brute")}.get(
+        workload, (1, "brute"))
+    op = oracle.Problem.from_scene(p, search=search)
+    edges = p.edges[::stride]
+    times = []
+    for r in range(reps + 1):
+        t0 = time.perf_counter()
         _, _, _, _, npairs = oracle.normal_eqs(op, p.init_poses, edges)
-        pairs += npairs
-        reps += 1
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} normal-equation evaluation(s) (loss, b, H; brute force over all point pairs, FP64) of "
-                      f"{len(edges)} of the {len(p.edges)} frame pairs at the initial poses: {pairs} in-radius "
-                      f"pairs in {dt:.2f} s"}
+        if r > 0:
+            times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    nproc, model = cpu_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
+    mode = "brute force over all point pairs" if search == "brute" else "cell-list search (27 world cells per point)"
+    return {"value": npairs / med, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model, "search": search,
+            "sample": f"median of {reps} normal-equation evaluations (loss, b, H; FP64, {mode}) after one warm-up, "
+                      f"of {len(edges)} of the {len(p.edges)} frame pairs (every {stride}th) at the initial poses: "
+                      f"{npairs} in-radius pairs in {med:.3f} s (runs {min(times):.3f}-{max(times):.3f} s)"}
 
 
 def main():
@@ -252,11 +309,9 @@ def main():
     ap.add_argument("--moment-path", type=int, default=0, help="0 library choice, 1 vector ALU, 2 matrix cores")
     ap.add_argument("--features", default="f32", choices=["f32", "bf16", "fp8"],
                     help="storage / inner-product precision of dense features (bf16, fp8: matrix cores)")
-    ap.add_argument("--workload", default="odometry", choices=["odometry", "lidar", "two_view", "dense64"],
-                    help="odometry is the headline configuration; the others are for kernel studies")
-    ap.add_argument("--cpu-edges", type=int, default=-1,
-                    help="frame pairs in the CPU oracle sample (0: skip; default: all 28 for odometry and dense64, "
-                         "2 for lidar, 1 for two_view)")
+    ap.add_argument("--workload", default="lidar", choices=["lidar", "odometry", "two_view", "dense64"],
+                    help="lidar is the headline configuration; the others are for kernel studies")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48,
                     help="requests in the serving measurement (0: skip); the serving workload's full stream is 512")
@@ -353,10 +408,14 @@ def main():
     flops_per_pair = FLOPS_PER_PAIR_GEOM + (2 * p.D if kind == "dense" else 0)
     mean_launch_s = pair_ms / max(pair_launches, 1) / 1e3
     achieved = flops_per_pair * gn_pairs_per_launch / mean_launch_s / 1e12 if mean_launch_s > 0 else 0.0
-    # the committed counters were taken on the odometry sweep in this configuration only
-    profiled = (args.workload == "odometry" and kind == "dense" and (cfg_subdiv, cfg_pass) == (8, 16)
-                and args.moment_path in (0, 1))
-    traffic = load_traffic() if profiled else None
+    # committed counters hold for the workload, feature storage and launch configuration they were taken on
+    traffic = load_traffic(args.workload, [kind, cfg_subdiv, cfg_pass]) if args.moment_path in (0, 1) else None
+    # voxel build bandwidth: bytes its kernels move by design over the measured build time
+    build_ms, build_n = prof["build"]
+    Dp = 0 if kind == "class" else next(w for w in ((8, 16, 24, 32, 64) if kind == "dense" else (32, 64)) if w >= p.D)
+    bpp, sort_passes = build_bytes_per_point(p, cfg_subdiv, kind, Dp)
+    n_points = int(sum(len(x) for x in p.points))
+    build_s = build_ms / max(build_n, 1) / 1e3
 
     result = {
         "metric": METRIC,
@@ -382,6 +441,8 @@ def main():
         "graph_replay_ms_per_step": graph_ms,
         "pairs_per_step": pairs_total // args.steps,
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "build": {"ms": build_s * 1e3, "points": n_points, "bytes_per_point": bpp, "sort_digit_passes": sort_passes,
+                  "GB_per_s": bpp * n_points / build_s / 1e9 if build_s > 0 else None, "peak_GB_per_s": 8000.0},
         "roofline": {
             "bound": "alu",
             "kernel": "k_sweep (candidate sweep, Gauss-Newton moments)" if cfg_pass in (8, 16) else "k_pairs (candidate sweep, Gauss-Newton moments)",
@@ -396,10 +457,10 @@ def main():
         },
     }
     rank = int(os.environ.get("RANK", "0"))
-    cpu_edges = args.cpu_edges if args.cpu_edges >= 0 else {"lidar": 2, "two_view": 1}.get(args.workload, 28)
-    if rank == 0 and cpu_edges > 0:
-        log(f"[bench] CPU oracle on {cpu_edges} frame pairs ...")
-        result["cpu_baseline"] = cpu_baseline(p, cpu_edges)
+    if rank == 0 and not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        result["cpu_baseline"] = cpu_baseline(p, args.workload)
+        log(f"[bench] CPU oracle: {result['cpu_baseline']['sample']}")
     # serving requests are generated only now, so that no worker process competes with the timed regions above
     gen_pool, gen_futures = start_request_generation(args.serving_requests, workers=8)
     if gen_futures:
@@ -408,7 +469,7 @@ def main():
             reqs.append(f.result())
             if (i + 1) % 32 == 0 and i + 1 < len(gen_futures):
                 log(f"[bench] serving: {i + 1} of {len(gen_futures)} requests generated")
-        gen_pool.shutdown()
+        stop_request_generation(gen_pool)
         log(f"[bench] serving: {len(reqs)} requests generated")
         result["serving"] = serving_benchmark(reqs, rkhsba, torch, log, lanes=args.serving_lanes,
                                               work_entries=args.serving_work_entries)

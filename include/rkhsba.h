@@ -250,6 +250,14 @@ int rkhsba_rotation_search(rkhsba_ctx* ctx, const double* poses, int m, int n, i
 int rkhsba_export_pairs(rkhsba_ctx* ctx, const double* poses, int m, int n, int64_t cap, int32_t* pairs,
                         int64_t* n_out);
 
+/* Debug/parity: how many pairs of edge (m, n) at `poses` each source point has
+ * inside the truncation radius with c_ij != 0 (Eq. (eq:double_sum) truncated as
+ * in Sec. III-B), as counted by the same candidate sweep (launch shape, cell
+ * size, pass table) that sums them in rkhsba_accumulate_normal_eqs: the sweep
+ * runs once with each source point's own count written out.  counts: N_m
+ * int64, indexed by the original point index of frame m (host buffer). */
+int rkhsba_export_source_counts(rkhsba_ctx* ctx, const double* poses, int m, int n, int64_t* counts);
+
 /* Debug/parity: the voxel structure of one frame.  perm (N_m int32): sorted
  * position -> original index; keys (N_m uint32): sorted cell keys; origin[3],
  * dims[3]: the frame's cell grid.  Any pointer may be NULL. */

@@ -747,6 +747,27 @@ int rkhsba_export_pairs(rkhsba_ctx* c, const double* poses, int m, int n, int64_
   });
 }
 
+int rkhsba_export_source_counts(rkhsba_ctx* c, const double* poses, int m, int n, int64_t* counts) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    Engine& g = *c->eng;
+    RK_REQUIRE(m >= 0 && n >= 0 && m < p->K && n < p->K && m != n, RKHSBA_EINVAL, "bad frame pair");
+    RK_REQUIRE(counts != nullptr, RKHSBA_EINVAL, "counts is NULL");
+    const int32_t edge[2] = {m, n};
+    g.prepare(c->lay_eval, {SetItem{p, edge, 1, -1, 0}});
+    g.upload_poses(p, poses);
+    g.source_counts = true;
+    struct Reset {
+      Engine& g;
+      ~Reset() { g.source_counts = false; }
+    } reset{g};
+    g.evaluate(c->lay_eval, MODE_NORMAL);
+    g.read_source_counts(p, m, counts);
+    g.prof_collect();
+    return RKHSBA_OK;
+  });
+}
+
 int rkhsba_export_voxels(rkhsba_ctx* c, int frame, int32_t* perm, uint32_t* keys, int32_t* origin, int32_t* dims) {
   return guarded(c, [&]() -> int {
     Problem* p = resident(c);

@@ -213,6 +213,7 @@ class Engine {
   int moment_path;
   bool use_graphs = true;
   bool fp32_sums = false;  // per-edge normal-equation sums in FP32 with Kahan compensation (else FP64)
+  bool source_counts = false;  // sweeps write every source point's own pair count (parity checks)
 
   // feature layout shared by all resident problems
   int feat_kind = -1, D = 0, Dp = 0;
@@ -269,6 +270,9 @@ class Engine {
 
   // results
   void read_history(Problem* p, int count, double* loss, double* pairs);  // synchronises
+  // After an evaluation with source_counts on, of a set whose first edge has source frame m of p:
+  // every source point's pair count, by its original index (frame m's point count; synchronises).
+  void read_source_counts(Problem* p, int m, int64_t* counts);
   int32_t read_status(Problem* p);                                         // synchronises
   const double* edge_out() const { return edge_out_.p; }
 

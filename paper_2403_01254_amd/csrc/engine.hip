@@ -649,6 +649,23 @@ void Engine::read_history(Problem* p, int count, double* loss, double* pairs) {
   RK_HIP(hipStreamSynchronize(st));
 }
 
+void Engine::read_source_counts(Problem* p, int m, int64_t* counts) {
+  RK_REQUIRE(m >= 0 && m < p->K && sorted_k_ && sorted_v_, RKHSBA_ESTATE, "no evaluation to read");
+  const FrameInfo& F = p->frames[m];
+  std::vector<uint32_t> c(F.n), k(F.n), v(F.n);
+  std::vector<int32_t> perm(F.n);
+  RK_HIP(hipMemcpyAsync(c.data(), cnt_.p, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(k.data(), sorted_k_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(v.data(), sorted_v_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(perm.data(), this->perm() + F.pt_off, sizeof(int32_t) * F.n, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipStreamSynchronize(st));
+  for (int32_t i = 0; i < F.n; ++i) counts[i] = 0;
+  for (int32_t e = 0; e < F.n; ++e) {
+    RK_REQUIRE(v[e] < (uint32_t)F.n, RKHSBA_EDEVICE, "binning value out of range");
+    counts[perm[v[e]]] = k[e] == kInvalidKey ? 0 : (int64_t)c[e];
+  }
+}
+
 int32_t Engine::read_status(Problem* p) {
   int32_t s[2] = {0, 0};
   RK_HIP(hipMemcpyAsync(s, static_cast<int32_t*>(state_.ptr(0)) + 2 * p->sbase, sizeof(s), hipMemcpyDeviceToHost,
@@ -929,7 +946,8 @@ void Engine::evaluate(SetLayout& lay, int mode) {
     pa.pass0 = gr.pass0;
     pa.n_pass = gr.n_pass;
     if (gr.pass_points == 16 || gr.pass_points == 8)
-      RK_HIP(launch_sweep(pa, mode, feat_path, gr.pass_points, moment_path == 2, st));
+      RK_HIP(launch_sweep(pa, mode, feat_path, gr.pass_points, moment_path == 2 && !source_counts,
+                          source_counts && mode == MODE_NORMAL, st));
     else
       RK_HIP(launch_pairs(pa, mode, feat_path, gr.pass_points, gr.topk, st));
   }

@@ -171,9 +171,11 @@ struct PairArgs {
 // 8 (class ids) and 16 (launch_sweep), 32, 64 = shared walk over the pass's box.
 hipError_t launch_pairs(const PairArgs& a, int mode, int feat_path, int pass_points, bool topk, hipStream_t st);
 
-// Tiled sweep for passes of 16 sources, or 8 with class ids.
+// Tiled sweep for passes of 16 sources, or 8 with class ids.  source_counts (Gauss-Newton moments on the
+// VALU only): each entry of a.cnt receives its own source point's pair count instead of the pass total on
+// the pass's first entry (the per-edge sums are the same).
 hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_points, bool matrix_moments,
-                        hipStream_t st);
+                        bool source_counts, hipStream_t st);
 
 struct FinArgs {
   const float4* pts;

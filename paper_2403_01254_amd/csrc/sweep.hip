@@ -130,7 +130,10 @@ __device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s
 //   A = M_1, B = A v - M_u, C = A v v^T - v M_u^T - M_u v^T + M_uu.
 // CM: the inner products as computed (0), negative ones clamped to 0 (1), or
 // known to be positive (2: the pair count then needs no c != 0 test).
-template <int MODE, int FEAT, int DP, int CM, bool MM, int P>
+// SC: every source point's own pair count goes to its entry of a.cnt (one more
+// VALU add per candidate; for parity checks of the pair set), instead of the
+// pass's count on its first entry (the per-edge totals are the same).
+template <int MODE, int FEAT, int DP, int CM, bool MM, int P, bool SC = false>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // P source points per pass (16, or 8 for class ids); lane (s, g) takes CPL candidates of every
   // 16-candidate sub-tile
@@ -232,6 +235,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Wr2 = 0.f;
   uint32_t cnt = 0;
+  uint32_t own = 0;  // SC: this lane's pairs
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
   const float* __restrict__ tf = static_cast<const float*>(a.feat) + Fn.pt_off * (FEAT == FEAT_DENSE ? DP : 0);
   const uint8_t* __restrict__ tl = static_cast<const uint8_t*>(a.feat) + Fn.pt_off * (int64_t)(LP ? ROWB : 0);
@@ -379,9 +383,15 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           }
           const float k = __builtin_amdgcn_exp2f(-alpha * s2);
           const float w = in ? c * k : 0.f;
-          // pairs counted per pass from the wavefront's lane masks (scalar unit)
-          if constexpr (FEAT == FEAT_CLASS || CM == 2) cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
-          else cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
+          // pairs counted per pass from the wavefront's lane masks (scalar unit), or per lane (SC)
+          if constexpr (SC) {
+            if constexpr (FEAT == FEAT_CLASS || CM == 2) own += in ? 1u : 0u;
+            else own += (in && c != 0.f) ? 1u : 0u;
+          } else if constexpr (FEAT == FEAT_CLASS || CM == 2) {
+            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
+          } else {
+            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
+          }
           if constexpr (MM) {
             macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
           } else {
@@ -429,8 +439,14 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Wr2 += __shfl_xor(Wr2, o, 64);
     }
   }
-  // the pass's pair count goes to its first entry, zeros to the others
-  if (g == 0 && in_range) a.cnt[entry] = s == 0 ? cnt : 0u;
+  if constexpr (SC) {
+#pragma unroll
+    for (int o = P; o < 64; o <<= 1) own += __shfl_xor(own, o, 64);
+    if (g == 0 && in_range) a.cnt[entry] = valid ? own : 0u;
+  } else {
+    // the pass's pair count goes to its first entry, zeros to the others
+    if (g == 0 && in_range) a.cnt[entry] = s == 0 ? cnt : 0u;
+  }
   if (g == 0 && valid) {
     const int64_t N = a.n_entries;
     a.mom[entry] = A;
@@ -442,41 +458,41 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   }
 }
 
-template <int MODE, int FEAT, int CM, bool MM>
+template <int MODE, int FEAT, int CM, bool MM, bool SC>
 hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, 0, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    k_sweep<MODE, FEAT, 0, 0, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
   } else if constexpr (feat_low_precision(FEAT)) {
-    if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
   } else {
-    if (DP <= 8) k_sweep<MODE, FEAT, 8, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
-    else k_sweep<MODE, FEAT, 64, CM, MM, 16><<<nb, kLanes, 0, st>>>(a);
+    if (DP <= 8) k_sweep<MODE, FEAT, 8, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 16) k_sweep<MODE, FEAT, 16, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 24) k_sweep<MODE, FEAT, 24, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    else if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 64, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
   }
   return hipGetLastError();
 }
 
 // clamped, known-positive (FP32 features, VALU moments) or plain inner products
-template <int MODE, int FEAT, bool MM>
+template <int MODE, int FEAT, bool MM, bool SC>
 hipError_t dispatch_clamp(const PairArgs& a, hipStream_t st) {
-  if (a.kc.clamp) return dispatch<MODE, FEAT, 1, MM>(a, a.kc.Dp, st);
+  if (a.kc.clamp) return dispatch<MODE, FEAT, 1, MM, SC>(a, a.kc.Dp, st);
   if constexpr (FEAT == FEAT_DENSE && !MM)
-    if (a.kc.c_positive) return dispatch<MODE, FEAT, 2, MM>(a, a.kc.Dp, st);
-  return dispatch<MODE, FEAT, 0, MM>(a, a.kc.Dp, st);
+    if (a.kc.c_positive) return dispatch<MODE, FEAT, 2, MM, SC>(a, a.kc.Dp, st);
+  return dispatch<MODE, FEAT, 0, MM, SC>(a, a.kc.Dp, st);
 }
 
-template <int MODE, bool MM>
+template <int MODE, bool MM, bool SC>
 hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
   switch (feat_path) {
-    case FEAT_CLASS: return dispatch<MODE, FEAT_CLASS, 0, MM>(a, 0, st);
-    case FEAT_DENSE: return dispatch_clamp<MODE, FEAT_DENSE, MM>(a, st);
-    case FEAT_BF16: return dispatch_clamp<MODE, FEAT_BF16, MM>(a, st);
-    default: return dispatch_clamp<MODE, FEAT_FP8, MM>(a, st);
+    case FEAT_CLASS: return dispatch<MODE, FEAT_CLASS, 0, MM, SC>(a, 0, st);
+    case FEAT_DENSE: return dispatch_clamp<MODE, FEAT_DENSE, MM, SC>(a, st);
+    case FEAT_BF16: return dispatch_clamp<MODE, FEAT_BF16, MM, SC>(a, st);
+    default: return dispatch_clamp<MODE, FEAT_FP8, MM, SC>(a, st);
   }
 }
 
@@ -485,16 +501,19 @@ hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
 // Tiled sweep for passes of 16 source points (8 for class ids on request).
 // Loss-only sums stay on the VALU; Gauss-Newton moments on the VALU or the matrix cores.
 hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_points, bool matrix_moments,
-                        hipStream_t st) {
+                        bool source_counts, hipStream_t st) {
+  if (source_counts && (mode != MODE_NORMAL || matrix_moments)) return hipErrorInvalidValue;
   if (pass_points == 8) {
     if (feat_path != FEAT_CLASS || a.n_pass == 0) return feat_path != FEAT_CLASS ? hipErrorInvalidValue : hipSuccess;
-    if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true><<<a.n_pass, kLanes, 0, st>>>(a);
+    else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
     else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
     return hipGetLastError();
   }
-  if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false>(a, feat_path, st);
-  return matrix_moments ? dispatch_mode<MODE_NORMAL, true>(a, feat_path, st)
-                        : dispatch_mode<MODE_NORMAL, false>(a, feat_path, st);
+  if (source_counts) return dispatch_mode<MODE_NORMAL, false, true>(a, feat_path, st);
+  if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false, false>(a, feat_path, st);
+  return matrix_moments ? dispatch_mode<MODE_NORMAL, true, false>(a, feat_path, st)
+                        : dispatch_mode<MODE_NORMAL, false, false>(a, feat_path, st);
 }
 
 }  // namespace rkhsba

@@ -124,6 +124,7 @@ def lib():
         L.rkhsba_gn_step.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _dp, _i64p]
         L.rkhsba_export_pairs.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _i64p]
         L.rkhsba_export_voxels.argtypes = [vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), _i32p, _i32p]
+        L.rkhsba_export_source_counts.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, _i64p]
         L.rkhsba_autotune.argtypes = [vp, ctypes.c_int, _i64p, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(vp), ctypes.c_int, _dp, ctypes.c_int, _i32p, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
@@ -314,6 +315,14 @@ class Context:
         self._check(lib().rkhsba_export_pairs(self._h, _p(p), int(m), int(n), total.value, _p(out, ctypes.c_int32),
                                               ctypes.byref(total)))
         return out[:total.value]
+
+    # -- rkhsba_export_source_counts
+    def export_source_counts(self, poses, m, n, n_points):
+        """Pair count of every source point of edge (m, n), from the sweep that sums the pairs."""
+        p = self._poses(poses)
+        out = np.zeros(int(n_points), dtype=np.int64)
+        self._check(lib().rkhsba_export_source_counts(self._h, _p(p), int(m), int(n), _p(out, ctypes.c_int64)))
+        return out
 
     # -- rkhsba_export_voxels
     def export_voxels(self, frame, n_points):
@@ -524,6 +533,10 @@ def rkhsba_gn_step(ctx: Context, poses, edges, n_iter):
 
 def rkhsba_export_pairs(ctx: Context, poses, m, n):
     return ctx.export_pairs(poses, m, n)
+
+
+def rkhsba_export_source_counts(ctx: Context, poses, m, n, n_points):
+    return ctx.export_source_counts(poses, m, n, n_points)
 
 
 def rkhsba_export_voxels(ctx: Context, frame, n_points):

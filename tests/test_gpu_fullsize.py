@@ -24,7 +24,6 @@ import numpy as np
 import pytest
 
 import oracle
-import scenes
 from helpers import REL_TOL, assert_blocks_close, bf16_round, e4m3_round, pose_errors
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
@@ -47,15 +46,13 @@ def rk():
 
 
 @pytest.fixture(scope="module")
-def odometry():
-    say("[fullsize] generating odometry (8 x 30,000)")
-    return scenes.odometry(0)
+def odometry(full_scenes):
+    return full_scenes.get("odometry")
 
 
 @pytest.fixture(scope="module")
-def lidar():
-    say("[fullsize] generating lidar (64 x 100,000)")
-    return scenes.lidar(0)
+def lidar(full_scenes):
+    return full_scenes.get("lidar")
 
 
 def context(rk, p, workload, feat_kind=None, points=None, feats=None):
@@ -136,9 +133,28 @@ def test_lidar_full_size_gauss_newton(rk, lidar):
     ctx.close()
 
 
+def test_sweep_source_counts_full_size(rk, odometry, lidar):
+    """Per-source pair counts written by the summing sweep itself (16-point passes on odometry, 8-point
+    passes on LiDAR, the benchmark's configurations), against the oracle's FP32-rule pair lists, point by
+    point, on sampled edges at full size (LiDAR lists from the oracle's cell-list search, which gives the
+    brute-force lists)."""
+    for name, p, sample, search in (("odometry", odometry, [0, 13, 27], "brute"), ("lidar", lidar, [0, 191], "cells")):
+        ctx = context(rk, p, name)
+        op = oracle.Problem.from_scene(p, search=search)
+        for idx in sample:
+            m, n = (int(v) for v in p.edges[idx])
+            got = ctx.export_source_counts(p.init_poses, m, n, len(p.points[m]))
+            ref = np.bincount(oracle.pairs(op, p.init_poses, m, n)[:, 0], minlength=len(p.points[m]))
+            say(f"[fullsize] {name} edge {idx} ({m},{n}): {got.sum()} pairs over {np.count_nonzero(ref)} source "
+                f"points, per-source counts equal: {np.array_equal(got, ref)}")
+            assert ref.sum() > 0
+            np.testing.assert_array_equal(got, ref)
+        ctx.close()
+
+
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
-def test_dense64_full_size_sampled_edge(rk, kind):
-    p = scenes.dense64(0)
+def test_dense64_full_size_sampled_edge(rk, kind, full_scenes):
+    p = full_scenes.get("dense64")
     rounded = [(bf16_round if kind == "bf16" else e4m3_round)(f) for f in p.feats]
     ctx = context(rk, p, "dense64", feat_kind=kind)
     check_edges(ctx, p, [0, 14], REL_TOL if kind == "bf16" else FP8_MFMA_TOL, feats=rounded, kind="dense",

@@ -125,6 +125,44 @@ def test_gauss_newton_parity(rk, scene):
     np.testing.assert_array_equal(poses[0], p.init_poses[0])  # the fixed frame does not move
 
 
+# scenes whose inner products are decided exactly on both sides (class ids, or features that are all
+# positive): a pair's c != 0 test cannot differ between the GPU's FP32 sums and the oracle's FP64 ones
+COUNT_SCENES = ["two_view_ragged", "odometry_small", "lidar_small", "lidar_k12"]
+_scene_cache = {}
+
+
+def scene_named(name):
+    if name not in _scene_cache:
+        _scene_cache[name] = SCENES[name]()
+    return _scene_cache[name]
+
+
+@pytest.mark.parametrize("pass_points,subdiv", [(16, 8), (16, 1), (8, 2), (8, 1), (32, 2), (64, 1), (1, 1), (1, 3)])
+def test_sweep_source_counts_bit_exact(rk, pass_points, subdiv):
+    """The pair set of the truncated double sum (Eq. (eq:double_sum), Sec. III-B) as the summing sweep
+    itself enumerates it: every source point's count of in-radius pairs with c != 0, written by the same
+    sweep launch (pass size, cell size, pass table) that accumulates the normal equations, equals the
+    oracle's count from its brute-force FP32-rule pair list, point by point."""
+    for name in COUNT_SCENES:
+        p = scene_named(name)
+        if pass_points == 8 and p.feat_kind != "class":
+            continue  # 8-point passes take class ids only
+        op = oracle.Problem.from_scene(p)
+        ctx = make_ctx(rk, p, pass_points=pass_points, cell_subdiv=subdiv)
+        assert ctx.config()[:2] == (subdiv, pass_points)
+        for poses in (p.init_poses, p.gt_poses):
+            for (m, n) in p.edges[:2]:
+                got = ctx.export_source_counts(poses, m, n, len(p.points[m]))
+                ref = np.bincount(oracle.pairs(op, poses, m, n)[:, 0], minlength=len(p.points[m]))
+                assert ref.sum() > 0
+                np.testing.assert_array_equal(got, ref)
+                # the same sweep's per-edge total, as the normal equations report it
+                _, _, _, npairs = ctx.accumulate_normal_eqs(poses, [[m, n]])
+                assert npairs == ref.sum()
+        say(f"[counts] {name} pass {pass_points} subdiv {subdiv}: per-source counts equal")
+        ctx.close()
+
+
 @pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1), (1, 1), (1, 3), (8, 1),
                                                 (8, 3)])
 def test_launch_shapes_agree(rk, pass_points, subdiv):
