@@ -46,6 +46,20 @@ __device__ inline float uniform_f(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Minimum / maximum over the P consecutive lanes of each lane group (P a power of two <= 64).
+template <int P>
+__device__ inline float group_min(float v) {
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int P>
+__device__ inline float group_max(float v) {
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ inline uint32_t wave_inclusive_scan(uint32_t v, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -201,13 +215,15 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       }
     }
   }
+  // box of the pass's transformed points: every group of P lanes holds all P sources, so the
+  // reduction runs over the P lanes of a group only
   float3 lo, hi;
-  lo.x = uniform_f(wave_min(valid ? q.x : FLT_MAX));
-  lo.y = uniform_f(wave_min(valid ? q.y : FLT_MAX));
-  lo.z = uniform_f(wave_min(valid ? q.z : FLT_MAX));
-  hi.x = uniform_f(wave_max(valid ? q.x : -FLT_MAX));
-  hi.y = uniform_f(wave_max(valid ? q.y : -FLT_MAX));
-  hi.z = uniform_f(wave_max(valid ? q.z : -FLT_MAX));
+  lo.x = uniform_f(group_min<P>(valid ? q.x : FLT_MAX));
+  lo.y = uniform_f(group_min<P>(valid ? q.y : FLT_MAX));
+  lo.z = uniform_f(group_min<P>(valid ? q.z : FLT_MAX));
+  hi.x = uniform_f(group_max<P>(valid ? q.x : -FLT_MAX));
+  hi.y = uniform_f(group_max<P>(valid ? q.y : -FLT_MAX));
+  hi.z = uniform_f(group_max<P>(valid ? q.z : -FLT_MAX));
   if (!(lo.x <= hi.x)) {  // no valid source point in this pass (uniform)
     if (g == 0 && in_range) a.cnt[entry] = 0u;
     return;
@@ -374,7 +390,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           const float4 z = z4[rr];
           float dx, dy, dz;
           const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
-          bool in = s2 <= rc2;
+          const bool near = s2 <= rc2;
+          bool in = near;
           float c = 1.f;
           if constexpr (FEAT == FEAT_CLASS) {
             in = in && (__float_as_uint(z.w) == lbl);
@@ -387,7 +404,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           if constexpr (SC) {
             if constexpr (FEAT == FEAT_CLASS || CM == 2) own += in ? 1u : 0u;
             else own += (in && c != 0.f) ? 1u : 0u;
-          } else if constexpr (FEAT == FEAT_CLASS || CM == 2) {
+          } else if constexpr (FEAT == FEAT_CLASS) {
+            // the two compares' lane masks, combined on the scalar unit (a ballot of the combined
+            // condition would first turn it into a vector value and back)
+            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near) &
+                                      __builtin_amdgcn_ballot_w64(__float_as_uint(z.w) == lbl));
+          } else if constexpr (CM == 2) {
             cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
           } else {
             cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
