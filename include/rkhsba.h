@@ -137,6 +137,20 @@ int rkhsba_build_neighbors(rkhsba_ctx* ctx, int K, const int64_t* n_points, cons
 int rkhsba_eval_loss(rkhsba_ctx* ctx, const double* poses, int E, const int32_t* edges,
                      double* loss_total, double* loss_per_edge, int64_t* n_pairs);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): rkhsba_eval_loss on the frames built before, with the same
+ * arguments, outputs and results (the same kernels; loss_per_edge, loss_total and n_pairs equal
+ * rkhsba_eval_loss's), but with no device allocation and no free: the edge layout and the evaluation's
+ * scratch (binning keys and values, their sort buffers, per-point sums, per-edge sums) live in a static
+ * device array of 64 MiB that each GPU the library runs on holds until the process ends.  That bounds
+ * one call to about 2 million (edge, source point) entries (each edge contributes its source frame's
+ * point count); a call that needs more returns RKHSBA_ENOMEM with a message and changes nothing.  Host
+ * bookkeeping only (no device memory) is allocated.  Every call on a GPU, from any context, shares that
+ * GPU's array and overwrites what the last call left there: calls that overlap on one GPU (from two
+ * threads, or on two streams whose work is in flight at once) race and must not be made. */
+int rkhsba_eval_loss_noalloc(rkhsba_ctx* ctx, const double* poses, int E, const int32_t* edges,
+                             double* loss_total, double* loss_per_edge, int64_t* n_pairs);
+
 /* H (6K x 6K, full, no frame removed), b (6K) and F at `poses` (Sec. V-A,
  * normal equations of Eq. (eq:irls_final) with the weights of
  * Eq. (eq:irls_weight) frozen).  H, b, loss_total, n_pairs are nullable. */

@@ -6,7 +6,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,8 +18,37 @@
 
 using namespace rkhsba;
 
+// Device scratch of rkhsba_eval_loss_noalloc: one static array per device the library runs on, held
+// until the process ends.  Its device address comes from hipGetSymbolAddress (per device, at context
+// creation); host code uses that address, never the array's name.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch_ptr;  // device ordinal -> address of that device's `scratch`
+
+// The device address of `scratch` on the current device `dev` (looked up once per device).
+hipError_t scratch_address(int dev, uint8_t** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = static_cast<uint8_t*>(ptr);
+  *out = static_cast<uint8_t*>(ptr);
+  return hipSuccess;
+}
+}  // namespace
+
 struct rkhsba_ctx {
   rkhsba_options opt{};
+  uint8_t* scratch_dev = nullptr;  // this device's static scratch (rkhsba_eval_loss_noalloc)
+  SetLayout lay_noalloc;           // layout tables of rkhsba_eval_loss_noalloc, in that scratch
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -157,7 +188,7 @@ int rkhsba_create(rkhsba_ctx** out, const rkhsba_options* opt) {
   rkhsba_ctx* c = new (std::nothrow) rkhsba_ctx();
   if (!c) return RKHSBA_ENOMEM;
   c->opt = *opt;
-  if (hipSetDevice(opt->device) != hipSuccess) {
+  if (hipSetDevice(opt->device) != hipSuccess || scratch_address(opt->device, &c->scratch_dev) != hipSuccess) {
     delete c;
     return RKHSBA_EDEVICE;
   }
@@ -190,6 +221,7 @@ void rkhsba_destroy(rkhsba_ctx* c) {
   c->lay_gn.drop_graph();
   c->lay_rot.drop_graph();
   c->lay_ell.drop_graph();
+  c->lay_noalloc.drop_graph();
   c->eng.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -312,6 +344,43 @@ int rkhsba_eval_loss(rkhsba_ctx* c, const double* poses, int E, const int32_t* e
     }
     if (loss_total) *loss_total = s2 * F;
     if (n_pairs) *n_pairs = (int64_t)np;
+    return RKHSBA_OK;
+  });
+}
+
+int rkhsba_eval_loss_noalloc(rkhsba_ctx* c, const double* poses, int E, const int32_t* edges, double* loss_total,
+                             double* loss_per_edge, int64_t* n_pairs) {
+  return guarded(c, [&]() -> int {
+    Problem* p = resident(c);
+    Engine& g = *c->eng;
+    RK_REQUIRE(c->scratch_dev != nullptr, RKHSBA_ESTATE, "no static scratch on this device");
+    // the layout tables and the loss evaluation's scratch in this device's static array; the last 256
+    // bytes hold the two totals
+    Arena arena;
+    arena.base = c->scratch_dev;
+    arena.cap = kNoallocScratchBytes - 256;
+    arena.mom_components = 1;
+    double* d_totals = reinterpret_cast<double*>(c->scratch_dev + kNoallocScratchBytes - 256);
+    g.set_arena(&arena);
+    struct Restore {
+      Engine& g;
+      ~Restore() { g.set_arena(nullptr); }
+    } restore{g};
+    g.prepare(c->lay_noalloc, {SetItem{p, edges, E, -1, 0}});
+    g.upload_poses(p, poses);
+    g.evaluate(c->lay_noalloc, MODE_LOSS);
+    RK_HIP(launch_edge_totals(g.edge_out(), E, d_totals, c->stream));
+    double tot[2] = {0.0, 0.0};
+    RK_HIP(hipMemcpyAsync(tot, d_totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+    if (loss_per_edge)
+      RK_HIP(hipMemcpy2DAsync(loss_per_edge, sizeof(double), g.edge_out(), sizeof(double) * kEdgeVals,
+                              sizeof(double), (size_t)E, hipMemcpyDeviceToHost, c->stream));
+    RK_HIP(hipStreamSynchronize(c->stream));
+    const double s2 = c->opt.sigma * c->opt.sigma;
+    if (loss_per_edge)
+      for (int e = 0; e < E; ++e) loss_per_edge[e] *= s2;
+    if (loss_total) *loss_total = s2 * tot[0];
+    if (n_pairs) *n_pairs = (int64_t)tot[1];
     return RKHSBA_OK;
   });
 }

@@ -45,23 +45,34 @@ struct Fail {
     if (!(cond)) throw ::rkhsba::Fail{(code), (msg)};          \
   } while (0)
 
-// Device buffer that grows on demand; contents are not preserved.
+// Device buffer that grows on demand; contents are not preserved.  A buffer
+// can instead view caller-provided device memory (attach): it is then never
+// freed or grown.
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  bool owned = true;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    owned = true;
+  }
+  void attach(T* ptr, size_t count) {
+    release();
+    p = ptr;
+    n = count;
+    owned = false;
   }
   hipError_t reserve(size_t count) {
     if (count == 0) count = 1;
     if (count <= n) return hipSuccess;
+    if (!owned) return hipErrorOutOfMemory;  // a view does not grow
     release();
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
     if (e != hipSuccess) {
@@ -72,6 +83,34 @@ struct DBuf {
     return hipSuccess;
   }
   size_t bytes() const { return n * sizeof(T); }
+};
+
+// Consecutive 256-byte aligned pieces of one caller-provided device region.
+struct Arena {
+  uint8_t* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  int mom_components = 10;  // moments per entry the evaluations need (1 for loss-only evaluations)
+  template <typename T>
+  T* take(size_t count) {
+    if (count == 0) count = 1;
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off + count * sizeof(T) > cap) return nullptr;
+    used = off + count * sizeof(T);
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// Per-evaluation device scratch of an engine: relative transforms, binning
+// keys and values (and their sort buffers), moments, pair counts, partial and
+// per-edge sums, and the assembled systems.
+struct EvalScratch {
+  DBuf<EdgeXf> xf;
+  DBuf<uint32_t> bk, bv, bk2, bv2, bhist;
+  DBuf<float> mom;
+  DBuf<uint32_t> cnt;
+  DBuf<double> partial, edge_out;
+  DBuf<double> H, b, delta;
 };
 
 // First-fit allocator of element ranges [0, capacity).
@@ -256,6 +295,11 @@ class Engine {
 
   // Set layout for the items (cached in `lay`; rebuilt when the items change).
   void prepare(SetLayout& lay, const std::vector<SetItem>& items);
+  // Allocation-free evaluations: while an arena is set, prepare() places the layout's tables and the
+  // per-evaluation scratch in it (no device allocation; a layout too large for it fails with
+  // RKHSBA_ENOMEM), skips the loss histories, and graphs and stage timing are off.  The layout must
+  // be one used only under this arena; it is rebuilt on every prepare().
+  void set_arena(Arena* a);
   // One evaluation of every item of the set at the device poses: per-edge sums in edge_out.
   void evaluate(SetLayout& lay, int mode);
   // Assembly (+ history entry) of every problem.
@@ -274,7 +318,7 @@ class Engine {
   // every source point's pair count, by its original index (frame m's point count; synchronises).
   void read_source_counts(Problem* p, int m, int64_t* counts);
   int32_t read_status(Problem* p);                                         // synchronises
-  const double* edge_out() const { return edge_out_.p; }
+  const double* edge_out() const { return sc_->edge_out.p; }
 
   // device views
   const float4* pts() const { return static_cast<const float4*>(points_.ptr(0)); }
@@ -329,13 +373,13 @@ class Engine {
   DBuf<uint32_t> row_sizes_, scan_tmp_;
   DBuf<uint64_t> d_total_;
 
-  // per-evaluation scratch (sized for the largest set so far)
-  DBuf<EdgeXf> xf_;
-  DBuf<uint32_t> bk_, bv_, bk2_, bv2_, bhist_;
-  DBuf<float> mom_;
-  DBuf<uint32_t> cnt_;
-  DBuf<double> partial_, edge_out_;
-  DBuf<double> H_, b_, delta_;
+  template <typename T>
+  void need(DBuf<T>& b, size_t count, const char* what);
+
+  // per-evaluation scratch (sized for the largest set so far), or views of the arena
+  EvalScratch own_sc_, arena_sc_;
+  EvalScratch* sc_ = &own_sc_;
+  Arena* arena_ = nullptr;
   const uint32_t* sorted_k_ = nullptr;
   const uint32_t* sorted_v_ = nullptr;
   uint64_t scratch_gen_ = 0;  // bumped when a scratch buffer moves

@@ -150,7 +150,7 @@ uint64_t Engine::generation() const {
 }
 
 hipEvent_t Engine::prof_begin() {
-  if (!prof) return nullptr;
+  if (!prof || arena_) return nullptr;
   hipEvent_t ev = nullptr;
   if (!event_pool_.empty()) {
     ev = event_pool_.back();
@@ -200,9 +200,10 @@ int64_t Engine::device_bytes() const {
                         state_.bytes());
   b += (int64_t)(raw_xyz_.bytes() + raw_feat_.bytes() + cell_.bytes() + k1_.bytes() + v1_.bytes() + k2_.bytes() +
                  v2_.bytes() + hist_scratch_.bytes() + row_sizes_.bytes() + scan_tmp_.bytes());
-  b += (int64_t)(xf_.bytes() + bk_.bytes() + bv_.bytes() + bk2_.bytes() + bv2_.bytes() + bhist_.bytes() +
-                 mom_.bytes() + cnt_.bytes() + partial_.bytes() + edge_out_.bytes() + H_.bytes() + b_.bytes() +
-                 delta_.bytes());
+  const EvalScratch& o = own_sc_;
+  b += (int64_t)(o.xf.bytes() + o.bk.bytes() + o.bv.bytes() + o.bk2.bytes() + o.bv2.bytes() + o.bhist.bytes() +
+                 o.mom.bytes() + o.cnt.bytes() + o.partial.bytes() + o.edge_out.bytes() + o.H.bytes() + o.b.bytes() +
+                 o.delta.bytes());
   return b;
 }
 
@@ -654,7 +655,7 @@ void Engine::read_source_counts(Problem* p, int m, int64_t* counts) {
   const FrameInfo& F = p->frames[m];
   std::vector<uint32_t> c(F.n), k(F.n), v(F.n);
   std::vector<int32_t> perm(F.n);
-  RK_HIP(hipMemcpyAsync(c.data(), cnt_.p, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(c.data(), sc_->cnt.p, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipMemcpyAsync(k.data(), sorted_k_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipMemcpyAsync(v.data(), sorted_v_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipMemcpyAsync(perm.data(), this->perm() + F.pt_off, sizeof(int32_t) * F.n, hipMemcpyDeviceToHost, st));
@@ -676,6 +677,25 @@ int32_t Engine::read_status(Problem* p) {
 
 // ---------------------------------------------------------------- set layout
 
+template <typename T>
+void Engine::need(DBuf<T>& b, size_t count, const char* what) {
+  if (!arena_) {
+    RK_HIP(b.reserve(count));
+    return;
+  }
+  T* p = arena_->take<T>(count);
+  RK_REQUIRE(p != nullptr, RKHSBA_ENOMEM,
+             std::string("allocation-free evaluation: the static scratch (") + std::to_string(arena_->cap) +
+                 " bytes) cannot hold the layout (exhausted at '" + what + "'); use fewer edges or points");
+  b.attach(p, count);
+}
+
+void Engine::set_arena(Arena* a) {
+  arena_ = a;
+  sc_ = a ? &arena_sc_ : &own_sc_;
+  if (a) a->used = 0;
+}
+
 void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   RK_REQUIRE(!items.empty(), RKHSBA_EINVAL, "empty set");
   for (const SetItem& it : items) {
@@ -690,7 +710,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       RK_REQUIRE(m >= 0 && n >= 0 && m < Kx && n < Kx, RKHSBA_EINVAL, "edge frame index out of range");
       RK_REQUIRE(m != n || it.allow_self, RKHSBA_EINVAL, "self-edge (m == n)");
     }
-    ensure_history(it.p, it.n_iter);
+    if (!arena_) ensure_history(it.p, it.n_iter);
   }
   std::vector<int32_t> key;  // (pass sizes and finalisation splits follow from the problems)
   std::vector<int> ids;
@@ -706,7 +726,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     key.push_back(it.p->kc_version);
     key.insert(key.end(), it.edges, it.edges + 2 * it.E);
   }
-  if (key == lay.edge_key && !lay.sys.empty()) return;
+  if (key == lay.edge_key && !lay.sys.empty() && !arena_) return;
   lay.drop_graph();
 
   int E_total = 0;
@@ -812,11 +832,11 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
              RKHSBA_EINVAL, "edge list too large");
   if (blist.empty()) blist.push_back(0);
   if (vlist.empty()) vlist.push_back(0);
-  RK_HIP(lay.d_edges.reserve(E_total));
-  RK_HIP(lay.d_ent_off.reserve(E_total));
-  RK_HIP(lay.d_fin_off.reserve(E_total));
-  RK_HIP(lay.d_etiles.reserve(tiles.size()));
-  RK_HIP(lay.d_esegs.reserve(E_total));
+  need(lay.d_edges, E_total, "edges");
+  need(lay.d_ent_off, E_total, "ent_off");
+  need(lay.d_fin_off, E_total, "fin_off");
+  need(lay.d_etiles, tiles.size(), "etiles");
+  need(lay.d_esegs, E_total, "esegs");
   // the pass table: the groups one after another, each edge's passes contiguous (filled on the device)
   std::vector<SetLayout::Group> groups;
   int64_t gbase[6], n_pass_table = 0;
@@ -842,13 +862,13 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       run[gi] += info[e].n_pass;
     }
   }
-  RK_HIP(lay.d_kcs.reserve(items.size()));
-  RK_HIP(lay.d_passes.reserve((size_t)n_pass_table));
-  RK_HIP(lay.d_sys.reserve(items.size()));
-  RK_HIP(lay.d_blk_start.reserve(bstart_all.size()));
-  RK_HIP(lay.d_blk_list.reserve(blist.size()));
-  RK_HIP(lay.d_vec_start.reserve(vstart_all.size()));
-  RK_HIP(lay.d_vec_list.reserve(vlist.size()));
+  need(lay.d_kcs, items.size(), "kcs");
+  need(lay.d_passes, (size_t)n_pass_table, "passes");
+  need(lay.d_sys, items.size(), "sys");
+  need(lay.d_blk_start, bstart_all.size(), "blk_start");
+  need(lay.d_blk_list, blist.size(), "blk_list");
+  need(lay.d_vec_start, vstart_all.size(), "vec_start");
+  need(lay.d_vec_list, vlist.size(), "vec_list");
   auto up = [&](void* dst, const void* src, size_t bytes) {
     if (bytes) RK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
   };
@@ -866,25 +886,26 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   up(lay.d_vec_list.p, vlist.data(), sizeof(int32_t) * vlist.size());
 
   // per-evaluation scratch
-  const void* before[] = {xf_.p, bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, mom_.p, cnt_.p, partial_.p, edge_out_.p,
-                          H_.p, b_.p, delta_.p};
-  RK_HIP(xf_.reserve(E_total));
-  RK_HIP(bk_.reserve(entries));
-  RK_HIP(bv_.reserve(entries));
-  RK_HIP(bk2_.reserve(entries));
-  RK_HIP(bv2_.reserve(entries));
-  RK_HIP(bhist_.reserve(tiles.size() * 256));
-  RK_HIP(mom_.reserve((size_t)entries * 10));
-  RK_HIP(cnt_.reserve(entries));
-  RK_HIP(partial_.reserve((size_t)fins * kFinStats));
-  RK_HIP(edge_out_.reserve((size_t)E_total * kEdgeVals));
-  RK_HIP(H_.reserve(h_total));
-  RK_HIP(b_.reserve(v_total));
-  RK_HIP(delta_.reserve(v_total));
-  const void* after[] = {xf_.p, bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, mom_.p, cnt_.p, partial_.p, edge_out_.p,
-                         H_.p, b_.p, delta_.p};
-  for (size_t i = 0; i < sizeof(before) / sizeof(before[0]); ++i)
-    if (before[i] != after[i]) ++scratch_gen_;
+  const void* before[] = {sc_->xf.p, sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, sc_->mom.p, sc_->cnt.p, sc_->partial.p, sc_->edge_out.p,
+                          sc_->H.p, sc_->b.p, sc_->delta.p};
+  need(sc_->xf, E_total, "xf");
+  need(sc_->bk, entries, "bk");
+  need(sc_->bv, entries, "bv");
+  need(sc_->bk2, entries, "bk2");
+  need(sc_->bv2, entries, "bv2");
+  need(sc_->bhist, tiles.size() * 256, "bhist");
+  need(sc_->mom, (size_t)entries * (arena_ ? arena_->mom_components : 10), "mom");
+  need(sc_->cnt, entries, "cnt");
+  need(sc_->partial, (size_t)fins * kFinStats, "partial");
+  need(sc_->edge_out, (size_t)E_total * kEdgeVals, "edge_out");
+  need(sc_->H, h_total, "H");
+  need(sc_->b, v_total, "b");
+  need(sc_->delta, v_total, "delta");
+  const void* after[] = {sc_->xf.p, sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, sc_->mom.p, sc_->cnt.p, sc_->partial.p, sc_->edge_out.p,
+                         sc_->H.p, sc_->b.p, sc_->delta.p};
+  if (!arena_)
+    for (size_t i = 0; i < sizeof(before) / sizeof(before[0]); ++i)
+      if (before[i] != after[i]) ++scratch_gen_;
   RK_HIP(hipStreamSynchronize(st));  // host tables above go out of scope
 
   lay.uses = 0;
@@ -909,15 +930,17 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
 // ---------------------------------------------------------------- launches
 
 void Engine::evaluate(SetLayout& lay, int mode) {
+  RK_REQUIRE(!arena_ || mode == MODE_LOSS || arena_->mom_components == 10, RKHSBA_ESTATE,
+             "the arena holds loss-evaluation moments only");
   hipEvent_t t0 = prof_begin();
-  RK_HIP(launch_edge_setup(poses(), lay.d_edges.p, lay.E, xf_.p, st));
-  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, xf_.p, lay.d_kcs.p, bk_.p,
-                    bv_.p, st));
+  RK_HIP(launch_edge_setup(poses(), lay.d_edges.p, lay.E, sc_->xf.p, st));
+  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p, sc_->bk.p,
+                    sc_->bv.p, st));
   bool in_tmp = false;
-  RK_HIP(launch_radix_sort(bk_.p, bv_.p, bk2_.p, bv2_.p, bhist_.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,
+  RK_HIP(launch_radix_sort(sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,
                            lay.E, lay.bin_bits, st, &in_tmp));
-  sorted_k_ = in_tmp ? bk2_.p : bk_.p;
-  sorted_v_ = in_tmp ? bv2_.p : bv_.p;
+  sorted_k_ = in_tmp ? sc_->bk2.p : sc_->bk.p;
+  sorted_v_ = in_tmp ? sc_->bv2.p : sc_->bv.p;
   prof_end(RKHSBA_PROF_BIN, t0);
   PairArgs pa{};
   pa.pts = pts();
@@ -926,11 +949,11 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   pa.xtab = xtab();
   pa.frames = frames();
   pa.edges = lay.d_edges.p;
-  pa.xf = xf_.p;
+  pa.xf = sc_->xf.p;
   pa.keys = sorted_k_;
   pa.vals = sorted_v_;
-  pa.mom = mom_.p;
-  pa.cnt = cnt_.p;
+  pa.mom = sc_->mom.p;
+  pa.cnt = sc_->cnt.p;
   pa.kcs = lay.d_kcs.p;
   pa.passes = lay.d_passes.p;
   pa.perm = perm();
@@ -955,32 +978,32 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   FinArgs fa{};
   fa.pts = pts();
   fa.edges = lay.d_edges.p;
-  fa.xf = xf_.p;
+  fa.xf = sc_->xf.p;
   fa.frames = frames();
   fa.keys = sorted_k_;
   fa.vals = sorted_v_;
-  fa.mom = mom_.p;
-  fa.cnt = cnt_.p;
+  fa.mom = sc_->mom.p;
+  fa.cnt = sc_->cnt.p;
   fa.kcs = lay.d_kcs.p;
-  fa.partial = partial_.p;
+  fa.partial = sc_->partial.p;
   fa.n_entries = lay.n_entries;
   fa.E = lay.E;
   fa.n_fin_total = lay.n_fin_total;
   hipEvent_t t2 = prof_begin();
   RK_HIP(launch_finalize(fa, lay.d_fin_off.p, mode, fp32_sums, st));
-  RK_HIP(launch_edge_reduce(partial_.p, lay.d_edges.p, xf_.p, lay.E, mode, fp32_sums, edge_out_.p, st));
+  RK_HIP(launch_edge_reduce(sc_->partial.p, lay.d_edges.p, sc_->xf.p, lay.E, mode, fp32_sums, sc_->edge_out.p, st));
   prof_end(RKHSBA_PROF_FINALIZE, t2);
 }
 
 SolveArgs Engine::solve_args(SetLayout& lay) {
   SolveArgs s{};
-  s.edge_out = edge_out_.p;
+  s.edge_out = sc_->edge_out.p;
   s.sys = lay.d_sys.p;
   s.n_prob = lay.n_prob;
   s.n_max = lay.n_max;
-  s.H = H_.p;
-  s.b = b_.p;
-  s.delta = delta_.p;
+  s.H = sc_->H.p;
+  s.b = sc_->b.p;
+  s.delta = sc_->delta.p;
   s.poses = poses();
   s.loss_hist = static_cast<double*>(hist_.ptr(0));
   s.pairs_hist = static_cast<double*>(hist_.ptr(1));

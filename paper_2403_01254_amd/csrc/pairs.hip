@@ -724,6 +724,24 @@ hipError_t launch_edge_reduce(const double* d_partial, const EdgeInfo* d_edges, 
   return hipGetLastError();
 }
 
+// Sum over edges, in edge order, of each edge's F and pair count (one thread: the same order as a host
+// loop over the per-edge values).
+__global__ void k_edge_totals(const double* __restrict__ edge_out, int E, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double F = 0.0, np = 0.0;
+  for (int e = 0; e < E; ++e) {
+    F += edge_out[(int64_t)e * kEdgeVals];
+    np += edge_out[(int64_t)e * kEdgeVals + 91];
+  }
+  out[0] = F;
+  out[1] = np;
+}
+
+hipError_t launch_edge_totals(const double* d_edge_out, int E, double* d_out, hipStream_t st) {
+  k_edge_totals<<<1, 64, 0, st>>>(d_edge_out, E, d_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
                                const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const void* d_feat,
                                const EdgeXf* d_xf, int m, int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,

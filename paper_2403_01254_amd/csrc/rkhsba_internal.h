@@ -248,6 +248,9 @@ hipError_t launch_loss_only(const SolveArgs& a, hipStream_t st);
 // is below its n_iter; advances the iteration count of every problem.
 hipError_t launch_solve_update(const SolveArgs& a, hipStream_t st);
 
+// out[0] = sum of F, out[1] = sum of pair counts over the E per-edge rows of edge_out (edge order).
+hipError_t launch_edge_totals(const double* d_edge_out, int E, double* d_out, hipStream_t st);
+
 hipError_t launch_export_pairs(const float4* d_pts, const int4* d_rows, const uint32_t* d_xtab,
                                const FrameInfo* d_frames, int n_src, const int32_t* d_perm, const void* d_feat,
                                const EdgeXf* d_xf, int m, int n, int feat_path, KConst kc, int64_t cap, int32_t* d_out,

@@ -120,6 +120,7 @@ def lib():
         L.rkhsba_build_neighbors.argtypes = [vp, ctypes.c_int, _i64p, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                              ctypes.POINTER(vp), ctypes.c_int]
         L.rkhsba_eval_loss.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _i64p]
+        L.rkhsba_eval_loss_noalloc.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _i64p]
         L.rkhsba_accumulate_normal_eqs.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _dp, _i64p]
         L.rkhsba_gn_step.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _dp, _i64p]
         L.rkhsba_export_pairs.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _i64p]
@@ -282,6 +283,17 @@ class Context:
         npairs = ctypes.c_int64()
         self._check(lib().rkhsba_eval_loss(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(F), _p(Fe),
                                            ctypes.byref(npairs)))
+        return F.value, Fe, npairs.value
+
+    # -- rkhsba_eval_loss_noalloc
+    def eval_loss_noalloc(self, poses, edges):
+        """As eval_loss, with no device allocation (the library's static scratch)."""
+        p, e = self._poses(poses), self._edges(edges)
+        F = ctypes.c_double()
+        Fe = np.zeros(len(e))
+        npairs = ctypes.c_int64()
+        self._check(lib().rkhsba_eval_loss_noalloc(self._h, _p(p), len(e), _p(e, ctypes.c_int32), ctypes.byref(F),
+                                                   _p(Fe), ctypes.byref(npairs)))
         return F.value, Fe, npairs.value
 
     # -- rkhsba_accumulate_normal_eqs
@@ -521,6 +533,10 @@ def rkhsba_build_neighbors(ctx: Context, points, feats, feat_kind="class"):
 
 def rkhsba_eval_loss(ctx: Context, poses, edges):
     return ctx.eval_loss(poses, edges)
+
+
+def rkhsba_eval_loss_noalloc(ctx: Context, poses, edges):
+    return ctx.eval_loss_noalloc(poses, edges)
 
 
 def rkhsba_accumulate_normal_eqs(ctx: Context, poses, edges):
