@@ -219,6 +219,12 @@ int64_t Engine::estimate_bytes(int K, const int64_t* n_points, int E, int64_t ro
   return N * per_point + (int64_t)E * nmax * per_entry + 2 * n * n * 8 + (int64_t)E * 2 * kEdgeVals * 8;
 }
 
+// Class-id sweep passes whose box is wider than this many truncation radii walk per source point.  On the
+// LiDAR map (64 x 100,000 points, 20% outliers) a fifth of the 8-point passes span more than 4 r_c and hold
+// under 1% of the pairs; measured per launch: no per-source walks 13.25 ms, threshold 1.5 r_c 11.20,
+// 2 r_c 10.83, 3 r_c 10.78, 4 r_c 10.80 (16-point passes: 2 r_c 10.20, 3 r_c 10.11).
+constexpr double kSpreadFactor = 3.0;
+
 void Engine::compute_constants(Problem* p) {
   const ProbParams& o = p->par;
   const double rc = o.cutoff_factor * o.ell;
@@ -236,6 +242,7 @@ void Engine::compute_constants(Problem* p) {
   k.Dp = Dp;
   k.topk = o.top_k;
   k.inv2l2 = 1.0 / (2.0 * o.ell * o.ell);
+  k.spread_limit = (float)(kSpreadFactor * rc);
   p->kc = k;
 }
 
@@ -598,6 +605,7 @@ void Engine::set_ell(Problem* p, double ell) {
   k.alpha = (float)(1.4426950408889634 / (2.0 * ell * ell));
   k.reach_cells = (int)std::ceil(k.reach * k.inv_cell) + 1;
   k.inv2l2 = 1.0 / (2.0 * ell * ell);
+  k.spread_limit = (float)(kSpreadFactor * rc);
   p->kc = k;
   ++p->kc_version;
 }

@@ -83,6 +83,7 @@ struct KConst {
   double inv2l2;     // 1 / (2 ell^2), for the FP64 ranking key of the topk selection
   int c_positive;    // FP32 dense features, none negative, and one dimension >= 1e-18 in every row: every
                      // inner product is > 0 (its term in that dimension is >= 1e-36, above FLT_MIN)
+  float spread_limit;  // class-id sweeps: passes whose box is wider than this walk per source point
 };
 constexpr int kMaxTopK = 8;
 

@@ -22,6 +22,9 @@
 //      W = sum w |d|^2; C_zz is not summed (the finaliser takes it from the
 //      trace, C_zz = W - C_xx - C_yy), which saves w d_z.  The four streams of
 //      each source are summed with cross-lane shuffles at the end.
+//   5. Spread passes (class ids): a pass whose box is wider than a few r_c
+//      (isolated outliers, jumps of the Morton order) skips steps 1-3: each
+//      source walks the rows of its own ball, its lanes splitting the rows.
 #include <cfloat>
 
 #include "rkhsba_device.h"
@@ -245,14 +248,68 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   const int y0 = max(clamp_floor_d(((double)lo.y - reach) * inv - Fn.org[1], -1, Fn.dim[1]), 0);
   const int y1 = min(clamp_floor_d(((double)hi.y + reach) * inv - Fn.org[1], -1, Fn.dim[1]), Fn.dim[1] - 1);
   const int ny = y1 - y0 + 1;
-  const int n_rows = (z1 >= z0 && y1 >= y0) ? (z1 - z0 + 1) * ny : 0;
+  int n_rows = (z1 >= z0 && y1 >= y0) ? (z1 - z0 + 1) * ny : 0;
 
   const float rc2 = kc.rc2, alpha = kc.alpha;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
   float Cxx = 0.f, Cxy = 0.f, Cxz = 0.f, Cyy = 0.f, Cyz = 0.f, Wr2 = 0.f;
   uint32_t cnt = 0;
-  uint32_t own = 0;  // SC: this lane's pairs
+  uint32_t own = 0;  // this lane's pairs (SC, spread passes)
   const float4* __restrict__ tp = a.pts + Fn.pt_off;
+
+  // Spread passes (class ids): when the pass's sources lie far apart (isolated outliers, a jump of the
+  // Morton order), the ball around their common box holds mostly candidates of no source.  Each source
+  // then walks the cell rows of its own ball only (the box shrunk to its point, the same row and x-range
+  // trimming), its G lanes taking every G-th row, and reads the candidates straight from the frame.
+  bool spread = false;
+  if constexpr (FEAT == FEAT_CLASS && !MM) {
+    spread = fmaxf(hi.x - lo.x, fmaxf(hi.y - lo.y, hi.z - lo.z)) > kc.spread_limit;  // uniform
+    if (spread) {
+      n_rows = 0;  // no shared walk
+      constexpr int G = 64 / P;
+      int zs0 = 0, zs1 = -1, ys0 = 0, ys1 = -1;
+      if (valid) {
+        zs0 = max(clamp_floor_d(((double)q.z - reach) * inv - Fn.org[2], -1, Fn.dim[2]), 0);
+        zs1 = min(clamp_floor_d(((double)q.z + reach) * inv - Fn.org[2], -1, Fn.dim[2]), Fn.dim[2] - 1);
+        ys0 = max(clamp_floor_d(((double)q.y - reach) * inv - Fn.org[1], -1, Fn.dim[1]), 0);
+        ys1 = min(clamp_floor_d(((double)q.y + reach) * inv - Fn.org[1], -1, Fn.dim[1]), Fn.dim[1] - 1);
+      }
+      const int nys = ys1 - ys0 + 1;
+      const int nr = (zs1 >= zs0 && ys1 >= ys0) ? (zs1 - zs0 + 1) * nys : 0;
+      for (int r = g; r < nr; r += G) {
+        const int kz = zs0 + r / nys, ky = ys0 + r % nys;
+        const double cz = (double)(kz + Fn.org[2]) * cell;
+        const double cy = (double)(ky + Fn.org[1]) * cell;
+        const double bz = fmax(0.0, fmax(cz - (double)q.z, (double)q.z - (cz + cell)));
+        const double by = fmax(0.0, fmax(cy - (double)q.y, (double)q.y - (cy + cell)));
+        const double r2 = kc.reach2 - by * by - bz * bz;
+        if (r2 < 0.0) continue;
+        const int4 R = a.rows[Fn.row_off + (int64_t)kz * Fn.dim[1] + ky];
+        if (R.y < R.x) continue;
+        const double h = sqrt(r2);
+        const int xa = max(clamp_floor_d(((double)q.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
+        const int xb = min(clamp_floor_d(((double)q.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R.y);
+        if (xa > xb) continue;
+        const uint32_t* xt = a.xtab + Fn.xt_off + (uint32_t)R.z;
+        const uint32_t j1 = xt[xb + 1 - R.x];
+        for (uint32_t j = xt[xa - R.x]; j < j1; ++j) {
+          const float4 z = tp[j];
+          float dx, dy, dz;
+          const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+          if (!(s2 <= rc2 && __float_as_uint(z.w) == lbl)) continue;
+          const float w = __builtin_amdgcn_exp2f(-alpha * s2);
+          own += 1u;
+          A += w;
+          if constexpr (MODE == MODE_NORMAL) {
+            const float wx = w * dx, wy = w * dy;
+            Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
+            Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
+          }
+        }
+      }
+    }
+  }
   const float* __restrict__ tf = static_cast<const float*>(a.feat) + Fn.pt_off * (FEAT == FEAT_DENSE ? DP : 0);
   const uint8_t* __restrict__ tl = static_cast<const uint8_t*>(a.feat) + Fn.pt_off * (int64_t)(LP ? ROWB : 0);
   const float far_ = 1.0e18f;
@@ -461,7 +518,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Wr2 += __shfl_xor(Wr2, o, 64);
     }
   }
-  if constexpr (SC) {
+  if (SC || spread) {  // every source point's own count
 #pragma unroll
     for (int o = P; o < 64; o <<= 1) own += __shfl_xor(own, o, 64);
     if (g == 0 && in_range) a.cnt[entry] = valid ? own : 0u;

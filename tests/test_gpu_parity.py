@@ -163,6 +163,41 @@ def test_sweep_source_counts_bit_exact(rk, pass_points, subdiv):
         ctx.close()
 
 
+@pytest.mark.parametrize("pass_points", [8, 16])
+def test_sparse_frames_walk_per_source(rk, pass_points):
+    """Frames so sparse that every sweep pass spans many truncation radii (the case of isolated outliers):
+    the class-id sweep then walks each source point's own cells.  Each point of frame 1 has a noisy copy in
+    frame 2 and a few random neighbours; per-source pair counts, F, b, H and Gauss-Newton poses against the
+    oracle."""
+    rng = np.random.default_rng(41)
+    n = 4000
+    x = rng.uniform(-100.0, 100.0, size=(n, 3))
+    near = x[rng.integers(0, n, size=n // 4)] + rng.normal(scale=0.1, size=(n // 4, 3))
+    pts = [np.concatenate([x, near]).astype(np.float32),
+           (np.concatenate([x, near]) + rng.normal(scale=0.05, size=(n + n // 4, 3))).astype(np.float32)]
+    lab = [rng.integers(0, 3, size=n + n // 4).astype(np.uint16)] * 2
+    ell = 0.1
+    op = oracle.Problem(pts, lab, "class", ell)
+    ctx = rk.Context(ell=ell, cell_subdiv=2, pass_points=pass_points)
+    ctx.build_neighbors(pts, lab, "class")
+    poses = np.stack([ident(), ident()])
+    got = ctx.export_source_counts(poses, 0, 1, len(pts[0]))
+    ref = np.bincount(oracle.pairs(op, poses, 0, 1)[:, 0], minlength=len(pts[0]))
+    np.testing.assert_array_equal(got, ref)
+    H, b, F, npairs = ctx.accumulate_normal_eqs(poses, [[0, 1], [1, 0]])
+    oF, ob, oH, _, onp = oracle.normal_eqs(op, poses, [[0, 1], [1, 0]], oracle.MEMBER_FP32_RULE)
+    say(f"[sparse] pass {pass_points}: {npairs} pairs / {onp}, F rel {abs(F - oF) / oF:.3g}")
+    assert npairs == onp and abs(F - oF) <= REL_TOL * oF
+    assert_blocks_close(b, ob, 6, what="sparse b")
+    assert_blocks_close(H, oH, 6, what="sparse H")
+    gposes, lpi, _ = ctx.gn_step(poses, [[0, 1]], 3)
+    oposes, olpi = oracle.gn(op, poses, [[0, 1]], 3, membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(gposes, oposes)
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+    ctx.close()
+
+
 @pytest.mark.parametrize("pass_points,subdiv", [(16, 1), (32, 2), (64, 3), (16, 4), (64, 1), (1, 1), (1, 3), (8, 1),
                                                 (8, 3)])
 def test_launch_shapes_agree(rk, pass_points, subdiv):
