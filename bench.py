@@ -187,6 +187,8 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
     pose_diff = {}
 
     def run_batched(kind, arrivals):
+        # two lanes: small requests batched in lane 0; requests whose measured work (entries x points per
+        # occupied r_c-cube) is large run one at a time in lane 1, beside them
         srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64, lanes=lanes, lane_work_entries=work_entries)
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05
@@ -211,15 +213,23 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
         end = time.perf_counter()
         st = srv.stats()
         srv.close()
-        diff = max(float(np.abs(r[0] - q[0]).max()) for r, q in zip(out, seq)
-                   if q is not None and r[5] == rkhsba.OK)
+        rot_d, tr_d = 0.0, 0.0
+        for r, q in zip(out, seq):
+            if q is None or r[5] != rkhsba.OK:
+                continue
+            for a, b in zip(r[0], q[0]):
+                Ra, Rb = a[:9].reshape(3, 3), b[:9].reshape(3, 3)
+                c = np.clip((np.trace(Ra.T @ Rb) - 1.0) / 2.0, -1.0, 1.0)
+                rot_d = max(rot_d, float(np.arccos(c)))
+                tr_d = max(tr_d, float(np.linalg.norm(a[9:] - b[9:])))
         not_pd_batched = sum(1 for r in out if r[5] != rkhsba.OK)
-        pose_diff[kind] = max(pose_diff.get(kind, 0.0), diff)
+        prev = pose_diff.get(kind, (0.0, 0.0))
+        pose_diff[kind] = (max(prev[0], rot_d), max(prev[1], tr_d))
         return {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
                 "solves_per_s": len(reqs) / (end - start), "pair_evals_per_s": st["pair_evals"] / (end - start),
                 "max_active": st["max_active"], "batch_iterations": st["batch_iterations"],
                 "mean_queue_ms": 1e3 * float(np.mean([r[4] for r in out])), "not_pd_requests": not_pd_batched,
-                "max_pose_entry_diff_vs_one_at_a_time_f32": diff}
+                "max_pose_diff_vs_one_at_a_time_f32": {"rot_rad": rot_d, "trans_m": tr_d}}
 
     # capacity of the batched forms: every request submitted at once
     saturated = {}
@@ -261,7 +271,9 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
             "capacity_batched_f32_solves_per_s": saturated["dense"]["solves_per_s"],
             "capacity_batched_bf16_solves_per_s": saturated["bf16"]["solves_per_s"],
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
-            "max_pose_entry_diff_vs_one_at_a_time_f32": pose_diff,
+            "max_pose_diff_vs_one_at_a_time_f32": {k: {"rot_rad": v[0], "trans_m": v[1]} for k, v in pose_diff.items()},
+            "pose_accuracy_vs_fp64_oracle": "tests/test_gpu_server.py::test_served_forms_against_oracle (FP32 forms "
+                                            "within 1e-4 rad / 1e-4 m; bf16 printed)",
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
                       "depth-camera trajectory with a 0.3 m minimum range (p = 1/2), 20-class Dirichlet(0.3) soft "
                       "labels (D = 20), ell in {0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs "

@@ -336,6 +336,12 @@ typedef struct {
                                active requests plus the request's stay within this (0: no limit, the default; a
                                request is always admitted into an idle lane).  It bounds the work of one batch
                                iteration, which every active request of the lane waits for. */
+  int lane1_max_active;     /* with 2 lanes: requests active together in lane 1 (default 1: a large request fills
+                               the device alone and large requests run in arrival order, beside lane 0's batch of
+                               small ones; 0: as max_active) */
+  double lane_split_work;   /* with 2 lanes: a request admitted to lane 0 whose entries times the points per
+                               occupied r_c-cube that its build measured (an estimate of the candidate pairs of one
+                               iteration) exceed this moves to lane 1, in arrival order (default 5e8; 0: off) */
 } rkhsba_server_options;
 
 typedef struct {

@@ -236,8 +236,15 @@ struct SetLayout {
   uint64_t graph_gen = 0;
   int graph_mode = -1;
   int uses = 0;                     // iterate() calls since the layout was built
+  // pinned staging of the host tables' uploads, free again once stage_ev has completed
+  uint8_t* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_ev = nullptr;
   ~SetLayout();
   void drop_graph();
+  // The staging buffer, at least `bytes` large, once its previous uploads are done (nullptr when no_alloc
+  // and it is too small).
+  uint8_t* stage_for(size_t bytes, bool no_alloc);
 };
 
 class Engine {
@@ -249,8 +256,10 @@ class Engine {
 
   int device;
   hipStream_t st;
+  hipStream_t build_st = nullptr;  // stream of add_problem's work (nullptr: st); st waits for a build's end
   int moment_path;
   bool use_graphs = true;
+  int graph_min_uses = 1;  // iterate(lay, 1) captures a graph once the layout has been used this often
   bool fp32_sums = false;  // per-edge normal-equation sums in FP32 with Kahan compensation (else FP64)
   bool source_counts = false;  // sweeps write every source point's own pair count (parity checks)
 
@@ -314,6 +323,9 @@ class Engine {
 
   // results
   void read_history(Problem* p, int count, double* loss, double* pairs);  // synchronises
+  // Queues copies of the poses (K*12), `count` history entries and the (iter, status) pair to host
+  // memory (pinned, for the copies to be asynchronous) on the engine's stream; does not wait.
+  void copy_results_async(Problem* p, int count, double* poses, double* loss, double* pairs, int32_t* state);
   // After an evaluation with source_counts on, of a set whose first edge has source frame m of p:
   // every source point's pair count, by its original index (frame m's point count; synchronises).
   void read_source_counts(Problem* p, int m, int64_t* counts);

@@ -99,6 +99,10 @@ int64_t Pool::alloc(int64_t n, hipStream_t st) {
   if (off >= 0) return off;
   const int64_t cap = ra_.capacity();
   const int64_t new_cap = std::max<int64_t>({cap + n, cap + cap / 2, 1024});
+  // The contents move to new arrays: work queued on any stream of the engine (a lane's iterations while
+  // a build on its own stream grows the pool) must have finished writing to the old ones first, and must
+  // not read them after they are freed.
+  RK_HIP(hipDeviceSynchronize());
   std::vector<void*> fresh(eb_.size(), nullptr);
   for (size_t i = 0; i < eb_.size(); ++i) {
     hipError_t e = hipMalloc(&fresh[i], eb_[i] * (size_t)new_cap);
@@ -129,7 +133,29 @@ void SetLayout::drop_graph() {
   graph_mode = -1;
 }
 
-SetLayout::~SetLayout() { drop_graph(); }
+uint8_t* SetLayout::stage_for(size_t bytes, bool no_alloc) {
+  if (no_alloc && stage_cap < bytes) return nullptr;  // allocation-free callers upload from their tables
+  if (stage_ev) RK_HIP(hipEventSynchronize(stage_ev));  // the last uploads from the buffer are done
+  if (stage_cap < bytes) {
+    if (stage) (void)hipHostFree(stage);
+    stage = nullptr;
+    stage_cap = 0;
+    const size_t cap = std::max<size_t>(bytes + bytes / 2, 1 << 16);
+    RK_HIP(hipHostMalloc(reinterpret_cast<void**>(&stage), cap, hipHostMallocDefault));
+    stage_cap = cap;
+  }
+  if (!stage_ev) RK_HIP(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
+  return stage;
+}
+
+SetLayout::~SetLayout() {
+  drop_graph();
+  if (stage_ev) {
+    (void)hipEventSynchronize(stage_ev);
+    (void)hipEventDestroy(stage_ev);
+  }
+  if (stage) (void)hipHostFree(stage);
+}
 
 // ---------------------------------------------------------------- Engine
 
@@ -265,6 +291,9 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
   RK_REQUIRE(par.top_k == 0 || par.pass_points == 1, RKHSBA_EINVAL, "top-k pair selection needs per-point walks");
   RK_REQUIRE(par.pass_points != 8 || kind == RKHSBA_FEAT_CLASS_ID, RKHSBA_EINVAL, "8-point passes need class ids");
   const int Dk = kind == RKHSBA_FEAT_CLASS_ID ? 0 : Din;
+  // builds run on their own stream when the engine has one (the server's lanes: a build then does not wait
+  // for the lane's queued iterations); the engine's stream is ordered after the build at the end
+  hipStream_t bst = build_st ? build_st : st;
   if (probs_.empty()) {
     feat_kind = kind;
     D = Dk;
@@ -323,20 +352,20 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       RK_HIP(raw_feat_.reserve((size_t)N * fbytes));
       for (int f = 0; f < K; ++f) {
         RK_HIP(hipMemcpyAsync(raw_xyz_.p + 3 * off[f], xyz[f], sizeof(float) * 3 * n_points[f],
-                              hipMemcpyHostToDevice, st));
+                              hipMemcpyHostToDevice, bst));
         RK_HIP(hipMemcpyAsync(raw_feat_.p + fbytes * off[f], feats[f], fbytes * n_points[f], hipMemcpyHostToDevice,
-                              st));
+                              bst));
         xp[f] = raw_xyz_.p + 3 * off[f];
         fp[f] = raw_feat_.p + fbytes * off[f];
       }
     }
-    hipEvent_t tb = prof_begin();
+    hipEvent_t tb = bst == st ? prof_begin() : nullptr;
     RK_HIP(d_xyz_ptrs_.reserve(K));
     RK_HIP(d_feat_ptrs_.reserve(K));
     RK_HIP(d_in_off_.reserve(K + 1));
-    RK_HIP(hipMemcpyAsync(d_xyz_ptrs_.p, xp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, st));
-    RK_HIP(hipMemcpyAsync(d_feat_ptrs_.p, fp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, st));
-    RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_xyz_ptrs_.p, xp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, bst));
+    RK_HIP(hipMemcpyAsync(d_feat_ptrs_.p, fp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, bst));
+    RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, bst));
 
     // cell coordinates and per-frame bounds
     const int n_dmin = kind == RKHSBA_FEAT_DENSE_F32 ? Dp : 0;  // per-dimension minima of FP32 features
@@ -352,10 +381,10 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     for (int d = 0; d < n_dmin; ++d) mm[6 * K + 3 + d] = 0x7f800000;  // feature minima (+inf until the build)
     RK_HIP(cell_.reserve((size_t)N * 3));
     RK_HIP(minmax_.reserve(mm.size()));
-    RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, st));
-    RK_HIP(launch_cell_coords(d_xyz_ptrs_.p, d_in_off_.p, K, N, kc0.inv_cell, cell_.p, minmax_.p, st));
-    RK_HIP(hipMemcpyAsync(mm.data(), minmax_.p, sizeof(int32_t) * mm.size(), hipMemcpyDeviceToHost, st));
-    RK_HIP(hipStreamSynchronize(st));
+    RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, bst));
+    RK_HIP(launch_cell_coords(d_xyz_ptrs_.p, d_in_off_.p, K, N, kc0.inv_cell, cell_.p, minmax_.p, bst));
+    RK_HIP(hipMemcpyAsync(mm.data(), minmax_.p, sizeof(int32_t) * mm.size(), hipMemcpyDeviceToHost, bst));
+    RK_HIP(hipStreamSynchronize(bst));
     RK_REQUIRE(mm[6 * K] == 0, RKHSBA_EINVAL, "non-finite or out-of-range point coordinate");
 
     // grids (frame-local offsets for the build)
@@ -394,12 +423,12 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_REQUIRE(rows_total < (1LL << 31), RKHSBA_ENOMEM, "cell-row table too large");
     p->bin_bits = 3 * bin_axis_bits;
     RK_HIP(d_bframes_.reserve(K));
-    RK_HIP(hipMemcpyAsync(d_bframes_.p, fr.data(), sizeof(FrameInfo) * K, hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_bframes_.p, fr.data(), sizeof(FrameInfo) * K, hipMemcpyHostToDevice, bst));
 
     // resident ranges
-    p->pbase = points_.alloc(N, st);
+    p->pbase = points_.alloc(N, bst);
     p->n_rows = std::max<int64_t>(rows_total, 1);
-    p->rbase = rows_.alloc(p->n_rows, st);
+    p->rbase = rows_.alloc(p->n_rows, bst);
     float4* d_pts = static_cast<float4*>(points_.ptr(0)) + p->pbase;
     int32_t* d_perm = static_cast<int32_t*>(points_.ptr(1)) + p->pbase;
     uint32_t* d_keys = static_cast<uint32_t*>(points_.ptr(2)) + p->pbase;
@@ -411,7 +440,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(v1_.reserve(N));
     RK_HIP(k2_.reserve(N));
     RK_HIP(v2_.reserve(N));
-    RK_HIP(launch_cell_keys(cell_.p, d_in_off_.p, d_bframes_.p, K, N, k1_.p, v1_.p, st));
+    RK_HIP(launch_cell_keys(cell_.p, d_in_off_.p, d_bframes_.p, K, N, k1_.p, v1_.p, bst));
     std::vector<SortTile> tiles;
     std::vector<SortSeg> segs(K);
     for (int f = 0; f < K; ++f) {
@@ -425,35 +454,35 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(d_tiles_.reserve(tiles.size()));
     RK_HIP(d_segs_.reserve(K));
     RK_HIP(hist_scratch_.reserve(tiles.size() * 256));
-    RK_HIP(hipMemcpyAsync(d_tiles_.p, tiles.data(), sizeof(SortTile) * tiles.size(), hipMemcpyHostToDevice, st));
-    RK_HIP(hipMemcpyAsync(d_segs_.p, segs.data(), sizeof(SortSeg) * K, hipMemcpyHostToDevice, st));
+    RK_HIP(hipMemcpyAsync(d_tiles_.p, tiles.data(), sizeof(SortTile) * tiles.size(), hipMemcpyHostToDevice, bst));
+    RK_HIP(hipMemcpyAsync(d_segs_.p, segs.data(), sizeof(SortSeg) * K, hipMemcpyHostToDevice, bst));
     int key_bits = 1;
     while (key_bits < 32 && (1ull << key_bits) < max_cells) ++key_bits;
     bool in_tmp = false;
     RK_HIP(launch_radix_sort(k1_.p, v1_.p, k2_.p, v2_.p, hist_scratch_.p, d_tiles_.p, (int)tiles.size(), d_segs_.p, K,
-                             key_bits, st, &in_tmp));
+                             key_bits, bst, &in_tmp));
     uint32_t* sk = in_tmp ? k2_.p : k1_.p;
     uint32_t* sv = in_tmp ? v2_.p : v1_.p;
     RK_HIP(launch_gather(d_xyz_ptrs_.p, d_feat_ptrs_.p, kind, D, std::max(Dp, 1),
-                         d_bframes_.p, d_in_off_.p, K, N, sv, d_pts, d_feat, d_perm, minmax_.p + 6 * K + 1, st));
-    RK_HIP(hipMemcpyAsync(d_keys, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, st));
+                         d_bframes_.p, d_in_off_.p, K, N, sv, d_pts, d_feat, d_perm, minmax_.p + 6 * K + 1, bst));
+    RK_HIP(hipMemcpyAsync(d_keys, sk, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, bst));
     RK_HIP(launch_feature_min(static_cast<const float*>(d_feat), N, n_dmin,
-                              reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 3), st));
+                              reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 3), bst));
 
     // cell-row tables
     RK_HIP(row_sizes_.reserve(rows_total));
     RK_HIP(scan_tmp_.reserve(rows_total / kScanTileElems + 2));
     RK_HIP(d_total_.reserve(1));
     RK_HIP(launch_rows(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows, rows_total, row_sizes_.p, scan_tmp_.p,
-                       d_total_.p, st));
+                       d_total_.p, bst));
     uint64_t xt_total = 0;
     int32_t neg = 0;
-    RK_HIP(hipMemcpyAsync(&xt_total, d_total_.p, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    RK_HIP(hipMemcpyAsync(&neg, minmax_.p + 6 * K + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipMemcpyAsync(&xt_total, d_total_.p, sizeof(uint64_t), hipMemcpyDeviceToHost, bst));
+    RK_HIP(hipMemcpyAsync(&neg, minmax_.p + 6 * K + 1, sizeof(int32_t), hipMemcpyDeviceToHost, bst));
     std::vector<uint32_t> dmin(std::max(n_dmin, 1));
     if (n_dmin > 0)
-      RK_HIP(hipMemcpyAsync(dmin.data(), minmax_.p + 6 * K + 3, sizeof(uint32_t) * n_dmin, hipMemcpyDeviceToHost, st));
-    RK_HIP(hipStreamSynchronize(st));
+      RK_HIP(hipMemcpyAsync(dmin.data(), minmax_.p + 6 * K + 3, sizeof(uint32_t) * n_dmin, hipMemcpyDeviceToHost, bst));
+    RK_HIP(hipStreamSynchronize(bst));
     p->negative_features = neg != 0;
     p->c_positive = false;
     if (!p->negative_features)
@@ -465,25 +494,25 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     compute_constants(p);
     RK_REQUIRE(xt_total < (1ull << 31), RKHSBA_ENOMEM, "cell table too large");
     p->n_xt = std::max<int64_t>((int64_t)xt_total, 1);
-    p->xbase = xtab_.alloc(p->n_xt, st);
+    p->xbase = xtab_.alloc(p->n_xt, bst);
     RK_HIP(launch_xtab(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows,
                        static_cast<uint32_t*>(xtab_.ptr(0)) + p->xbase,
-                       reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 2), st));
+                       reinterpret_cast<uint32_t*>(minmax_.p + 6 * K + 2), bst));
     uint32_t n_cells = 0;
-    RK_HIP(hipMemcpyAsync(&n_cells, minmax_.p + 6 * K + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    RK_HIP(hipMemcpyAsync(&n_cells, minmax_.p + 6 * K + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, bst));
 
     // frame table entries with pool offsets
-    p->slot0 = slots_.alloc(K, st);
-    p->sbase = state_.alloc(1, st);
+    p->slot0 = slots_.alloc(K, bst);
+    p->sbase = state_.alloc(1, bst);
     for (int f = 0; f < K; ++f) {
       fr[f].pt_off += p->pbase;
       fr[f].row_off += p->rbase;
       fr[f].xt_off = p->xbase;
     }
     RK_HIP(hipMemcpyAsync(static_cast<FrameInfo*>(slots_.ptr(0)) + p->slot0, fr.data(), sizeof(FrameInfo) * K,
-                          hipMemcpyHostToDevice, st));
+                          hipMemcpyHostToDevice, bst));
     prof_end(RKHSBA_PROF_BUILD, tb);
-    RK_HIP(hipStreamSynchronize(st));
+    RK_HIP(hipStreamSynchronize(bst));
     prof_collect();
     p->frames = std::move(fr);
     p->occupancy = (double)N / std::max<uint32_t>(n_cells, 1u);
@@ -675,6 +704,17 @@ void Engine::read_source_counts(Problem* p, int m, int64_t* counts) {
   }
 }
 
+void Engine::copy_results_async(Problem* p, int count, double* poses, double* loss, double* pairs, int32_t* state) {
+  RK_REQUIRE(p->hbase >= 0 && count <= p->n_hist, RKHSBA_ESTATE, "no history of that length");
+  RK_HIP(hipMemcpyAsync(poses, poses_ptr(p), sizeof(double) * 12 * p->K, hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(loss, static_cast<double*>(hist_.ptr(0)) + p->hbase, sizeof(double) * count,
+                        hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(pairs, static_cast<double*>(hist_.ptr(1)) + p->hbase, sizeof(double) * count,
+                        hipMemcpyDeviceToHost, st));
+  RK_HIP(hipMemcpyAsync(state, static_cast<int32_t*>(state_.ptr(0)) + 2 * p->sbase, 2 * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+}
+
 int32_t Engine::read_status(Problem* p) {
   int32_t s[2] = {0, 0};
   RK_HIP(hipMemcpyAsync(s, static_cast<int32_t*>(state_.ptr(0)) + 2 * p->sbase, sizeof(s), hipMemcpyDeviceToHost,
@@ -688,6 +728,8 @@ int32_t Engine::read_status(Problem* p) {
 template <typename T>
 void Engine::need(DBuf<T>& b, size_t count, const char* what) {
   if (!arena_) {
+    // growing frees the old buffer, which work still queued on the stream may use
+    if (std::max<size_t>(count, 1) > b.n && b.p) RK_HIP(hipStreamSynchronize(st));
     RK_HIP(b.reserve(count));
     return;
   }
@@ -877,8 +919,32 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   need(lay.d_blk_list, blist.size(), "blk_list");
   need(lay.d_vec_start, vstart_all.size(), "vec_start");
   need(lay.d_vec_list, vlist.size(), "vec_list");
+  // The host tables go to the device through the layout's pinned staging buffer, whose previous uploads
+  // must have completed before it is rewritten (the host then need not wait for the stream here).
+  size_t stage_bytes = 0;
+  auto stage_size = [&](size_t bytes) { stage_bytes += (bytes + 255) & ~(size_t)255; };
+  stage_size(sizeof(EdgeInfo) * E_total);
+  stage_size(sizeof(int64_t) * E_total);
+  stage_size(sizeof(int32_t) * E_total);
+  stage_size(sizeof(SortTile) * tiles.size());
+  stage_size(sizeof(SortSeg) * E_total);
+  stage_size(sizeof(KConst) * kcs.size());
+  stage_size(sizeof(ProbSys) * sys.size());
+  stage_size(sizeof(int32_t) * bstart_all.size());
+  stage_size(sizeof(int32_t) * blist.size());
+  stage_size(sizeof(int32_t) * vstart_all.size());
+  stage_size(sizeof(int32_t) * vlist.size());
+  uint8_t* stage = lay.stage_for(stage_bytes, arena_ != nullptr);
+  size_t stage_off = 0;
   auto up = [&](void* dst, const void* src, size_t bytes) {
-    if (bytes) RK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    if (!bytes) return;
+    if (!stage) {
+      RK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+      return;
+    }
+    std::memcpy(stage + stage_off, src, bytes);
+    RK_HIP(hipMemcpyAsync(dst, stage + stage_off, bytes, hipMemcpyHostToDevice, st));
+    stage_off += (bytes + 255) & ~(size_t)255;
   };
   up(lay.d_edges.p, info.data(), sizeof(EdgeInfo) * E_total);
   up(lay.d_ent_off.p, ent.data(), sizeof(int64_t) * E_total);
@@ -914,7 +980,11 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   if (!arena_)
     for (size_t i = 0; i < sizeof(before) / sizeof(before[0]); ++i)
       if (before[i] != after[i]) ++scratch_gen_;
-  RK_HIP(hipStreamSynchronize(st));  // host tables above go out of scope
+  if (stage) {
+    RK_HIP(hipEventRecord(lay.stage_ev, st));  // the staging buffer is free again once this completes
+  } else {
+    RK_HIP(hipStreamSynchronize(st));  // host tables above go out of scope
+  }
 
   lay.uses = 0;
   lay.ids = std::move(ids);
@@ -1045,7 +1115,7 @@ void Engine::iterate(SetLayout& lay, int n) {
   if (n <= 0) return;
   // A graph pays for its capture only when it is replayed: capture on a
   // layout's second use, or when this call runs several iterations.
-  const bool graph = use_graphs && !prof && (n > 1 || lay.uses >= 1);
+  const bool graph = use_graphs && !prof && (n > 1 || lay.uses >= graph_min_uses);
   ++lay.uses;
   if (!graph) {
     for (int i = 0; i < n; ++i) record_iteration(lay);

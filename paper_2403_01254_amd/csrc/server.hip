@@ -65,16 +65,41 @@ struct Req {
 
 namespace {
 
+// A retiring request: its results on their way to a pinned host slot.
+struct Retiring {
+  std::shared_ptr<Req> q;
+  hipEvent_t ev = nullptr;
+  int slot = -1;
+};
+
+constexpr int kRetireSlots = 128;
+constexpr size_t kRetireSlotBytes = 16384;  // poses, loss and pair-count histories, status
+
 struct Lane {
   int id = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t build_stream = nullptr;        // admission builds (the lane's iterations keep running)
   std::unique_ptr<Engine> eng;
   SetLayout lay;
   std::thread worker;
   std::deque<std::shared_ptr<Req>> queue;    // guarded by the server mutex
   std::vector<std::shared_ptr<Req>> active;  // worker thread only
   int64_t dev_bytes = 0;                     // the engine's device memory, guarded by the server mutex
+  hipEvent_t iter_ev[2] = {nullptr, nullptr};  // the last two batch iterations (bounds the host's lead)
+  int iter_next = 0;
+  // Retirement: the worker queues the copy of a finished request's results to a pinned slot; the
+  // completer thread waits for each copy in order, hands the results to the waiter, and returns the
+  // request's problem to the worker, which frees its device memory (guarded by rmu).
+  std::mutex rmu;
+  std::condition_variable rcv;
+  std::deque<Retiring> retiring;
+  std::vector<int> done_probs;
+  bool rstop = false;
+  std::thread completer;
+  uint8_t* pinned = nullptr;
+  std::vector<int> free_slots;
+  std::vector<hipEvent_t> free_events;
 };
 
 }  // namespace
@@ -132,6 +157,103 @@ struct rkhsba_server {
     finish(q, status, msg);
   }
 
+  // Bytes of a request's results in a pinned slot: poses, loss and pair-count histories, (iter, status).
+  static size_t result_bytes(const Req& q) { return sizeof(double) * (12 * (size_t)q.K + 2 * (size_t)(q.n_iter + 1)) + 8; }
+
+  // Starts the copy of a finished request's results to a pinned slot and hands it to the lane's completer
+  // thread; the request's device memory stays reserved until the copy has completed.  Falls back to the
+  // synchronous retire() when no slot fits.
+  void retire_async(Lane& L, const std::shared_ptr<Req>& q) {
+    Retiring r;
+    {
+      std::lock_guard<std::mutex> lk(L.rmu);
+      if (L.free_slots.empty() || result_bytes(*q) > kRetireSlotBytes) {
+        r.slot = -1;
+      } else {
+        r.slot = L.free_slots.back();
+        L.free_slots.pop_back();
+        if (!L.free_events.empty()) {
+          r.ev = L.free_events.back();
+          L.free_events.pop_back();
+        }
+      }
+    }
+    if (r.slot < 0) {
+      retire(L, q);
+      return;
+    }
+    r.q = q;
+    if (!r.ev) RK_HIP(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+    uint8_t* dst = L.pinned + (size_t)r.slot * kRetireSlotBytes;
+    double* poses = reinterpret_cast<double*>(dst);
+    double* loss = poses + 12 * q->K;
+    double* pairs = loss + (q->n_iter + 1);
+    L.eng->copy_results_async(L.eng->problem(q->prob), q->n_iter + 1, poses, loss, pairs,
+                              reinterpret_cast<int32_t*>(pairs + q->n_iter + 1));
+    RK_HIP(hipEventRecord(r.ev, L.stream));
+    {
+      std::lock_guard<std::mutex> lk(L.rmu);
+      L.retiring.push_back(r);
+    }
+    L.rcv.notify_all();
+  }
+
+  // Completer thread of a lane: delivers results in the order their copies were queued.
+  void complete(Lane& L) {
+    (void)hipSetDevice(opt.device);
+    for (;;) {
+      Retiring r;
+      {
+        std::unique_lock<std::mutex> lk(L.rmu);
+        L.rcv.wait(lk, [&] { return L.rstop || !L.retiring.empty(); });
+        if (L.retiring.empty()) return;  // stopping and drained
+        r = L.retiring.front();
+      }
+      const hipError_t e = hipEventSynchronize(r.ev);
+      const std::shared_ptr<Req> q = r.q;
+      int status = e == hipSuccess ? RKHSBA_OK : RKHSBA_EDEVICE;
+      std::string msg = e == hipSuccess ? "" : std::string("result copy: ") + hipGetErrorString(e);
+      if (e == hipSuccess) {
+        const uint8_t* src = L.pinned + (size_t)r.slot * kRetireSlotBytes;
+        const double* poses = reinterpret_cast<const double*>(src);
+        const double* loss = poses + 12 * q->K;
+        const double* pairs = loss + (q->n_iter + 1);
+        const int32_t* state = reinterpret_cast<const int32_t*>(pairs + q->n_iter + 1);
+        std::copy(poses, poses + 12 * q->K, q->poses.begin());
+        q->loss.assign(loss, loss + q->n_iter + 1);
+        q->pairs.assign(pairs, pairs + q->n_iter + 1);
+        if (state[1] != 0) {
+          status = RKHSBA_ENOTPD;
+          msg = "Cholesky pivot not positive in a Gauss-Newton step";
+        }
+      }
+      {
+        std::lock_guard<std::mutex> lk(L.rmu);
+        L.retiring.pop_front();
+        L.free_slots.push_back(r.slot);
+        L.free_events.push_back(r.ev);
+        L.done_probs.push_back(q->prob);
+      }
+      L.rcv.notify_all();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (double v : q->pairs) stats.pair_evals += (int64_t)v;
+      }
+      q->prob = -1;
+      finish(q, status, msg);
+    }
+  }
+
+  // Frees the device memory of the requests the completer has delivered (worker thread).
+  void release_delivered(Lane& L) {
+    std::vector<int> probs;
+    {
+      std::lock_guard<std::mutex> lk(L.rmu);
+      probs.swap(L.done_probs);
+    }
+    for (int id : probs) L.eng->remove_problem(id);
+  }
+
   void drop(Lane& L, const std::shared_ptr<Req>& q, int code, const std::string& msg) {
     if (q->prob >= 0) L.eng->remove_problem(q->prob);
     q->prob = -1;
@@ -140,15 +262,19 @@ struct rkhsba_server {
 
   void run(Lane& L) {
     (void)hipSetDevice(opt.device);
+    // lane 1 (large requests) runs at most lane1_max_active of them at once
+    const int max_active = (L.id == 1 && opt.lane1_max_active > 0) ? std::min(opt.lane1_max_active, opt.max_active)
+                                                                   : opt.max_active;
     for (;;) {
       std::vector<std::shared_ptr<Req>> admit;
+      release_delivered(L);
       {
         std::unique_lock<std::mutex> lk(mu);
         if (L.active.empty()) cv_work.wait(lk, [&] { return stop || !L.queue.empty(); });
         if (stop) break;
         int64_t work = 0;
         for (const auto& a : L.active) work += a->entries;
-        while (!L.queue.empty() && (int)(L.active.size() + admit.size()) < opt.max_active) {
+        while (!L.queue.empty() && (int)(L.active.size() + admit.size()) < max_active) {
           const std::shared_ptr<Req>& q = L.queue.front();
           const bool idle = L.active.empty() && admit.empty();
           if (!idle && committed + q->est_bytes > opt.hbm_budget_bytes) break;
@@ -165,6 +291,28 @@ struct rkhsba_server {
           q->prob = L.eng->add_problem_auto(q->par, q->K, q->n_points.data(), q->xyz.data(), q->feat_kind, q->D,
                                             q->feats.data(), q->is_device != 0);
           Problem* p = L.eng->problem(q->prob);
+          if (L.id == 0 && lanes.size() > 1 && opt.lane_split_work > 0.0) {
+            // The build measured the points per occupied r_c-cube: entries x that occupancy estimates the
+            // candidates a Gauss-Newton iteration tests.  A request above the split goes to lane 1 (it is
+            // built there again), so that it does not slow the iterations of the small requests here.
+            const double occ = p->occupancy_r > 0.0 ? p->occupancy_r : p->occupancy;
+            if ((double)q->entries * occ > opt.lane_split_work) {
+              L.eng->remove_problem(q->prob);
+              q->prob = -1;
+              {
+                std::lock_guard<std::mutex> lk(mu);
+                committed -= q->est_bytes;
+                q->admitted = false;
+                auto& Q = lanes[1]->queue;
+                auto pos = std::find_if(Q.begin(), Q.end(), [&](const std::shared_ptr<Req>& o) {
+                  return o->ticket > q->ticket;
+                });
+                Q.insert(pos, q);
+              }
+              cv_work.notify_all();
+              continue;
+            }
+          }
           L.eng->upload_poses(p, q->poses.data());
           L.eng->reset_state(p);
           q->t_admit = Clock::now();
@@ -183,6 +331,9 @@ struct rkhsba_server {
           items.push_back(SetItem{L.eng->problem(q->prob), q->edges.data(), q->E, q->par.fixed_frame, q->n_iter});
           all_final = all_final && q->evals == q->n_iter;
         }
+        // at most two batch iterations in flight: the host prepares the next while the device runs one
+        hipEvent_t& slot = L.iter_ev[L.iter_next];
+        if (slot) RK_HIP(hipEventSynchronize(slot));
         L.eng->prepare(L.lay, items);
         if (all_final) {
           L.eng->evaluate(L.lay, MODE_LOSS);
@@ -190,6 +341,9 @@ struct rkhsba_server {
         } else {
           L.eng->iterate(L.lay, 1);
         }
+        if (!slot) RK_HIP(hipEventCreateWithFlags(&slot, hipEventDisableTiming));
+        RK_HIP(hipEventRecord(slot, L.stream));
+        L.iter_next ^= 1;
         const int64_t mine = L.eng->device_bytes();
         {
           std::lock_guard<std::mutex> lk(mu);
@@ -203,7 +357,7 @@ struct rkhsba_server {
         std::vector<std::shared_ptr<Req>> still;
         for (auto& q : L.active) {
           q->evals += 1;
-          if (q->evals > q->n_iter) retire(L, q);
+          if (q->evals > q->n_iter) retire_async(L, q);
           else still.push_back(q);
         }
         L.active.swap(still);
@@ -212,7 +366,14 @@ struct rkhsba_server {
         L.active.clear();
       }
     }
-    // shutting down: drop what is active or queued in this lane
+    // shutting down: results in flight are delivered; drop what is active or queued in this lane
+    {
+      std::unique_lock<std::mutex> lk(L.rmu);
+      L.rcv.wait(lk, [&] { return L.retiring.empty(); });
+      L.rstop = true;
+    }
+    L.rcv.notify_all();
+    release_delivered(L);
     for (auto& q : L.active) drop(L, q, RKHSBA_ESTATE, "server shut down");
     L.active.clear();
     std::deque<std::shared_ptr<Req>> rest;
@@ -231,12 +392,26 @@ struct rkhsba_server {
     cv_work.notify_all();
     for (auto& L : lanes)
       if (L->worker.joinable()) L->worker.join();
+    for (auto& L : lanes) {
+      {
+        std::lock_guard<std::mutex> lk(L->rmu);
+        L->rstop = true;
+      }
+      L->rcv.notify_all();
+      if (L->completer.joinable()) L->completer.join();
+    }
     (void)hipSetDevice(opt.device);
     for (auto& L : lanes) {
       if (L->stream) (void)hipStreamSynchronize(L->stream);
+      if (L->build_stream) (void)hipStreamSynchronize(L->build_stream);
       L->lay.drop_graph();
       L->eng.reset();
       if (L->own_stream) (void)hipStreamDestroy(L->stream);
+      if (L->build_stream) (void)hipStreamDestroy(L->build_stream);
+      if (L->pinned) (void)hipHostFree(L->pinned);
+      for (hipEvent_t ev : L->free_events) (void)hipEventDestroy(ev);
+      for (hipEvent_t ev : L->iter_ev)
+        if (ev) (void)hipEventDestroy(ev);
     }
     lanes.clear();
   }
@@ -259,6 +434,8 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->lanes = 1;
   o->lane_split_entries = 2000000;
   o->lane_work_entries = 0;
+  o->lane1_max_active = 1;
+  o->lane_split_work = 5e8;
 }
 
 int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
@@ -269,7 +446,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
        opt->pass_points != 32 && opt->pass_points != 64) ||
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)) || opt->lanes < 1 ||
-      opt->lanes > 2 || opt->lane_split_entries < 0 || opt->lane_work_entries < 0)
+      opt->lanes > 2 || opt->lane_split_entries < 0 || opt->lane_work_entries < 0 || opt->lane1_max_active < 0 ||
+      !(opt->lane_split_work >= 0.0))
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -304,12 +482,24 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
       L->eng.reset(new Engine(opt->device, L->stream, 0));
       L->eng->use_graphs = opt->use_graphs != 0;
       L->eng->fp32_sums = opt->hessian_fp32 != 0;
+      // a batch iteration's graph pays for its capture only if the active set stays the same a while
+      L->eng->graph_min_uses = 3;
+      if (hipStreamCreateWithFlags(&L->build_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void**>(&L->pinned), kRetireSlots * kRetireSlotBytes,
+                        hipHostMallocDefault) != hipSuccess) {
+        rc = RKHSBA_EDEVICE;
+        s->lanes.push_back(std::move(L));
+        break;
+      }
+      L->eng->build_st = L->build_stream;
+      for (int k = kRetireSlots - 1; k >= 0; --k) L->free_slots.push_back(k);
       s->lanes.push_back(std::move(L));
     }
     if (rc == RKHSBA_OK)
       for (auto& L : s->lanes) {
         Lane* lp = L.get();
         L->worker = std::thread([s, lp] { s->run(*lp); });
+        L->completer = std::thread([s, lp] { s->complete(*lp); });
       }
   } catch (...) {
     rc = RKHSBA_EDEVICE;

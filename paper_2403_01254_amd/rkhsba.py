@@ -62,6 +62,8 @@ class ServerOptions(ctypes.Structure):
         ("lanes", ctypes.c_int),
         ("lane_split_entries", ctypes.c_int64),
         ("lane_work_entries", ctypes.c_int64),
+        ("lane1_max_active", ctypes.c_int),
+        ("lane_split_work", ctypes.c_double),
     ]
 
 
@@ -425,7 +427,7 @@ class Server:
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
                  use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000,
-                 lane_work_entries=0):
+                 lane_work_entries=0, lane1_max_active=1, lane_split_work=5e8):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
@@ -436,6 +438,8 @@ class Server:
         o.stream = ctypes.c_void_p(int(stream)) if stream else None
         o.lanes, o.lane_split_entries = int(lanes), int(lane_split_entries)
         o.lane_work_entries = int(lane_work_entries)
+        o.lane1_max_active = int(lane1_max_active)
+        o.lane_split_work = float(lane_split_work)
         self.opts = o
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))
