@@ -325,7 +325,7 @@ def main():
                     help="lidar is the headline configuration; the others are for kernel studies")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=48,
+    ap.add_argument("--serving-requests", type=int, default=128,
                     help="requests in the serving measurement (0: skip); the serving workload's full stream is 512")
     ap.add_argument("--serving-lanes", type=int, default=2, choices=[1, 2],
                     help="concurrent batches of the request server (large requests in the second)")
