@@ -274,9 +274,15 @@ int rkhsba_export_source_counts(rkhsba_ctx* ctx, const double* poses, int m, int
 
 /* Debug/parity: the voxel structure of one frame.  perm (N_m int32): sorted
  * position -> original index; keys (N_m uint32): sorted cell keys; origin[3],
- * dims[3]: the frame's cell grid.  Any pointer may be NULL. */
+ * dims[3]: the frame's cell grid (cells of edge r_c / cell_subdiv, keys
+ * ((kz * NY) + ky) * NX + kx relative to the origin).  label_layers: 0, or for
+ * class ids in a label-stacked frame the number of class-id layers (largest id
+ * + 1); the key's z index is then id * NZ + kz, so that the points of one id
+ * are contiguous.  Class ids are stacked when every frame's keys fit 32 bits
+ * and the cell-row tables stay within 16 rows per point (+ 2^20).  Any pointer
+ * may be NULL. */
 int rkhsba_export_voxels(rkhsba_ctx* ctx, int frame, int32_t* perm, uint32_t* keys, int32_t* origin,
-                         int32_t* dims);
+                         int32_t* dims, int32_t* label_layers);
 
 /* Stage timing for measurement.  When enabled, the context brackets each
  * stage's launches with HIP events on its own stream and, at the end of every

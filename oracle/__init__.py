@@ -74,7 +74,7 @@ def lib():
         L.oracle_edge_sums.argtypes = [P, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp]
         L.oracle_pairs.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ip]
         L.oracle_pairs.restype = ctypes.c_int64
-        L.oracle_voxels.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+        L.oracle_voxels.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                     ip, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.oracle_se3_exp.argtypes = [dp, dp]
         L.oracle_cholesky_solve.argtypes = [ctypes.c_int, dp, dp, dp]
@@ -193,15 +193,18 @@ def pairs(prob: Problem, poses, m, n):
     return out[:total]
 
 
-def voxels(xyz, inv_cell, margin=0):
-    """Stable voxel sort of one frame: (perm, keys, origin, dims)."""
+def voxels(xyz, inv_cell, margin=0, labels=None):
+    """Stable voxel sort of one frame: (perm, keys, origin, dims); with class
+    ids (labels) the label-stacked keys (one layer of the z extent per id)."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
     N = len(xyz)
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint16).reshape(N)
     perm = np.zeros(N, dtype=np.int32)
     keys = np.zeros(N, dtype=np.uint32)
     origin = np.zeros(3, dtype=np.int32)
     dims = np.zeros(3, dtype=np.int32)
-    rc = lib().oracle_voxels(xyz.ctypes.data, N, float(inv_cell), int(margin), _ptr(perm, ctypes.c_int32),
+    rc = lib().oracle_voxels(xyz.ctypes.data, None if lab is None else lab.ctypes.data, N, float(inv_cell),
+                             int(margin), _ptr(perm, ctypes.c_int32),
                              _ptr(keys, ctypes.c_uint32), _ptr(origin, ctypes.c_int32), _ptr(dims, ctypes.c_int32))
     if rc != 0:
         raise ValueError("oracle_voxels failed")

@@ -767,7 +767,7 @@ static int cmp_key_idx(const void* a, const void* b) {
   return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
 }
 
-int oracle_voxels(const float* xyz, int64_t N, double inv_cell, int margin,
+int oracle_voxels(const float* xyz, const uint16_t* labels, int64_t N, double inv_cell, int margin,
                   int32_t* perm, uint32_t* keys, int32_t* origin, int32_t* dims) {
   if (N < 1 || N > 0x7fffffff || !(inv_cell > 0.0) || margin < 0) return -1;
   int64_t lo[3], hi[3];
@@ -785,13 +785,18 @@ int oracle_voxels(const float* xyz, int64_t N, double inv_cell, int margin,
     origin[a] = (int32_t)(lo[a] - margin);
     dims[a] = (int32_t)d[a];
   }
-  if (total >= 0xffffffffLL) {
+  int64_t layers = 1;
+  if (labels)
+    for (int64_t i = 0; i < N; ++i)
+      if ((int64_t)labels[i] + 1 > layers) layers = (int64_t)labels[i] + 1;
+  if (total * layers >= 0xffffffffLL) {
     free(k);
     return -1;
   }
   key_idx* ki = (key_idx*)malloc(sizeof(key_idx) * (size_t)N);
   for (int64_t i = 0; i < N; ++i) {
     int64_t kx = k[3 * i] - origin[0], ky = k[3 * i + 1] - origin[1], kz = k[3 * i + 2] - origin[2];
+    if (labels) kz += (int64_t)labels[i] * d[2];
     ki[i].key = (uint32_t)((kz * d[1] + ky) * d[0] + kx);
     ki[i].idx = (int32_t)i;
   }

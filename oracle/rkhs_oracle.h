@@ -79,9 +79,12 @@ int64_t oracle_pairs(const oracle_problem* P, const double* poses, int m, int n,
 /* Voxel structure of one frame: cell coordinates k = floor(x * inv_cell)
  * (FP64), grid origin = min k - margin, dims = max k - min k + 1 + 2 margin,
  * linear key ((kz-oz)*NY + (ky-oy))*NX + (kx-ox), points stably sorted by
- * key.  Outputs perm (sorted position -> original index), sorted keys, and
- * origin[3], dims[3].  Returns 0 or -1. */
-int oracle_voxels(const float* xyz, int64_t N, double inv_cell, int margin,
+ * key.  With class ids (labels != NULL) the frame is label-stacked: the z
+ * index becomes label*NZ + (kz-oz), one layer of NZ cells per class id.
+ * Outputs perm (sorted position -> original index), sorted keys, and
+ * origin[3], dims[3] (the geometric grid).  Returns 0 or -1 (keys would not
+ * fit 32 bits). */
+int oracle_voxels(const float* xyz, const uint16_t* labels, int64_t N, double inv_cell, int margin,
                   int32_t* perm, uint32_t* keys, int32_t* origin, int32_t* dims);
 
 /* SE(3) exponential of xi = [rho; phi] (closed form); T: 12 doubles. */

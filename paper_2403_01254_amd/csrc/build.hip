@@ -18,12 +18,14 @@ __device__ inline void frame_of(const int64_t* __restrict__ off, int K, int64_t 
   local = i - off[f];
 }
 
-// k = floor(x * inv_cell) per axis (FP64), and per-frame min/max.
+// k = floor(x * inv_cell) per axis (FP64), and per-frame min/max (and, with
+// class ids, the largest id).
 // minmax layout: [f*6 + 0..2] min, [f*6 + 3..5] max; [K*6] error flag.
 __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __restrict__ xyz,
                                                           const int64_t* __restrict__ off, int K, int64_t n_total,
-                                                          double inv_cell, int32_t* __restrict__ cell,
-                                                          int32_t* __restrict__ minmax) {
+                                                          double inv_cell, const void* const* __restrict__ cls,
+                                                          int32_t* __restrict__ cell, int32_t* __restrict__ minmax,
+                                                          int32_t* __restrict__ label_max) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool live = i < n_total;
   int f = -1;
@@ -63,11 +65,23 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __
       atomicMax(&minmax[f * 6 + 3 + a], mx);
     }
   }
+  if (label_max) {
+    int lb = live ? (int)static_cast<const uint16_t*>(cls[f])[l] : -1;
+    if (same) {
+      for (int o = 32; o > 0; o >>= 1) lb = max(lb, __shfl_xor(lb, o, 64));
+      if ((threadIdx.x & 63) == 0 && f0 >= 0) atomicMax(&label_max[f0], lb);
+    } else if (live) {
+      atomicMax(&label_max[f], lb);
+    }
+  }
 }
 
+// Cell key of every point; in a label-stacked frame the class id selects the
+// layer of NZ cells that the point's z cell lies in (kz' = id * NZ + kz).
 __global__ __launch_bounds__(kThreads) void k_cell_keys(const int32_t* __restrict__ cell,
                                                         const int64_t* __restrict__ off,
                                                         const FrameInfo* __restrict__ frames, int K, int64_t n_total,
+                                                        const void* const* __restrict__ cls,
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n_total) return;
@@ -77,9 +91,31 @@ __global__ __launch_bounds__(kThreads) void k_cell_keys(const int32_t* __restric
   const FrameInfo& F = frames[f];
   const uint32_t kx = (uint32_t)(cell[3 * i] - F.org[0]);
   const uint32_t ky = (uint32_t)(cell[3 * i + 1] - F.org[1]);
-  const uint32_t kz = (uint32_t)(cell[3 * i + 2] - F.org[2]);
+  uint32_t kz = (uint32_t)(cell[3 * i + 2] - F.org[2]);
+  if (F.n_lab > 0) kz += (uint32_t)static_cast<const uint16_t*>(cls[f])[l] * (uint32_t)F.dim[2];
   keys[i] = (kz * (uint32_t)F.dim[1] + ky) * (uint32_t)F.dim[0] + kx;
   vals[i] = (uint32_t)l;
+}
+
+// One block per frame: the first point (frame-local sorted index) of each
+// label layer of a label-stacked frame, by binary search over its sorted keys.
+__global__ __launch_bounds__(kThreads) void k_label_starts(const uint32_t* __restrict__ keys,
+                                                           const FrameInfo* __restrict__ frames,
+                                                           const int64_t* __restrict__ lab_off,
+                                                           int32_t* __restrict__ out) {
+  const FrameInfo F = frames[blockIdx.x];
+  if (F.n_lab <= 0) return;
+  const uint32_t* k = keys + F.pt_off;
+  const uint64_t layer = (uint64_t)F.dim[0] * F.dim[1] * F.dim[2];
+  for (int L = threadIdx.x; L <= F.n_lab; L += kThreads) {
+    const uint64_t first = (uint64_t)L * layer;  // smallest key of layer L
+    int lo = 0, hi = F.n;                        // first index with key >= first
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((uint64_t)k[mid] < first) lo = mid + 1; else hi = mid;
+    }
+    out[lab_off[blockIdx.x] + L] = lo;
+  }
 }
 
 // Round to nearest even: float32 -> bfloat16 (finite inputs).
@@ -285,16 +321,27 @@ hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipS
 }
 
 hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
-                              double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st) {
+                              double inv_cell, const void* const* d_class_ptrs, int32_t* d_cell, int32_t* d_minmax,
+                              int32_t* d_label_max, hipStream_t st) {
+  if (d_label_max && !d_class_ptrs) return hipErrorInvalidValue;
   if (n_total > 0)
-    k_cell_coords<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_in_off, K, n_total, inv_cell, d_cell, d_minmax);
+    k_cell_coords<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_in_off, K, n_total, inv_cell, d_class_ptrs,
+                                                        d_cell, d_minmax, d_label_max);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, const FrameInfo* d_frames, int K,
-                            int64_t n_total, uint32_t* d_keys, uint32_t* d_vals, hipStream_t st) {
+                            int64_t n_total, const void* const* d_class_ptrs, uint32_t* d_keys, uint32_t* d_vals,
+                            hipStream_t st) {
   if (n_total > 0)
-    k_cell_keys<<<blocks(n_total), kThreads, 0, st>>>(d_cell, d_in_off, d_frames, K, n_total, d_keys, d_vals);
+    k_cell_keys<<<blocks(n_total), kThreads, 0, st>>>(d_cell, d_in_off, d_frames, K, n_total, d_class_ptrs, d_keys,
+                                                      d_vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_starts(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_lab_off, int K,
+                               int32_t* d_out, hipStream_t st) {
+  if (K > 0) k_label_starts<<<K, kThreads, 0, st>>>(d_keys, d_frames, d_lab_off, d_out);
   return hipGetLastError();
 }
 

@@ -837,7 +837,8 @@ int rkhsba_export_source_counts(rkhsba_ctx* c, const double* poses, int m, int n
   });
 }
 
-int rkhsba_export_voxels(rkhsba_ctx* c, int frame, int32_t* perm, uint32_t* keys, int32_t* origin, int32_t* dims) {
+int rkhsba_export_voxels(rkhsba_ctx* c, int frame, int32_t* perm, uint32_t* keys, int32_t* origin, int32_t* dims,
+                         int32_t* label_layers) {
   return guarded(c, [&]() -> int {
     Problem* p = resident(c);
     Engine& g = *c->eng;
@@ -852,6 +853,7 @@ int rkhsba_export_voxels(rkhsba_ctx* c, int frame, int32_t* perm, uint32_t* keys
       if (origin) origin[a] = F.org[a];
       if (dims) dims[a] = F.dim[a];
     }
+    if (label_layers) *label_layers = F.n_lab;
     return RKHSBA_OK;
   });
 }

@@ -183,6 +183,9 @@ struct Problem {
   int64_t hbase = -1, n_hist = 0;   // history pool range (loss, pair count per evaluation)
   int64_t sbase = -1;               // state pool entry (iter, status)
   int bin_bits = 3;
+  bool stacked = false;             // class ids stacked into label layers in every frame (FrameInfo::n_lab)
+  std::vector<int64_t> lab_off;     // per frame: first entry of its layer starts in lab_start
+  std::vector<int32_t> lab_start;   // per stacked frame, n_lab + 1 entries: first point of each layer
   std::vector<FrameInfo> frames;    // pool offsets
   std::vector<int64_t> n_points;
   int64_t resident_bytes = 0;       // pool bytes held by the problem
@@ -212,7 +215,8 @@ struct SetLayout {
   uint64_t gen = 0;                 // pool generation the tables were built for
   int n_prob = 0, n_max = 0, E = 0;
   int64_t n_entries = 0;
-  int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, bin_bits = 3;
+  int n_pass_total = 0, n_fin_total = 0, n_edge_tiles = 0, n_edge_segs = 0, bin_bits = 3;
+  bool stacked = false;             // every problem of the set is label-stacked
   struct Group {
     int pass_points, pass0, n_pass;
     bool topk;
@@ -288,6 +292,8 @@ class Engine {
   }
   // The same estimate for a given feature row size (bytes per point), without engine state.
   static int64_t estimate_bytes(int K, const int64_t* n_points, int E, int64_t row_bytes);
+  // The resident (pool) part of estimate_bytes; a built problem's resident_bytes replaces it.
+  static int64_t estimate_resident_bytes(int K, const int64_t* n_points, int64_t row_bytes);
 
   void upload_poses(Problem* p, const double* poses);   // host K*12
   // count alias slots of `frame` with the given host poses (count*12); replaces earlier aliases
@@ -384,6 +390,8 @@ class Engine {
   DBuf<SortSeg> d_segs_;
   DBuf<uint32_t> row_sizes_, scan_tmp_;
   DBuf<uint64_t> d_total_;
+  DBuf<int64_t> d_lab_off_;
+  DBuf<int32_t> d_lab_start_;
 
   template <typename T>
   void need(DBuf<T>& b, size_t count, const char* what);

@@ -233,16 +233,19 @@ int64_t Engine::device_bytes() const {
   return b;
 }
 
+int64_t Engine::estimate_resident_bytes(int K, const int64_t* n_points, int64_t row_bytes) {
+  int64_t N = 0;
+  for (int f = 0; f < K; ++f) N += n_points[f];
+  return N * (28 + row_bytes + 12);  // pools + cell tables (typical occupancy)
+}
+
 int64_t Engine::estimate_bytes(int K, const int64_t* n_points, int E, int64_t row_bytes) {
-  int64_t N = 0, nmax = 0;
-  for (int f = 0; f < K; ++f) {
-    N += n_points[f];
-    nmax = std::max(nmax, n_points[f]);
-  }
-  const int64_t per_point = 28 + row_bytes + 12;  // pools + cell tables (typical occupancy)
+  int64_t nmax = 0;
+  for (int f = 0; f < K; ++f) nmax = std::max(nmax, n_points[f]);
   const int64_t per_entry = 16 + 40 + 4 + 3;                // binning keys/values (x2), moments, count, partials
   const int64_t n = 6 * (int64_t)K;
-  return N * per_point + (int64_t)E * nmax * per_entry + 2 * n * n * 8 + (int64_t)E * 2 * kEdgeVals * 8;
+  return estimate_resident_bytes(K, n_points, row_bytes) + (int64_t)E * nmax * per_entry + 2 * n * n * 8 +
+         (int64_t)E * 2 * kEdgeVals * 8;
 }
 
 // Class-id sweep passes whose box is wider than this many truncation radii walk per source point.  On the
@@ -367,9 +370,11 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(hipMemcpyAsync(d_feat_ptrs_.p, fp.data(), sizeof(void*) * K, hipMemcpyHostToDevice, bst));
     RK_HIP(hipMemcpyAsync(d_in_off_.p, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, bst));
 
-    // cell coordinates and per-frame bounds
+    // cell coordinates and per-frame bounds (and largest class ids)
     const int n_dmin = kind == RKHSBA_FEAT_DENSE_F32 ? Dp : 0;  // per-dimension minima of FP32 features
-    std::vector<int32_t> mm(6 * K + 3 + n_dmin);
+    const bool class_ids = kind == RKHSBA_FEAT_CLASS_ID;
+    const int lab0 = 6 * K + 3 + n_dmin;                          // per-frame largest class id
+    std::vector<int32_t> mm(lab0 + (class_ids ? K : 0), -1);
     for (int f = 0; f < K; ++f)
       for (int a = 0; a < 3; ++a) {
         mm[6 * f + a] = INT_MAX;
@@ -382,7 +387,8 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(cell_.reserve((size_t)N * 3));
     RK_HIP(minmax_.reserve(mm.size()));
     RK_HIP(hipMemcpyAsync(minmax_.p, mm.data(), sizeof(int32_t) * mm.size(), hipMemcpyHostToDevice, bst));
-    RK_HIP(launch_cell_coords(d_xyz_ptrs_.p, d_in_off_.p, K, N, kc0.inv_cell, cell_.p, minmax_.p, bst));
+    RK_HIP(launch_cell_coords(d_xyz_ptrs_.p, d_in_off_.p, K, N, kc0.inv_cell, d_feat_ptrs_.p, cell_.p, minmax_.p,
+                              class_ids ? minmax_.p + lab0 : nullptr, bst));
     RK_HIP(hipMemcpyAsync(mm.data(), minmax_.p, sizeof(int32_t) * mm.size(), hipMemcpyDeviceToHost, bst));
     RK_HIP(hipStreamSynchronize(bst));
     RK_REQUIRE(mm[6 * K] == 0, RKHSBA_EINVAL, "non-finite or out-of-range point coordinate");
@@ -407,9 +413,9 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       RK_REQUIRE(cells < 0xffffffffull, RKHSBA_ENOMEM,
                  "frame spans more than 2^32 cells; raise ell or lower cell_subdiv");
       max_cells = std::max(max_cells, cells);
-      F.row_off = rows_total;
-      rows_total += (int64_t)F.dim[1] * F.dim[2];
       F.xt_off = 0;
+      F.n_lab = 0;
+      F.pad_ = 0;
       int ext_max = 0;
       for (int a = 0; a < 3; ++a) ext_max = std::max(ext_max, F.dim[a] + 2 * kc0.reach_cells);
       int shift = 0;
@@ -420,6 +426,28 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       while ((1 << bits) < maxc + 2) ++bits;
       bin_axis_bits = std::max(bin_axis_bits, bits);
     }
+    // Class ids: every frame stacks one layer of its z extent per class id (0 .. its largest id) along z,
+    // so that points of one id are contiguous and the sweeps walk only the candidates that can pair.  Kept
+    // only while the keys fit 32 bits and the row table stays within 16 rows per point (+ 2^20).
+    bool stacked = class_ids;
+    {
+      int64_t rows_stacked = 0;
+      for (int f = 0; f < K && stacked; ++f) {
+        const int64_t n_lab = (int64_t)mm[lab0 + f] + 1;
+        const uint64_t cells = (uint64_t)fr[f].dim[0] * fr[f].dim[1] * fr[f].dim[2];
+        stacked = n_lab >= 1 && cells * (uint64_t)n_lab < 0xffffffffull;
+        rows_stacked += (int64_t)fr[f].dim[1] * fr[f].dim[2] * n_lab;
+      }
+      stacked = stacked && rows_stacked < (1LL << 31) && rows_stacked <= 16 * N + (1LL << 20);
+    }
+    for (int f = 0; f < K; ++f) {
+      FrameInfo& F = fr[f];
+      F.n_lab = stacked ? mm[lab0 + f] + 1 : 0;
+      F.row_off = rows_total;
+      rows_total += (int64_t)F.dim[1] * F.dim[2] * std::max(F.n_lab, 1);
+      max_cells = std::max(max_cells, (uint64_t)F.dim[0] * F.dim[1] * F.dim[2] * std::max(F.n_lab, 1));
+    }
+    p->stacked = stacked;
     RK_REQUIRE(rows_total < (1LL << 31), RKHSBA_ENOMEM, "cell-row table too large");
     p->bin_bits = 3 * bin_axis_bits;
     RK_HIP(d_bframes_.reserve(K));
@@ -440,7 +468,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(v1_.reserve(N));
     RK_HIP(k2_.reserve(N));
     RK_HIP(v2_.reserve(N));
-    RK_HIP(launch_cell_keys(cell_.p, d_in_off_.p, d_bframes_.p, K, N, k1_.p, v1_.p, bst));
+    RK_HIP(launch_cell_keys(cell_.p, d_in_off_.p, d_bframes_.p, K, N, d_feat_ptrs_.p, k1_.p, v1_.p, bst));
     std::vector<SortTile> tiles;
     std::vector<SortSeg> segs(K);
     for (int f = 0; f < K; ++f) {
@@ -448,7 +476,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       segs[f].count = n_points[f];
       segs[f].tile0 = (int32_t)tiles.size();
       for (int64_t s = 0; s < n_points[f]; s += kSortTile)
-        tiles.push_back(SortTile{off[f] + s, (int32_t)std::min<int64_t>(kSortTile, n_points[f] - s), f});
+        tiles.push_back(SortTile{off[f] + s, (int32_t)std::min<int64_t>(kSortTile, n_points[f] - s), f, f, 0});
       segs[f].n_tiles = (int32_t)tiles.size() - segs[f].tile0;
     }
     RK_HIP(d_tiles_.reserve(tiles.size()));
@@ -475,6 +503,22 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     RK_HIP(d_total_.reserve(1));
     RK_HIP(launch_rows(d_keys, d_bframes_.p, d_in_off_.p, K, N, d_rows, rows_total, row_sizes_.p, scan_tmp_.p,
                        d_total_.p, bst));
+    // first point of every label layer (pass segments of the edges that start in the frame)
+    p->lab_off.assign(K, -1);
+    p->lab_start.clear();
+    if (stacked) {
+      int64_t n_ls = 0;
+      for (int f = 0; f < K; ++f) {
+        p->lab_off[f] = n_ls;
+        n_ls += fr[f].n_lab + 1;
+      }
+      p->lab_start.resize(n_ls);
+      RK_HIP(d_lab_off_.reserve(K));
+      RK_HIP(d_lab_start_.reserve(n_ls));
+      RK_HIP(hipMemcpyAsync(d_lab_off_.p, p->lab_off.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, bst));
+      RK_HIP(launch_label_starts(d_keys, d_bframes_.p, d_lab_off_.p, K, d_lab_start_.p, bst));
+      RK_HIP(hipMemcpyAsync(p->lab_start.data(), d_lab_start_.p, sizeof(int32_t) * n_ls, hipMemcpyDeviceToHost, bst));
+    }
     uint64_t xt_total = 0;
     int32_t neg = 0;
     RK_HIP(hipMemcpyAsync(&xt_total, d_total_.p, sizeof(uint64_t), hipMemcpyDeviceToHost, bst));
@@ -785,8 +829,10 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   std::vector<int64_t> ent(E_total);
   std::vector<int32_t> foff(E_total);
   std::vector<SortTile> tiles;
-  std::vector<SortSeg> segs(E_total);
+  std::vector<SortSeg> segs;
+  segs.reserve(E_total);
   std::vector<KConst> kcs(items.size());
+  bool all_stacked = !items.empty();
   // one launch per group of equal pass size; group 4: per-point walks with top-k selection
   const int group_order[6] = {16, 1, 32, 64, 1, 8};
   int64_t gcount[6] = {0, 0, 0, 0, 0, 0};  // passes per group
@@ -805,6 +851,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
     clamp = clamp || p->kc.clamp;
     positive = positive && p->kc.c_positive;
     bin_bits = std::max(bin_bits, p->bin_bits);
+    all_stacked = all_stacked && p->stacked;
     ProbSys& S = sys[pi];
     S.K = p->K;
     S.fixed = it.fixed;
@@ -837,7 +884,34 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       const int P = pp == 1 ? 64 : pp;  // per-point walks: 64 sources (one per lane) per pass
       const int gi = p->par.top_k > 0 ? 4 : pp == 16 ? 0 : pp == 1 ? 1 : pp == 32 ? 2 : pp == 64 ? 3 : 5;
       I.pass_size = pp;
-      I.n_pass = (I.n_src + P - 1) / P;
+      // binning segments: the source frame's label layers (a pass's sources then share one class id), or
+      // the whole frame
+      I.seg0 = (int32_t)segs.size();
+      I.n_pass = 0;
+      {
+        const int mf = m < K ? m : p->alias_of;
+        std::vector<std::pair<int64_t, int64_t>> parts;  // (first source point, count)
+        if (p->stacked) {
+          const int32_t* ls = p->lab_start.data() + p->lab_off[mf];
+          for (int L = 0; L < p->frames[mf].n_lab; ++L)
+            if (ls[L + 1] > ls[L]) parts.emplace_back(ls[L], ls[L + 1] - ls[L]);
+        } else if (I.n_src > 0) {
+          parts.emplace_back(0, I.n_src);
+        }
+        for (const auto& pr : parts) {
+          SortSeg S0;
+          S0.start = entries + pr.first;
+          S0.count = pr.second;
+          S0.tile0 = (int32_t)tiles.size();
+          for (int64_t s = 0; s < pr.second; s += kSortTile)
+            tiles.push_back(SortTile{S0.start + s, (int32_t)std::min<int64_t>(kSortTile, pr.second - s),
+                                     (int32_t)segs.size(), e_glob, 0});
+          S0.n_tiles = (int32_t)tiles.size() - S0.tile0;
+          segs.push_back(S0);
+          I.n_pass += (int32_t)((pr.second + P - 1) / P);
+        }
+      }
+      I.n_seg = (int32_t)segs.size() - I.seg0;
       I.fin_off = (int32_t)fins;
       // finalisation split from the edge's own size: 1..16 entries per thread
       I.fin_pt = std::min(16, std::max(1, I.n_src / 4096));
@@ -847,12 +921,6 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
       egroup[e_glob] = (int8_t)gi;
       ent[e_glob] = entries;
       foff[e_glob] = I.fin_off;
-      segs[e_glob].start = entries;
-      segs[e_glob].count = I.n_src;
-      segs[e_glob].tile0 = (int32_t)tiles.size();
-      for (int64_t s = 0; s < I.n_src; s += kSortTile)
-        tiles.push_back(SortTile{entries + s, (int32_t)std::min<int64_t>(kSortTile, I.n_src - s), e_glob});
-      segs[e_glob].n_tiles = (int32_t)tiles.size() - segs[e_glob].tile0;
       entries += I.n_src;
       passes += I.n_pass;
       fins += I.n_fin;
@@ -886,7 +954,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   need(lay.d_ent_off, E_total, "ent_off");
   need(lay.d_fin_off, E_total, "fin_off");
   need(lay.d_etiles, tiles.size(), "etiles");
-  need(lay.d_esegs, E_total, "esegs");
+  need(lay.d_esegs, std::max<size_t>(segs.size(), 1), "esegs");
   // the pass table: the groups one after another, each edge's passes contiguous (filled on the device)
   std::vector<SetLayout::Group> groups;
   int64_t gbase[6], n_pass_table = 0;
@@ -927,7 +995,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   stage_size(sizeof(int64_t) * E_total);
   stage_size(sizeof(int32_t) * E_total);
   stage_size(sizeof(SortTile) * tiles.size());
-  stage_size(sizeof(SortSeg) * E_total);
+  stage_size(sizeof(SortSeg) * segs.size());
   stage_size(sizeof(KConst) * kcs.size());
   stage_size(sizeof(ProbSys) * sys.size());
   stage_size(sizeof(int32_t) * bstart_all.size());
@@ -950,9 +1018,9 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   up(lay.d_ent_off.p, ent.data(), sizeof(int64_t) * E_total);
   up(lay.d_fin_off.p, foff.data(), sizeof(int32_t) * E_total);
   up(lay.d_etiles.p, tiles.data(), sizeof(SortTile) * tiles.size());
-  up(lay.d_esegs.p, segs.data(), sizeof(SortSeg) * E_total);
+  up(lay.d_esegs.p, segs.data(), sizeof(SortSeg) * segs.size());
   up(lay.d_kcs.p, kcs.data(), sizeof(KConst) * kcs.size());
-  RK_HIP(launch_fill_passes(lay.d_edges.p, E_total, frames(), lay.d_passes.p, st));
+  RK_HIP(launch_fill_passes(lay.d_edges.p, E_total, frames(), lay.d_esegs.p, lay.d_passes.p, st));
   up(lay.d_sys.p, sys.data(), sizeof(ProbSys) * sys.size());
   up(lay.d_blk_start.p, bstart_all.data(), sizeof(int32_t) * bstart_all.size());
   up(lay.d_blk_list.p, blist.data(), sizeof(int32_t) * blist.size());
@@ -998,6 +1066,8 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   lay.groups = std::move(groups);
   lay.n_fin_total = (int)fins;
   lay.n_edge_tiles = (int)tiles.size();
+  lay.n_edge_segs = (int)segs.size();
+  lay.stacked = all_stacked;
   lay.bin_bits = bin_bits;
   lay.clamp = clamp;
   lay.c_positive = positive && !items.empty();
@@ -1016,7 +1086,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
                     sc_->bv.p, st));
   bool in_tmp = false;
   RK_HIP(launch_radix_sort(sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,
-                           lay.E, lay.bin_bits, st, &in_tmp));
+                           lay.n_edge_segs, lay.bin_bits, st, &in_tmp));
   sorted_k_ = in_tmp ? sc_->bk2.p : sc_->bk.p;
   sorted_v_ = in_tmp ? sc_->bv2.p : sc_->bv.p;
   prof_end(RKHSBA_PROF_BIN, t0);
@@ -1041,6 +1111,7 @@ void Engine::evaluate(SetLayout& lay, int mode) {
   pa.kc.Dp = Dp;
   pa.kc.clamp = lay.clamp ? 1 : 0;
   pa.kc.c_positive = lay.c_positive ? 1 : 0;
+  pa.stacked = lay.stacked && feat_kind == RKHSBA_FEAT_CLASS_ID ? 1 : 0;
   const int feat_path = feat_kind;
   hipEvent_t t1 = prof_begin();
   for (const SetLayout::Group& gr : lay.groups) {

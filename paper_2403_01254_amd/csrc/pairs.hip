@@ -39,10 +39,12 @@ __device__ inline int clamp_floor(double v, int lo, int hi) {
 // box [lo, hi] can touch and calls fn(j0, j1) with each contiguous range of
 // target points (frame-local sorted indices).  Every target point whose
 // distance to some point of the box is <= reach lies in one of the ranges.
+// lrow: the first row of the label layer walked (label_rows; < 0: no rows).
 template <typename Fn>
 __device__ inline void for_each_range(const FrameInfo& T, const int4* __restrict__ rows,
                                       const uint32_t* __restrict__ xtab, const KConst& kc, float3 lo, float3 hi,
-                                      Fn&& fn) {
+                                      int64_t lrow, Fn&& fn) {
+  if (lrow < 0) return;
   const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
   const int z0 = clamp_floor(((double)lo.z - reach) * inv - T.org[2], -1, T.dim[2]);
   const int z1 = clamp_floor(((double)hi.z + reach) * inv - T.org[2], -1, T.dim[2]);
@@ -57,7 +59,7 @@ __device__ inline void for_each_range(const FrameInfo& T, const int4* __restrict
       const double r2 = kc.reach2 - by * by - bz * bz;
       if (r2 < 0.0) continue;
       const double h = sqrt(r2);
-      const int4 R = rows[T.row_off + (int64_t)kz * T.dim[1] + ky];
+      const int4 R = rows[T.row_off + lrow + (int64_t)kz * T.dim[1] + ky];
       if (R.y < R.x) continue;
       const int xa = max(clamp_floor(((double)lo.x - h) * inv - T.org[0], -1, T.dim[0]), R.x);
       const int xb = min(clamp_floor(((double)hi.x + h) * inv - T.org[0], -1, T.dim[0]), R.y);
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__
                                                       const EdgeXf* __restrict__ xf, const KConst* __restrict__ kcs,
                                                       uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const SortTile t = tiles[blockIdx.x];
-  const int e = t.seg;
+  const int e = t.edge;
   const EdgeInfo ed = edges[e];
   const KConst kc = kcs[ed.prob];
   const FrameInfo Fm = frames[ed.m];
@@ -115,23 +117,31 @@ __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__
 
 // ---------------------------------------------------------------- pass table
 
-// One block per edge: the edge's passes, in entry order.
+// One block per edge: the edge's passes, segment after segment, each
+// segment's in entry order.
 __global__ __launch_bounds__(256) void k_fill_passes(const EdgeInfo* __restrict__ edges,
                                                      const FrameInfo* __restrict__ frames,
+                                                     const SortSeg* __restrict__ segs,
                                                      PassInfo* __restrict__ passes) {
   const int e = blockIdx.x;
   const EdgeInfo ed = edges[e];
   const int P = ed.pass_size == 1 ? 64 : ed.pass_size;  // per-point walks: one source per lane
   const int64_t src_off = frames[ed.m].pt_off;
-  for (int k = threadIdx.x; k < ed.n_pass; k += blockDim.x) {
-    PassInfo Q;
-    Q.entry0 = ed.ent_off + (int64_t)k * P;
-    Q.src_off = src_off;
-    Q.e = e;
-    Q.count = min(P, ed.n_src - k * P);
-    Q.tgt = ed.n;
-    Q.prob = ed.prob;
-    passes[(int64_t)ed.pass0 + k] = Q;
+  int64_t base = ed.pass0;
+  for (int sg = 0; sg < ed.n_seg; ++sg) {  // uniform
+    const SortSeg S = segs[ed.seg0 + sg];
+    const int n_pass = (int)((S.count + P - 1) / P);
+    for (int k = threadIdx.x; k < n_pass; k += blockDim.x) {
+      PassInfo Q;
+      Q.entry0 = S.start + (int64_t)k * P;
+      Q.src_off = src_off;
+      Q.e = e;
+      Q.count = (int)min((int64_t)P, S.count - (int64_t)k * P);
+      Q.tgt = ed.n;
+      Q.prob = ed.prob;
+      passes[base + k] = Q;
+    }
+    base += n_pass;
   }
 }
 
@@ -199,10 +209,15 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     lo = make_float3(FLT_MAX, FLT_MAX, FLT_MAX);
     hi = make_float3(-FLT_MAX, -FLT_MAX, -FLT_MAX);
   }
+  // the label layer walked in a label-stacked target frame: each lane's own (LOCAL), or the pass's (its
+  // sources share one class id: passes never straddle a class id of a stacked source frame)
+  uint32_t wl = lbl;
+  if constexpr (!LOCAL) wl = (uint32_t)__shfl((int)lbl, __builtin_ctzll(__ballot(valid)), 64);
+  const int64_t lrow = label_rows(Fn, wl);
   TopK<(TOPK > 0 ? TOPK : 1)> best;
   if constexpr (TOPK > 0) best.clear();
   const int topk = kc.topk;
-  for_each_range(Fn, a.rows, a.xtab, kc, lo, hi, [&](uint32_t j0, uint32_t j1) {
+  for_each_range(Fn, a.rows, a.xtab, kc, lo, hi, lrow, [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0 + g; j < j1; j += G) {
       const float4 z = tp[j];
       float dx, dy, dz;
@@ -592,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void k_export_pairs(const float4* __restr
   if constexpr (TOPK && FEAT != FEAT_CLASS) load_feature_row<FEAT, DP>(feat, Fm.pt_off + i, fs);
   TopK<kMaxTopK> best;
   if constexpr (TOPK) best.clear();
-  for_each_range(Fn, rows, xtab, kc, q, q, [&](uint32_t j0, uint32_t j1) {
+  for_each_range(Fn, rows, xtab, kc, q, q, label_rows(Fn, lbl), [&](uint32_t j0, uint32_t j1) {
     for (uint32_t j = j0; j < j1; ++j) {
       const float4 z = pts[Fn.pt_off + j];
       float dx, dy, dz;
@@ -668,9 +683,9 @@ int dense_pad(int D, int feat_path) {
   return D <= 8 ? 8 : D <= 16 ? 16 : D <= 24 ? 24 : D <= 32 ? 32 : 64;
 }
 
-hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, PassInfo* d_passes,
-                              hipStream_t st) {
-  if (E > 0) k_fill_passes<<<E, 256, 0, st>>>(d_edges, d_frames, d_passes);
+hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, const SortSeg* d_segs,
+                              PassInfo* d_passes, hipStream_t st) {
+  if (E > 0) k_fill_passes<<<E, 256, 0, st>>>(d_edges, d_frames, d_segs, d_passes);
   return hipGetLastError();
 }
 

@@ -4,8 +4,9 @@
 //                          .w holds the class id bits (class features) or 0
 //   feat  float[N_total*Dp] dense feature rows in the same order (zero padded to Dp)
 //   perm  int32[N_total]   sorted position -> original index within the frame
-//   keys  uint32[N_total]  sorted cell keys
-//   rows  int4[sum NY*NZ]  per (ky,kz) row of cells: (x_lo, x_hi, xtab offset, 0)
+//   keys  uint32[N_total]  sorted cell keys, ((kz' * NY) + ky) * NX + kx with kz' = kz, or for class ids in a
+//                          label-stacked frame kz' = label * NZ + kz (each class id has a layer of NZ cells)
+//   rows  int4[sum NY*NZ*L] per (ky,kz') row of cells: (x_lo, x_hi, xtab offset, 0); L label layers (1 unstacked)
 //   xtab  uint32[...]      per row, for x in [x_lo, x_hi+1]: first point of cell x
 #pragma once
 
@@ -36,7 +37,17 @@ struct FrameInfo {
   int32_t mort_shift;  // source-binning Morton code: (k + reach) >> mort_shift
   int64_t row_off;   // first row descriptor of the frame
   int64_t xt_off;    // first xtab entry of the frame
+  int32_t n_lab;     // label layers of a label-stacked frame (class id + 1 of its largest id), 0: not stacked
+  int32_t pad_;
 };
+
+// First row descriptor (relative to row_off) of the layer of class id lbl: 0 in a frame that is not
+// label-stacked, -1 where the frame has no layer for that id (no point of the frame carries it).
+__host__ __device__ inline int64_t label_rows(const FrameInfo& T, uint32_t lbl) {
+  if (T.n_lab <= 0) return 0;
+  if (lbl >= (uint32_t)T.n_lab) return -1;
+  return (int64_t)lbl * T.dim[1] * T.dim[2];
+}
 
 // Static per-edge layout of one edge list (host-computed once per list).
 struct EdgeInfo {
@@ -50,9 +61,11 @@ struct EdgeInfo {
   int32_t fin_pt;    // entries per finalize thread (a block covers kFinThreads * fin_pt entries)
   int32_t prob;      // problem of the edge within the evaluated set (constants, system)
   int32_t pass0;     // first pass of the edge in the set's pass table
+  int32_t seg0;      // first binning segment of the edge (one per class id of a label-stacked source frame,
+  int32_t n_seg;     // else one): passes never straddle a segment
 };
 
-// One sweep pass: up to pass-size consecutive binning entries of one edge.
+// One sweep pass: up to pass-size consecutive binning entries of one segment of an edge.
 struct PassInfo {
   int64_t entry0;    // first binning entry
   int64_t src_off;   // pool offset of the source frame's points
@@ -92,6 +105,8 @@ struct SortTile {
   int64_t start;     // first element
   int32_t count;     // elements (<= kSortTile)
   int32_t seg;       // segment id
+  int32_t edge;      // edge of the binning entries (edge sorts), or the frame (point sorts)
+  int32_t pad_;
 };
 struct SortSeg {
   int64_t start;
@@ -117,10 +132,18 @@ constexpr int kScanTileElems = 2048;
 // Padded feature row length: 8, 16, 24, 32 or 64 (FP32), 32 or 64 (bfloat16, fp8: whole 32-wide MFMA slices).
 int dense_pad(int D, int feat_path);
 
+// d_label_max (class ids, else null): per frame, the largest class id (max-combined; the caller sets -1).
 hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_in_off, int K, int64_t n_total,
-                              double inv_cell, int32_t* d_cell, int32_t* d_minmax, hipStream_t st);
+                              double inv_cell, const void* const* d_class_ptrs, int32_t* d_cell, int32_t* d_minmax,
+                              int32_t* d_label_max, hipStream_t st);
+// Cell keys; frames with n_lab > 0 take the class ids (d_class_ptrs) into kz'.
 hipError_t launch_cell_keys(const int32_t* d_cell, const int64_t* d_in_off, const FrameInfo* d_frames, int K,
-                            int64_t n_total, uint32_t* d_keys, uint32_t* d_vals, hipStream_t st);
+                            int64_t n_total, const void* const* d_class_ptrs, uint32_t* d_keys, uint32_t* d_vals,
+                            hipStream_t st);
+// For every label-stacked frame f (frame-local key order) and class id l in [0, n_lab]: the first point
+// of layer l (l = n_lab: the frame's count), at d_out[d_lab_off[f] + l].
+hipError_t launch_label_starts(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_lab_off, int K,
+                               int32_t* d_out, hipStream_t st);
 hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_feat_ptrs, int feat_kind, int D, int Dp,
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
                          const uint32_t* d_sorted_vals, float4* d_pts, void* d_feat, int32_t* d_perm,
@@ -138,9 +161,9 @@ hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipStream_t st);
 
 // The pass table of a set from its edge table: passes pass0 .. pass0 + n_pass - 1
-// of each edge cover its entries in runs of pass_size (64 for per-point walks).
-hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, PassInfo* d_passes,
-                              hipStream_t st);
+// of each edge cover each of its segments in runs of pass_size (64 for per-point walks).
+hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, const SortSeg* d_segs,
+                              PassInfo* d_passes, hipStream_t st);
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
 // Binning keys and source indices of every entry, one block per sort tile of an edge.
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges,
@@ -167,6 +190,8 @@ struct PairArgs {
   int32_t pass0;          // first pass of this launch in the pass table
   int32_t n_pass;         // passes of this launch
   KConst kc;              // set-wide: Dp and clamp (clamping is exact for non-negative features)
+  int32_t stacked;        // every frame of the set is label-stacked (class ids): a candidate of the pass's
+                          // layer always carries the pass's class id, and the sweeps skip that test
 };
 // Passes of pass_points sources: 1 = each lane walks its own point's cells,
 // 8 (class ids) and 16 (launch_sweep), 32, 64 = shared walk over the pass's box.

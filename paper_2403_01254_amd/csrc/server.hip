@@ -313,6 +313,15 @@ struct rkhsba_server {
               continue;
             }
           }
+          {
+            // the admission estimate's resident part becomes the built problem's pools (label-stacked
+            // class-id grids can hold several cell-row descriptors per point)
+            const int64_t d = p->resident_bytes - Engine::estimate_resident_bytes(q->K, q->n_points.data(),
+                                                                                  row_bytes);
+            std::lock_guard<std::mutex> lk(mu);
+            committed += d;
+            q->est_bytes += d;
+          }
           L.eng->upload_poses(p, q->poses.data());
           L.eng->reset_state(p);
           q->t_admit = Clock::now();

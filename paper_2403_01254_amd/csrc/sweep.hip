@@ -150,11 +150,15 @@ __device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s
 // SC: every source point's own pair count goes to its entry of a.cnt (one more
 // VALU add per candidate; for parity checks of the pair set), instead of the
 // pass's count on its first entry (the per-edge totals are the same).
-template <int MODE, int FEAT, int DP, int CM, bool MM, int P, bool SC = false>
+// LS (class ids, every frame label-stacked): the pass walks the layer of its
+// sources' class id, whose candidates all carry that id, so the id test is
+// skipped.
+template <int MODE, int FEAT, int DP, int CM, bool MM, int P, bool SC = false, bool LS = false>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // P source points per pass (16, or 8 for class ids); lane (s, g) takes CPL candidates of every
   // 16-candidate sub-tile
   static_assert(P == 16 || (P == 8 && FEAT == FEAT_CLASS && !MM), "8-point passes: class ids only");
+  static_assert(!LS || FEAT == FEAT_CLASS, "label layers: class ids only");
   constexpr int CPL = P / 4;
   constexpr bool LP = feat_low_precision(FEAT);
   constexpr int FS = FEAT == FEAT_DENSE ? DP + 1 : 1;  // LDS FP32 feature row stride (odd: conflict-free column reads)
@@ -249,6 +253,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   const int y1 = min(clamp_floor_d(((double)hi.y + reach) * inv - Fn.org[1], -1, Fn.dim[1]), Fn.dim[1] - 1);
   const int ny = y1 - y0 + 1;
   int n_rows = (z1 >= z0 && y1 >= y0) ? (z1 - z0 + 1) * ny : 0;
+  // rows of the label layer the pass walks in a label-stacked target frame: the sources of a pass share
+  // one class id (passes never straddle a class id of a stacked source frame)
+  const int64_t lrow = label_rows(Fn, (uint32_t)__builtin_amdgcn_readlane((int)lbl, __builtin_ctzll(__ballot(valid))));
+  if (lrow < 0) n_rows = 0;  // no point of the target frame carries the id
+  const int4* __restrict__ trows = a.rows + Fn.row_off + (lrow < 0 ? 0 : lrow);
 
   const float rc2 = kc.rc2, alpha = kc.alpha;
   float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         ys1 = min(clamp_floor_d(((double)q.y + reach) * inv - Fn.org[1], -1, Fn.dim[1]), Fn.dim[1] - 1);
       }
       const int nys = ys1 - ys0 + 1;
-      const int nr = (zs1 >= zs0 && ys1 >= ys0) ? (zs1 - zs0 + 1) * nys : 0;
+      const int nr = (zs1 >= zs0 && ys1 >= ys0 && lrow >= 0) ? (zs1 - zs0 + 1) * nys : 0;
       for (int r = g; r < nr; r += G) {
         const int kz = zs0 + r / nys, ky = ys0 + r % nys;
         const double cz = (double)(kz + Fn.org[2]) * cell;
@@ -284,7 +293,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         const double by = fmax(0.0, fmax(cy - (double)q.y, (double)q.y - (cy + cell)));
         const double r2 = kc.reach2 - by * by - bz * bz;
         if (r2 < 0.0) continue;
-        const int4 R = a.rows[Fn.row_off + (int64_t)kz * Fn.dim[1] + ky];
+        const int4 R = trows[(int64_t)kz * Fn.dim[1] + ky];
         if (R.y < R.x) continue;
         const double h = sqrt(r2);
         const int xa = max(clamp_floor_d(((double)q.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
@@ -296,7 +305,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           const float4 z = tp[j];
           float dx, dy, dz;
           const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
-          if (!(s2 <= rc2 && __float_as_uint(z.w) == lbl)) continue;
+          if (!(s2 <= rc2 && (LS || __float_as_uint(z.w) == lbl))) continue;
           const float w = __builtin_amdgcn_exp2f(-alpha * s2);
           own += 1u;
           A += w;
@@ -326,7 +335,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       const double by = fmax(0.0, fmax(cy - (double)hi.y, (double)lo.y - (cy + cell)));
       const double r2 = kc.reach2 - by * by - bz * bz;
       if (r2 >= 0.0) {
-        const int4 R = a.rows[Fn.row_off + (int64_t)kz * Fn.dim[1] + ky];
+        const int4 R = trows[(int64_t)kz * Fn.dim[1] + ky];
         if (R.y >= R.x) {
           const double h = sqrt(r2);
           const int xa = max(clamp_floor_d(((double)lo.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
@@ -451,7 +460,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           bool in = near;
           float c = 1.f;
           if constexpr (FEAT == FEAT_CLASS) {
-            in = in && (__float_as_uint(z.w) == lbl);
+            if constexpr (!LS) in = in && (__float_as_uint(z.w) == lbl);
           } else {
             c = CM == 1 ? fmaxf(cur[rr], 0.f) : cur[rr];
           }
@@ -461,6 +470,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
           if constexpr (SC) {
             if constexpr (FEAT == FEAT_CLASS || CM == 2) own += in ? 1u : 0u;
             else own += (in && c != 0.f) ? 1u : 0u;
+          } else if constexpr (LS) {
+            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near));
           } else if constexpr (FEAT == FEAT_CLASS) {
             // the two compares' lane masks, combined on the scalar unit (a ballot of the combined
             // condition would first turn it into a vector value and back)
@@ -542,7 +553,8 @@ hipError_t dispatch(const PairArgs& a, int DP, hipStream_t st) {
   const unsigned nb = (unsigned)a.n_pass;
   if (nb == 0) return hipSuccess;
   if constexpr (FEAT == FEAT_CLASS) {
-    k_sweep<MODE, FEAT, 0, 0, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
+    if (a.stacked) k_sweep<MODE, FEAT, 0, 0, MM, 16, SC, true><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE, FEAT, 0, 0, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
   } else if constexpr (feat_low_precision(FEAT)) {
     if (DP <= 32) k_sweep<MODE, FEAT, 32, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
     else k_sweep<MODE, FEAT, 64, CM, MM, 16, SC><<<nb, kLanes, 0, st>>>(a);
@@ -584,9 +596,16 @@ hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_poi
   if (source_counts && (mode != MODE_NORMAL || matrix_moments)) return hipErrorInvalidValue;
   if (pass_points == 8) {
     if (feat_path != FEAT_CLASS || a.n_pass == 0) return feat_path != FEAT_CLASS ? hipErrorInvalidValue : hipSuccess;
-    if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true><<<a.n_pass, kLanes, 0, st>>>(a);
-    else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
-    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    if (a.stacked) {
+      if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true, true><<<a.n_pass, kLanes, 0, st>>>(a);
+      else if (mode == MODE_LOSS)
+        k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8, false, true><<<a.n_pass, kLanes, 0, st>>>(a);
+      else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, false, true><<<a.n_pass, kLanes, 0, st>>>(a);
+    } else {
+      if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true><<<a.n_pass, kLanes, 0, st>>>(a);
+      else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+      else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
+    }
     return hipGetLastError();
   }
   if (source_counts) return dispatch_mode<MODE_NORMAL, false, true>(a, feat_path, st);

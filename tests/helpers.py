@@ -109,3 +109,14 @@ def scene_digest(points, feats, poses, edges):
         h.update(str(a.dtype).encode() + str(a.shape).encode())
         h.update(a.tobytes())
     return h.hexdigest()
+
+
+def label_stacked(class_ids, dims):
+    """Whether a build stacks the class ids of its frames into label layers (the documented rule): every
+    frame's cells x (largest id + 1) fit 32-bit keys and the stacked cell-row tables hold at most 16 rows
+    per point + 2^20.  class_ids: per frame; dims: per frame, the cell grid's extent (x, y, z)."""
+    layers = [int(f.max()) + 1 for f in class_ids]
+    fits = all(int(np.prod(np.asarray(d, dtype=np.int64))) * L < 2**32 - 1 for d, L in zip(dims, layers))
+    rows = sum(int(d[1]) * int(d[2]) * L for d, L in zip(dims, layers))
+    n = sum(len(f) for f in class_ids)
+    return fits and rows < 2**31 and rows <= 16 * n + 2**20

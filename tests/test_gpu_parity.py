@@ -13,8 +13,8 @@ import pytest
 
 import oracle
 import scenes
-from helpers import (REL_TOL, ROT_TOL, TRANS_TOL, assert_blocks_close, ident, inv_cell, normwise_rel,
-                     pose_errors)
+from helpers import (REL_TOL, ROT_TOL, TRANS_TOL, assert_blocks_close, ident, inv_cell, label_stacked,
+                     normwise_rel, pose_errors)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 
@@ -58,9 +58,14 @@ def test_voxel_structure_bit_exact(rk, scene):
     for subdiv in (1, 3):
         ctx = make_ctx(rk, p, cell_subdiv=subdiv)
         inv = inv_cell(p.ell, p.cutoff_factor, subdiv)
+        vox = [ctx.export_voxels(f, len(p.points[f])) for f in range(p.K)]
+        stacked = p.feat_kind == "class" and label_stacked(p.feats, [v[3] for v in vox])
+        say(f"[voxels] {name} subdiv {subdiv}: label-stacked {stacked}")
         for f in range(p.K):
-            perm, keys, org, dims = ctx.export_voxels(f, len(p.points[f]))
-            operm, okeys, oorg, odims = oracle.voxels(p.points[f], inv, margin=0)
+            perm, keys, org, dims, layers = vox[f]
+            assert layers == (int(p.feats[f].max()) + 1 if stacked else 0)
+            operm, okeys, oorg, odims = oracle.voxels(p.points[f], inv, margin=0,
+                                                      labels=p.feats[f] if stacked else None)
             np.testing.assert_array_equal(org, oorg)
             np.testing.assert_array_equal(dims, odims)
             np.testing.assert_array_equal(keys, okeys)

@@ -396,6 +396,40 @@ def test_voxel_sort_properties():
     assert np.all(k.min(0) - origin == 1) and np.all(dims - (k.max(0) - origin) - 1 == 1)
 
 
+def test_label_stacked_voxel_sort_properties():
+    """With class ids the sort groups the points by id first: each key
+    decodes to (id, cell) with z index id * NZ + kz, the points of one id are
+    contiguous and in the unlabelled sort's order among themselves, and
+    without labels (or with all ids 0) the keys are the unlabelled ones."""
+    rng = np.random.default_rng(17)
+    x = (rng.normal(size=(4000, 3)) * 1.5).astype(np.float32)
+    lab = rng.integers(0, 7, size=4000).astype(np.uint16)
+    inv = 1.0 / 0.25
+    perm0, keys0, origin0, dims0 = oracle.voxels(x, inv)
+    perm, keys, origin, dims = oracle.voxels(x, inv, labels=lab)
+    np.testing.assert_array_equal(origin, origin0)
+    np.testing.assert_array_equal(dims, dims0)
+    assert sorted(perm.tolist()) == list(range(4000))
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+    k = np.floor(x[perm].astype(np.float64) * inv).astype(np.int64) - origin
+    kx = keys % dims[0]
+    ky = (keys // dims[0]) % dims[1]
+    kzl = keys.astype(np.int64) // (dims[0] * dims[1])
+    np.testing.assert_array_equal(kx, k[:, 0])
+    np.testing.assert_array_equal(ky, k[:, 1])
+    np.testing.assert_array_equal(kzl % dims[2], k[:, 2])
+    np.testing.assert_array_equal(kzl // dims[2], lab[perm])
+    assert np.all(np.diff(lab[perm].astype(np.int64)) >= 0)
+    rank0 = np.empty(4000, np.int64)
+    rank0[perm0] = np.arange(4000)
+    for L in range(7):
+        sub = perm[lab[perm] == L]
+        assert np.all(np.diff(rank0[sub]) > 0)
+    perm_z, keys_z, _, _ = oracle.voxels(x, inv, labels=np.zeros(4000, np.uint16))
+    np.testing.assert_array_equal(perm_z, perm0)
+    np.testing.assert_array_equal(keys_z, keys0)
+
+
 # ----------------------------------------------------------------------------- one Gauss-Newton step
 
 def test_gn_step_is_the_damped_solve_with_right_update():
