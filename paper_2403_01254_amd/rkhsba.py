@@ -126,7 +126,8 @@ def lib():
         L.rkhsba_accumulate_normal_eqs.argtypes = [vp, _dp, ctypes.c_int, _i32p, _dp, _dp, _dp, _i64p]
         L.rkhsba_gn_step.argtypes = [vp, _dp, ctypes.c_int, _i32p, ctypes.c_int, _dp, _i64p]
         L.rkhsba_export_pairs.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _i64p]
-        L.rkhsba_export_voxels.argtypes = [vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), _i32p, _i32p]
+        L.rkhsba_export_voxels.argtypes = [vp, ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), _i32p, _i32p,
+                                           _i32p]
         L.rkhsba_export_source_counts.argtypes = [vp, _dp, ctypes.c_int, ctypes.c_int, _i64p]
         L.rkhsba_autotune.argtypes = [vp, ctypes.c_int, _i64p, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(vp), ctypes.c_int, _dp, ctypes.c_int, _i32p, ctypes.c_int,
@@ -344,10 +345,11 @@ class Context:
         keys = np.zeros(n_points, dtype=np.uint32)
         org = np.zeros(3, dtype=np.int32)
         dims = np.zeros(3, dtype=np.int32)
+        layers = np.zeros(1, dtype=np.int32)
         self._check(lib().rkhsba_export_voxels(self._h, int(frame), _p(perm, ctypes.c_int32),
                                                _p(keys, ctypes.c_uint32), _p(org, ctypes.c_int32),
-                                               _p(dims, ctypes.c_int32)))
-        return perm, keys, org, dims
+                                               _p(dims, ctypes.c_int32), _p(layers, ctypes.c_int32)))
+        return perm, keys, org, dims, int(layers[0])
 
 
     # -- rkhsba_ell_gradient
