@@ -139,6 +139,17 @@ __device__ inline floatx4 tile_products_lp(const uint8_t* __restrict__ tl, int s
   return acc;
 }
 
+// Squared distance of candidate z to the box [lo, hi], rounded like the membership rule: each axis term
+// max(lo - z, z - hi, 0) and the fused sum in rule_s2's order.  Rounding is monotone, so for every point q of
+// the box this is at most rule_s2(q, z): a candidate above rc2 here fails the rule for every source in the box.
+__device__ inline float box_s2(float3 lo, float3 hi, float4 z) {
+#pragma clang fp contract(off)
+  const float bx = fmaxf(fmaxf(lo.x - z.x, z.x - hi.x), 0.f);
+  const float by = fmaxf(fmaxf(lo.y - z.y, z.y - hi.y), 0.f);
+  const float bz = fmaxf(fmaxf(lo.z - z.z, z.z - hi.z), 0.f);
+  return fmaf(bz, bz, fmaf(by, by, bx * bx));
+}
+
 // MM: the moments are accumulated on the matrix core.  With u = z - ref (ref =
 // centre of the pass's box) and Phi(u) = [1, u, u u^T] (10 of 16 columns), the
 // sums M[s][f] = sum_j w_sj Phi_f(u_j) over all candidates are one MFMA chain
@@ -159,6 +170,9 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // 16-candidate sub-tile
   static_assert(P == 16 || (P == 8 && FEAT == FEAT_CLASS && !MM), "8-point passes: class ids only");
   static_assert(!LS || FEAT == FEAT_CLASS, "label layers: class ids only");
+  // CF (class ids, VALU moments): the candidates of each fetched tile that lie beyond the reach of the
+  // pass's box are dropped and the rest compacted into full blocks of 64 before any source tests them
+  constexpr bool CF = FEAT == FEAT_CLASS && !MM;
   constexpr int CPL = P / 4;
   constexpr bool LP = feat_low_precision(FEAT);
   constexpr int FS = FEAT == FEAT_DENSE ? DP + 1 : 1;  // LDS FP32 feature row stride (odd: conflict-free column reads)
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   __shared__ uint32_t row_j0[kLanes];
   __shared__ uint32_t row_off[kLanes];
   __shared__ uint32_t marker[kLanes];
-  __shared__ float4 tpos[kTile];
+  __shared__ float4 tpos[CF ? 2 * kTile : kTile];  // CF: a ring of two blocks
   __shared__ float tfeat[FEAT == FEAT_DENSE ? kTile * FS : 1];
   __shared__ __align__(16) uint8_t tlp[LP ? kTile * RB : 16];
   __shared__ float tphi[MM ? kTile * PHS : 1];
@@ -323,6 +337,81 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   const uint8_t* __restrict__ tl = static_cast<const uint8_t*>(a.feat) + Fn.pt_off * (int64_t)(LP ? ROWB : 0);
   const float far_ = 1.0e18f;
 
+  // The sub-tiles of one block of 64 candidates (blk: their positions in LDS; dense features, products and
+  // Phi from the tile buffers) against the pass's sources: the moments and pair counts above.
+  auto process = [&](const float4* __restrict__ blk, int n_sub) __attribute__((always_inline)) {
+    floatx4 cv = {1.f, 1.f, 1.f, 1.f};
+    if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
+    if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
+    // unrolled over the four sub-tiles: the products and the LDS offsets of each sub-tile get registers
+    // and immediates of their own (no register copies or address updates between sub-tiles)
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+      if (sub >= n_sub) break;  // uniform
+      // this lane's four candidates of the sub-tile, read before any use
+      const float4* zp = blk + 16 * sub + CPL * g;
+      float4 z4[CPL];
+#pragma unroll
+      for (int rr = 0; rr < CPL; ++rr) z4[rr] = zp[rr];
+      float phi4[4] = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (MM) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) phi4[rr] = tphi[(16 * sub + 4 * g + rr) * PHS + s];
+      }
+      floatx4 cur = cv;
+      if constexpr (FEAT == FEAT_DENSE) {
+        // issue the next sub-tile's products now: the matrix core works while the VALU runs below
+        if (sub + 1 < n_sub) cv = tile_products<DP, FS>(tfeat, s, g, sub + 1, fsrc);
+      } else if constexpr (LP) {
+        if (sub + 1 < n_sub) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, sub + 1, slp);
+      }
+#pragma unroll
+      for (int rr = 0; rr < CPL; ++rr) {
+        const float4 z = z4[rr];
+        float dx, dy, dz;
+        const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+        const bool near = s2 <= rc2;
+        bool in = near;
+        float c = 1.f;
+        if constexpr (FEAT == FEAT_CLASS) {
+          if constexpr (!LS) in = in && (__float_as_uint(z.w) == lbl);
+        } else {
+          c = CM == 1 ? fmaxf(cur[rr], 0.f) : cur[rr];
+        }
+        const float k = __builtin_amdgcn_exp2f(-alpha * s2);
+        const float w = in ? c * k : 0.f;
+        // pairs counted per pass from the wavefront's lane masks (scalar unit), or per lane (SC)
+        if constexpr (SC) {
+          if constexpr (FEAT == FEAT_CLASS || CM == 2) own += in ? 1u : 0u;
+          else own += (in && c != 0.f) ? 1u : 0u;
+        } else if constexpr (LS) {
+          cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near));
+        } else if constexpr (FEAT == FEAT_CLASS) {
+          // the two compares' lane masks, combined on the scalar unit (a ballot of the combined
+          // condition would first turn it into a vector value and back)
+          cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near) &
+                                    __builtin_amdgcn_ballot_w64(__float_as_uint(z.w) == lbl));
+        } else if constexpr (CM == 2) {
+          cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
+        } else {
+          cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
+        }
+        if constexpr (MM) {
+          macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
+        } else {
+          A += w;
+        }
+        if constexpr (MODE == MODE_NORMAL && !MM) {
+          const float wx = w * dx, wy = w * dy;
+          Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
+          Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+          Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
+        }
+      }
+    }
+  };
+
+  uint32_t head = 0, tail = 0;  // CF: the ring holds the kept candidates head .. tail - 1 (uniform)
   for (int rb = 0; rb < n_rows; rb += kLanes) {
     // ---- one row per lane: its contiguous candidate range
     uint32_t j0 = 0, cntr = 0;
@@ -398,6 +487,23 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     u32x4 nlp[LP ? ROWB / 16 : 1];
     fetch((uint32_t)lane, npos, nfeat, nlp, npad);
     for (uint32_t cb = 0; cb < total; cb += kTile) {
+      if constexpr (CF) {
+        // keep the candidates within reach of the pass's box, appended to the ring in list order
+        const bool keep = !npad && box_s2(lo, hi, npos) <= rc2;
+        const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
+        if (keep)
+          tpos[(tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u))) &
+               (2 * kTile - 1)] = npos;
+        tail += (uint32_t)__popcll(km);
+        wave_sync();
+        if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
+        if (tail - head >= (uint32_t)kTile) {  // a full block (at most one per fetched tile)
+          process(tpos + (head & (2 * kTile - 1)), 4);
+          head += kTile;
+          wave_sync();  // the block's slots are refilled next
+        }
+        continue;
+      }
       tpos[lane] = npos;
       if constexpr (MM) {
         float* ph = tphi + lane * PHS;
@@ -425,77 +531,16 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       wave_sync();
       if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
       const uint32_t left = total - cb;
-      const int n_sub = left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16);
-      floatx4 cv = {1.f, 1.f, 1.f, 1.f};
-      if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
-      if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
-      // unrolled over the four sub-tiles: the products and the LDS offsets of each sub-tile get registers
-      // and immediates of their own (no register copies or address updates between sub-tiles)
-#pragma unroll
-      for (int sub = 0; sub < 4; ++sub) {
-        if (sub >= n_sub) break;  // uniform
-        // this lane's four candidates of the sub-tile, read before any use
-        const float4* zp = tpos + 16 * sub + CPL * g;
-        float4 z4[CPL];
-#pragma unroll
-        for (int rr = 0; rr < CPL; ++rr) z4[rr] = zp[rr];
-        float phi4[4] = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (MM) {
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) phi4[rr] = tphi[(16 * sub + 4 * g + rr) * PHS + s];
-        }
-        floatx4 cur = cv;
-        if constexpr (FEAT == FEAT_DENSE) {
-          // issue the next sub-tile's products now: the matrix core works while the VALU runs below
-          if (sub + 1 < n_sub) cv = tile_products<DP, FS>(tfeat, s, g, sub + 1, fsrc);
-        } else if constexpr (LP) {
-          if (sub + 1 < n_sub) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, sub + 1, slp);
-        }
-#pragma unroll
-        for (int rr = 0; rr < CPL; ++rr) {
-          const float4 z = z4[rr];
-          float dx, dy, dz;
-          const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
-          const bool near = s2 <= rc2;
-          bool in = near;
-          float c = 1.f;
-          if constexpr (FEAT == FEAT_CLASS) {
-            if constexpr (!LS) in = in && (__float_as_uint(z.w) == lbl);
-          } else {
-            c = CM == 1 ? fmaxf(cur[rr], 0.f) : cur[rr];
-          }
-          const float k = __builtin_amdgcn_exp2f(-alpha * s2);
-          const float w = in ? c * k : 0.f;
-          // pairs counted per pass from the wavefront's lane masks (scalar unit), or per lane (SC)
-          if constexpr (SC) {
-            if constexpr (FEAT == FEAT_CLASS || CM == 2) own += in ? 1u : 0u;
-            else own += (in && c != 0.f) ? 1u : 0u;
-          } else if constexpr (LS) {
-            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near));
-          } else if constexpr (FEAT == FEAT_CLASS) {
-            // the two compares' lane masks, combined on the scalar unit (a ballot of the combined
-            // condition would first turn it into a vector value and back)
-            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(near) &
-                                      __builtin_amdgcn_ballot_w64(__float_as_uint(z.w) == lbl));
-          } else if constexpr (CM == 2) {
-            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
-          } else {
-            cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(c != 0.f));
-          }
-          if constexpr (MM) {
-            macc[rr & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, phi4[rr], macc[rr & 1], 0, 0, 0);
-          } else {
-            A += w;
-          }
-          if constexpr (MODE == MODE_NORMAL && !MM) {
-            const float wx = w * dx, wy = w * dy;
-            Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
-            Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
-          }
-        }
-      }
+      process(tpos, left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16));
       wave_sync();  // the tile buffer is rewritten next
+    }
+  }
+  if constexpr (CF) {
+    if (tail > head) {  // the last, partial block; its empty slots hold far padding candidates
+      const uint32_t rem = tail - head;
+      if ((uint32_t)lane >= rem) tpos[(head + lane) & (2 * kTile - 1)] = make_float4(far_, far_, far_, 0.f);
+      wave_sync();
+      process(tpos + (head & (2 * kTile - 1)), (int)((rem + 15) / 16));
     }
   }
 
