@@ -419,7 +419,7 @@ int rkhsba_gn_step(rkhsba_ctx* c, double* poses, int E, const int32_t* edges, in
     g.upload_poses(p, poses);
     g.reset_state(p);
     g.iterate(c->lay_gn, n_iter);
-    g.evaluate(c->lay_gn, MODE_LOSS);
+    g.evaluate(c->lay_gn, MODE_LOSS, n_iter > 0);  // the binning of this call's first iteration
     g.loss_only(c->lay_gn);
     std::vector<double> lh(n_iter + 1), ph(n_iter + 1);
     g.download_poses(p, poses);

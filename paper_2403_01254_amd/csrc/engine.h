@@ -240,6 +240,14 @@ struct SetLayout {
   uint64_t graph_gen = 0;
   int graph_mode = -1;
   int uses = 0;                     // iterate() calls since the layout was built
+  // the binning (sorted entries) of the layout's last full binning, while the scratch still holds it
+  bool binned = false;
+  uint64_t bin_gen = 0;             // scratch generation it was written under
+  const void* bin_sc = nullptr;     // scratch set it lives in
+  const uint32_t* bin_k = nullptr;
+  const uint32_t* bin_v = nullptr;
+  hipGraphExec_t graph_rest = nullptr;  // iterations after the first of an iterate() call (binning reused)
+  uint64_t graph_rest_gen = 0;
   // pinned staging of the host tables' uploads, free again once stage_ev has completed
   uint8_t* stage = nullptr;
   size_t stage_cap = 0;
@@ -316,7 +324,10 @@ class Engine {
   // be one used only under this arena; it is rebuilt on every prepare().
   void set_arena(Arena* a);
   // One evaluation of every item of the set at the device poses: per-edge sums in edge_out.
-  void evaluate(SetLayout& lay, int mode);
+  // reuse_binning: keep the order of the layout's last binning (its passes stay spatially compact while
+  // the poses move a little) and only recompute which sources fall outside their target grids; done in
+  // full when the scratch no longer holds that binning.
+  void evaluate(SetLayout& lay, int mode, bool reuse_binning = false);
   // Assembly (+ history entry) of every problem.
   void assemble(SetLayout& lay);
   // Damped solve + pose update of every problem still iterating.
@@ -365,7 +376,8 @@ class Engine {
 
  private:
   void compute_constants(Problem* p);
-  void record_iteration(SetLayout& lay);
+  void record_iteration(SetLayout& lay, bool reuse_binning);
+  const SetLayout* binned_lay_ = nullptr;  // layout whose binning the scratch holds
 
   std::map<int, std::unique_ptr<Problem>> probs_;
   int next_id_ = 0;

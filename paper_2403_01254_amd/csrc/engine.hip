@@ -129,7 +129,9 @@ int64_t Pool::alloc(int64_t n, hipStream_t st) {
 
 void SetLayout::drop_graph() {
   if (graph) (void)hipGraphExecDestroy(graph);
+  if (graph_rest) (void)hipGraphExecDestroy(graph_rest);
   graph = nullptr;
+  graph_rest = nullptr;
   graph_mode = -1;
 }
 
@@ -744,7 +746,7 @@ void Engine::read_source_counts(Problem* p, int m, int64_t* counts) {
   for (int32_t i = 0; i < F.n; ++i) counts[i] = 0;
   for (int32_t e = 0; e < F.n; ++e) {
     RK_REQUIRE(v[e] < (uint32_t)F.n, RKHSBA_EDEVICE, "binning value out of range");
-    counts[perm[v[e]]] = k[e] == kInvalidKey ? 0 : (int64_t)c[e];
+    counts[perm[v[e]]] = (k[e] & kInvalidBit) ? 0 : (int64_t)c[e];
   }
 }
 
@@ -1055,6 +1057,7 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
   }
 
   lay.uses = 0;
+  lay.binned = false;
   lay.ids = std::move(ids);
   lay.edge_key = std::move(key);
   lay.sys = std::move(sys);
@@ -1077,18 +1080,33 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
 
 // ---------------------------------------------------------------- launches
 
-void Engine::evaluate(SetLayout& lay, int mode) {
+void Engine::evaluate(SetLayout& lay, int mode, bool reuse_binning) {
   RK_REQUIRE(!arena_ || mode == MODE_LOSS || arena_->mom_components == 10, RKHSBA_ESTATE,
              "the arena holds loss-evaluation moments only");
   hipEvent_t t0 = prof_begin();
   RK_HIP(launch_edge_setup(poses(), lay.d_edges.p, lay.E, sc_->xf.p, st));
-  RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p, sc_->bk.p,
-                    sc_->bv.p, st));
-  bool in_tmp = false;
-  RK_HIP(launch_radix_sort(sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, lay.d_etiles.p, lay.n_edge_tiles, lay.d_esegs.p,
-                           lay.n_edge_segs, lay.bin_bits, st, &in_tmp));
-  sorted_k_ = in_tmp ? sc_->bk2.p : sc_->bk.p;
-  sorted_v_ = in_tmp ? sc_->bv2.p : sc_->bv.p;
+  const bool reuse = reuse_binning && lay.binned && binned_lay_ == &lay && lay.bin_sc == sc_ &&
+                     lay.bin_gen == scratch_gen_;
+  if (reuse) {
+    sorted_k_ = lay.bin_k;
+    sorted_v_ = lay.bin_v;
+    RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
+                      const_cast<uint32_t*>(sorted_k_), const_cast<uint32_t*>(sorted_v_), true, st));
+  } else {
+    RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
+                      sc_->bk.p, sc_->bv.p, false, st));
+    bool in_tmp = false;
+    RK_HIP(launch_radix_sort(sc_->bk.p, sc_->bv.p, sc_->bk2.p, sc_->bv2.p, sc_->bhist.p, lay.d_etiles.p,
+                             lay.n_edge_tiles, lay.d_esegs.p, lay.n_edge_segs, lay.bin_bits, st, &in_tmp));
+    sorted_k_ = in_tmp ? sc_->bk2.p : sc_->bk.p;
+    sorted_v_ = in_tmp ? sc_->bv2.p : sc_->bv.p;
+    lay.binned = true;
+    lay.bin_gen = scratch_gen_;
+    lay.bin_sc = sc_;
+    lay.bin_k = sorted_k_;
+    lay.bin_v = sorted_v_;
+    binned_lay_ = &lay;
+  }
   prof_end(RKHSBA_PROF_BIN, t0);
   PairArgs pa{};
   pa.pts = pts();
@@ -1174,8 +1192,8 @@ void Engine::solve(SetLayout& lay) {
   prof_end(RKHSBA_PROF_SOLVE, t);
 }
 
-void Engine::record_iteration(SetLayout& lay) {
-  evaluate(lay, MODE_NORMAL);
+void Engine::record_iteration(SetLayout& lay, bool reuse_binning) {
+  evaluate(lay, MODE_NORMAL, reuse_binning);
   hipEvent_t t = prof_begin();
   RK_HIP(launch_assemble(solve_args(lay), st));
   RK_HIP(launch_solve_update(solve_args(lay), st));
@@ -1188,17 +1206,17 @@ void Engine::iterate(SetLayout& lay, int n) {
   // layout's second use, or when this call runs several iterations.
   const bool graph = use_graphs && !prof && (n > 1 || lay.uses >= graph_min_uses);
   ++lay.uses;
+  // The first iteration bins the sources afresh; the later ones keep its order (see evaluate).
   if (!graph) {
-    for (int i = 0; i < n; ++i) record_iteration(lay);
+    for (int i = 0; i < n; ++i) record_iteration(lay, i > 0);
     return;
   }
   const uint64_t g = generation();
-  if (!lay.graph || lay.graph_gen != g) {
-    lay.drop_graph();
+  auto capture = [&](bool reuse) -> hipGraphExec_t {
     RK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipGraph_t graph = nullptr;
     try {
-      record_iteration(lay);
+      record_iteration(lay, reuse);
     } catch (...) {
       (void)hipStreamEndCapture(st, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -1209,11 +1227,25 @@ void Engine::iterate(SetLayout& lay, int n) {
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     RK_HIP(e);
-    lay.graph = exec;
+    return exec;
+  };
+  if (!lay.graph || lay.graph_gen != g) {
+    lay.drop_graph();
+    lay.graph = capture(false);
     lay.graph_gen = g;
     lay.graph_mode = MODE_NORMAL;
   }
-  for (int i = 0; i < n; ++i) RK_HIP(hipGraphLaunch(lay.graph, st));
+  // the replay bins into the scratch as the capture did: the host-side record of the binning follows it
+  binned_lay_ = &lay;
+  lay.binned = true;
+  if (n > 1 && (!lay.graph_rest || lay.graph_rest_gen != g)) {
+    if (lay.graph_rest) (void)hipGraphExecDestroy(lay.graph_rest);
+    lay.graph_rest = nullptr;
+    lay.graph_rest = capture(true);
+    lay.graph_rest_gen = g;
+  }
+  RK_HIP(hipGraphLaunch(lay.graph, st));
+  for (int i = 1; i < n; ++i) RK_HIP(hipGraphLaunch(lay.graph_rest, st));
 }
 
 }  // namespace rkhsba

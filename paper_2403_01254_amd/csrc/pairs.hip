@@ -82,8 +82,11 @@ __global__ void k_edge_setup(const double* __restrict__ poses, const EdgeInfo* _
 }
 
 // One block per sort tile (kSortTile consecutive entries of one edge): the
-// Morton code of each source point's target-frame cell, or kInvalidKey when
-// the point falls outside the target grid (it has no pair).
+// Morton code of each source point's target-frame cell, clamped to the grid
+// and its margin of reach cells, with kInvalidBit set when the point lies
+// beyond them (it has no pair).  SORTED: the entries already hold sorted
+// source indices (an earlier binning of the same set); only keys are written.
+template <bool SORTED>
 __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__ pts,
                                                       const FrameInfo* __restrict__ frames,
                                                       const EdgeInfo* __restrict__ edges,
@@ -101,17 +104,21 @@ __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__
   const int lim = 1 << 30;
   for (int k = threadIdx.x; k < t.count; k += kSortThreads) {
     const int64_t i = t.start + k;
-    const uint32_t src = (uint32_t)(i - ed.ent_off);
+    const uint32_t src = SORTED ? vals[i] : (uint32_t)(i - ed.ent_off);
     const float4 x = pts[Fm.pt_off + src];
     const float3 q = rule_q32(X, x.x, x.y, x.z);
-    const int cx = clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r;
-    const int cy = clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r;
-    const int cz = clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r;
-    uint32_t key = kInvalidKey;
-    if (cx >= 0 && cy >= 0 && cz >= 0 && cx < Fn.dim[0] + 2 * r && cy < Fn.dim[1] + 2 * r && cz < Fn.dim[2] + 2 * r)
-      key = morton3((uint32_t)cx >> Fn.mort_shift, (uint32_t)cy >> Fn.mort_shift, (uint32_t)cz >> Fn.mort_shift);
-    keys[i] = key;
-    vals[i] = src;
+    int c[3] = {clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r,
+                clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r,
+                clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r};
+    uint32_t invalid = 0u;
+    for (int a = 0; a < 3; ++a) {
+      const int top = Fn.dim[a] + 2 * r - 1;
+      if (c[a] < 0 || c[a] > top) invalid = kInvalidBit;
+      c[a] = min(max(c[a], 0), top);
+    }
+    keys[i] = invalid | morton3((uint32_t)c[0] >> Fn.mort_shift, (uint32_t)c[1] >> Fn.mort_shift,
+                                (uint32_t)c[2] >> Fn.mort_shift);
+    if constexpr (!SORTED) vals[i] = src;
   }
 }
 
@@ -172,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
   bool valid = in_range;
   uint32_t src = 0;
   if (valid) {
-    valid = a.keys[entry] != kInvalidKey;
+    valid = !(a.keys[entry] & kInvalidBit);
     src = a.vals[entry];
   }
   float3 q = make_float3(0.f, 0.f, 0.f);
@@ -362,9 +369,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
     if (entry >= end) break;
     cnt_sum += (double)a.cnt[entry];  // per-entry or per-pass pair counts
     if constexpr (MODE == MODE_LOSS) {
-      if (a.keys[entry] != kInvalidKey) st[0].add((T)a.mom[entry]);
+      if (!(a.keys[entry] & kInvalidBit)) st[0].add((T)a.mom[entry]);
     } else {
-      if (a.keys[entry] == kInvalidKey) continue;
+      if (a.keys[entry] & kInvalidBit) continue;
       const T A = a.mom[entry];
       T B[3], C[6], x[3], q[3];
       for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
@@ -696,9 +703,14 @@ hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int
 
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges,
                       const SortTile* d_tiles, int n_tiles, const EdgeXf* d_xf, const KConst* d_kcs, uint32_t* d_keys,
-                      uint32_t* d_vals, hipStream_t st) {
-  if (n_tiles > 0)
-    k_bin<<<(unsigned)n_tiles, kSortThreads, 0, st>>>(d_pts, d_frames, d_edges, d_tiles, d_xf, d_kcs, d_keys, d_vals);
+                      uint32_t* d_vals, bool rebin_sorted, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (rebin_sorted)
+    k_bin<true><<<(unsigned)n_tiles, kSortThreads, 0, st>>>(d_pts, d_frames, d_edges, d_tiles, d_xf, d_kcs, d_keys,
+                                                            d_vals);
+  else
+    k_bin<false><<<(unsigned)n_tiles, kSortThreads, 0, st>>>(d_pts, d_frames, d_edges, d_tiles, d_xf, d_kcs, d_keys,
+                                                             d_vals);
   return hipGetLastError();
 }
 

@@ -17,7 +17,10 @@
 
 namespace rkhsba {
 
-constexpr uint32_t kInvalidKey = 0xffffffffu;
+// Binning keys: a 30-bit Morton code of the source point's target-frame cell (clamped to the grid and its
+// margin), with this bit set when the point lies outside both (it has no pair).  The sort orders the code
+// bits only, so a point keeps its place when a later evaluation with the same binning flips the bit.
+constexpr uint32_t kInvalidBit = 0x80000000u;
 constexpr int kMaxDense = 64;
 
 enum Mode { MODE_LOSS = 0, MODE_NORMAL = 1 };
@@ -165,10 +168,12 @@ hipError_t launch_frame_centroid(const float4* d_pts, int n, double* d_out, hipS
 hipError_t launch_fill_passes(const EdgeInfo* d_edges, int E, const FrameInfo* d_frames, const SortSeg* d_segs,
                               PassInfo* d_passes, hipStream_t st);
 hipError_t launch_edge_setup(const double* d_poses, const EdgeInfo* d_edges, int E, EdgeXf* d_xf, hipStream_t st);
-// Binning keys and source indices of every entry, one block per sort tile of an edge.
+// Binning keys and source indices of every entry, one block per sort tile of an edge.  rebin_sorted: the
+// entries hold the sorted source indices of an earlier binning (d_vals, read only); only the keys, and with
+// them the invalid bits, are recomputed at the current transforms.
 hipError_t launch_bin(const float4* d_pts, const FrameInfo* d_frames, const EdgeInfo* d_edges,
                       const SortTile* d_tiles, int n_tiles, const EdgeXf* d_xf, const KConst* d_kcs, uint32_t* d_keys,
-                      uint32_t* d_vals, hipStream_t st);
+                      uint32_t* d_vals, bool rebin_sorted, hipStream_t st);
 
 struct PairArgs {
   const float4* pts;

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   bool valid = in_range;
   uint32_t src = 0;
   if (valid) {
-    valid = a.keys[entry] != kInvalidKey;
+    valid = !(a.keys[entry] & kInvalidBit);
     src = a.vals[entry];
   }
   float3 q = make_float3(0.f, 0.f, 0.f);

@@ -63,6 +63,10 @@ def test_alone_and_in_mix_agree(rk, requests, lanes, split_work, lane1_max):
 
 
 def test_served_matches_context_and_oracle(rk, requests):
+    """Each served solve against the same solve on a context and against the oracle.  The context keeps its
+    first iteration's binning of the source points for the later ones, the server bins every batch
+    iteration afresh: the passes, and with them the FP32 summation order, differ after the first step, so the
+    two agree to rounding (poses within 1e-6, pair counts within 1e-6 relative), not bit for bit."""
     with rk.Server(feat_kind="dense", D=20, max_active=8) as srv:
         tickets = [submit(srv, p) for p in requests]
         served = [srv.wait(t, timeout=120) for t in tickets]
@@ -70,8 +74,9 @@ def test_served_matches_context_and_oracle(rk, requests):
         ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, cell_subdiv=0)
         ctx.build_neighbors(p.points, p.feats, p.feat_kind)
         cposes, clpi, cppi = ctx.gn_step(p.init_poses, p.edges, p.n_iter)
-        np.testing.assert_array_equal(poses, cposes)
-        np.testing.assert_array_equal(ppi, cppi)
+        rot_c, tr_c = pose_errors(poses, cposes)
+        assert rot_c.max() <= 1e-6 and tr_c.max() <= 1e-6
+        np.testing.assert_allclose(ppi, cppi, rtol=1e-6)
         np.testing.assert_allclose(lpi, clpi, rtol=1e-6)
         op = oracle.Problem.from_scene(p)
         oposes, olpi = oracle.gn(op, p.init_poses, p.edges, p.n_iter, membership=oracle.MEMBER_FP32_RULE)
