@@ -170,9 +170,9 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // 16-candidate sub-tile
   static_assert(P == 16 || (P == 8 && FEAT == FEAT_CLASS && !MM), "8-point passes: class ids only");
   static_assert(!LS || FEAT == FEAT_CLASS, "label layers: class ids only");
-  // CF (class ids, VALU moments): the candidates of each fetched tile that lie beyond the reach of the
-  // pass's box are dropped and the rest compacted into full blocks of 64 before any source tests them
-  constexpr bool CF = FEAT == FEAT_CLASS && !MM;
+  // CF (class ids): the candidates of each fetched tile that lie beyond the reach of the pass's box are
+  // dropped and the rest compacted into full blocks of 64 before any source tests them
+  constexpr bool CF = FEAT == FEAT_CLASS;
   constexpr int CPL = P / 4;
   constexpr bool LP = feat_low_precision(FEAT);
   constexpr int FS = FEAT == FEAT_DENSE ? DP + 1 : 1;  // LDS FP32 feature row stride (odd: conflict-free column reads)
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   __shared__ float4 tpos[CF ? 2 * kTile : kTile];  // CF: a ring of two blocks
   __shared__ float tfeat[FEAT == FEAT_DENSE ? kTile * FS : 1];
   __shared__ __align__(16) uint8_t tlp[LP ? kTile * RB : 16];
-  __shared__ float tphi[MM ? kTile * PHS : 1];
+  __shared__ float tphi[MM ? (CF ? 2 : 1) * kTile * PHS : 1];  // Phi rows of the candidates in tpos
   __shared__ float mt[MM ? 16 * 17 : 1];
 
   const int lane = threadIdx.x;
@@ -257,8 +257,21 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   floatx4 macc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
   if constexpr (MM) {
 #pragma unroll
-    for (int k = 10; k < 16; ++k) tphi[lane * PHS + k] = 0.f;  // unused Phi columns stay zero
+    for (int k = 10; k < 16; ++k) {  // unused Phi columns stay zero
+      tphi[lane * PHS + k] = 0.f;
+      if constexpr (CF) tphi[(kTile + lane) * PHS + k] = 0.f;
+    }
   }
+  // Phi of candidate position p (zero for padding)
+  auto write_phi = [&](float* ph, float4 p, bool pad) __attribute__((always_inline)) {
+    const float ux = pad ? 0.f : p.x - ref.x;
+    const float uy = pad ? 0.f : p.y - ref.y;
+    const float uz = pad ? 0.f : p.z - ref.z;
+    ph[0] = pad ? 0.f : 1.f;
+    ph[1] = ux; ph[2] = uy; ph[3] = uz;
+    ph[4] = ux * ux; ph[5] = ux * uy; ph[6] = ux * uz;
+    ph[7] = uy * uy; ph[8] = uy * uz; ph[9] = uz * uz;
+  };
 
   const double inv = kc.inv_cell, cell = kc.cell, reach = kc.reach;
   const int z0 = max(clamp_floor_d(((double)lo.z - reach) * inv - Fn.org[2], -1, Fn.dim[2]), 0);
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   // then walks the cell rows of its own ball only (the box shrunk to its point, the same row and x-range
   // trimming), its G lanes taking every G-th row, and reads the candidates straight from the frame.
   bool spread = false;
-  if constexpr (FEAT == FEAT_CLASS && !MM) {
+  if constexpr (FEAT == FEAT_CLASS) {
     spread = fmaxf(hi.x - lo.x, fmaxf(hi.y - lo.y, hi.z - lo.z)) > kc.spread_limit;  // uniform
     if (spread) {
       n_rows = 0;  // no shared walk
@@ -339,7 +352,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
 
   // The sub-tiles of one block of 64 candidates (blk: their positions in LDS; dense features, products and
   // Phi from the tile buffers) against the pass's sources: the moments and pair counts above.
-  auto process = [&](const float4* __restrict__ blk, int n_sub) __attribute__((always_inline)) {
+  auto process = [&](const float4* __restrict__ blk, const float* __restrict__ bphi, int n_sub)
+                     __attribute__((always_inline)) {
     floatx4 cv = {1.f, 1.f, 1.f, 1.f};
     if constexpr (FEAT == FEAT_DENSE) cv = tile_products<DP, FS>(tfeat, s, g, 0, fsrc);
     if constexpr (LP) cv = tile_products_lp<FEAT, DP, RB>(tlp, s, g, 0, slp);
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       float phi4[4] = {0.f, 0.f, 0.f, 0.f};
       if constexpr (MM) {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) phi4[rr] = tphi[(16 * sub + 4 * g + rr) * PHS + s];
+        for (int rr = 0; rr < 4; ++rr) phi4[rr] = bphi[(16 * sub + 4 * g + rr) * PHS + s];
       }
       floatx4 cur = cv;
       if constexpr (FEAT == FEAT_DENSE) {
@@ -491,30 +505,25 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         // keep the candidates within reach of the pass's box, appended to the ring in list order
         const bool keep = !npad && box_s2(lo, hi, npos) <= rc2;
         const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
-        if (keep)
-          tpos[(tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u))) &
-               (2 * kTile - 1)] = npos;
+        if (keep) {
+          const uint32_t slot =
+              (tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u))) &
+              (2 * kTile - 1);
+          tpos[slot] = npos;
+          if constexpr (MM) write_phi(tphi + slot * PHS, npos, false);
+        }
         tail += (uint32_t)__popcll(km);
         wave_sync();
         if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
         if (tail - head >= (uint32_t)kTile) {  // a full block (at most one per fetched tile)
-          process(tpos + (head & (2 * kTile - 1)), 4);
+          process(tpos + (head & (2 * kTile - 1)), tphi + (head & (2 * kTile - 1)) * PHS, 4);
           head += kTile;
           wave_sync();  // the block's slots are refilled next
         }
         continue;
       }
       tpos[lane] = npos;
-      if constexpr (MM) {
-        float* ph = tphi + lane * PHS;
-        const float ux = npad ? 0.f : npos.x - ref.x;
-        const float uy = npad ? 0.f : npos.y - ref.y;
-        const float uz = npad ? 0.f : npos.z - ref.z;
-        ph[0] = npad ? 0.f : 1.f;
-        ph[1] = ux; ph[2] = uy; ph[3] = uz;
-        ph[4] = ux * ux; ph[5] = ux * uy; ph[6] = ux * uz;
-        ph[7] = uy * uy; ph[8] = uy * uz; ph[9] = uz * uz;
-      }
+      if constexpr (MM) write_phi(tphi + lane * PHS, npos, npad);
       if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
         for (int k = 0; k < DP; ++k) tfeat[lane * FS + k] = nfeat[k];
@@ -531,42 +540,49 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       wave_sync();
       if (cb + kTile < total) fetch(cb + kTile + lane, npos, nfeat, nlp, npad);
       const uint32_t left = total - cb;
-      process(tpos, left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16));
+      process(tpos, tphi, left >= (uint32_t)kTile ? 4 : (int)((left + 15) / 16));
       wave_sync();  // the tile buffer is rewritten next
     }
   }
   if constexpr (CF) {
     if (tail > head) {  // the last, partial block; its empty slots hold far padding candidates
       const uint32_t rem = tail - head;
-      if ((uint32_t)lane >= rem) tpos[(head + lane) & (2 * kTile - 1)] = make_float4(far_, far_, far_, 0.f);
+      if ((uint32_t)lane >= rem) {
+        const uint32_t slot = (head + lane) & (2 * kTile - 1);
+        tpos[slot] = make_float4(far_, far_, far_, 0.f);
+        if constexpr (MM) write_phi(tphi + slot * PHS, tpos[slot], true);
+      }
       wave_sync();
-      process(tpos + (head & (2 * kTile - 1)), (int)((rem + 15) / 16));
+      process(tpos + (head & (2 * kTile - 1)), tphi + (head & (2 * kTile - 1)) * PHS, (int)((rem + 15) / 16));
     }
   }
 
   if constexpr (MM) {
-    // lane (s, g) holds M[source 4g + r][column s]; regroup per source through LDS
-    wave_sync();
+    if (!spread) {  // (uniform; spread passes summed their moments on the VALU)
+      // lane (s, g) holds M[source 4g + r][column s]; regroup per source through LDS
+      wave_sync();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) mt[(4 * g + r) * 17 + s] = macc[0][r] + macc[1][r];
-    wave_sync();
-    if (g == 0) {
-      const float* m = mt + s * 17;
-      const float vx = q.x - ref.x, vy = q.y - ref.y, vz = q.z - ref.z;
-      A = m[0];
-      const float mx = m[1], my = m[2], mz = m[3];
-      Bx = A * vx - mx; By = A * vy - my; Bz = A * vz - mz;
-      Cxx = A * vx * vx - 2.f * vx * mx + m[4];
-      Cxy = A * vx * vy - vx * my - mx * vy + m[5];
-      Cxz = A * vx * vz - vx * mz - mx * vz + m[6];
-      Cyy = A * vy * vy - 2.f * vy * my + m[7];
-      Cyz = A * vy * vz - vy * mz - my * vz + m[8];
-      Wr2 = Cxx + Cyy + (A * vz * vz - 2.f * vz * mz + m[9]);
+      for (int r = 0; r < 4; ++r) mt[(4 * g + r) * 17 + s] = macc[0][r] + macc[1][r];
+      wave_sync();
+      if (g == 0) {
+        const float* m = mt + s * 17;
+        const float vx = q.x - ref.x, vy = q.y - ref.y, vz = q.z - ref.z;
+        A = m[0];
+        const float mx = m[1], my = m[2], mz = m[3];
+        Bx = A * vx - mx; By = A * vy - my; Bz = A * vz - mz;
+        Cxx = A * vx * vx - 2.f * vx * mx + m[4];
+        Cxy = A * vx * vy - vx * my - mx * vy + m[5];
+        Cxz = A * vx * vz - vx * mz - mx * vz + m[6];
+        Cyy = A * vy * vy - 2.f * vy * my + m[7];
+        Cyz = A * vy * vz - vy * mz - my * vz + m[8];
+        Wr2 = Cxx + Cyy + (A * vz * vz - 2.f * vz * mz + m[9]);
+      }
     }
   }
+
   // sum the four candidate streams of each source point
 #pragma unroll
-  for (int o = P; o < 64 && !MM; o <<= 1) {
+  for (int o = P; o < 64 && (!MM || spread); o <<= 1) {
     A += __shfl_xor(A, o, 64);
     if constexpr (MODE == MODE_NORMAL) {
       Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);

@@ -116,6 +116,26 @@ def test_normal_equations_parity(rk, scene):
     np.testing.assert_allclose(H, H.T, rtol=0, atol=1e-12 * np.abs(H).max())
 
 
+@pytest.mark.parametrize("moment_path", [1, 2])
+def test_normal_equations_parity_per_moment_path(rk, scene, moment_path):
+    """The 16-point tiled sweep with its Gauss-Newton moments summed on the vector ALU (1) or on the matrix
+    cores (2: moments about the pass's box centre, A, B, C recovered from them) against the oracle, at
+    1-r_c and 1/2-r_c cells."""
+    name, p = scene
+    op = oracle.Problem.from_scene(p)
+    oF, ob, oH, oFe, onp = oracle.normal_eqs(op, p.init_poses, p.edges, oracle.MEMBER_FP32_RULE)
+    for subdiv in (1, 2):
+        ctx = make_ctx(rk, p, pass_points=16, cell_subdiv=subdiv, moment_path=moment_path)
+        H, b, F, npairs = ctx.accumulate_normal_eqs(p.init_poses, p.edges)
+        say(f"[moments] {name} path {moment_path} subdiv {subdiv}: b rel {normwise_rel(b, ob):.3g} "
+            f"H rel {normwise_rel(H, oH):.3g}")
+        assert npairs == onp
+        assert abs(F - oF) <= REL_TOL * abs(oF)
+        assert_blocks_close(b, ob, 6, what=f"{name} b")
+        assert_blocks_close(H, oH, 6, what=f"{name} H")
+        ctx.close()
+
+
 def test_gauss_newton_parity(rk, scene):
     name, p = scene
     op = oracle.Problem.from_scene(p)
