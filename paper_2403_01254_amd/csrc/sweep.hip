@@ -312,35 +312,65 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       }
       const int nys = ys1 - ys0 + 1;
       const int nr = (zs1 >= zs0 && ys1 >= ys0 && lrow >= 0) ? (zs1 - zs0 + 1) * nys : 0;
-      for (int r = g; r < nr; r += G) {
-        const int kz = zs0 + r / nys, ky = ys0 + r % nys;
-        const double cz = (double)(kz + Fn.org[2]) * cell;
-        const double cy = (double)(ky + Fn.org[1]) * cell;
-        const double bz = fmax(0.0, fmax(cz - (double)q.z, (double)q.z - (cz + cell)));
-        const double by = fmax(0.0, fmax(cy - (double)q.y, (double)q.y - (cy + cell)));
-        const double r2 = kc.reach2 - by * by - bz * bz;
-        if (r2 < 0.0) continue;
-        const int4 R = trows[(int64_t)kz * Fn.dim[1] + ky];
-        if (R.y < R.x) continue;
-        const double h = sqrt(r2);
-        const int xa = max(clamp_floor_d(((double)q.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
-        const int xb = min(clamp_floor_d(((double)q.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R.y);
-        if (xa > xb) continue;
-        const uint32_t* xt = a.xtab + Fn.xt_off + (uint32_t)R.z;
-        const uint32_t j1 = xt[xb + 1 - R.x];
-        for (uint32_t j = xt[xa - R.x]; j < j1; ++j) {
-          const float4 z = tp[j];
-          float dx, dy, dz;
-          const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
-          if (!(s2 <= rc2 && (LS || __float_as_uint(z.w) == lbl))) continue;
-          const float w = __builtin_amdgcn_exp2f(-alpha * s2);
-          own += 1u;
-          A += w;
-          if constexpr (MODE == MODE_NORMAL) {
-            const float wx = w * dx, wy = w * dy;
-            Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
-            Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
-            Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
+      // Rows g, g + G, ... of the ball, kR at a time: the row descriptors of a batch are read together, then
+      // their x ranges' table entries, then the candidates kU at a time, so that the reads of a lane do not
+      // wait on each other.
+      constexpr int kR = 2, kU = 4;
+      for (int r0 = g; r0 < nr; r0 += G * kR) {
+        int4 R[kR];
+        double r2s[kR];
+#pragma unroll
+        for (int t = 0; t < kR; ++t) {
+          const int r = r0 + G * t;
+          R[t] = make_int4(1, 0, 0, 0);  // empty
+          r2s[t] = -1.0;
+          if (r < nr) {
+            const int kz = zs0 + r / nys, ky = ys0 + r % nys;
+            const double cz = (double)(kz + Fn.org[2]) * cell;
+            const double cy = (double)(ky + Fn.org[1]) * cell;
+            const double bz = fmax(0.0, fmax(cz - (double)q.z, (double)q.z - (cz + cell)));
+            const double by = fmax(0.0, fmax(cy - (double)q.y, (double)q.y - (cy + cell)));
+            r2s[t] = kc.reach2 - by * by - bz * bz;
+            if (r2s[t] >= 0.0) R[t] = trows[(int64_t)kz * Fn.dim[1] + ky];
+          }
+        }
+        uint32_t j0[kR], j1[kR];
+#pragma unroll
+        for (int t = 0; t < kR; ++t) {
+          j0[t] = j1[t] = 0u;
+          if (r2s[t] >= 0.0 && R[t].y >= R[t].x) {
+            const double h = sqrt(r2s[t]);
+            const int xa = max(clamp_floor_d(((double)q.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R[t].x);
+            const int xb = min(clamp_floor_d(((double)q.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R[t].y);
+            if (xa <= xb) {
+              const uint32_t* xt = a.xtab + Fn.xt_off + (uint32_t)R[t].z;
+              j0[t] = xt[xa - R[t].x];
+              j1[t] = xt[xb + 1 - R[t].x];
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kR; ++t) {
+          for (uint32_t jb = j0[t]; jb < j1[t]; jb += kU) {
+            float4 zu[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) zu[u] = tp[jb + u < j1[t] ? jb + u : jb];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+              const float4 z = zu[u];
+              float dx, dy, dz;
+              const float s2 = rule_s2(q, z.x, z.y, z.z, dx, dy, dz);
+              if (!(jb + u < j1[t] && s2 <= rc2 && (LS || __float_as_uint(z.w) == lbl))) continue;
+              const float w = __builtin_amdgcn_exp2f(-alpha * s2);
+              own += 1u;
+              A += w;
+              if constexpr (MODE == MODE_NORMAL) {
+                const float wx = w * dx, wy = w * dy;
+                Bx += wx; By += wy; Bz = fmaf(w, dz, Bz);
+                Cxx = fmaf(wx, dx, Cxx); Cxy = fmaf(wx, dy, Cxy); Cxz = fmaf(wx, dz, Cxz);
+                Cyy = fmaf(wy, dy, Cyy); Cyz = fmaf(wy, dz, Cyz); Wr2 = fmaf(w, s2, Wr2);
+              }
+            }
           }
         }
       }
@@ -477,11 +507,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       const int rid = tile_rows(c - (uint32_t)lane);
       const uint32_t jc = row_j0[rid] + (c - row_off[rid]);
       pad = c >= total || jc >= (uint32_t)Fn.n;  // the second test only bounds the reads below
-      // padding lanes read the frame's first point (always present when there are candidates) and
-      // move it far away: it fails every membership test and its products stay finite
+      // padding lanes read the frame's first point (always present when there are candidates); the consumer
+      // moves it far away, where it fails every membership test and its products stay finite (replacing
+      // the loaded value here would wait for the read and stall the prefetch)
       const uint32_t j = pad ? 0u : jc;
       pos = tp[j];
-      if (pad) pos = make_float4(far_, far_, far_, 0.f);
       if constexpr (FEAT == FEAT_DENSE) {
         const float4* f4 = reinterpret_cast<const float4*>(tf + (int64_t)j * DP);
 #pragma unroll
@@ -522,7 +552,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         }
         continue;
       }
-      tpos[lane] = npos;
+      tpos[lane] = npad ? make_float4(far_, far_, far_, 0.f) : npos;
       if constexpr (MM) write_phi(tphi + lane * PHS, npos, npad);
       if constexpr (FEAT == FEAT_DENSE) {
 #pragma unroll
