@@ -62,6 +62,26 @@ def test_alone_and_in_mix_agree(rk, requests, lanes, split_work, lane1_max):
         np.testing.assert_array_equal(a[2], m[2])          # pair counts
 
 
+def test_large_systems_alone_and_batched_agree(rk):
+    """Requests of 24 frames (138 unknowns: the blocked Cholesky solve, beyond the in-LDS one), served alone
+    and together: each system is factored by a workgroup of its own either way, so the poses agree bit for
+    bit, and the first request's poses meet the oracle's."""
+    reqs = [scenes.request(s, k_range=(24, 24), n_range=(600, 900), n_iter=3) for s in (31, 32)]
+    say("[server] large systems: " + "; ".join(p.recipe[:50] for p in reqs))
+    with rk.Server(feat_kind="dense", D=20, max_active=8, lanes=1) as srv:
+        alone = [srv.wait(submit(srv, p), timeout=120) for p in reqs]
+        tickets = [submit(srv, p) for p in reqs]
+        both = [srv.wait(t, timeout=120) for t in tickets]
+        assert srv.stats()["max_active"] == 2
+    for p, a, m in zip(reqs, alone, both):
+        np.testing.assert_array_equal(a[0], m[0])
+        np.testing.assert_array_equal(a[1], m[1])
+    op = oracle.Problem.from_scene(reqs[0], search="cells")
+    oposes, _ = oracle.gn(op, reqs[0].init_poses, reqs[0].edges, reqs[0].n_iter, membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(alone[0][0], oposes)
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+
+
 def test_served_matches_context_and_oracle(rk, requests):
     """Each served solve against the same solve on a context and against the oracle.  The context keeps its
     first iteration's binning of the source points for the later ones, the server bins every batch
