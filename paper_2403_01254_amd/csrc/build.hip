@@ -21,59 +21,83 @@ __device__ inline void frame_of(const int64_t* __restrict__ off, int K, int64_t 
 // k = floor(x * inv_cell) per axis (FP64), and per-frame min/max (and, with
 // class ids, the largest id).
 // minmax layout: [f*6 + 0..2] min, [f*6 + 3..5] max; [K*6] error flag.
+// A block takes kCoordItems consecutive points per thread-column (threads
+// read consecutive points); the bounds of the block's first frame are reduced
+// in the block (wavefront shuffles, then LDS) and written with one atomic per
+// value, so a frame's few bound words see a handful of atomics per block
+// instead of one per wavefront.  Points of any later frame in the block (at
+// most a frame boundary or a few small frames) use per-point atomics.
+constexpr int kCoordItems = 16;
+
 __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __restrict__ xyz,
                                                           const int64_t* __restrict__ off, int K, int64_t n_total,
                                                           double inv_cell, const void* const* __restrict__ cls,
                                                           int32_t* __restrict__ cell, int32_t* __restrict__ minmax,
                                                           int32_t* __restrict__ label_max) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const bool live = i < n_total;
-  int f = -1;
-  int64_t l = 0;
-  if (live) frame_of(off, K, i, f, l);
-  int k[3] = {0, 0, 0};
+  __shared__ int32_t sb[7];  // the first frame's min x, y, z, max x, y, z, largest id
+  const int t = threadIdx.x;
+  if (t < 3) {
+    sb[t] = INT_MAX;
+    sb[3 + t] = INT_MIN;
+  }
+  if (t == 6) sb[6] = -1;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kThreads * kCoordItems;
+  const int f0 = upper_segment(off, K, base);
+  int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN}, lb = -1;
   bool bad = false;
-  if (live) {
+  for (int it = 0; it < kCoordItems; ++it) {
+    const int64_t i = base + (int64_t)it * kThreads + t;
+    if (i >= n_total) break;
+    int f;
+    int64_t l;
+    frame_of(off, K, i, f, l);
     const float* p = xyz[f] + 3 * l;
+    int k[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a) {
-      const double s = (double)p[a] * inv_cell;
-      if (!(fabs(s) < 1.0e9)) bad = true;  // NaN, Inf or beyond the int32 cell range
-      else k[a] = (int)floor(s);
+      const double sv = (double)p[a] * inv_cell;
+      if (!(fabs(sv) < 1.0e9)) bad = true;  // NaN, Inf or beyond the int32 cell range
+      else k[a] = (int)floor(sv);
       cell[3 * i + a] = k[a];
+    }
+    const int lab = label_max ? (int)static_cast<const uint16_t*>(cls[f])[l] : -1;
+    if (f == f0) {
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = min(mn[a], k[a]);
+        mx[a] = max(mx[a], k[a]);
+      }
+      lb = max(lb, lab);
+    } else {  // a later frame starts inside this block
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&minmax[f * 6 + a], k[a]);
+        atomicMax(&minmax[f * 6 + 3 + a], k[a]);
+      }
+      if (label_max) atomicMax(&label_max[f], lab);
     }
   }
   if (__ballot(bad)) {
     if (bad) atomicOr(&minmax[K * 6], 1);
   }
-  // One atomic per wavefront when all its live lanes belong to one frame (the
-  // common case); per-lane atomics at frame boundaries.
-  const int f0 = __builtin_amdgcn_readfirstlane(f);
-  const bool same = __ballot(live && f != f0) == 0ull;
-  for (int a = 0; a < 3; ++a) {
-    int mn = live ? k[a] : INT_MAX, mx = live ? k[a] : INT_MIN;
-    if (same) {
-      for (int o = 32; o > 0; o >>= 1) {
-        mn = min(mn, __shfl_xor(mn, o, 64));
-        mx = max(mx, __shfl_xor(mx, o, 64));
-      }
-      if ((threadIdx.x & 63) == 0 && f0 >= 0) {
-        atomicMin(&minmax[f0 * 6 + a], mn);
-        atomicMax(&minmax[f0 * 6 + 3 + a], mx);
-      }
-    } else if (live) {
-      atomicMin(&minmax[f * 6 + a], mn);
-      atomicMax(&minmax[f * 6 + 3 + a], mx);
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = min(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = max(mx[a], __shfl_xor(mx[a], o, 64));
     }
+    lb = max(lb, __shfl_xor(lb, o, 64));
   }
-  if (label_max) {
-    int lb = live ? (int)static_cast<const uint16_t*>(cls[f])[l] : -1;
-    if (same) {
-      for (int o = 32; o > 0; o >>= 1) lb = max(lb, __shfl_xor(lb, o, 64));
-      if ((threadIdx.x & 63) == 0 && f0 >= 0) atomicMax(&label_max[f0], lb);
-    } else if (live) {
-      atomicMax(&label_max[f], lb);
+  if ((t & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&sb[a], mn[a]);
+      atomicMax(&sb[3 + a], mx[a]);
     }
+    atomicMax(&sb[6], lb);
   }
+  __syncthreads();
+  if (t < 3) {
+    if (sb[t] != INT_MAX) atomicMin(&minmax[f0 * 6 + t], sb[t]);
+    if (sb[3 + t] != INT_MIN) atomicMax(&minmax[f0 * 6 + 3 + t], sb[3 + t]);
+  }
+  if (t == 6 && label_max && sb[6] >= 0) atomicMax(&label_max[f0], sb[6]);
 }
 
 // Cell key of every point; in a label-stacked frame the class id selects the
@@ -210,6 +234,9 @@ __global__ __launch_bounds__(kThreads) void k_row_init(int4* __restrict__ rows, 
   if (r < n_rows) rows[r] = make_int4(INT_MAX, INT_MIN, 0, 0);
 }
 
+// The x extent of every occupied row: a frame's points are sorted by key, so
+// the points of one row are contiguous, and its first and last points give
+// x_lo and x_hi (plain stores, no atomics).
 __global__ __launch_bounds__(kThreads) void k_row_extent(const uint32_t* __restrict__ keys,
                                                          const FrameInfo* __restrict__ frames,
                                                          const int64_t* __restrict__ off, int K, int64_t n_total,
@@ -220,11 +247,14 @@ __global__ __launch_bounds__(kThreads) void k_row_extent(const uint32_t* __restr
   int64_t s;
   frame_of(off, K, p, f, s);
   const FrameInfo& F = frames[f];
-  int kx, ky, kz;
-  decode(keys[p], F, kx, ky, kz);
-  int4* row = rows + F.row_off + (int64_t)kz * F.dim[1] + ky;
-  atomicMin(&row->x, kx);
-  atomicMax(&row->y, kx);
+  const uint32_t nx = (uint32_t)F.dim[0];
+  const uint32_t key = keys[p];
+  const uint32_t row = key / nx;
+  const bool head = s == 0 || keys[p - 1] / nx != row;
+  const bool tail = s + 1 == F.n || keys[p + 1] / nx != row;
+  int4* R = rows + F.row_off + (int64_t)row;
+  if (head) R->x = (int)(key - row * nx);
+  if (tail) R->y = (int)(key - row * nx);
 }
 
 __global__ __launch_bounds__(kThreads) void k_row_sizes(const int4* __restrict__ rows, int64_t n_rows,
@@ -325,8 +355,9 @@ hipError_t launch_cell_coords(const float* const* d_xyz_ptrs, const int64_t* d_i
                               int32_t* d_label_max, hipStream_t st) {
   if (d_label_max && !d_class_ptrs) return hipErrorInvalidValue;
   if (n_total > 0)
-    k_cell_coords<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_in_off, K, n_total, inv_cell, d_class_ptrs,
-                                                        d_cell, d_minmax, d_label_max);
+    k_cell_coords<<<(unsigned)((n_total + (int64_t)kThreads * kCoordItems - 1) / ((int64_t)kThreads * kCoordItems)),
+                    kThreads, 0, st>>>(d_xyz_ptrs, d_in_off, K, n_total, inv_cell, d_class_ptrs, d_cell, d_minmax,
+                                       d_label_max);
   return hipGetLastError();
 }
 
