@@ -49,27 +49,62 @@ __device__ inline float uniform_f(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Minimum / maximum over the P consecutive lanes of each lane group (P a power of two <= 64).
+// Cross-lane moves within rows of 16 lanes (DPP: no LDS round trip).
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppXor1 = 0xb1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4e;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each half row
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within each row
+constexpr int kDppRor8 = 0x128;        // lane i <- lane (i + 8) mod 16 within each row, i.e. i ^ 8
+
+// Minimum / maximum over the P consecutive lanes of each lane group (P = 8 or 16): the quad, then the
+// other quad of the half row, then the other half row.
 template <int P>
 __device__ inline float group_min(float v) {
-#pragma unroll
-  for (int o = 1; o < P; o <<= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  static_assert(P == 8 || P == 16, "groups of 8 or 16 lanes");
+  v = fminf(v, dpp_f<kDppXor1>(v));
+  v = fminf(v, dpp_f<kDppXor2>(v));
+  v = fminf(v, dpp_f<kDppHalfMirror>(v));
+  if constexpr (P == 16) v = fminf(v, dpp_f<kDppMirror>(v));
   return v;
 }
 template <int P>
 __device__ inline float group_max(float v) {
-#pragma unroll
-  for (int o = 1; o < P; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  static_assert(P == 8 || P == 16, "groups of 8 or 16 lanes");
+  v = fmaxf(v, dpp_f<kDppXor1>(v));
+  v = fmaxf(v, dpp_f<kDppXor2>(v));
+  v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+  if constexpr (P == 16) v = fmaxf(v, dpp_f<kDppMirror>(v));
   return v;
 }
 
-__device__ inline uint32_t wave_inclusive_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
+// v + (v of lane ^ O), the same sum in both lanes (addition is commutative): a DPP row rotation for O = 8,
+// a cross-lane read through the LDS crossbar for 16 and 32.
+template <int O, typename T>
+__device__ inline T xor_add(T v) {
+  static_assert(O == 8 || O == 16 || O == 32, "lane distance");
+  if constexpr (O == 8) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    return v + __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppRor8, 0xf, 0xf, false));
+  } else {
+    return v + __shfl_xor(v, O, 64);
   }
-  return v;
+}
+
+// Inclusive add-scan of unsigned values over the wavefront's 64 lanes, in the same DPP steps as the max-scan
+// below (row shifts, then the last lane of a row added to the rows after it).
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+  int m = (int)v;
+  m += __builtin_amdgcn_update_dpp(0, m, 0x111, 0xf, 0xf, true);   // row_shr:1
+  m += __builtin_amdgcn_update_dpp(0, m, 0x112, 0xf, 0xf, true);   // row_shr:2
+  m += __builtin_amdgcn_update_dpp(0, m, 0x114, 0xf, 0xf, true);   // row_shr:4
+  m += __builtin_amdgcn_update_dpp(0, m, 0x118, 0xf, 0xf, true);   // row_shr:8
+  m += __builtin_amdgcn_update_dpp(0, m, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  m += __builtin_amdgcn_update_dpp(0, m, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)m;
 }
 
 // Inclusive max-scan of unsigned values over the wavefront's 64 lanes: four
@@ -481,7 +516,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
         }
       }
     }
-    const uint32_t incl = wave_inclusive_scan(cntr, lane);
+    const uint32_t incl = wave_inclusive_scan(cntr);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     wave_sync();  // previous users of row_j0/row_off are done
     row_j0[lane] = j0;
@@ -611,18 +646,23 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   }
 
   // sum the four candidate streams of each source point
-#pragma unroll
-  for (int o = P; o < 64 && (!MM || spread); o <<= 1) {
-    A += __shfl_xor(A, o, 64);
+  auto sum_streams = [&](auto xa) __attribute__((always_inline)) {
+    A = xa(A);
     if constexpr (MODE == MODE_NORMAL) {
-      Bx += __shfl_xor(Bx, o, 64); By += __shfl_xor(By, o, 64); Bz += __shfl_xor(Bz, o, 64);
-      Cxx += __shfl_xor(Cxx, o, 64); Cxy += __shfl_xor(Cxy, o, 64); Cxz += __shfl_xor(Cxz, o, 64);
-      Cyy += __shfl_xor(Cyy, o, 64); Cyz += __shfl_xor(Cyz, o, 64); Wr2 += __shfl_xor(Wr2, o, 64);
+      Bx = xa(Bx); By = xa(By); Bz = xa(Bz);
+      Cxx = xa(Cxx); Cxy = xa(Cxy); Cxz = xa(Cxz);
+      Cyy = xa(Cyy); Cyz = xa(Cyz); Wr2 = xa(Wr2);
     }
+  };
+  if (!MM || spread) {
+    if constexpr (P == 8) sum_streams([](float v) { return xor_add<8>(v); });
+    sum_streams([](float v) { return xor_add<16>(v); });
+    sum_streams([](float v) { return xor_add<32>(v); });
   }
   if (SC || spread) {  // every source point's own count
-#pragma unroll
-    for (int o = P; o < 64; o <<= 1) own += __shfl_xor(own, o, 64);
+    if constexpr (P == 8) own = xor_add<8>(own);
+    own = xor_add<16>(own);
+    own = xor_add<32>(own);
     if (g == 0 && in_range) a.cnt[entry] = valid ? own : 0u;
   } else {
     // the pass's pair count goes to its first entry, zeros to the others
