@@ -364,21 +364,44 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   const int64_t N = a.n_entries;
   Acc<T> st[NS];
   double cnt_sum = 0.0;  // pair counts: integers, exact in FP64
-  for (int j = 0; j < ed.fin_pt; ++j) {
-    const int64_t entry = base + (int64_t)j * kFinThreads + threadIdx.x;
-    if (entry >= end) break;
-    cnt_sum += (double)a.cnt[entry];  // per-entry or per-pass pair counts
+  // The next entry's count, key, source index and moments are read while the current one is processed
+  // (three waves per SIMD at this register count hide little of the reads' latency otherwise).
+  constexpr int NM = MODE == MODE_LOSS ? 1 : 10;
+  struct In {
+    uint32_t cnt, key, val;
+    float m[NM];
+  };
+  auto load = [&](int64_t entry, In& in) __attribute__((always_inline)) {
+    in.cnt = a.cnt[entry];
+    in.key = a.keys[entry];
+    if constexpr (MODE != MODE_LOSS) in.val = a.vals[entry];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) in.m[k] = a.mom[k * N + entry];
+  };
+  In cur, nxt;
+  int64_t entry = base + threadIdx.x;
+  bool have = entry < end;
+  if (have) load(entry, cur);
+  for (int j = 0; j < ed.fin_pt && have; ++j) {
+    const int64_t nentry = entry + kFinThreads;
+    const bool nhave = j + 1 < ed.fin_pt && nentry < end;
+    if (nhave) load(nentry, nxt);
+    const In in = cur;
+    cur = nxt;
+    entry = nentry;
+    have = nhave;
+    cnt_sum += (double)in.cnt;  // per-entry or per-pass pair counts
     if constexpr (MODE == MODE_LOSS) {
-      if (!(a.keys[entry] & kInvalidBit)) st[0].add((T)a.mom[entry]);
+      if (!(in.key & kInvalidBit)) st[0].add((T)in.m[0]);
     } else {
-      if (a.keys[entry] & kInvalidBit) continue;
-      const T A = a.mom[entry];
+      if (in.key & kInvalidBit) continue;
+      const T A = in.m[0];
       T B[3], C[6], x[3], q[3];
-      for (int k = 0; k < 3; ++k) B[k] = a.mom[(1 + k) * N + entry];
-      for (int k = 0; k < 5; ++k) C[k] = a.mom[(4 + k) * N + entry];
-      T Wr2 = a.mom[9 * N + entry];  // the sweeps store sum w |d|^2 in place of C_zz
+      for (int k = 0; k < 3; ++k) B[k] = in.m[1 + k];
+      for (int k = 0; k < 5; ++k) C[k] = in.m[4 + k];
+      T Wr2 = in.m[9];  // the sweeps store sum w |d|^2 in place of C_zz
       C[5] = Wr2 - C[0] - C[3];
-      const float4 p = src_pts[a.vals[entry]];
+      const float4 p = src_pts[in.val];
       const double3 q64 = rule_q64(X, p.x, p.y, p.z);
       x[0] = p.x; x[1] = p.y; x[2] = p.z;
       q[0] = (T)q64.x; q[1] = (T)q64.y; q[2] = (T)q64.z;
