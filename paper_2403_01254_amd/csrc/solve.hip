@@ -224,8 +224,24 @@ __device__ void solve_lds(const ProbSys& S, const SolveArgs& a, double mu, doubl
 constexpr int NB = 32;
 constexpr int kPanelCols = (kLdsDoubles - NB * (NB + 1) - 2 * NB) / NB;  // rows of a column-major panel
 
-__device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, double* buf, int32_t* status) {
+// Zero rows of L21: many systems are block-sparse (each frame has a few neighbours in the pose graph), and
+// the factor keeps the profile of the matrix.  For systems whose panels all fit in LDS, flags[p * W + w] (W =
+// ceil(n / 32) words per panel) records, bit b, whether row 32 w + b of the factor has a nonzero entry in panel
+// p's columns; the row solve, the trailing update and both triangular solves skip what a zero row would
+// contribute (exact zeros: the factor and the solution are the same bit for bit).  flags == nullptr: every row
+// counts as nonzero.
+constexpr int kFlagRows = NB + kPanelCols;  // the largest system every panel of which is solved in LDS
+constexpr int kFlagWords = ((kFlagRows + 31) / 32) * ((kFlagRows + 31) / 32);
+
+__device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, double* buf, int32_t* status,
+                              uint32_t* flags) {
   const int n = S.n, t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  const int W = (n + 31) / 32;
+  if (n > kFlagRows) flags = nullptr;
+  static_assert(NB == 32, "one flag word per panel row chunk");
+  __shared__ int32_t live_chunks[(kFlagRows + 31) / 32];
+  __shared__ int32_t n_live;
+  __shared__ uint32_t chunk_mask;  // bit c: rows m0 + 32 c .. m0 + 32 c + 31 hold a nonzero row of L21
   double* H = a.H + S.h_off;
   double* Dg = buf;                       // NB x (NB + 1) diagonal block
   double* rd = buf + NB * (NB + 1);       // NB reciprocal pivots / diagonal
@@ -258,38 +274,84 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
     if (t < nb) rd[t] = 1.0 / Dg[t * (NB + 1) + t];
     __syncthreads();
     if (m <= kPanelCols) {
-      // panel rows in registers, stored column-major: P[j * m + r] = L21[r][j]
-      for (int r = t; r < m; r += kSolveThreads) {
-        double* row = H + (int64_t)(m0 + r) * n + kb;
-        double x[NB];
+      // panel rows in registers, stored column-major: P[j * m + r] = L21[r][j]; a zero row of A21 stays zero
+      const int pw = kb / 32;  // this panel's flag words start at pw * W
+      for (int r0 = 0; r0 < m; r0 += kSolveThreads) {  // uniform trip count (the ballot below)
+        const int r = r0 + t;
+        bool nz = false;
+        if (r < m) {
+          double* row = H + (int64_t)(m0 + r) * n + kb;
+          double x[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) x[j] = j < nb ? row[j] : 0.0;
+          for (int j = 0; j < NB; ++j) x[j] = j < nb ? row[j] : 0.0;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (j < nb) {
-            const double* Lj = Dg + j * (NB + 1);
-            double s0 = x[j], s1 = 0.0;
+          for (int j = 0; j < NB; ++j) nz = nz || x[j] != 0.0;
+          if (nz) {
 #pragma unroll
-            for (int k = 0; k + 1 < j; k += 2) {
-              s0 -= Lj[k] * x[k];
-              s1 -= Lj[k + 1] * x[k + 1];
+            for (int j = 0; j < NB; ++j) {
+              if (j < nb) {
+                const double* Lj = Dg + j * (NB + 1);
+                double s0 = x[j], s1 = 0.0;
+#pragma unroll
+                for (int k = 0; k + 1 < j; k += 2) {
+                  s0 -= Lj[k] * x[k];
+                  s1 -= Lj[k + 1] * x[k + 1];
+                }
+                if (j & 1) s0 -= Lj[j - 1] * x[j - 1];
+                x[j] = (s0 + s1) * rd[j];
+              }
             }
-            if (j & 1) s0 -= Lj[j - 1] * x[j - 1];
-            x[j] = (s0 + s1) * rd[j];
           }
-        }
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j < nb) {
-            row[j] = x[j];
-            P[j * m + r] = x[j];
-          }
+          for (int j = 0; j < NB; ++j)
+            if (j < nb) {
+              if (nz) row[j] = x[j];
+              P[j * m + r] = x[j];
+            }
+        }
+        if (flags) {  // rows m0 + r0 + 64 w' + lane: two whole words per wavefront (m0 and r0 are multiples of 32)
+          const uint64_t bits = __ballot(nz);
+          const int wd = (m0 + r0 + (t & ~63)) / 32;
+          if ((t & 63) == 0 && wd < W) flags[pw * W + wd] = (uint32_t)bits;
+          if ((t & 63) == 32 && wd + 1 < W) flags[pw * W + wd + 1] = (uint32_t)(bits >> 32);
+        }
       }
       __syncthreads();
-      // A22 -= L21 L21^T over 128 x 128 blocks on or below the diagonal; thread (tx, ty) takes rows
-      // a0 + ty + 32p and columns b0 + tx + 32q
+      // the 32-row chunks of A22 with a nonzero row of L21 in this panel
+      if (t == 0) {  // (m == 0, the last panel, has no chunk; otherwise m0 is a multiple of 32)
+        int c = 0;
+        uint32_t mask = 0;
+        for (int w = m0 / 32; m > 0 && w < W; ++w)
+          if (!flags || flags[pw * W + w]) {
+            live_chunks[c++] = w * 32 - m0;
+            mask |= 1u << (w - m0 / 32);
+          }
+        n_live = c;
+        chunk_mask = mask;
+      }
+      __syncthreads();
+      const int nl = n_live, nc = (m + 31) / 32;
+      if (2 * nl <= nc) {
+        // few live chunks: one 32 x 32 tile per pair of them, one entry per thread, the NB products summed in
+        // the same order as below
+        for (int u = 0; u < nl; ++u)
+          for (int v = 0; v <= u; ++v) {
+            const int i = live_chunks[u] + ty, k = live_chunks[v] + tx;
+            if (i < m && k <= i) {
+              double acc = 0.0;
+              for (int j = 0; j < nb; ++j) acc = fma(P[j * m + i], P[j * m + k], acc);
+              H[(int64_t)(m0 + i) * n + m0 + k] -= acc;
+            }
+          }
+        __syncthreads();
+        continue;
+      }
+      // A22 -= L21 L21^T over 128 x 128 blocks on or below the diagonal (those with a nonzero row of L21 on
+      // both sides); thread (tx, ty) takes rows a0 + ty + 32p and columns b0 + tx + 32q
+      const uint32_t cm = chunk_mask;
       for (int a0 = 0; a0 < m; a0 += 128)
         for (int b0 = 0; b0 <= a0; b0 += 128) {
+          if (!((cm >> (a0 / 32)) & 0xFu) || !((cm >> (b0 / 32)) & 0xFu)) continue;
           double acc[4][4];
 #pragma unroll
           for (int p = 0; p < 4; ++p)
@@ -401,6 +463,7 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
     }
     __syncthreads();
     for (int i = kb + nb + t; i < n; i += kSolveThreads) {
+      if (flags && !((flags[(kb / 32) * W + i / 32] >> (i & 31)) & 1u)) continue;  // zero row of this panel
       const double* row = H + (int64_t)i * n + kb;
       double v = y[i];
       for (int j = 0; j < nb; ++j) v -= row[j] * yb[j];
@@ -426,6 +489,7 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
     }
     __syncthreads();
     for (int i = t; i < kb; i += kSolveThreads) {
+      if (flags && !flags[(i / 32) * W + kb / 32]) continue;  // rows kb .. kb + nb - 1 are zero in i's panel
       double v = y[i];
       for (int j = 0; j < nb; ++j) v -= H[(int64_t)(kb + j) * n + i] * yb[j];
       y[i] = v;
@@ -439,6 +503,7 @@ __device__ void solve_blocked(const ProbSys& S, const SolveArgs& a, double mu, d
 // loss) is left unchanged.  Every branch below is block-uniform.
 __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
   __shared__ double buf[kLdsDoubles];
+  __shared__ uint32_t zflags[kFlagWords];
   __shared__ double rd[kLdsSystem];
   __shared__ double sh[kSolveThreads / 64];
   const ProbSys S = a.sys[blockIdx.x];
@@ -455,7 +520,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_update(SolveArgs a) {
     if (tr > 0.0) {  // otherwise no pair touches a free frame: nothing moves
       const double mu = S.damping_rel * tr / n;
       if (n <= kLdsSystem) solve_lds(S, a, mu, buf, rd, st + 1);
-      else solve_blocked(S, a, mu, buf, st + 1);
+      else solve_blocked(S, a, mu, buf, st + 1, zflags);
       __syncthreads();
       if (st[1] == 0) {
         const double* y = a.delta + S.v_off;
