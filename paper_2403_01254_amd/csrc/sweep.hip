@@ -131,8 +131,13 @@ __device__ inline floatx4 tile_products(const float* __restrict__ tfeat, int s, 
                                         const float (&fsrc)[DP / 4]) {
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   const float* arow = tfeat + (16 * sub + s) * FS + g;
+  // every A element read before the first product: one LDS round trip per sub-tile, not one per pair of slices
+  float av[DP / 4];
 #pragma unroll
-  for (int k = 0; k < DP / 4; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * k], fsrc[k], acc, 0, 0, 0);
+  for (int k = 0; k < DP / 4; ++k) av[k] = arow[4 * k];
+  __builtin_amdgcn_sched_barrier(0);  // (the scheduler would otherwise interleave reads and products again)
+#pragma unroll
+  for (int k = 0; k < DP / 4; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], fsrc[k], acc, 0, 0, 0);
   return acc;
 }
 
