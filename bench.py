@@ -188,7 +188,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
 
     def run_batched(kind, arrivals):
         # two lanes: small requests batched in lane 0; requests whose measured work (entries x points per
-        # occupied r_c-cube) is large run one at a time in lane 1, beside them
+        # occupied r_c-cube) is large run one at a time in lane 1; the lanes' iterations take turns on the device
         srv = rkhsba.Server(feat_kind=kind, D=D, max_active=64, lanes=lanes, lane_work_entries=work_entries)
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05

@@ -308,7 +308,8 @@ int rkhsba_profile_read(rkhsba_ctx* ctx, int stage, double* total_ms, int64_t* l
  * frames, edge list, ell, n_iter and initial poses) solved exactly as
  * rkhsba_gn_step solves it; with two lanes, large requests (by their
  * (edge, source point) entries) go to the second lane, so that small ones do
- * not wait for their iterations.  In a lane, requests wait in FIFO order and
+ * not wait for their iterations, and the lanes' batch iterations take turns
+ * on the device in proportion to lane0_weight.  In a lane, requests wait in FIFO order and
  * are admitted while fewer than max_active are active in the lane and the sum
  * of the estimated device footprints of all admitted requests stays within
  * hbm_budget_bytes (one request is always admitted when its lane is idle).  Admission builds the
@@ -348,6 +349,10 @@ typedef struct {
   double lane_split_work;   /* with 2 lanes: a request admitted to lane 0 whose entries times the points per
                                occupied r_c-cube that its build measured (an estimate of the candidate pairs of one
                                iteration) exceed this moves to lane 1, in arrival order (default 5e8; 0: off) */
+  double lane0_weight;      /* with 2 lanes: the two lanes' batch iterations take turns on the device; while both
+                               have active requests, lane 0 launches its next iteration only when its measured
+                               device time divided by this weight is not ahead of lane 1's time, which caps its
+                               share at w / (1 + w) (default 0.25; must be > 0) */
 } rkhsba_server_options;
 
 typedef struct {

@@ -335,7 +335,7 @@ class Engine {
   // History entry only (after a loss evaluation).
   void loss_only(SetLayout& lay);
   // n Gauss-Newton iterations (evaluate, assemble, solve) over the set; graph-replayed when enabled.
-  void iterate(SetLayout& lay, int n);
+  void iterate(SetLayout& lay, int n, bool continue_binning = false);
   SolveArgs solve_args(SetLayout& lay);
 
   // results

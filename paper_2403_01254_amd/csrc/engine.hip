@@ -1200,15 +1200,18 @@ void Engine::record_iteration(SetLayout& lay, bool reuse_binning) {
   prof_end(RKHSBA_PROF_SOLVE, t);
 }
 
-void Engine::iterate(SetLayout& lay, int n) {
+void Engine::iterate(SetLayout& lay, int n, bool continue_binning) {
   if (n <= 0) return;
   // A graph pays for its capture only when it is replayed: capture on a
   // layout's second use, or when this call runs several iterations.
   const bool graph = use_graphs && !prof && (n > 1 || lay.uses >= graph_min_uses);
   ++lay.uses;
-  // The first iteration bins the sources afresh; the later ones keep its order (see evaluate).
+  // The first iteration bins the sources afresh; the later ones keep its order (see evaluate).  With
+  // continue_binning, an iteration right after one of the same layout keeps that order too.
+  const bool warm = continue_binning && lay.binned && binned_lay_ == &lay && lay.bin_sc == sc_ &&
+                    lay.bin_gen == scratch_gen_;
   if (!graph) {
-    for (int i = 0; i < n; ++i) record_iteration(lay, i > 0);
+    for (int i = 0; i < n; ++i) record_iteration(lay, i > 0 || warm);
     return;
   }
   const uint64_t g = generation();
@@ -1229,8 +1232,9 @@ void Engine::iterate(SetLayout& lay, int n) {
     RK_HIP(e);
     return exec;
   };
-  if (!lay.graph || lay.graph_gen != g) {
-    lay.drop_graph();
+  if (!warm && (!lay.graph || lay.graph_gen != g)) {
+    if (lay.graph) (void)hipGraphExecDestroy(lay.graph);
+    lay.graph = nullptr;
     lay.graph = capture(false);
     lay.graph_gen = g;
     lay.graph_mode = MODE_NORMAL;
@@ -1238,14 +1242,14 @@ void Engine::iterate(SetLayout& lay, int n) {
   // the replay bins into the scratch as the capture did: the host-side record of the binning follows it
   binned_lay_ = &lay;
   lay.binned = true;
-  if (n > 1 && (!lay.graph_rest || lay.graph_rest_gen != g)) {
+  if ((warm || n > 1) && (!lay.graph_rest || lay.graph_rest_gen != g)) {
     if (lay.graph_rest) (void)hipGraphExecDestroy(lay.graph_rest);
     lay.graph_rest = nullptr;
     lay.graph_rest = capture(true);
     lay.graph_rest_gen = g;
   }
-  RK_HIP(hipGraphLaunch(lay.graph, st));
-  for (int i = 1; i < n; ++i) RK_HIP(hipGraphLaunch(lay.graph_rest, st));
+  if (!warm) RK_HIP(hipGraphLaunch(lay.graph, st));
+  for (int i = warm ? 0 : 1; i < n; ++i) RK_HIP(hipGraphLaunch(lay.graph_rest, st));
 }
 
 }  // namespace rkhsba

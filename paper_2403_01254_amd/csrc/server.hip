@@ -87,7 +87,11 @@ struct Lane {
   std::vector<std::shared_ptr<Req>> active;  // worker thread only
   int64_t dev_bytes = 0;                     // the engine's device memory, guarded by the server mutex
   hipEvent_t iter_ev[2] = {nullptr, nullptr};  // the last two batch iterations (bounds the host's lead)
+  hipEvent_t iter_start[2] = {nullptr, nullptr};
+  double iter_charge[2] = {0.0, 0.0};  // device ms charged to the lane when the iteration was launched
+  int64_t iter_epoch[2] = {-1, -1};    // the sharing epoch of that charge (-1: none)
   int iter_next = 0;
+  bool busy = false;  // has active requests (guarded by the server mutex)
   // Retirement: the worker queues the copy of a finished request's results to a pinned slot; the
   // completer thread waits for each copy in order, hands the results to the waiter, and returns the
   // request's problem to the worker, which frees its device memory (guarded by rmu).
@@ -116,6 +120,47 @@ struct rkhsba_server {
   int64_t row_bytes = 4;  // stored feature bytes per point (admission estimates)
   rkhsba_server_stats stats{};
   std::string err;
+  // Device time of the two lanes.  Their batch iterations run one after another on the device (each lane's
+  // stream waits for the other lane's last launched iteration), and while both lanes have active requests a
+  // lane launches its next iteration only when its device time so far, divided by its weight, is not ahead
+  // of the other lane's: lane 0 (small requests) gets at most w / (1 + w) of the device, w = lane0_weight.
+  // Run side by side instead, the small requests' short kernels waited behind the large requests' sweeps
+  // for most of each iteration.  The times are measured with events over each iteration (charged with the
+  // lane's running estimate at launch); they restart from zero whenever a lane becomes active.
+  double used_ms[2] = {0.0, 0.0};
+  double est_ms[2] = {0.0, 0.0};
+  int64_t share_epoch = 0;
+  hipEvent_t last_end[2] = {nullptr, nullptr};  // guarded by mu
+  std::mutex launch_mu;                          // held by a lane while it launches an iteration (taken before mu)
+
+  bool may_run(int id) const {
+    const int o = 1 - id;
+    if (!lanes[o]->busy) return true;
+    const double w[2] = {opt.lane0_weight, 1.0};
+    return used_ms[id] / w[id] <= used_ms[o] / w[o];
+  }
+
+  void set_busy(Lane& L, bool b) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (b && !L.busy) {
+      share_epoch += 1;
+      used_ms[0] = used_ms[1] = 0.0;
+    }
+    L.busy = b;
+    cv_work.notify_all();
+  }
+
+  // The measured time of a completed iteration replaces its charge.
+  void account(Lane& L, int slot) {
+    if (L.iter_epoch[slot] < 0) return;
+    float ms = 0.f;
+    RK_HIP(hipEventElapsedTime(&ms, L.iter_start[slot], L.iter_ev[slot]));
+    std::lock_guard<std::mutex> lk(mu);
+    if (L.iter_epoch[slot] == share_epoch) used_ms[L.id] += (double)ms - L.iter_charge[slot];
+    est_ms[L.id] = est_ms[L.id] > 0.0 ? 0.75 * est_ms[L.id] + 0.25 * (double)ms : (double)ms;
+    L.iter_epoch[slot] = -1;
+    cv_work.notify_all();
+  }
 
   void finish(const std::shared_ptr<Req>& q, int status, const std::string& msg) {
     std::lock_guard<std::mutex> lk(mu);
@@ -341,17 +386,54 @@ struct rkhsba_server {
           all_final = all_final && q->evals == q->n_iter;
         }
         // at most two batch iterations in flight: the host prepares the next while the device runs one
-        hipEvent_t& slot = L.iter_ev[L.iter_next];
-        if (slot) RK_HIP(hipEventSynchronize(slot));
-        L.eng->prepare(L.lay, items);
-        if (all_final) {
-          L.eng->evaluate(L.lay, MODE_LOSS);
-          L.eng->loss_only(L.lay);
-        } else {
-          L.eng->iterate(L.lay, 1);
+        const int si = L.iter_next;
+        hipEvent_t& slot = L.iter_ev[si];
+        if (slot) {
+          RK_HIP(hipEventSynchronize(slot));
+          account(L, si);
         }
-        if (!slot) RK_HIP(hipEventCreateWithFlags(&slot, hipEventDisableTiming));
-        RK_HIP(hipEventRecord(slot, L.stream));
+        const bool shared = lanes.size() > 1;
+        if (shared) {
+          set_busy(L, true);
+          std::unique_lock<std::mutex> lk(mu);
+          cv_work.wait(lk, [&] { return stop || may_run(L.id); });
+        }
+        L.eng->prepare(L.lay, items);
+        if (!slot) RK_HIP(hipEventCreate(&slot));
+        if (!L.iter_start[si]) RK_HIP(hipEventCreate(&L.iter_start[si]));
+        {
+          // The lanes launch one at a time, each iteration after the other lane's last one.  (The other
+          // lane's event is then neither being recorded again nor on a stream in graph capture, which the
+          // runtime would take as a dependency on captured work.)
+          std::unique_lock<std::mutex> dl(launch_mu, std::defer_lock);
+          hipEvent_t after = nullptr;
+          if (shared) {
+            dl.lock();
+            std::lock_guard<std::mutex> lk(mu);
+            after = last_end[1 - L.id];
+          }
+          if (after) RK_HIP(hipStreamWaitEvent(L.stream, after, 0));
+          RK_HIP(hipEventRecord(L.iter_start[si], L.stream));
+          // A lane that runs one request at a time keeps the binning order of the request's first
+          // iteration, as rkhsba_gn_step does; a batch sorts afresh every iteration, so that a request's
+          // result does not depend on when other requests join or leave.
+          const bool solo = max_active == 1;
+          if (all_final) {
+            L.eng->evaluate(L.lay, MODE_LOSS, solo);
+            L.eng->loss_only(L.lay);
+          } else {
+            L.eng->iterate(L.lay, 1, solo);
+          }
+          RK_HIP(hipEventRecord(slot, L.stream));
+          if (shared) {
+            std::lock_guard<std::mutex> lk(mu);
+            last_end[L.id] = slot;
+            L.iter_charge[si] = est_ms[L.id];
+            L.iter_epoch[si] = share_epoch;
+            used_ms[L.id] += est_ms[L.id];
+            cv_work.notify_all();
+          }
+        }
         L.iter_next ^= 1;
         const int64_t mine = L.eng->device_bytes();
         {
@@ -370,9 +452,11 @@ struct rkhsba_server {
           else still.push_back(q);
         }
         L.active.swap(still);
+        if (L.active.empty() && lanes.size() > 1) set_busy(L, false);
       } catch (const Fail& f) {
         for (auto& q : L.active) drop(L, q, f.code, f.msg);
         L.active.clear();
+        if (lanes.size() > 1) set_busy(L, false);
       }
     }
     // shutting down: results in flight are delivered; drop what is active or queued in this lane
@@ -421,6 +505,8 @@ struct rkhsba_server {
       for (hipEvent_t ev : L->free_events) (void)hipEventDestroy(ev);
       for (hipEvent_t ev : L->iter_ev)
         if (ev) (void)hipEventDestroy(ev);
+      for (hipEvent_t ev : L->iter_start)
+        if (ev) (void)hipEventDestroy(ev);
     }
     lanes.clear();
   }
@@ -445,6 +531,7 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->lane_work_entries = 0;
   o->lane1_max_active = 1;
   o->lane_split_work = 5e8;
+  o->lane0_weight = 0.25;
 }
 
 int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
@@ -456,7 +543,7 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)) || opt->lanes < 1 ||
       opt->lanes > 2 || opt->lane_split_entries < 0 || opt->lane_work_entries < 0 || opt->lane1_max_active < 0 ||
-      !(opt->lane_split_work >= 0.0))
+      !(opt->lane_split_work >= 0.0) || !(opt->lane0_weight > 0.0 && opt->lane0_weight < 1e6))
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;

@@ -64,6 +64,7 @@ class ServerOptions(ctypes.Structure):
         ("lane_work_entries", ctypes.c_int64),
         ("lane1_max_active", ctypes.c_int),
         ("lane_split_work", ctypes.c_double),
+        ("lane0_weight", ctypes.c_double),
     ]
 
 
@@ -429,7 +430,7 @@ class Server:
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
                  use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000,
-                 lane_work_entries=0, lane1_max_active=1, lane_split_work=5e8):
+                 lane_work_entries=0, lane1_max_active=1, lane_split_work=5e8, lane0_weight=0.25):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
@@ -442,6 +443,7 @@ class Server:
         o.lane_work_entries = int(lane_work_entries)
         o.lane1_max_active = int(lane1_max_active)
         o.lane_split_work = float(lane_split_work)
+        o.lane0_weight = float(lane0_weight)
         self.opts = o
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))

@@ -107,6 +107,25 @@ def test_served_matches_context_and_oracle(rk, requests):
         np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
 
 
+def test_single_request_lane_matches_context(rk, requests):
+    """A lane that runs one request at a time keeps the binning order of the request's first iteration, as
+    the context's gn_step does: the served poses, loss and pair-count histories equal the context's bit for
+    bit."""
+    with rk.Server(feat_kind="dense", D=20, max_active=1) as srv:
+        tickets = [submit(srv, p) for p in requests]
+        served = [srv.wait(t, timeout=120) for t in tickets]
+        assert srv.stats()["max_active"] == 1
+    for p, (poses, lpi, ppi, _, _) in zip(requests, served):
+        ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, cell_subdiv=0)
+        ctx.build_neighbors(p.points, p.feats, p.feat_kind)
+        cposes, clpi, cppi = ctx.gn_step(p.init_poses, p.edges, p.n_iter)
+        ctx.close()
+        say(f"[server] one at a time: {p.recipe[:50]}")
+        np.testing.assert_array_equal(poses, cposes)
+        np.testing.assert_array_equal(lpi, clpi)
+        np.testing.assert_array_equal(ppi, cppi)
+
+
 def test_admission_by_footprint(rk, requests):
     """With a budget smaller than any request, requests run one at a time
     (a request is always admitted when nothing is active), with the same
