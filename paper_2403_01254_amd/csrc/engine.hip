@@ -400,6 +400,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
     int64_t rows_total = 0;
     uint64_t max_cells = 1;
     int bin_axis_bits = 1;
+    std::vector<int> frame_bits(K);  // per-axis bits of a frame's cell coordinates (negative: coarsened)
     for (int f = 0; f < K; ++f) {
       FrameInfo& F = fr[f];
       F.pt_off = off[f];
@@ -417,7 +418,7 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       max_cells = std::max(max_cells, cells);
       F.xt_off = 0;
       F.n_lab = 0;
-      F.pad_ = 0;
+      F.key_sub = 0;
       int ext_max = 0;
       for (int a = 0; a < 3; ++a) ext_max = std::max(ext_max, F.dim[a] + 2 * kc0.reach_cells);
       int shift = 0;
@@ -426,7 +427,19 @@ int Engine::add_problem(const ProbParams& par, int K, const int64_t* n_points, c
       const int maxc = (ext_max - 1) >> shift;
       int bits = 1;
       while ((1 << bits) < maxc + 2) ++bits;
+      frame_bits[f] = shift == 0 ? bits : -bits;
       bin_axis_bits = std::max(bin_axis_bits, bits);
+    }
+    // The binning keys order the source points of a cell by sub-cell (Morton order at a finer grid), as
+    // far as that fits the radix passes the cells already take: the passes' groups of consecutive points
+    // then span smaller boxes, whose walks hold fewer candidates that pair with none of the group.
+    {
+      const int axis_room = (8 * ((3 * bin_axis_bits + 7) / 8)) / 3;  // axis bits the same digit passes sort
+      for (int f = 0; f < K; ++f) {
+        if (frame_bits[f] < 0) continue;  // coarsened grid (mort_shift > 0)
+        fr[f].key_sub = std::max(0, std::min({3, axis_room - frame_bits[f], 10 - frame_bits[f]}));
+        bin_axis_bits = std::max(bin_axis_bits, frame_bits[f] + fr[f].key_sub);
+      }
     }
     // Class ids: every frame stacks one layer of its z extent per class id (0 .. its largest id) along z,
     // so that points of one id are contiguous and the sweeps walk only the candidates that can pair.  Kept

@@ -107,17 +107,21 @@ __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__
     const uint32_t src = SORTED ? vals[i] : (uint32_t)(i - ed.ent_off);
     const float4 x = pts[Fm.pt_off + src];
     const float3 q = rule_q32(X, x.x, x.y, x.z);
-    int c[3] = {clamp_floor((double)q.x * kc.inv_cell - Fn.org[0], -lim, lim) + r,
-                clamp_floor((double)q.y * kc.inv_cell - Fn.org[1], -lim, lim) + r,
-                clamp_floor((double)q.z * kc.inv_cell - Fn.org[2], -lim, lim) + r};
+    // cell coordinates (validity) and sub-cell coordinates (the key): scaling by 2^key_sub is exact, so a
+    // sub-cell coordinate shifted right by key_sub is its cell coordinate
+    const double u[3] = {(double)q.x * kc.inv_cell - Fn.org[0], (double)q.y * kc.inv_cell - Fn.org[1],
+                         (double)q.z * kc.inv_cell - Fn.org[2]};
+    const int sub = Fn.key_sub;
     uint32_t invalid = 0u;
+    uint32_t kk[3];
     for (int a = 0; a < 3; ++a) {
+      const int c = clamp_floor(u[a], -lim, lim) + r;
       const int top = Fn.dim[a] + 2 * r - 1;
-      if (c[a] < 0 || c[a] > top) invalid = kInvalidBit;
-      c[a] = min(max(c[a], 0), top);
+      if (c < 0 || c > top) invalid = kInvalidBit;
+      const int cf = clamp_floor(u[a] * (double)(1 << sub), -lim, lim) + (r << sub);
+      kk[a] = (uint32_t)min(max(cf, 0), ((top + 1) << sub) - 1) >> Fn.mort_shift;
     }
-    keys[i] = invalid | morton3((uint32_t)c[0] >> Fn.mort_shift, (uint32_t)c[1] >> Fn.mort_shift,
-                                (uint32_t)c[2] >> Fn.mort_shift);
+    keys[i] = invalid | morton3(kk[0], kk[1], kk[2]);
     if constexpr (!SORTED) vals[i] = src;
   }
 }

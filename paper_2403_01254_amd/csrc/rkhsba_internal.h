@@ -41,7 +41,7 @@ struct FrameInfo {
   int64_t row_off;   // first row descriptor of the frame
   int64_t xt_off;    // first xtab entry of the frame
   int32_t n_lab;     // label layers of a label-stacked frame (class id + 1 of its largest id), 0: not stacked
-  int32_t pad_;
+  int32_t key_sub;   // source-binning key resolution: 2^key_sub sub-cells per cell and axis
 };
 
 // First row descriptor (relative to row_off) of the layer of class id lbl: 0 in a frame that is not
