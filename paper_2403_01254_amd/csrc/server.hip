@@ -126,7 +126,8 @@ struct rkhsba_server {
   // of the other lane's: lane 0 (small requests) gets at most w / (1 + w) of the device, w = lane0_weight.
   // Run side by side instead, the small requests' short kernels waited behind the large requests' sweeps
   // for most of each iteration.  The times are measured with events over each iteration (charged with the
-  // lane's running estimate at launch); they restart from zero whenever a lane becomes active.
+  // lane's running estimate at launch); a lane that becomes active while the other one is busy starts level
+  // with it, and both restart from zero when the other one is idle.
   double used_ms[2] = {0.0, 0.0};
   double est_ms[2] = {0.0, 0.0};
   int64_t share_epoch = 0;
@@ -143,8 +144,16 @@ struct rkhsba_server {
   void set_busy(Lane& L, bool b) {
     std::lock_guard<std::mutex> lk(mu);
     if (b && !L.busy) {
-      share_epoch += 1;
-      used_ms[0] = used_ms[1] = 0.0;
+      const int o = 1 - L.id;
+      if (lanes[o]->busy) {
+        // A lane that becomes active starts level with the other one (the same device time per weight), so
+        // that neither lane's time before counts for or against it.
+        const double w[2] = {opt.lane0_weight, 1.0};
+        used_ms[L.id] = used_ms[o] / w[o] * w[L.id];
+      } else {
+        share_epoch += 1;
+        used_ms[0] = used_ms[1] = 0.0;
+      }
     }
     L.busy = b;
     cv_work.notify_all();
