@@ -28,23 +28,33 @@ __device__ inline void frame_of(const int64_t* __restrict__ off, int K, int64_t 
 // instead of one per wavefront.  Points of any later frame in the block (at
 // most a frame boundary or a few small frames) use per-point atomics.
 constexpr int kCoordItems = 16;
+constexpr int kXtabItems = 4;  // points per thread of the x-table fill
 
 __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __restrict__ xyz,
                                                           const int64_t* __restrict__ off, int K, int64_t n_total,
                                                           double inv_cell, const void* const* __restrict__ cls,
                                                           int32_t* __restrict__ cell, int32_t* __restrict__ minmax,
                                                           int32_t* __restrict__ label_max) {
-  __shared__ int32_t sb[7];  // the first frame's min x, y, z, max x, y, z, largest id
+  // min x, y, z, max x, y, z and largest id of the block's first frame (sb[0][.]) and of the next one
+  // (sb[1][.]: a block that straddles a frame boundary)
+  __shared__ int32_t sb[2][7];
   const int t = threadIdx.x;
-  if (t < 3) {
-    sb[t] = INT_MAX;
-    sb[3 + t] = INT_MIN;
+  if (t < 2) {
+    for (int a = 0; a < 3; ++a) {
+      sb[t][a] = INT_MAX;
+      sb[t][3 + a] = INT_MIN;
+    }
+    sb[t][6] = -1;
   }
-  if (t == 6) sb[6] = -1;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kThreads * kCoordItems;
   const int f0 = upper_segment(off, K, base);
-  int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN}, lb = -1;
+  int mn[2][3], mx[2][3], lb[2] = {-1, -1};
+  for (int h = 0; h < 2; ++h)
+    for (int a = 0; a < 3; ++a) {
+      mn[h][a] = INT_MAX;
+      mx[h][a] = INT_MIN;
+    }
   bool bad = false;
   for (int it = 0; it < kCoordItems; ++it) {
     const int64_t i = base + (int64_t)it * kThreads + t;
@@ -61,13 +71,14 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __
       cell[3 * i + a] = k[a];
     }
     const int lab = label_max ? (int)static_cast<const uint16_t*>(cls[f])[l] : -1;
-    if (f == f0) {
+    if (f <= f0 + 1) {
+      const int h = f - f0;
       for (int a = 0; a < 3; ++a) {
-        mn[a] = min(mn[a], k[a]);
-        mx[a] = max(mx[a], k[a]);
+        mn[h][a] = min(mn[h][a], k[a]);
+        mx[h][a] = max(mx[h][a], k[a]);
       }
-      lb = max(lb, lab);
-    } else {  // a later frame starts inside this block
+      lb[h] = max(lb[h], lab);
+    } else {  // a third frame inside this block (frames of fewer points than a block)
       for (int a = 0; a < 3; ++a) {
         atomicMin(&minmax[f * 6 + a], k[a]);
         atomicMax(&minmax[f * 6 + 3 + a], k[a]);
@@ -78,26 +89,38 @@ __global__ __launch_bounds__(kThreads) void k_cell_coords(const float* const* __
   if (__ballot(bad)) {
     if (bad) atomicOr(&minmax[K * 6], 1);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = min(mn[a], __shfl_xor(mn[a], o, 64));
-      mx[a] = max(mx[a], __shfl_xor(mx[a], o, 64));
+  for (int h = 0; h < 2; ++h) {
+    for (int o = 32; o > 0; o >>= 1) {
+      for (int a = 0; a < 3; ++a) {
+        mn[h][a] = min(mn[h][a], __shfl_xor(mn[h][a], o, 64));
+        mx[h][a] = max(mx[h][a], __shfl_xor(mx[h][a], o, 64));
+      }
+      lb[h] = max(lb[h], __shfl_xor(lb[h], o, 64));
     }
-    lb = max(lb, __shfl_xor(lb, o, 64));
-  }
-  if ((t & 63) == 0) {
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&sb[a], mn[a]);
-      atomicMax(&sb[3 + a], mx[a]);
+    if ((t & 63) == 0) {
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&sb[h][a], mn[h][a]);
+        atomicMax(&sb[h][3 + a], mx[h][a]);
+      }
+      atomicMax(&sb[h][6], lb[h]);
     }
-    atomicMax(&sb[6], lb);
   }
   __syncthreads();
-  if (t < 3) {
-    if (sb[t] != INT_MAX) atomicMin(&minmax[f0 * 6 + t], sb[t]);
-    if (sb[3 + t] != INT_MIN) atomicMax(&minmax[f0 * 6 + 3 + t], sb[3 + t]);
+  // one atomic per bound, frame and block: every block of a frame updates the same few bound words, where
+  // per-point atomics (as a straddling block's second frame once had) serialise
+  if (t < 14) {
+    const int h = t / 7, a = t % 7, f = f0 + h;
+    const int32_t v = sb[h][a];
+    if (f < K) {
+      if (a < 3) {
+        if (v != INT_MAX) atomicMin(&minmax[f * 6 + a], v);
+      } else if (a < 6) {
+        if (v != INT_MIN) atomicMax(&minmax[f * 6 + a], v);
+      } else if (label_max && v >= 0) {
+        atomicMax(&label_max[f], v);
+      }
+    }
   }
-  if (t == 6 && label_max && sb[6] >= 0) atomicMax(&label_max[f0], sb[6]);
 }
 
 // Cell key of every point; in a label-stacked frame the class id selects the
@@ -277,13 +300,10 @@ __global__ __launch_bounds__(kThreads) void k_row_store_offsets(const uint32_t* 
 // the head of each occupied cell fills the entries from the previous occupied
 // cell of the row (exclusive) up to its own; the row's last point writes the
 // end entry.
-__global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restrict__ keys,
-                                                        const FrameInfo* __restrict__ frames,
-                                                        const int64_t* __restrict__ off, int K, int64_t n_total,
-                                                        const int4* __restrict__ rows, uint32_t* __restrict__ xtab,
-                                                        uint32_t* __restrict__ n_cells) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (p >= n_total) return;
+__device__ __forceinline__ void xtab_point(const uint32_t* __restrict__ keys, const FrameInfo* __restrict__ frames,
+                                           const int64_t* __restrict__ off, int K, int64_t p,
+                                           const int4* __restrict__ rows, uint32_t* __restrict__ xtab,
+                                           uint32_t* heads_sh) {
   int f;
   int64_t s;
   frame_of(off, K, p, f, s);
@@ -298,9 +318,9 @@ __global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restri
   const bool has_next = s + 1 < F.n;
   const uint32_t kprev = has_prev ? keys[p - 1] : 0u;
   const bool head = !has_prev || kprev != key;
-  {  // occupied cells: one atomic per wavefront
+  {  // occupied cells: the wavefront's heads into the block's count
     const unsigned long long heads = __ballot(head), live = __ballot(1);
-    if ((int)(threadIdx.x & 63) == __builtin_ctzll(live)) atomicAdd(n_cells, (uint32_t)__popcll(heads));
+    if ((int)(threadIdx.x & 63) == __builtin_ctzll(live)) atomicAdd(heads_sh, (uint32_t)__popcll(heads));
   }
   if (head) {  // head of an occupied cell
     int x0 = R.x;
@@ -318,6 +338,23 @@ __global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restri
     row_end = (int64_t)nz * F.dim[1] + ny != row;
   }
   if (row_end) xt[R.y + 1 - R.x] = (uint32_t)(s + 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_xtab_fill(const uint32_t* __restrict__ keys,
+                                                        const FrameInfo* __restrict__ frames,
+                                                        const int64_t* __restrict__ off, int K, int64_t n_total,
+                                                        const int4* __restrict__ rows, uint32_t* __restrict__ xtab,
+                                                        uint32_t* __restrict__ n_cells) {
+  __shared__ uint32_t heads_sh;  // occupied cells among the block's points
+  if (threadIdx.x == 0) heads_sh = 0u;
+  __syncthreads();
+  for (int it = 0; it < kXtabItems; ++it) {
+    const int64_t p = ((int64_t)blockIdx.x * kXtabItems + it) * kThreads + threadIdx.x;
+    if (p < n_total) xtab_point(keys, frames, off, K, p, rows, xtab, &heads_sh);
+  }
+  __syncthreads();
+  // one atomic per block on the single counter (one per wavefront serialised there)
+  if (threadIdx.x == 0 && heads_sh) atomicAdd(n_cells, heads_sh);
 }
 
 // Centroid of one frame: each thread sums a strided subset in FP64, then the
@@ -412,7 +449,8 @@ hipError_t launch_rows(const uint32_t* d_keys, const FrameInfo* d_frames, const 
 hipError_t launch_xtab(const uint32_t* d_keys, const FrameInfo* d_frames, const int64_t* d_in_off, int K,
                        int64_t n_total, const int4* d_rows, uint32_t* d_xtab, uint32_t* d_n_cells, hipStream_t st) {
   if (n_total > 0)
-    k_xtab_fill<<<blocks(n_total), kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows, d_xtab,
+    k_xtab_fill<<<(unsigned)((n_total + (int64_t)kThreads * kXtabItems - 1) / ((int64_t)kThreads * kXtabItems)),
+                  kThreads, 0, st>>>(d_keys, d_frames, d_in_off, K, n_total, d_rows, d_xtab,
                                                       d_n_cells);
   return hipGetLastError();
 }
