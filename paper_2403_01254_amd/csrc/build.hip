@@ -221,7 +221,12 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restr
       else if (feat_kind == 2) static_cast<uint16_t*>(feat)[p * Dp + k] = f32_to_bf16(v);
       else static_cast<uint8_t*>(feat)[p * Dp + k] = f32_to_e4m3(v);
     }
-    if (neg) atomicOr(neg_flag, 1);  // some inner products may be negative
+    // some inner products may be negative: one atomic per wavefront with such a row, none once the flag is set
+    // (a per-point atomic on the one flag word serialises)
+    const unsigned long long negs = __ballot(neg);
+    if (negs && (int)(threadIdx.x & 63) == __builtin_ctzll(negs) &&
+        __atomic_load_n(neg_flag, __ATOMIC_RELAXED) == 0)
+      atomicOr(neg_flag, 1);
   }
 }
 
