@@ -749,17 +749,16 @@ void Engine::read_history(Problem* p, int count, double* loss, double* pairs) {
 void Engine::read_source_counts(Problem* p, int m, int64_t* counts) {
   RK_REQUIRE(m >= 0 && m < p->K && sorted_k_ && sorted_v_, RKHSBA_ESTATE, "no evaluation to read");
   const FrameInfo& F = p->frames[m];
-  std::vector<uint32_t> c(F.n), k(F.n), v(F.n);
+  std::vector<uint32_t> c(F.n), v(F.n);
   std::vector<int32_t> perm(F.n);
   RK_HIP(hipMemcpyAsync(c.data(), sc_->cnt.p, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
-  RK_HIP(hipMemcpyAsync(k.data(), sorted_k_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipMemcpyAsync(v.data(), sorted_v_, sizeof(uint32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipMemcpyAsync(perm.data(), this->perm() + F.pt_off, sizeof(int32_t) * F.n, hipMemcpyDeviceToHost, st));
   RK_HIP(hipStreamSynchronize(st));
   for (int32_t i = 0; i < F.n; ++i) counts[i] = 0;
   for (int32_t e = 0; e < F.n; ++e) {
     RK_REQUIRE(v[e] < (uint32_t)F.n, RKHSBA_EDEVICE, "binning value out of range");
-    counts[perm[v[e]]] = (k[e] & kInvalidBit) ? 0 : (int64_t)c[e];
+    counts[perm[v[e]]] = (int64_t)c[e];  // (the sweeps count zero for a source outside the target grid)
   }
 }
 
@@ -1103,8 +1102,13 @@ void Engine::evaluate(SetLayout& lay, int mode, bool reuse_binning) {
   if (reuse) {
     sorted_k_ = lay.bin_k;
     sorted_v_ = lay.bin_v;
-    RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
-                      const_cast<uint32_t*>(sorted_k_), const_cast<uint32_t*>(sorted_v_), true, st));
+    // The keys are read only for their out-of-grid bit, and only by the per-point walks and the larger passes:
+    // the tiled sweeps test the grid from the transformed point themselves.
+    bool keys_read = false;
+    for (const SetLayout::Group& gr : lay.groups) keys_read = keys_read || (gr.pass_points != 16 && gr.pass_points != 8);
+    if (keys_read)
+      RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
+                        const_cast<uint32_t*>(sorted_k_), const_cast<uint32_t*>(sorted_v_), true, st));
   } else {
     RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
                       sc_->bk.p, sc_->bv.p, false, st));

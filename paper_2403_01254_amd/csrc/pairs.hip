@@ -112,12 +112,10 @@ __global__ __launch_bounds__(kSortThreads) void k_bin(const float4* __restrict__
     const double u[3] = {(double)q.x * kc.inv_cell - Fn.org[0], (double)q.y * kc.inv_cell - Fn.org[1],
                          (double)q.z * kc.inv_cell - Fn.org[2]};
     const int sub = Fn.key_sub;
-    uint32_t invalid = 0u;
+    const uint32_t invalid = source_in_grid(q, Fn, kc) ? 0u : kInvalidBit;
     uint32_t kk[3];
     for (int a = 0; a < 3; ++a) {
-      const int c = clamp_floor(u[a], -lim, lim) + r;
       const int top = Fn.dim[a] + 2 * r - 1;
-      if (c < 0 || c > top) invalid = kInvalidBit;
       const int cf = clamp_floor(u[a] * (double)(1 << sub), -lim, lim) + (r << sub);
       kk[a] = (uint32_t)min(max(cf, 0), ((top + 1) << sub) - 1) >> Fn.mort_shift;
     }
@@ -204,7 +202,10 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     hi.y = wave_max(valid ? q.y : -FLT_MAX);
     hi.z = wave_max(valid ? q.z : -FLT_MAX);
     if (lo.x > hi.x) {  // no valid source point in the pass (uniform)
-      if (g == 0 && in_range) a.cnt[entry] = 0u;
+      if (g == 0 && in_range) {
+        a.cnt[entry] = 0u;
+        store_zero_moments<MODE>(a, entry);
+      }
       return;
     }
   }
@@ -288,13 +289,14 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs a) {
     }
   }
   if (g == 0 && in_range) a.cnt[entry] = valid ? cnt : 0u;
-  if (g == 0 && valid) {
+  if (g == 0 && in_range) {  // zero moments for a source outside the target grid (the finaliser sums every entry)
     const int64_t N = a.n_entries;
-    a.mom[entry] = A;
+    auto v = [&](float m) { return valid ? m : 0.f; };
+    a.mom[entry] = v(A);
     if constexpr (MODE == MODE_NORMAL) {
-      a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
-      a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
-      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Wr2;
+      a.mom[1 * N + entry] = v(Bx); a.mom[2 * N + entry] = v(By); a.mom[3 * N + entry] = v(Bz);
+      a.mom[4 * N + entry] = v(Cxx); a.mom[5 * N + entry] = v(Cxy); a.mom[6 * N + entry] = v(Cxz);
+      a.mom[7 * N + entry] = v(Cyy); a.mom[8 * N + entry] = v(Cyz); a.mom[9 * N + entry] = v(Wr2);
     }
   }
 }
@@ -372,12 +374,11 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
   // (three waves per SIMD at this register count hide little of the reads' latency otherwise).
   constexpr int NM = MODE == MODE_LOSS ? 1 : 10;
   struct In {
-    uint32_t cnt, key, val;
+    uint32_t cnt, val;
     float m[NM];
   };
   auto load = [&](int64_t entry, In& in) __attribute__((always_inline)) {
     in.cnt = a.cnt[entry];
-    in.key = a.keys[entry];
     if constexpr (MODE != MODE_LOSS) in.val = a.vals[entry];
 #pragma unroll
     for (int k = 0; k < NM; ++k) in.m[k] = a.mom[k * N + entry];
@@ -395,10 +396,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinArgs a, const int32
     entry = nentry;
     have = nhave;
     cnt_sum += (double)in.cnt;  // per-entry or per-pass pair counts
+    // a source outside the target grid has zero moments (the sweeps store them), so every entry is summed
     if constexpr (MODE == MODE_LOSS) {
-      if (!(in.key & kInvalidBit)) st[0].add((T)in.m[0]);
+      st[0].add((T)in.m[0]);
     } else {
-      if (in.key & kInvalidBit) continue;
       const T A = in.m[0];
       T B[3], C[6], x[3], q[3];
       for (int k = 0; k < 3; ++k) B[k] = in.m[1 + k];

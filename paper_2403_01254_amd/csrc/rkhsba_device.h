@@ -36,6 +36,30 @@ __device__ inline float3 rule_q32(const EdgeXf& xf, float x0, float x1, float x2
   return make_float3((float)q.x, (float)q.y, (float)q.z);
 }
 
+// Whether a transformed source point lies in the target frame's cell grid extended by the reach on every
+// side, with cell coordinates as the build's (floor of q / cell in FP64).  A source outside has no candidate:
+// the binning sorts it to the grid's edge, the sweeps leave it out of their boxes and store zero moments.
+__device__ inline bool source_in_grid(float3 q, const FrameInfo& F, const KConst& kc) {
+  const double u[3] = {(double)q.x * kc.inv_cell - F.org[0], (double)q.y * kc.inv_cell - F.org[1],
+                       (double)q.z * kc.inv_cell - F.org[2]};
+  const double lim = (double)(1 << 30);
+  const int r = kc.reach_cells;
+  bool in = true;
+  for (int a = 0; a < 3; ++a) {
+    const int c = (int)fmin(fmax(floor(u[a]), -lim), lim) + r;
+    in = in && c >= 0 && c <= F.dim[a] + 2 * r - 1;
+  }
+  return in;
+}
+
+// Zero moments for an entry whose source has no candidate (the finaliser sums every entry).
+template <int MODE>
+__device__ inline void store_zero_moments(const PairArgs& a, int64_t entry) {
+  a.mom[entry] = 0.f;
+  if constexpr (MODE == MODE_NORMAL)
+    for (int k = 1; k < 10; ++k) a.mom[k * a.n_entries + entry] = 0.f;
+}
+
 // Exact widening of the stored low-precision feature formats.
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // OCP e4m3 (bias 7; no infinities; the one NaN code is never stored).

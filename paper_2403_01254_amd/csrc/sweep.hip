@@ -242,11 +242,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   const int64_t entry = pi.entry0 + s;
   const bool in_range = s < pi.count;
   bool valid = in_range;
-  uint32_t src = 0;
-  if (valid) {
-    valid = !(a.keys[entry] & kInvalidBit);
-    src = a.vals[entry];
-  }
+  const uint32_t src = in_range ? a.vals[entry] : 0u;
   float3 q = make_float3(0.f, 0.f, 0.f);
   uint32_t lbl = 0;
   float fsrc[FEAT == FEAT_DENSE ? DP / 4 : 1] = {};
@@ -254,6 +250,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   if (valid) {
     const float4 x = a.pts[pi.src_off + src];
     q = rule_q32(X, x.x, x.y, x.z);
+    valid = source_in_grid(q, Fn, kc);  // (the features below are read for any entry of the pass)
     lbl = __float_as_uint(x.w);
     if constexpr (FEAT == FEAT_DENSE) {
       // B operand of the MFMA: feature 4k + g of this lane's source point
@@ -286,7 +283,10 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   hi.y = uniform_f(group_max<P>(valid ? q.y : -FLT_MAX));
   hi.z = uniform_f(group_max<P>(valid ? q.z : -FLT_MAX));
   if (!(lo.x <= hi.x)) {  // no valid source point in this pass (uniform)
-    if (g == 0 && in_range) a.cnt[entry] = 0u;
+    if (g == 0 && in_range) {
+      a.cnt[entry] = 0u;
+      store_zero_moments<MODE>(a, entry);
+    }
     return;
   }
   const float3 ref = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
@@ -673,13 +673,14 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
     // the pass's pair count goes to its first entry, zeros to the others
     if (g == 0 && in_range) a.cnt[entry] = s == 0 ? cnt : 0u;
   }
-  if (g == 0 && valid) {
+  if (g == 0 && in_range) {  // zero moments for a source outside the target grid (the finaliser sums every entry)
     const int64_t N = a.n_entries;
-    a.mom[entry] = A;
+    auto v = [&](float m) { return valid ? m : 0.f; };
+    a.mom[entry] = v(A);
     if constexpr (MODE == MODE_NORMAL) {
-      a.mom[1 * N + entry] = Bx; a.mom[2 * N + entry] = By; a.mom[3 * N + entry] = Bz;
-      a.mom[4 * N + entry] = Cxx; a.mom[5 * N + entry] = Cxy; a.mom[6 * N + entry] = Cxz;
-      a.mom[7 * N + entry] = Cyy; a.mom[8 * N + entry] = Cyz; a.mom[9 * N + entry] = Wr2;
+      a.mom[1 * N + entry] = v(Bx); a.mom[2 * N + entry] = v(By); a.mom[3 * N + entry] = v(Bz);
+      a.mom[4 * N + entry] = v(Cxx); a.mom[5 * N + entry] = v(Cxy); a.mom[6 * N + entry] = v(Cxz);
+      a.mom[7 * N + entry] = v(Cyy); a.mom[8 * N + entry] = v(Cyz); a.mom[9 * N + entry] = v(Wr2);
     }
   }
 }
