@@ -68,9 +68,10 @@ def load_traffic(workload, config):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("config") != list(config):
-        return None
-    return t.get("bytes_per_launch")
+    for e in (t if isinstance(t, list) else [t]):  # one summary per profiled configuration
+        if e.get("kernel_source_sha256_16") == kernel_source_hash() and e.get("config") == list(config):
+            return e.get("bytes_per_launch")
+    return None
 
 
 def cpu_info():

@@ -1092,6 +1092,12 @@ void Engine::prepare(SetLayout& lay, const std::vector<SetItem>& items) {
 
 // ---------------------------------------------------------------- launches
 
+// Pass sizes that the tiled sweep takes (16 points; 8 or 32 with class ids); the others (per-point walks, 32 or
+// 64 points with dense features) run in the untiled pass kernel.
+static bool tiled_sweep(int pass_points, int feat_kind) {
+  return pass_points == 16 || ((pass_points == 8 || pass_points == 32) && feat_kind == RKHSBA_FEAT_CLASS_ID);
+}
+
 void Engine::evaluate(SetLayout& lay, int mode, bool reuse_binning) {
   RK_REQUIRE(!arena_ || mode == MODE_LOSS || arena_->mom_components == 10, RKHSBA_ESTATE,
              "the arena holds loss-evaluation moments only");
@@ -1105,7 +1111,7 @@ void Engine::evaluate(SetLayout& lay, int mode, bool reuse_binning) {
     // The keys are read only for their out-of-grid bit, and only by the per-point walks and the larger passes:
     // the tiled sweeps test the grid from the transformed point themselves.
     bool keys_read = false;
-    for (const SetLayout::Group& gr : lay.groups) keys_read = keys_read || (gr.pass_points != 16 && gr.pass_points != 8);
+    for (const SetLayout::Group& gr : lay.groups) keys_read = keys_read || !tiled_sweep(gr.pass_points, feat_kind);
     if (keys_read)
       RK_HIP(launch_bin(pts(), frames(), lay.d_edges.p, lay.d_etiles.p, lay.n_edge_tiles, sc_->xf.p, lay.d_kcs.p,
                         const_cast<uint32_t*>(sorted_k_), const_cast<uint32_t*>(sorted_v_), true, st));
@@ -1152,7 +1158,7 @@ void Engine::evaluate(SetLayout& lay, int mode, bool reuse_binning) {
   for (const SetLayout::Group& gr : lay.groups) {
     pa.pass0 = gr.pass0;
     pa.n_pass = gr.n_pass;
-    if (gr.pass_points == 16 || gr.pass_points == 8)
+    if (tiled_sweep(gr.pass_points, feat_kind))
       RK_HIP(launch_sweep(pa, mode, feat_path, gr.pass_points, moment_path == 2 && !source_counts,
                           source_counts && mode == MODE_NORMAL, st));
     else

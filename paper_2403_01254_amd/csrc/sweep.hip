@@ -60,24 +60,26 @@ constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each half row
 constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within each row
 constexpr int kDppRor8 = 0x128;        // lane i <- lane (i + 8) mod 16 within each row, i.e. i ^ 8
 
-// Minimum / maximum over the P consecutive lanes of each lane group (P = 8 or 16): the quad, then the
-// other quad of the half row, then the other half row.
+// Minimum / maximum over the P consecutive lanes of each lane group (P = 8, 16 or 32): the quad, then the
+// other quad of the half row, then the other half row, then the other row of the 32.
 template <int P>
 __device__ inline float group_min(float v) {
-  static_assert(P == 8 || P == 16, "groups of 8 or 16 lanes");
+  static_assert(P == 8 || P == 16 || P == 32, "groups of 8, 16 or 32 lanes");
   v = fminf(v, dpp_f<kDppXor1>(v));
   v = fminf(v, dpp_f<kDppXor2>(v));
   v = fminf(v, dpp_f<kDppHalfMirror>(v));
-  if constexpr (P == 16) v = fminf(v, dpp_f<kDppMirror>(v));
+  if constexpr (P >= 16) v = fminf(v, dpp_f<kDppMirror>(v));
+  if constexpr (P == 32) v = fminf(v, __shfl_xor(v, 16, 64));
   return v;
 }
 template <int P>
 __device__ inline float group_max(float v) {
-  static_assert(P == 8 || P == 16, "groups of 8 or 16 lanes");
+  static_assert(P == 8 || P == 16 || P == 32, "groups of 8, 16 or 32 lanes");
   v = fmaxf(v, dpp_f<kDppXor1>(v));
   v = fmaxf(v, dpp_f<kDppXor2>(v));
   v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
-  if constexpr (P == 16) v = fmaxf(v, dpp_f<kDppMirror>(v));
+  if constexpr (P >= 16) v = fmaxf(v, dpp_f<kDppMirror>(v));
+  if constexpr (P == 32) v = fmaxf(v, __shfl_xor(v, 16, 64));
   return v;
 }
 
@@ -206,9 +208,9 @@ __device__ inline float box_s2(float3 lo, float3 hi, float4 z) {
 // skipped.
 template <int MODE, int FEAT, int DP, int CM, bool MM, int P, bool SC = false, bool LS = false>
 __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
-  // P source points per pass (16, or 8 for class ids); lane (s, g) takes CPL candidates of every
+  // P source points per pass (16; 8 or 32 for class ids); lane (s, g) takes CPL candidates of every
   // 16-candidate sub-tile
-  static_assert(P == 16 || (P == 8 && FEAT == FEAT_CLASS && !MM), "8-point passes: class ids only");
+  static_assert(P == 16 || ((P == 8 || P == 32) && FEAT == FEAT_CLASS && !MM), "8 or 32-point passes: class ids only");
   static_assert(!LS || FEAT == FEAT_CLASS, "label layers: class ids only");
   // CF (class ids): the candidates of each fetched tile that lie beyond the reach of the pass's box are
   // dropped and the rest compacted into full blocks of 64 before any source tests them
@@ -661,12 +663,12 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
   };
   if (!MM || spread) {
     if constexpr (P == 8) sum_streams([](float v) { return xor_add<8>(v); });
-    sum_streams([](float v) { return xor_add<16>(v); });
+    if constexpr (P <= 16) sum_streams([](float v) { return xor_add<16>(v); });
     sum_streams([](float v) { return xor_add<32>(v); });
   }
   if (SC || spread) {  // every source point's own count
     if constexpr (P == 8) own = xor_add<8>(own);
-    own = xor_add<16>(own);
+    if constexpr (P <= 16) own = xor_add<16>(own);
     own = xor_add<32>(own);
     if (g == 0 && in_range) a.cnt[entry] = valid ? own : 0u;
   } else {
@@ -724,26 +726,33 @@ hipError_t dispatch_mode(const PairArgs& a, int feat_path, hipStream_t st) {
   }
 }
 
+// Class ids in passes of P = 8 or 32 source points (moments on the VALU).
+template <int P>
+hipError_t dispatch_class(const PairArgs& a, int mode, bool source_counts, hipStream_t st) {
+  const unsigned nb = (unsigned)a.n_pass;
+  if (a.stacked) {
+    if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, P, true, true><<<nb, kLanes, 0, st>>>(a);
+    else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, P, false, true><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, P, false, true><<<nb, kLanes, 0, st>>>(a);
+  } else {
+    if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, P, true><<<nb, kLanes, 0, st>>>(a);
+    else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, P><<<nb, kLanes, 0, st>>>(a);
+    else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, P><<<nb, kLanes, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
-// Tiled sweep for passes of 16 source points (8 for class ids on request).
+// Tiled sweep for passes of 16 source points (8 or 32 for class ids on request).
 // Loss-only sums stay on the VALU; Gauss-Newton moments on the VALU or the matrix cores.
 hipError_t launch_sweep(const PairArgs& a, int mode, int feat_path, int pass_points, bool matrix_moments,
                         bool source_counts, hipStream_t st) {
   if (source_counts && (mode != MODE_NORMAL || matrix_moments)) return hipErrorInvalidValue;
-  if (pass_points == 8) {
+  if (pass_points == 8 || pass_points == 32) {
     if (feat_path != FEAT_CLASS || a.n_pass == 0) return feat_path != FEAT_CLASS ? hipErrorInvalidValue : hipSuccess;
-    if (a.stacked) {
-      if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true, true><<<a.n_pass, kLanes, 0, st>>>(a);
-      else if (mode == MODE_LOSS)
-        k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8, false, true><<<a.n_pass, kLanes, 0, st>>>(a);
-      else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, false, true><<<a.n_pass, kLanes, 0, st>>>(a);
-    } else {
-      if (source_counts) k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8, true><<<a.n_pass, kLanes, 0, st>>>(a);
-      else if (mode == MODE_LOSS) k_sweep<MODE_LOSS, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
-      else k_sweep<MODE_NORMAL, FEAT_CLASS, 0, 0, false, 8><<<a.n_pass, kLanes, 0, st>>>(a);
-    }
-    return hipGetLastError();
+    return pass_points == 8 ? dispatch_class<8>(a, mode, source_counts, st)
+                            : dispatch_class<32>(a, mode, source_counts, st);
   }
   if (source_counts) return dispatch_mode<MODE_NORMAL, false, true>(a, feat_path, st);
   if (mode == MODE_LOSS) return dispatch_mode<MODE_LOSS, false, false>(a, feat_path, st);

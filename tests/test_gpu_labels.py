@@ -81,9 +81,9 @@ def test_voxels_and_pairs(rk, name):
             ref = oracle.pairs(op, poses, m, n)
             assert len(ref) > 0
             np.testing.assert_array_equal(ctx.export_pairs(poses, m, n), ref)
-            if pp != 32:  # per-source counts: the tiled sweeps and the per-point walks
-                got = ctx.export_source_counts(poses, m, n, len(p.points[m]))
-                np.testing.assert_array_equal(got, np.bincount(ref[:, 0], minlength=len(p.points[m])))
+            # per-source counts from the kernel that sums (tiled sweeps of 8, 16 and 32 points, per-point walks)
+            got = ctx.export_source_counts(poses, m, n, len(p.points[m]))
+            np.testing.assert_array_equal(got, np.bincount(ref[:, 0], minlength=len(p.points[m])))
         edges = [[0, 1], [1, 0]]
         H, b, F, npairs = ctx.accumulate_normal_eqs(poses, edges)
         oF, ob, oH, _, onp = oracle.normal_eqs(op, poses, edges, oracle.MEMBER_FP32_RULE)
