@@ -252,9 +252,10 @@ int64_t Engine::estimate_bytes(int K, const int64_t* n_points, int E, int64_t ro
 
 // Class-id sweep passes whose box is wider than this many truncation radii walk per source point.  On the
 // LiDAR map (64 x 100,000 points, 20% outliers) a fifth of the 8-point passes span more than 4 r_c and hold
-// under 1% of the pairs; measured per launch: no per-source walks 13.25 ms, threshold 1.5 r_c 11.20,
-// 2 r_c 10.83, 3 r_c 10.78, 4 r_c 10.80 (16-point passes: 2 r_c 10.20, 3 r_c 10.11).
-constexpr double kSpreadFactor = 3.0;
+// under 1% of the pairs.  With the box filter, label layers and sub-cell keys of the shared walk, 16-point
+// passes measured per launch against 3 r_c: 2.25 r_c +1%, 4.5 r_c -0.7%, 6 r_c -1.4%, 9 r_c -1%, 12 r_c
+// -1.9%, 16 r_c +2.5%, 24 r_c +2.6%, no per-source walks +40%.
+constexpr double kSpreadFactor = 6.0;
 
 void Engine::compute_constants(Problem* p) {
   const ProbParams& o = p->par;
