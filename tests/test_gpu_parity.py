@@ -150,6 +150,26 @@ def test_gauss_newton_parity(rk, scene):
     np.testing.assert_array_equal(poses[0], p.init_poses[0])  # the fixed frame does not move
 
 
+@pytest.mark.parametrize("pass_points,subdiv", [(1, 1), (32, 2), (64, 1), (8, 1)])
+def test_gauss_newton_parity_kept_binning(rk, pass_points, subdiv):
+    """Gauss-Newton steps that keep the first iteration's binning order with the untiled pass kernel (per-point
+    walks, 32- and 64-point passes: the later iterations recompute the keys' out-of-grid bit) and with the
+    tiled 8-point class-id sweep (which tests the grid itself), against the oracle's steps."""
+    if pass_points == 8:
+        p = scenes.lidar(2, n_frames=3, n_points=4000, n_neighbours=2, n_iter=3, spacing=3.125)
+    else:
+        p = scenes.odometry(4, n_frames=3, n_points=3000, n_iter=3)
+    op = oracle.Problem.from_scene(p)
+    ctx = make_ctx(rk, p, pass_points=pass_points, cell_subdiv=subdiv)
+    poses, lpi, ppi = ctx.gn_step(p.init_poses, p.edges, p.n_iter)
+    oposes, olpi = oracle.gn(op, p.init_poses, p.edges, p.n_iter, membership=oracle.MEMBER_FP32_RULE)
+    rot, tr = pose_errors(poses, oposes)
+    say(f"[gn-kept] pass {pass_points} subdiv {subdiv}: rot err {rot.max():.3g} trans err {tr.max():.3g}")
+    assert rot.max() <= ROT_TOL and tr.max() <= TRANS_TOL
+    np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
+    ctx.close()
+
+
 # scenes whose inner products are decided exactly on both sides (class ids, or features that are all
 # positive): a pair's c != 0 test cannot differ between the GPU's FP32 sums and the oracle's FP64 ones
 COUNT_SCENES = ["two_view_ragged", "odometry_small", "lidar_small", "lidar_k12"]
