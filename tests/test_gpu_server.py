@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import scenes
-from helpers import REL_TOL, ROT_TOL, TRANS_TOL, pose_errors
+from helpers import REL_TOL, ROT_TOL, TRANS_TOL, bf16_round, pose_errors
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 
@@ -191,7 +191,8 @@ def test_served_forms_against_oracle(rk):
     FP32 features (cell-list search, FP32 membership rule): one request at a time in FP32, the batched
     FP32 server (two lanes), and the batched server with bfloat16 features.  The FP32 forms meet the
     pose tolerance; the bfloat16 form's error, which comes from rounding the features, is printed and
-    held to 5e-3."""
+    held to 5e-3, and against the oracle run on the same features rounded to bfloat16 (nearest even,
+    as the library stores them) the bfloat16 form meets the pose tolerance."""
     reqs = [scenes.request(s, k_range=(2, 6), n_range=(4000, 15000), n_iter=10) for s in range(2000, 2006)]
     one = []
     for p in reqs:
@@ -204,18 +205,23 @@ def test_served_forms_against_oracle(rk):
         with rk.Server(feat_kind=kind, D=20, max_active=8, lanes=2, lane_work_entries=8_000_000) as srv:
             tickets = [submit(srv, p) for p in reqs]
             served[kind] = [srv.wait(t, timeout=120)[0] for t in tickets]
-    worst = {"one at a time, f32": [0.0, 0.0], "batched, f32": [0.0, 0.0], "batched, bf16": [0.0, 0.0]}
+    rounded = "batched, bf16 (oracle on bf16-rounded features)"
+    worst = {"one at a time, f32": [0.0, 0.0], "batched, f32": [0.0, 0.0], "batched, bf16": [0.0, 0.0],
+             rounded: [0.0, 0.0]}
     for i, p in enumerate(reqs):
         op = oracle.Problem.from_scene(p, search="cells")
         oposes, _ = oracle.gn(op, p.init_poses, p.edges, p.n_iter, membership=oracle.MEMBER_FP32_RULE)
-        for name, poses in (("one at a time, f32", one[i]), ("batched, f32", served["dense"][i]),
-                            ("batched, bf16", served["bf16"][i])):
-            rot, tr = pose_errors(poses, oposes)
+        opr = oracle.Problem(p.points, [bf16_round(f) for f in p.feats], p.feat_kind, p.ell, p.cutoff_factor,
+                             search="cells")
+        rposes, _ = oracle.gn(opr, p.init_poses, p.edges, p.n_iter, membership=oracle.MEMBER_FP32_RULE)
+        for name, poses, ref in (("one at a time, f32", one[i], oposes), ("batched, f32", served["dense"][i], oposes),
+                                 ("batched, bf16", served["bf16"][i], oposes), (rounded, served["bf16"][i], rposes)):
+            rot, tr = pose_errors(poses, ref)
             worst[name][0] = max(worst[name][0], rot.max())
             worst[name][1] = max(worst[name][1], tr.max())
     for name, (r, t) in worst.items():
         say(f"[served-vs-oracle] {name}: largest rotation error {r:.3g} rad, translation error {t:.3g} m "
             f"over {len(reqs)} requests")
-    for name in ("one at a time, f32", "batched, f32"):
+    for name in ("one at a time, f32", "batched, f32", rounded):
         assert worst[name][0] <= ROT_TOL and worst[name][1] <= TRANS_TOL
     assert worst["batched, bf16"][0] <= 5e-3 and worst["batched, bf16"][1] <= 5e-3
