@@ -274,7 +274,9 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
             "pair_evals_per_s_one_at_a_time": seq_pairs / cap_s, "runs": runs,
             "max_pose_diff_vs_one_at_a_time_f32": {k: {"rot_rad": v[0], "trans_m": v[1]} for k, v in pose_diff.items()},
             "pose_accuracy_vs_fp64_oracle": "tests/test_gpu_server.py::test_served_forms_against_oracle (FP32 forms "
-                                            "within 1e-4 rad / 1e-4 m; bf16 printed)",
+                                            "within 1e-4 rad / 1e-4 m; the bf16 form within 1e-4 rad / 1e-4 m "
+                                            "of the oracle on bf16-rounded features, its difference to the "
+                                            "unrounded oracle printed)",
             "recipe": "requests: K ~ U{2..16} frames, N_m log-uniform in [5e3, 1.2e5], copies-of-a-scene or "
                       "depth-camera trajectory with a 0.3 m minimum range (p = 1/2), 20-class Dirichlet(0.3) soft "
                       "labels (D = 20), ell in {0.08, 0.3} m, all i<j pairs, 10 Gauss-Newton iterations, inputs "
