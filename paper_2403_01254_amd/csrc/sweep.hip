@@ -358,30 +358,46 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       // their x ranges' table entries, then the candidates kU at a time, so that the reads of a lane do not
       // wait on each other.
       constexpr int kR = 2, kU = 4;
+      // this lane's rows r = g, g + G, ... as (z, y) offsets r = oz * nys + oy, stepped without a division
+      int oz = 0, oy = 0, gz = 0, gy = 0;
+      if (nr > 0) {
+        oz = g / nys; oy = g - oz * nys;
+        gz = G / nys; gy = G - gz * nys;
+      }
       for (int r0 = g; r0 < nr; r0 += G * kR) {
         int4 R[kR];
         double r2s[kR];
+        int64_t ri[kR];
 #pragma unroll
         for (int t = 0; t < kR; ++t) {
-          const int r = r0 + G * t;
-          R[t] = make_int4(1, 0, 0, 0);  // empty
+          const int kz = zs0 + oz, ky = ys0 + oy;
+          oy += gy; oz += gz;
+          if (oy >= nys) { oy -= nys; ++oz; }
           r2s[t] = -1.0;
-          if (r < nr) {
-            const int kz = zs0 + r / nys, ky = ys0 + r % nys;
+          ri[t] = 0;  // rows outside the ball read the layer's first row, which exists, and drop it below
+          if (r0 + G * t < nr) {
             const double cz = (double)(kz + Fn.org[2]) * cell;
             const double cy = (double)(ky + Fn.org[1]) * cell;
             const double bz = fmax(0.0, fmax(cz - (double)q.z, (double)q.z - (cz + cell)));
             const double by = fmax(0.0, fmax(cy - (double)q.y, (double)q.y - (cy + cell)));
             r2s[t] = kc.reach2 - by * by - bz * bz;
-            if (r2s[t] >= 0.0) R[t] = trows[(int64_t)kz * Fn.dim[1] + ky];
+            if (r2s[t] >= 0.0) ri[t] = (int64_t)kz * Fn.dim[1] + ky;
           }
         }
+        // the batch's descriptor reads are issued together, then the rows outside the ball emptied
+#pragma unroll
+        for (int t = 0; t < kR; ++t) R[t] = trows[ri[t]];
+#pragma unroll
+        for (int t = 0; t < kR; ++t)
+          if (!(r2s[t] >= 0.0)) R[t] = make_int4(1, 0, 0, 0);
         uint32_t j0[kR], j1[kR];
 #pragma unroll
         for (int t = 0; t < kR; ++t) {
           j0[t] = j1[t] = 0u;
           if (r2s[t] >= 0.0 && R[t].y >= R[t].x) {
-            const double h = sqrt(r2s[t]);
+            // half-width of the ball's chord in x: the hardware FP32 root (within an ulp) widened by 2^-16,
+            // which exceeds the root's and the conversion's rounding, so no cell of the chord is lost
+            const double h = (double)__builtin_amdgcn_sqrtf((float)r2s[t]) * (1.0 + 0x1p-16);
             const int xa = max(clamp_floor_d(((double)q.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R[t].x);
             const int xb = min(clamp_floor_d(((double)q.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R[t].y);
             if (xa <= xb) {
@@ -512,7 +528,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep(PairArgs a) {
       if (r2 >= 0.0) {
         const int4 R = trows[(int64_t)kz * Fn.dim[1] + ky];
         if (R.y >= R.x) {
-          const double h = sqrt(r2);
+          const double h = (double)__builtin_amdgcn_sqrtf((float)r2) * (1.0 + 0x1p-16);  // widened as above
           const int xa = max(clamp_floor_d(((double)lo.x - h) * inv - Fn.org[0], -1, Fn.dim[0]), R.x);
           const int xb = min(clamp_floor_d(((double)hi.x + h) * inv - Fn.org[0], -1, Fn.dim[0]), R.y);
           if (xa <= xb) {
