@@ -190,16 +190,13 @@ __device__ inline uint8_t f32_to_e4m3(float v) {
   return (uint8_t)(sign | code);
 }
 
-// Gathers points (and features) into key order.  pts.w carries the class id
-// bits for one-hot features; dense rows are stored in the feature path's
-// element type, zero padded to Dp.
+// Gathers points into key order.  pts.w carries the class id bits for one-hot
+// features.
 __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restrict__ xyz,
-                                                     const void* const* __restrict__ feats, int feat_kind, int D,
-                                                     int Dp, const FrameInfo* __restrict__ frames,
+                                                     const void* const* __restrict__ feats, int feat_kind,
                                                      const int64_t* __restrict__ off, int K, int64_t n_total,
                                                      const uint32_t* __restrict__ sorted_vals,
-                                                     float4* __restrict__ pts, void* __restrict__ feat,
-                                                     int32_t* __restrict__ perm, int32_t* __restrict__ neg_flag) {
+                                                     float4* __restrict__ pts, int32_t* __restrict__ perm) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n_total) return;
   int f;
@@ -211,23 +208,39 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* const* __restr
   if (feat_kind == 0) w = __uint_as_float((uint32_t)((const uint16_t*)feats[f])[o]);
   pts[p] = make_float4(x[0], x[1], x[2], w);
   perm[p] = (int32_t)o;
-  if (feat_kind != 0) {
-    const float* src = (const float*)feats[f] + o * D;
-    bool neg = false;
-    for (int k = 0; k < Dp; ++k) {
-      const float v = k < D ? src[k] : 0.0f;
-      neg = neg || v < 0.0f;
-      if (feat_kind == 1) static_cast<float*>(feat)[p * Dp + k] = v;
-      else if (feat_kind == 2) static_cast<uint16_t*>(feat)[p * Dp + k] = f32_to_bf16(v);
-      else static_cast<uint8_t*>(feat)[p * Dp + k] = f32_to_e4m3(v);
-    }
-    // some inner products may be negative: one atomic per wavefront with such a row, none once the flag is set
-    // (a per-point atomic on the one flag word serialises)
-    const unsigned long long negs = __ballot(neg);
-    if (negs && (int)(threadIdx.x & 63) == __builtin_ctzll(negs) &&
-        __atomic_load_n(neg_flag, __ATOMIC_RELAXED) == 0)
-      atomicOr(neg_flag, 1);
+}
+
+// Gathers dense feature rows into key order, stored in the feature path's
+// element type and zero padded to Dp.  One thread per stored element, in
+// storage order: consecutive threads read consecutive elements of a point's
+// input row and write consecutive stored elements (one thread per point would
+// touch 64 scattered rows with every load and store).  IDX: the element index
+// type (32 bits whenever n_total * Dp fits).
+template <typename IDX>
+__global__ __launch_bounds__(kThreads) void k_gather_feat(const void* const* __restrict__ feats, int feat_kind, int D,
+                                                          int Dp, const int64_t* __restrict__ off, int K,
+                                                          int64_t n_total, const uint32_t* __restrict__ sorted_vals,
+                                                          void* __restrict__ feat, int32_t* __restrict__ neg_flag) {
+  const IDX i = (IDX)blockIdx.x * kThreads + threadIdx.x;
+  bool neg = false;
+  if ((int64_t)i < n_total * Dp) {
+    const IDX p = i / (IDX)Dp;
+    const int k = (int)(i - p * (IDX)Dp);
+    int f;
+    int64_t s;
+    frame_of(off, K, (int64_t)p, f, s);
+    const int64_t o = sorted_vals[p];
+    const float v = k < D ? static_cast<const float*>(feats[f])[o * D + k] : 0.0f;
+    neg = v < 0.0f;
+    if (feat_kind == 1) static_cast<float*>(feat)[i] = v;
+    else if (feat_kind == 2) static_cast<uint16_t*>(feat)[i] = f32_to_bf16(v);
+    else static_cast<uint8_t*>(feat)[i] = f32_to_e4m3(v);
   }
+  // some inner products may be negative: one atomic per wavefront with such an element, none once the flag is
+  // set (a per-element atomic on the one flag word serialises)
+  const unsigned long long negs = __ballot(neg);
+  if (negs && (int)(threadIdx.x & 63) == __builtin_ctzll(negs) && __atomic_load_n(neg_flag, __ATOMIC_RELAXED) == 0)
+    atomicOr(neg_flag, 1);
 }
 
 __device__ inline void decode(uint32_t key, const FrameInfo& F, int& kx, int& ky, int& kz) {
@@ -422,9 +435,19 @@ hipError_t launch_gather(const float* const* d_xyz_ptrs, const void* const* d_fe
                          const FrameInfo* d_frames, const int64_t* d_in_off, int K, int64_t n_total,
                          const uint32_t* d_sorted_vals, float4* d_pts, void* d_feat, int32_t* d_perm,
                          int32_t* d_neg_flag, hipStream_t st) {
-  if (n_total > 0)
-    k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, D, Dp, d_frames, d_in_off, K,
-                                                   n_total, d_sorted_vals, d_pts, d_feat, d_perm, d_neg_flag);
+  (void)d_frames;
+  if (n_total <= 0) return hipSuccess;
+  k_gather<<<blocks(n_total), kThreads, 0, st>>>(d_xyz_ptrs, d_feat_ptrs, feat_kind, d_in_off, K, n_total,
+                                                 d_sorted_vals, d_pts, d_perm);
+  if (feat_kind != 0) {
+    const int64_t total = n_total * Dp;
+    if (total <= (int64_t)UINT32_MAX - kThreads)
+      k_gather_feat<uint32_t><<<blocks(total), kThreads, 0, st>>>(d_feat_ptrs, feat_kind, D, Dp, d_in_off, K, n_total,
+                                                                  d_sorted_vals, d_feat, d_neg_flag);
+    else
+      k_gather_feat<uint64_t><<<blocks(total), kThreads, 0, st>>>(d_feat_ptrs, feat_kind, D, Dp, d_in_off, K, n_total,
+                                                                  d_sorted_vals, d_feat, d_neg_flag);
+  }
   return hipGetLastError();
 }
 
