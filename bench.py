@@ -267,6 +267,7 @@ def serving_benchmark(reqs, rkhsba, torch, log, seed=0, lanes=2, work_entries=8_
     for c in ctxs.values():
         c.close()
     return {"requests": len(reqs), "lanes": lanes, "lane_work_entries": work_entries,
+            "lane1_order": "built ahead, shortest estimated service less waiting time first (library default)",
             "capacity_one_at_a_time_solves_per_s": capacity,
             "not_pd_requests_one_at_a_time": len(not_pd),
             "capacity_batched_f32_solves_per_s": saturated["dense"]["solves_per_s"],

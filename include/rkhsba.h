@@ -344,8 +344,8 @@ typedef struct {
                                request is always admitted into an idle lane).  It bounds the work of one batch
                                iteration, which every active request of the lane waits for. */
   int lane1_max_active;     /* with 2 lanes: requests active together in lane 1 (default 1: a large request fills
-                               the device alone and large requests run in arrival order, beside lane 0's batch of
-                               small ones; 0: as max_active) */
+                               the device alone and large requests run one after another, in the order lane1_order
+                               sets, beside lane 0's batch of small ones; 0: as max_active) */
   double lane_split_work;   /* with 2 lanes: a request admitted to lane 0 whose entries times the points per
                                occupied r_c-cube that its build measured (an estimate of the candidate pairs of one
                                iteration) exceed this moves to lane 1, in arrival order (default 5e8; 0: off) */
@@ -353,6 +353,12 @@ typedef struct {
                                have active requests, lane 0 launches its next iteration only when its measured
                                device time divided by this weight is not ahead of lane 1's time, which caps its
                                share at w / (1 + w) (default 0.25; must be > 0) */
+  int lane1_order;          /* with 2 lanes and lane1_max_active 1: 1 (default) builds up to four of lane 1's
+                               waiting requests ahead while it runs one, and starts the built request whose
+                               estimated service time (its entries x the points per occupied r_c-cube its build
+                               measured x its evaluations, at the rate of lane 1's completed requests) less the time
+                               it has waited since submission is smallest; 0 starts them in arrival order.  Results
+                               do not depend on the order. */
 } rkhsba_server_options;
 
 typedef struct {

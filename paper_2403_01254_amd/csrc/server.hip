@@ -50,6 +50,8 @@ struct Req {
   int64_t est_bytes = 0;
   int64_t entries = 0;    // (edge, source point) entries: the request's share of every launch
   bool admitted = false;  // est_bytes counted in the server's committed total
+  double work = 0.0;      // entries x measured points per occupied r_c-cube x evaluations (set at the build)
+  bool timed = false;     // its service time feeds the estimate of lane 1's rate
   // progress (worker thread)
   int prob = -1;
   int evals = 0;
@@ -84,6 +86,7 @@ struct Lane {
   SetLayout lay;
   std::thread worker;
   std::deque<std::shared_ptr<Req>> queue;    // guarded by the server mutex
+  std::deque<std::shared_ptr<Req>> ready;    // built ahead, waiting to start (guarded by the server mutex)
   std::vector<std::shared_ptr<Req>> active;  // worker thread only
   int64_t dev_bytes = 0;                     // the engine's device memory, guarded by the server mutex
   hipEvent_t iter_ev[2] = {nullptr, nullptr};  // the last two batch iterations (bounds the host's lead)
@@ -117,6 +120,8 @@ struct rkhsba_server {
   bool stop = false;
   int64_t next_ticket = 1;
   int64_t committed = 0;  // estimated bytes of admitted requests (all lanes)
+  // lane 1's service rate: seconds from start to completion per unit of work, over its completed requests
+  double l1_work = 0.0, l1_secs = 0.0;
   int64_t row_bytes = 4;  // stored feature bytes per point (admission estimates)
   rkhsba_server_stats stats{};
   std::string err;
@@ -181,6 +186,10 @@ struct rkhsba_server {
     else stats.failed += 1;
     if (q->admitted) committed -= q->est_bytes;
     q->admitted = false;
+    if (status == RKHSBA_OK && q->timed && q->work > 0.0) {
+      l1_work += q->work;
+      l1_secs += std::chrono::duration<double>(q->t_done - q->t_admit).count();
+    }
     cv_done.notify_all();
     cv_work.notify_all();  // memory was released: other lanes may admit
   }
@@ -314,21 +323,58 @@ struct rkhsba_server {
     finish(q, code, msg);
   }
 
+  // Lane 1 with reordering: the built request to start next is the one whose estimated service time less
+  // the time it has waited since submission is smallest (arrival order until a completed request has given
+  // the lane a rate).  Waiting time enters one for one, so a long request is not passed over for ever.
+  // Called with the server mutex held.
+  std::shared_ptr<Req> pick_ready(Lane& L) {
+    const double rate = l1_work > 0.0 ? l1_secs / l1_work : 0.0;
+    const Clock::time_point now = Clock::now();
+    size_t best = 0;
+    double best_key = 0.0;
+    for (size_t i = 0; i < L.ready.size(); ++i) {
+      const double waited = std::chrono::duration<double>(now - L.ready[i]->t_submit).count();
+      const double key = L.ready[i]->work * rate - waited;
+      if (i == 0 || key < best_key) {
+        best = i;
+        best_key = key;
+      }
+    }
+    std::shared_ptr<Req> q = L.ready[best];
+    L.ready.erase(L.ready.begin() + (std::ptrdiff_t)best);
+    return q;
+  }
+
+  // Estimated work of a built request: entries x the points per occupied r_c-cube its build measured (the
+  // candidates of one iteration, up to a factor) x its evaluations.
+  static double request_work(const Req& q, const Problem* p) {
+    const double occ = p->occupancy_r > 0.0 ? p->occupancy_r : p->occupancy;
+    return (double)q.entries * occ * (double)(q.n_iter + 1);
+  }
+
   void run(Lane& L) {
     (void)hipSetDevice(opt.device);
     // lane 1 (large requests) runs at most lane1_max_active of them at once
     const int max_active = (L.id == 1 && opt.lane1_max_active > 0) ? std::min(opt.lane1_max_active, opt.max_active)
                                                                    : opt.max_active;
+    // lane 1 running one request at a time may start its waiting requests out of arrival order: while it runs
+    // one, it builds up to kReady of the next ahead (their builds measure the density that the service
+    // estimate needs), and starts the built one that pick_ready chooses
+    const bool reorder = L.id == 1 && max_active == 1 && opt.lane1_order == 1;
+    constexpr size_t kReady = 4;
     for (;;) {
       std::vector<std::shared_ptr<Req>> admit;
+      std::shared_ptr<Req> started, pre;
       release_delivered(L);
       {
         std::unique_lock<std::mutex> lk(mu);
-        if (L.active.empty()) cv_work.wait(lk, [&] { return stop || !L.queue.empty(); });
+        if (L.active.empty()) cv_work.wait(lk, [&] { return stop || !L.queue.empty() || !L.ready.empty(); });
         if (stop) break;
+        const bool running = !L.active.empty();
+        if (reorder && !running && !L.ready.empty()) started = pick_ready(L);
         int64_t work = 0;
         for (const auto& a : L.active) work += a->entries;
-        while (!L.queue.empty() && (int)(L.active.size() + admit.size()) < max_active) {
+        while (!started && !L.queue.empty() && (int)(L.active.size() + admit.size()) < max_active) {
           const std::shared_ptr<Req>& q = L.queue.front();
           const bool idle = L.active.empty() && admit.empty();
           if (!idle && committed + q->est_bytes > opt.hbm_budget_bytes) break;
@@ -339,6 +385,18 @@ struct rkhsba_server {
           admit.push_back(q);
           L.queue.pop_front();
         }
+        if (reorder && running && L.ready.size() < kReady && !L.queue.empty() &&
+            committed + L.queue.front()->est_bytes <= opt.hbm_budget_bytes) {
+          pre = L.queue.front();
+          L.queue.pop_front();
+          committed += pre->est_bytes;
+          pre->admitted = true;
+        }
+      }
+      if (started) {
+        started->t_admit = Clock::now();
+        started->timed = true;
+        L.active.push_back(started);
       }
       for (auto& q : admit) {
         try {
@@ -378,12 +436,35 @@ struct rkhsba_server {
           }
           L.eng->upload_poses(p, q->poses.data());
           L.eng->reset_state(p);
+          q->work = request_work(*q, p);
+          q->timed = reorder;
           q->t_admit = Clock::now();
           L.active.push_back(q);
         } catch (const Fail& f) {
           drop(L, q, f.code, f.msg);
         } catch (...) {
           drop(L, q, RKHSBA_EDEVICE, "unexpected exception at admission");
+        }
+      }
+      if (pre) {
+        // built while the lane's iterations run (at most two are in flight); it starts later
+        try {
+          pre->prob = L.eng->add_problem_auto(pre->par, pre->K, pre->n_points.data(), pre->xyz.data(),
+                                              pre->feat_kind, pre->D, pre->feats.data(), pre->is_device != 0);
+          Problem* p = L.eng->problem(pre->prob);
+          L.eng->upload_poses(p, pre->poses.data());
+          L.eng->reset_state(p);
+          pre->work = request_work(*pre, p);
+          const int64_t d = p->resident_bytes - Engine::estimate_resident_bytes(pre->K, pre->n_points.data(),
+                                                                                row_bytes);
+          std::lock_guard<std::mutex> lk(mu);
+          committed += d;
+          pre->est_bytes += d;
+          L.ready.push_back(pre);
+        } catch (const Fail& f) {
+          drop(L, pre, f.code, f.msg);
+        } catch (...) {
+          drop(L, pre, RKHSBA_EDEVICE, "unexpected exception at admission");
         }
       }
       if (L.active.empty()) continue;
@@ -478,6 +559,12 @@ struct rkhsba_server {
     release_delivered(L);
     for (auto& q : L.active) drop(L, q, RKHSBA_ESTATE, "server shut down");
     L.active.clear();
+    std::deque<std::shared_ptr<Req>> built;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      built.swap(L.ready);
+    }
+    for (auto& q : built) drop(L, q, RKHSBA_ESTATE, "server shut down");
     std::deque<std::shared_ptr<Req>> rest;
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -541,6 +628,7 @@ void rkhsba_server_default_options(rkhsba_server_options* o) {
   o->lane1_max_active = 1;
   o->lane_split_work = 5e8;
   o->lane0_weight = 0.25;
+  o->lane1_order = 1;
 }
 
 int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) {
@@ -552,7 +640,8 @@ int rkhsba_server_create(rkhsba_server** out, const rkhsba_server_options* opt) 
       opt->feat_kind < RKHSBA_FEAT_CLASS_ID || opt->feat_kind > RKHSBA_FEAT_DENSE_FP8 ||
       (opt->feat_kind != RKHSBA_FEAT_CLASS_ID && (opt->D < 1 || opt->D > kMaxDense)) || opt->lanes < 1 ||
       opt->lanes > 2 || opt->lane_split_entries < 0 || opt->lane_work_entries < 0 || opt->lane1_max_active < 0 ||
-      !(opt->lane_split_work >= 0.0) || !(opt->lane0_weight > 0.0 && opt->lane0_weight < 1e6))
+      !(opt->lane_split_work >= 0.0) || !(opt->lane0_weight > 0.0 && opt->lane0_weight < 1e6) ||
+      (opt->lane1_order != 0 && opt->lane1_order != 1))
     return RKHSBA_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) return RKHSBA_EDEVICE;
@@ -716,7 +805,7 @@ int rkhsba_server_stats_get(rkhsba_server* s, rkhsba_server_stats* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->stats;
   out->queued = 0;
-  for (const auto& L : s->lanes) out->queued += (int64_t)L->queue.size();
+  for (const auto& L : s->lanes) out->queued += (int64_t)(L->queue.size() + L->ready.size());
   return RKHSBA_OK;
 }
 

@@ -65,6 +65,7 @@ class ServerOptions(ctypes.Structure):
         ("lane1_max_active", ctypes.c_int),
         ("lane_split_work", ctypes.c_double),
         ("lane0_weight", ctypes.c_double),
+        ("lane1_order", ctypes.c_int),
     ]
 
 
@@ -430,7 +431,8 @@ class Server:
 
     def __init__(self, feat_kind="class", D=0, max_active=64, hbm_budget_bytes=0, device=0, pass_points=0,
                  use_graphs=True, hessian_fp32=False, stream=None, lanes=1, lane_split_entries=2_000_000,
-                 lane_work_entries=0, lane1_max_active=1, lane_split_work=5e8, lane0_weight=0.25):
+                 lane_work_entries=0, lane1_max_active=1, lane_split_work=5e8, lane0_weight=0.25,
+                 lane1_order=1):
         o = ServerOptions()
         lib().rkhsba_server_default_options(ctypes.byref(o))
         o.device = device
@@ -444,6 +446,7 @@ class Server:
         o.lane1_max_active = int(lane1_max_active)
         o.lane_split_work = float(lane_split_work)
         o.lane0_weight = float(lane0_weight)
+        o.lane1_order = int(lane1_order)
         self.opts = o
         self._h = ctypes.c_void_p()
         rc = lib().rkhsba_server_create(ctypes.byref(self._h), ctypes.byref(o))

@@ -57,17 +57,18 @@ def test_default_options_and_create_without_device(lib):
 
 def test_server_default_options_and_validation_without_device(lib):
     """The server's defaults as documented in the header, and argument checks that come before any device
-    call (lane count, work limit, split threshold, lane weight)."""
+    call (lane count, work limit, split threshold, lane weight, lane-1 order)."""
     from paper_2403_01254_amd import rkhsba
     o = rkhsba.ServerOptions()
     rkhsba.lib().rkhsba_server_default_options(ctypes.byref(o))
     assert (o.max_active, o.hbm_budget_bytes, o.pass_points, o.use_graphs, o.lanes) == (64, 0, 0, 1, 1)
     assert o.lane_split_entries == 2_000_000 and o.lane_work_entries == 0
     assert o.lane1_max_active == 1 and o.lane_split_work == 5e8 and o.lane0_weight == 0.25
+    assert o.lane1_order == 1
     h = ctypes.c_void_p()
     for field, value in (("lanes", 0), ("lanes", 3), ("lane_work_entries", -1), ("lane_split_entries", -1),
                          ("max_active", 0), ("lane0_weight", 0.0), ("lane0_weight", -1.0),
-                         ("lane0_weight", float("nan"))):
+                         ("lane0_weight", float("nan")), ("lane1_order", 2), ("lane1_order", -1)):
         bad = rkhsba.ServerOptions()
         rkhsba.lib().rkhsba_server_default_options(ctypes.byref(bad))
         setattr(bad, field, value)

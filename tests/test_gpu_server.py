@@ -36,16 +36,18 @@ def submit(srv, p):
     return srv.submit(p.points, p.feats, p.init_poses, p.edges, p.ell, p.n_iter)
 
 
-@pytest.mark.parametrize("lanes,split_work,lane1_max", [(1, 5e8, 1), (2, 5e8, 1), (2, 5e8, 0), (2, 1.0, 1)])
-def test_alone_and_in_mix_agree(rk, requests, lanes, split_work, lane1_max):
+@pytest.mark.parametrize("lanes,split_work,lane1_max,lane1_order",
+                         [(1, 5e8, 1, 1), (2, 5e8, 1, 1), (2, 5e8, 0, 1), (2, 1.0, 1, 1), (2, 1.0, 1, 0)])
+def test_alone_and_in_mix_agree(rk, requests, lanes, split_work, lane1_max, lane1_order):
     # plus one request with frames large enough for several entries per finalisation thread (with two
     # lanes it is the only one above the entry split and runs in the second lane, beside the others; with
-    # a work split of 1 every request built in lane 0 moves to lane 1 and is built again there)
+    # a work split of 1 every request built in lane 0 moves to lane 1 and is built again there, where it
+    # waits built ahead and starts in the order of its service estimate (lane1_order 1) or of arrival)
     requests = requests + [scenes.request(7, k_range=(3, 3), n_range=(40000, 60000), n_iter=2)]
-    say(f"[server] lanes {lanes} work split {split_work} lane-1 limit {lane1_max}: " +
+    say(f"[server] lanes {lanes} work split {split_work} lane-1 limit {lane1_max} order {lane1_order}: " +
         "; ".join(p.recipe[:60] for p in requests))
     with rk.Server(feat_kind="dense", D=20, max_active=8, lanes=lanes, lane_split_entries=60000,
-                   lane_split_work=split_work, lane1_max_active=lane1_max) as srv:
+                   lane_split_work=split_work, lane1_max_active=lane1_max, lane1_order=lane1_order) as srv:
         alone = [srv.wait(submit(srv, p), timeout=120) for p in requests]
         assert srv.stats()["max_active"] == 1
         tickets = [submit(srv, p) for p in requests]       # all in flight together
@@ -107,14 +109,18 @@ def test_served_matches_context_and_oracle(rk, requests):
         np.testing.assert_allclose(lpi, olpi, rtol=REL_TOL)
 
 
-def test_single_request_lane_matches_context(rk, requests):
+@pytest.mark.parametrize("lanes,lane1_order", [(1, 1), (2, 1), (2, 0)])
+def test_single_request_lane_matches_context(rk, requests, lanes, lane1_order):
     """A lane that runs one request at a time keeps the binning order of the request's first iteration, as
     the context's gn_step does: the served poses, loss and pair-count histories equal the context's bit for
-    bit."""
-    with rk.Server(feat_kind="dense", D=20, max_active=1) as srv:
+    bit.  With two lanes and no entry split every request goes to lane 1, which builds waiting requests
+    ahead and, with lane1_order 1, starts them out of arrival order: the results are the same."""
+    with rk.Server(feat_kind="dense", D=20, max_active=1 if lanes == 1 else 8, lanes=lanes, lane_split_entries=0,
+                   lane1_order=lane1_order) as srv:
         tickets = [submit(srv, p) for p in requests]
         served = [srv.wait(t, timeout=120) for t in tickets]
-        assert srv.stats()["max_active"] == 1
+        st = srv.stats()
+        assert st["max_active"] == 1 and st["completed"] == len(requests) and st["queued"] == 0
     for p, (poses, lpi, ppi, _, _) in zip(requests, served):
         ctx = rk.Context(ell=p.ell, cutoff_factor=p.cutoff_factor, cell_subdiv=0)
         ctx.build_neighbors(p.points, p.feats, p.feat_kind)
