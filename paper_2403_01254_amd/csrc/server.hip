@@ -323,6 +323,16 @@ struct rkhsba_server {
     finish(q, code, msg);
   }
 
+  // Builds a request's voxel structures in the lane's engine.  A build that grows a pool waits for the whole
+  // device, which the runtime refuses while any stream is capturing a graph; with two lanes the build
+  // therefore holds the launch lock, under which the other lane launches and captures its iterations.
+  int build_problem(Lane& L, const Req& q) {
+    std::unique_lock<std::mutex> dl(launch_mu, std::defer_lock);
+    if (lanes.size() > 1) dl.lock();
+    return L.eng->add_problem_auto(q.par, q.K, q.n_points.data(), q.xyz.data(), q.feat_kind, q.D, q.feats.data(),
+                                   q.is_device != 0);
+  }
+
   // Lane 1 with reordering: the built request to start next is the one whose estimated service time less
   // the time it has waited since submission is smallest (arrival order until a completed request has given
   // the lane a rate).  Waiting time enters one for one, so a long request is not passed over for ever.
@@ -400,8 +410,7 @@ struct rkhsba_server {
       }
       for (auto& q : admit) {
         try {
-          q->prob = L.eng->add_problem_auto(q->par, q->K, q->n_points.data(), q->xyz.data(), q->feat_kind, q->D,
-                                            q->feats.data(), q->is_device != 0);
+          q->prob = build_problem(L, *q);
           Problem* p = L.eng->problem(q->prob);
           if (L.id == 0 && lanes.size() > 1 && opt.lane_split_work > 0.0) {
             // The build measured the points per occupied r_c-cube: entries x that occupancy estimates the
@@ -449,8 +458,7 @@ struct rkhsba_server {
       if (pre) {
         // built while the lane's iterations run (at most two are in flight); it starts later
         try {
-          pre->prob = L.eng->add_problem_auto(pre->par, pre->K, pre->n_points.data(), pre->xyz.data(),
-                                              pre->feat_kind, pre->D, pre->feats.data(), pre->is_device != 0);
+          pre->prob = build_problem(L, *pre);
           Problem* p = L.eng->problem(pre->prob);
           L.eng->upload_poses(p, pre->poses.data());
           L.eng->reset_state(p);
