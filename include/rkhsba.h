@@ -26,6 +26,13 @@
  *     matrix with the weights frozen).  Frame-major, [rho(3); phi(3)] per frame.
  *   - Every call returns an rkhsba_status; rkhsba_last_error() describes the
  *     last failure on that context.  Calls on one context must not overlap.
+ *     Contexts on one device may be used from different threads, with one
+ *     limit: a call that has to grow one of its context's device pools (a
+ *     build, or the first solve of a larger problem) waits for the whole
+ *     device, which the HIP runtime refuses while another thread's call is
+ *     capturing its HIP graph (use_graphs); that call then fails with
+ *     RKHSBA_EDEVICE.  Serialize such calls across threads (the request
+ *     server does so for its two lanes).
  *   - Membership in the truncation radius is decided by the FP32 rule below,
  *     so the pair set is exactly reproducible on a CPU.
  *   - Values: the pair terms are FP32, from d = q32 - z of the rule.  F is
